@@ -1,0 +1,210 @@
+/*
+ * nyx.h -- C ABI of the MI355X per-ROI GLCM texture library (libnyx.so).
+ *
+ * The problem follows the paper's statement of regional feature extraction:
+ * an intensity image and a label mask go in, one row of measurements per
+ * unique nonzero label comes out (Supplementary Table S7, "ROI/FOV"; Main
+ * section, regional features).  The measurements are the grey-level
+ * co-occurrence (GLCM) features of Supplementary Table S3 (rows 140-174 with
+ * the NY mark; AVEAMP is not defined by the paper and is left out), in 2D
+ * and in 3D (Table S5, row 361), with the two hyper-parameters the paper
+ * names for texture cost O(m, g, s): the number of grey levels g and the
+ * spatial offset s (Materials and methods, "Feature Control and Tunability").
+ *
+ * Conventions shared by every call
+ *  - Images are [nz][ny][nx], x fastest; 2D images have nz = 1.  Label 0 is
+ *    background; all voxels with the same nonzero label form one ROI,
+ *    connected or not.
+ *  - Grey levels: fixed bin number over the ROI's own [min, max]:
+ *    level = 1 + floor(n_bins (I - min) / (max - min)), clamped to n_bins;
+ *    a constant ROI is level 1.  Computed exactly in integers.
+ *  - A voxel pair (v, v + d) is counted only when both voxels are inside the
+ *    image and carry the ROI's label.  Matrices are symmetric, P = C + C^T.
+ *  - ROIs are ordered by (image index, label), ascending.  Output rows follow
+ *    that order.
+ *  - Feature table: row r holds (n_offsets + 1) blocks of 30 values; block
+ *    k < n_offsets is direction k, the last block is the mean over the
+ *    directions that have at least one pair.  Element type float (NYX_FP32)
+ *    or double (NYX_FP64).  Undefined values (a direction with no pair) are
+ *    quiet NaN.  Column order: nyx_feature_name(0..29).
+ *  - Pointers are DEVICE pointers (HIP device memory, e.g. torch CUDA
+ *    tensors) unless the name ends in _host.  The caller owns all input and
+ *    output buffers; the library owns only scratch memory inside a context
+ *    or plan.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = null stream).  Calls
+ *    that must report a size to the host (nyx_bin_rois, nyx_glcm_accumulate,
+ *    nyx_plan_create) synchronise that stream once.
+ *  - Errors: a nyx_status is returned; on failure nyx_last_error(ctx) gives a
+ *    message (valid until the next call on that ctx).  Arguments are
+ *    validated before any device work: NYX_ERR_INVALID for n_bins outside
+ *    [2, 65535], n_offsets outside [1, 64], an offset (0,0,0), a non-positive
+ *    or too large dimension, dz != 0 on a 2D image, a NULL required pointer.
+ *    A too small output capacity gives NYX_ERR_CAPACITY with the required
+ *    size written to the *_host count (call once with capacity 0 to query).
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef NYX_H
+#define NYX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum nyx_status {
+    NYX_OK = 0,
+    NYX_ERR_INVALID = 1,
+    NYX_ERR_OOM = 2,
+    NYX_ERR_DEVICE = 3,
+    NYX_ERR_CAPACITY = 4,
+    NYX_ERR_UNSUPPORTED = 5,
+    NYX_ERR_INTERNAL = 6
+} nyx_status;
+
+typedef enum nyx_precision { NYX_FP32 = 0, NYX_FP64 = 1 } nyx_precision;
+
+typedef struct nyx_ctx nyx_ctx;
+typedef struct nyx_plan nyx_plan;
+typedef void *nyx_stream; /* hipStream_t */
+
+/* One neighbour offset (dz, dy, dx); y grows downward. */
+typedef struct nyx_offset { int32_t dz, dy, dx; } nyx_offset;
+
+/* One image: device arrays of nz*ny*nx elements (each dimension <= 65535 and
+ * nz*ny*nx < 2^31). */
+typedef struct nyx_image {
+    const uint16_t *intensity;
+    const uint32_t *labels;
+    int64_t nz, ny, nx;
+} nyx_image;
+
+/* Per-ROI statistics (device arrays of `capacity` entries; any array may be
+ * NULL when not wanted).  bbox holds 6 int32 per ROI: x_min, y_min, z_min,
+ * x_max, y_max, z_max (inclusive). */
+typedef struct nyx_roi_table {
+    uint32_t *label;
+    uint32_t *image;
+    uint64_t *n_vox;
+    uint16_t *vmin;
+    uint16_t *vmax;
+    int32_t *bbox;
+    int64_t capacity;
+    int64_t *n_rois_host; /* out: number of ROIs found */
+} nyx_roi_table;
+
+/* Sparse co-occurrence counts: the upper triangle U(i, j), i <= j, of each
+ * symmetric matrix, U(i, j) = P(i, j) for i < j and U(i, i) = P(i, i) / 2,
+ * as a COO list sorted by key.  key = roi << 38 | dir << 32 | (i - 1) << 16
+ * | (j - 1) with 1-based levels i <= j; count is exact (64-bit). */
+typedef struct nyx_glcm {
+    uint64_t *key;
+    uint64_t *count;
+    int64_t capacity;
+    int64_t *nnz_host;  /* out: number of nonzero cells */
+    int32_t n_bins;     /* set by nyx_glcm_accumulate */
+    int32_t n_offsets;  /* set by nyx_glcm_accumulate */
+    int32_t symmetric;  /* always 1 */
+    int64_t n_rois;     /* set by nyx_glcm_accumulate */
+} nyx_glcm;
+
+typedef struct nyx_extract_opts {
+    int32_t n_bins;
+    const nyx_offset *offsets_host;
+    int32_t n_offsets;
+    int32_t symmetric;           /* must be 1 */
+    nyx_precision precision;     /* feature output type */
+    int32_t autotune;            /* 1: time candidate kernel configurations at plan time */
+    int64_t workspace_cap_bytes; /* 0 = no cap; exceeding it gives NYX_ERR_OOM */
+} nyx_extract_opts;
+
+/* Context on one device (hipSetDevice ordinal).  NYX_ERR_DEVICE if absent. */
+nyx_status nyx_create(nyx_ctx **out, int device_ordinal);
+void nyx_destroy(nyx_ctx *ctx);
+const char *nyx_last_error(const nyx_ctx *ctx);
+const char *nyx_status_string(nyx_status s);
+
+/* Default offsets at a distance: dims 2 -> 0, 45, 90, 135 degrees
+ * ((0,0,1), (0,-1,1), (0,-1,0), (0,-1,-1)); dims 3 -> the 13 directions
+ * that represent the 26-neighbourhood up to sign.  out_host needs room for
+ * 13 entries; *n receives 4 or 13. */
+nyx_status nyx_offsets_default(int32_t dims, int32_t distance, nyx_offset *out_host, int32_t *n);
+
+int32_t nyx_feature_count(void);               /* 30 */
+const char *nyx_feature_name(int32_t f);       /* NULL outside [0, 30) */
+
+/* ROI discovery and per-ROI statistics (count, min, max, bbox) over a batch
+ * of images; optionally the per-voxel grey level under each voxel's own ROI
+ * (0 for background) into bins_out, laid out like the input images one after
+ * another.  Synchronises once to report the ROI count. */
+nyx_status nyx_bin_rois(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n_images, int32_t n_bins,
+                        nyx_roi_table *rois, uint16_t *bins_out, nyx_stream stream);
+
+/* Co-occurrence counts of the ROIs in `rois` (as produced by nyx_bin_rois,
+ * with *rois->n_rois_host rows) for the given offsets, as a sorted COO list.
+ * `bins` (nullable) is a bin image as written by nyx_bin_rois; when NULL,
+ * levels are computed on the fly from intensity and the ROI min/max.
+ * Synchronises to report the nonzero count. */
+nyx_status nyx_glcm_accumulate(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n_images,
+                               const nyx_roi_table *rois, const uint16_t *bins,
+                               const nyx_offset *offsets_host, int32_t n_offsets, int32_t symmetric,
+                               int32_t n_bins, nyx_glcm *out, nyx_stream stream);
+
+/* Feature table from a COO list as written by nyx_glcm_accumulate.
+ * table has room for table_capacity_rows rows (glcm->n_rois needed). */
+nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, nyx_precision prec, void *table,
+                             int64_t table_capacity_rows, nyx_stream stream);
+
+/* Whole path in one call: plan, execute once, destroy the plan. */
+nyx_status nyx_extract_batch(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n_images,
+                             const nyx_extract_opts *opts, nyx_roi_table *rois, void *table,
+                             int64_t table_capacity_rows, nyx_stream stream);
+
+/* Plan for repeated extraction over images with the same geometry and
+ * labels-per-image capacity: discovers the ROIs once (one synchronisation),
+ * sizes the work queue and scratch, and (with opts->autotune) picks the
+ * kernel configuration by timing.  *n_rois_host receives the ROI count.
+ * The image arrays must stay valid (and may change contents) while the plan
+ * lives; a later execution whose labels exceed the planned capacity reports
+ * NYX_ERR_CAPACITY from nyx_plan_check. */
+nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n_images,
+                           const nyx_extract_opts *opts, nyx_plan **out, int64_t *n_rois_host);
+
+/* One full pass of the batched path (ROI discovery, binning, accumulation,
+ * features) as one graph replay on `stream`.  rois may be NULL. */
+nyx_status nyx_plan_execute(nyx_plan *plan, nyx_roi_table *rois, void *table, nyx_stream stream);
+
+/* The same pass with one kernel launch per ROI (comparison baseline). */
+nyx_status nyx_plan_execute_per_roi(nyx_plan *plan, nyx_roi_table *rois, void *table,
+                                    nyx_stream stream);
+
+/* Phases of one step, in order (indices into nyx_plan_profile's output). */
+typedef enum nyx_phase {
+    NYX_PHASE_RESET = 0,     /* clear per-label statistics and counters */
+    NYX_PHASE_SCAN = 1,      /* ROI discovery: count, min, max, bbox per label */
+    NYX_PHASE_COMPACT = 2,   /* ROI table and size-sorted work queue */
+    NYX_PHASE_ZERO = 3,      /* clear the global matrices of split ROIs */
+    NYX_PHASE_BATCH = 4,     /* binning, co-occurrence counts, features */
+    NYX_PHASE_FINALIZE = 5,  /* features of split ROIs from global matrices */
+    NYX_PHASE_COUNT = 6
+} nyx_phase;
+
+/* Runs one step eagerly (no graph) on `stream` with HIP events between its
+ * phases, synchronises, and writes the duration of each phase in
+ * milliseconds to ms_host[NYX_PHASE_COUNT].  Results land in `table` as with
+ * nyx_plan_execute.  For measurement only. */
+nyx_status nyx_plan_profile(nyx_plan *plan, void *table, float *ms_host, nyx_stream stream);
+
+/* Synchronises `stream` and reports any device-side capacity overflow of
+ * the last execution. */
+nyx_status nyx_plan_check(nyx_plan *plan, nyx_stream stream);
+
+/* Human-readable description of the configuration the plan uses. */
+const char *nyx_plan_describe(const nyx_plan *plan);
+
+void nyx_plan_destroy(nyx_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NYX_H */

@@ -1,0 +1,876 @@
+// nyx_kernels.hip -- HIP kernels for CDNA4 (gfx950): per-ROI GLCM texture.
+//
+//   k_max_label        planning: largest label per image
+//   k_reset            clear the per-label statistics and counters
+//   k_scan             ROI discovery: per-label count, min, max, bbox
+//   k_compact_*        ROI table in (image, label) order + size-sorted work queue
+//   k_bin_image        per-voxel grey levels (explicit binning output)
+//   k_batch            persistent work-stealing accumulation + features
+//   k_split_features   features of ROIs whose matrices were merged in global memory
+//   k_rows             feature rows (direction blocks + mean) from a scratch table
+//   k_coo_*            sorted COO export / import of the co-occurrence counts
+//
+// The method: the paper's regional texture extraction (one row per unique
+// label, Supplementary Table S7) with the GLCM features of Table S3 under
+// fixed-bin-number discretisation and symmetric matrices over the given
+// offsets (Materials and methods, "Feature Control and Tunability").
+#include <hip/hip_runtime.h>
+#include <limits.h>
+
+#include "nyx_device.h"
+#include "nyx_features.h"
+#include "nyx_launch.h"
+
+namespace nyx {
+
+__device__ __forceinline__ int find_image_chunk(const ImgDesc *imgs, int n, uint32_t chunk) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (imgs[mid].chunk_base <= chunk) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int find_image_entry(const ImgDesc *imgs, int n, uint32_t e) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (imgs[mid].tab_base <= e) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------------ planning
+__global__ void k_max_label(const ImgDesc *imgs, int n_images, uint32_t *out) {
+    int im = blockIdx.y;
+    if (im >= n_images) return;
+    const ImgDesc d = imgs[im];
+    uint32_t m = 0;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < d.nvox; v += gridDim.x * blockDim.x)
+        m = max(m, d.L[v]);
+    m = wave_max(m);
+    if (lane() == 0) atomicMax(&out[im], m);
+}
+
+// ------------------------------------------------------------------ reset
+__global__ void k_reset(StepArgs a, uint32_t n_counters) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t e = i; e < a.tab.total; e += stride) {
+        a.tab.cnt[e] = 0u;
+        a.tab.mn[e] = 0xFFFFFFFFu;
+        a.tab.mx[e] = 0u;
+        a.tab.x0[e] = INT_MAX; a.tab.y0[e] = INT_MAX; a.tab.z0[e] = INT_MAX;
+        a.tab.x1[e] = -1; a.tab.y1[e] = -1; a.tab.z1[e] = -1;
+        a.tab.row[e] = kNone;
+    }
+    for (uint32_t e = i; e < n_counters; e += stride) a.counters[e] = 0u;
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Zero the global matrices of the split slots the last compaction assigned.
+__global__ void k_zero_split(StepArgs a) {
+    uint32_t used = a.counters[C_NSPLIT];
+    if (used > a.g_cap) used = a.g_cap;
+    uint64_t n = (uint64_t)used * a.K * (uint64_t)a.ng * a.ng;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        a.G[i] = 0ull;
+}
+
+// ------------------------------------------------------------------ scan
+// Each lane takes 8 consecutive voxels; a wavefront then folds the statistics
+// of each distinct label present in its 512 voxels and one lane per label
+// updates the global per-label entry.
+__global__ __launch_bounds__(256) void k_scan(StepArgs a) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = c < a.total_chunks;
+    const int im = find_image_chunk(a.imgs, a.n_images, in ? c : 0u);
+    const ImgDesc d = a.imgs[im];
+    const uint32_t v0 = (c - d.chunk_base) * 8u;
+    uint32_t lab[8], val[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) { lab[j] = 0u; val[j] = 0u; }
+    if (in && v0 < d.nvox) {
+        if (d.vec_ok) {
+            uint4 l0 = *reinterpret_cast<const uint4 *>(d.L + v0);
+            uint4 l1 = *reinterpret_cast<const uint4 *>(d.L + v0 + 4);
+            uint4 iv = *reinterpret_cast<const uint4 *>(d.I + v0);
+            lab[0] = l0.x; lab[1] = l0.y; lab[2] = l0.z; lab[3] = l0.w;
+            lab[4] = l1.x; lab[5] = l1.y; lab[6] = l1.z; lab[7] = l1.w;
+            val[0] = iv.x & 0xFFFFu; val[1] = iv.x >> 16; val[2] = iv.y & 0xFFFFu; val[3] = iv.y >> 16;
+            val[4] = iv.z & 0xFFFFu; val[5] = iv.z >> 16; val[6] = iv.w & 0xFFFFu; val[7] = iv.w >> 16;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                uint32_t v = v0 + j;
+                if (v < d.nvox) { lab[j] = d.L[v]; val[j] = d.I[v]; }
+            }
+        }
+    }
+    uint32_t key[8];
+    uint32_t pend = 0u, bad = 0u;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        uint32_t l = lab[j];
+        key[j] = kNone;
+        if (l != 0u) {
+            if (l > d.max_label) bad = 1u;
+            else { key[j] = d.tab_base + l; pend |= 1u << j; }
+        }
+    }
+    if (bad) atomicOr(&a.counters[C_ERR], (uint32_t)E_LABEL_RANGE);
+    const uint32_t nx = (uint32_t)d.nx, ny = (uint32_t)d.ny;
+    uint32_t rowi = v0 / nx;
+    int32_t x = (int32_t)(v0 - rowi * nx);
+    uint32_t zz = rowi / ny;
+    int32_t y = (int32_t)(rowi - zz * ny), z = (int32_t)zz;
+    int32_t xs[8], ys[8], zs[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        xs[j] = x; ys[j] = y; zs[j] = z;
+        if (++x == (int32_t)nx) { x = 0; if (++y == (int32_t)ny) { y = 0; ++z; } }
+    }
+    while (true) {
+        uint64_t act = __ballot(pend != 0u);
+        if (act == 0ull) break;
+        int leader = __ffsll((unsigned long long)act) - 1;
+        uint32_t mine = kNone;
+#pragma unroll
+        for (int j = 7; j >= 0; --j)
+            if ((pend >> j) & 1u) mine = key[j];
+        uint32_t K = __shfl(mine, leader);
+        uint32_t cnt = 0u, mn = 0xFFFFu, mx = 0u;
+        int32_t bx0 = INT_MAX, by0 = INT_MAX, bz0 = INT_MAX, bx1 = -1, by1 = -1, bz1 = -1;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (((pend >> j) & 1u) && key[j] == K) {
+                ++cnt;
+                mn = min(mn, val[j]); mx = max(mx, val[j]);
+                bx0 = min(bx0, xs[j]); bx1 = max(bx1, xs[j]);
+                by0 = min(by0, ys[j]); by1 = max(by1, ys[j]);
+                bz0 = min(bz0, zs[j]); bz1 = max(bz1, zs[j]);
+                pend &= ~(1u << j);
+            }
+        }
+        cnt = wave_sum(cnt);
+        mn = wave_min(mn); mx = wave_max(mx);
+        bx0 = wave_min(bx0); by0 = wave_min(by0); bz0 = wave_min(bz0);
+        bx1 = wave_max(bx1); by1 = wave_max(by1); bz1 = wave_max(bz1);
+        if (lane() == leader) {
+            atomicAdd(&a.tab.cnt[K], cnt);
+            atomicMin(&a.tab.mn[K], mn);
+            atomicMax(&a.tab.mx[K], mx);
+            atomicMin(&a.tab.x0[K], bx0); atomicMin(&a.tab.y0[K], by0); atomicMin(&a.tab.z0[K], bz0);
+            atomicMax(&a.tab.x1[K], bx1); atomicMax(&a.tab.y1[K], by1); atomicMax(&a.tab.z1[K], bz1);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ compaction
+__global__ __launch_bounds__(1024) void k_compact_count(StepArgs a) {
+    __shared__ uint32_t wc[16];
+    uint32_t e = blockIdx.x * 1024u + threadIdx.x;
+    bool p = e < a.tab.total && a.tab.cnt[e] > 0u;
+    uint64_t m = __ballot(p);
+    if (lane() == 0) wc[threadIdx.x / 64] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int w = 0; w < 16; ++w) s += wc[w];
+        a.counters[C_BLOCKS + blockIdx.x] = s;
+    }
+}
+
+// Rows are assigned in (image, label) order.  Each ROI is cut into tiles of
+// bbox rows when large, and its tiles are appended to the bucket of their size
+// class, so the persistent kernel can drain the largest work first.
+__global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi_lo, uint32_t roi_hi) {
+    __shared__ uint32_t wc[16], wpre[16], s_part[16], s_prefix;
+    uint32_t part = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += 1024u) part += a.counters[C_BLOCKS + b];
+    part = wave_sum(part);
+    if (lane() == 0) s_part[threadIdx.x / 64] = part;
+    uint32_t e = blockIdx.x * 1024u + threadIdx.x;
+    bool p = e < a.tab.total && a.tab.cnt[e] > 0u;
+    uint64_t m = __ballot(p);
+    if (lane() == 0) wc[threadIdx.x / 64] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0, acc = 0;
+        for (int w = 0; w < 16; ++w) s += s_part[w];
+        s_prefix = s;
+        for (int w = 0; w < 16; ++w) { wpre[w] = acc; acc += wc[w]; }
+        if (blockIdx.x == gridDim.x - 1) a.counters[C_NROIS] = s + acc;
+    }
+    __syncthreads();
+    if (!p) return;
+    const uint32_t rank = (uint32_t)__popcll(m & __lanemask_lt());
+    const uint32_t row = s_prefix + wpre[threadIdx.x / 64] + rank;
+    if (row >= a.roi_cap) { atomicOr(&a.counters[C_ERR], (uint32_t)E_ROI_CAP); return; }
+    const int im = find_image_entry(a.imgs, a.n_images, e);
+    const uint32_t label = e - a.imgs[im].tab_base;
+    RoiDesc rd;
+    rd.label = label;
+    rd.image = (uint32_t)im;
+    rd.n = a.tab.cnt[e];
+    rd.vmin = a.tab.mn[e];
+    rd.vmax = a.tab.mx[e];
+    rd.x0 = a.tab.x0[e]; rd.y0 = a.tab.y0[e]; rd.z0 = a.tab.z0[e];
+    rd.x1 = a.tab.x1[e]; rd.y1 = a.tab.y1[e]; rd.z1 = a.tab.z1[e];
+    rd.rows = (uint32_t)(rd.z1 - rd.z0 + 1) * (uint32_t)(rd.y1 - rd.y0 + 1);
+    rd.pad1 = 0u;
+    a.tab.row[e] = row;
+    const bool take = a.enqueue && row >= roi_lo && row < roi_hi;
+    const Tiling tl = tiles_for(rd.n, rd.rows, (uint32_t)(rd.x1 - rd.x0 + 1), a.split_vox, a.tile_vox);
+    const uint32_t nt = tl.row_blocks * tl.col_blocks;
+    rd.n_tiles = nt;
+    rd.tcols = tl.col_blocks;
+    rd.gslot = kNone;
+    if (take && (nt > 1u || a.force_split)) {
+        uint32_t s = a.force_split ? row - roi_lo : atomicAdd(&a.counters[C_NSPLIT], 1u);
+        if (s >= a.g_cap) {
+            atomicOr(&a.counters[C_ERR], (uint32_t)E_SPLIT_CAP);
+        } else {
+            rd.gslot = s;
+            a.split_roi[s] = row;
+        }
+    }
+    a.rois[row] = rd;
+    if (take && (rd.gslot != kNone || nt == 1u)) {
+        uint32_t cls = size_class((rd.n + nt - 1u) / nt);
+        uint32_t pos = atomicAdd(&a.counters[C_CLASS + cls], nt);
+        if (pos + nt > a.bucket_cap) {
+            atomicOr(&a.counters[C_ERR], (uint32_t)E_ITEM_CAP);
+        } else {
+            for (uint32_t t = 0; t < nt; ++t) a.buckets[cls * a.bucket_cap + pos + t] = make_uint2(row, t);
+        }
+    }
+    if (a.o_label) a.o_label[row] = label;
+    if (a.o_image) a.o_image[row] = (uint32_t)im;
+    if (a.o_n) a.o_n[row] = rd.n;
+    if (a.o_min) a.o_min[row] = (uint16_t)rd.vmin;
+    if (a.o_max) a.o_max[row] = (uint16_t)rd.vmax;
+    if (a.o_bbox) {
+        int32_t *b = a.o_bbox + 6ull * row;
+        b[0] = rd.x0; b[1] = rd.y0; b[2] = rd.z0; b[3] = rd.x1; b[4] = rd.y1; b[5] = rd.z1;
+    }
+}
+
+// In force_split mode the split-slot count is the ROI range size.
+__global__ void k_set_nsplit(StepArgs a, uint32_t roi_lo, uint32_t roi_hi) {
+    uint32_t n = a.counters[C_NROIS];
+    uint32_t hi = roi_hi < n ? roi_hi : n;
+    a.counters[C_NSPLIT] = hi > roi_lo ? hi - roi_lo : 0u;
+}
+
+// ------------------------------------------------------------------ binning
+__global__ __launch_bounds__(256) void k_bin_image(StepArgs a, uint16_t *bins_out, uint64_t total_vox,
+                                                   const uint64_t *img_vox_base) {
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < total_vox;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = a.n_images - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (img_vox_base[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        const ImgDesc &d = a.imgs[lo];
+        uint32_t v = (uint32_t)(g - img_vox_base[lo]);
+        uint32_t l = d.L[v];
+        uint16_t b = 0;
+        if (l != 0u && l <= d.max_label) {
+            uint32_t r = a.tab.row[d.tab_base + l];
+            if (r != kNone && r < a.roi_cap) {
+                const RoiDesc &rd = a.rois[r];
+                uint32_t D = rd.vmax - rd.vmin;
+                b = (uint16_t)fbn_level(d.I[v], rd.vmin, D, D ? 1.0f / (float)D : 0.0f, (uint32_t)a.ng);
+            }
+        }
+        bins_out[g] = b;
+    }
+}
+
+// ------------------------------------------------------------------ batch
+// Exact q = f / W for f < 2^31 and 1 <= W < 2^31: the double-precision
+// estimate is within one of the quotient.
+__device__ __forceinline__ uint32_t udiv_exact(uint32_t f, uint32_t W, double rcpW) {
+    int64_t q = (int64_t)((double)f * rcpW);
+    int64_t r = (int64_t)f - q * (int64_t)W;
+    if (r < 0) { --q; r += (int64_t)W; }
+    if (r >= (int64_t)W) { ++q; }
+    return (uint32_t)q;
+}
+
+struct ItemCtx {
+    const uint16_t *I;
+    const uint32_t *L;
+    const uint16_t *B;
+    int32_t nx, ny, nz;
+    uint32_t label, vmin, D, ng;
+    float rcpD;
+    uint32_t *err;
+    // Level of voxel v; a caller-supplied bin image is clamped to [1, ng]
+    // (flagging the error) so no LDS address can leave its triangle.
+    __device__ __forceinline__ uint32_t level(uint32_t v) const {
+        if (!B) return fbn_level(I[v], vmin, D, rcpD, ng);
+        uint32_t b = B[v];
+        if (b == 0u || b > ng) {
+            atomicOr(err, (uint32_t)E_BIN_RANGE);
+            b = b == 0u ? 1u : ng;
+        }
+        return b;
+    }
+};
+
+// Add one unordered level pair (1-based a, b) to local direction dl.
+template <int MODE>
+__device__ __forceinline__ void add_pair(const StepArgs &a, uint8_t *smem, uint32_t dl, uint32_t la,
+                                         uint32_t lb) {
+    const LdsLayout &Ly = a.lds;
+    uint32_t lo = (la < lb ? la : lb) - 1u, hi = (la < lb ? lb : la) - 1u;
+    uint32_t *LCNT = reinterpret_cast<uint32_t *>(smem + Ly.lcnt_off);
+    uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off) + dl * Ly.list_cap;
+    if (MODE == 0) {
+        uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
+        uint32_t old = atomicAdd(&U[tri_idx(lo, hi)], 1u);
+        bool fresh = old == 0u;
+        uint64_t m = __ballot(fresh);
+        if (m) {
+            int leader = __ffsll((unsigned long long)m) - 1;
+            uint32_t base = 0;
+            if (lane() == leader) base = atomicAdd(&LCNT[dl], (uint32_t)__popcll(m));
+            base = __shfl(base, leader);
+            if (fresh) {
+                uint32_t pos = base + (uint32_t)__popcll(m & __lanemask_lt());
+                if (pos < Ly.list_cap) LST[pos] = lo | (hi << 16);
+                else atomicOr(&a.counters[C_ERR], (uint32_t)E_LIST_CAP);
+            }
+        }
+    } else {
+        uint32_t *HK = reinterpret_cast<uint32_t *>(smem + Ly.hkey_off);
+        uint32_t *HC = reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off);
+        const uint32_t key = (dl << 26) | (hi << 13) | lo;
+        const uint32_t mask = Ly.hash_cap - 1u;
+        uint32_t h = hash_u32(key) & mask;
+        bool done = false;
+        for (uint32_t probe = 0; probe < Ly.hash_cap; ++probe) {
+            uint32_t cur = atomicCAS(&HK[h], kNone, key);
+            if (cur == kNone || cur == key) {
+                atomicAdd(&HC[h], 1u);
+                if (cur == kNone) {
+                    uint32_t pos = atomicAdd(&LCNT[dl], 1u);
+                    if (pos < Ly.list_cap) LST[pos] = h;
+                    else atomicOr(&a.counters[C_ERR], (uint32_t)E_LIST_CAP);
+                }
+                done = true;
+                break;
+            }
+            h = (h + 1u) & mask;
+        }
+        if (!done) atomicOr(&a.counters[C_ERR], (uint32_t)E_HASH_FULL);
+    }
+}
+
+// Accumulate the pairs owned by the voxels of bbox rows [ra, rb) for the
+// directions [d0, d1): each voxel owns the pair (v, v + d) of each offset.
+template <int MODE>
+__device__ void accumulate_rows(const StepArgs &a, uint8_t *smem, const RoiDesc &rd, const ItemCtx &c,
+                                uint32_t ra, uint32_t rb, uint32_t ca, uint32_t cb, int d0, int d1) {
+    const uint32_t W = cb - ca, H = (uint32_t)(rd.y1 - rd.y0 + 1);
+    const double rcpW = 1.0 / (double)W, rcpH = 1.0 / (double)H;
+    const uint32_t nv = (rb - ra) * W;
+    const int64_t plane = (int64_t)c.ny * c.nx;
+    for (uint32_t f = threadIdx.x; f < nv; f += blockDim.x) {
+        uint32_t q = udiv_exact(f, W, rcpW);
+        int32_t x = rd.x0 + (int32_t)ca + (int32_t)(f - q * W);
+        uint32_t rr = ra + q;
+        uint32_t zq = udiv_exact(rr, H, rcpH);
+        int32_t y = rd.y0 + (int32_t)(rr - zq * H);
+        int32_t z = rd.z0 + (int32_t)zq;
+        int64_t v = (int64_t)z * plane + (int64_t)y * c.nx + x;
+        if (c.L[v] != c.label) continue;
+        uint32_t bv = c.level((uint32_t)v);
+        for (int d = d0; d < d1; ++d) {
+            int32_t dz = a.off[d][0], dy = a.off[d][1], dx = a.off[d][2];
+            int32_t wz = z + dz, wy = y + dy, wx = x + dx;
+            if (wz < 0 || wz >= c.nz || wy < 0 || wy >= c.ny || wx < 0 || wx >= c.nx) continue;
+            int64_t w = v + (int64_t)dz * plane + (int64_t)dy * c.nx + dx;
+            if (c.L[w] != c.label) continue;
+            add_pair<MODE>(a, smem, (uint32_t)(d - d0), bv, c.level((uint32_t)w));
+        }
+    }
+}
+
+template <class OutT>
+__device__ void write_row(const StepArgs &a, uint32_t row, const double *feat, int K) {
+    if (row >= a.table_rows) {
+        if (threadIdx.x == 0) atomicOr(&a.counters[C_ERR], (uint32_t)E_TABLE_CAP);
+        return;
+    }
+    OutT *out = reinterpret_cast<OutT *>(a.table) + (uint64_t)row * (K + 1) * kNumFeat;
+    for (int t = threadIdx.x; t < (K + 1) * kNumFeat; t += blockDim.x) {
+        int blk = t / kNumFeat, f = t - blk * kNumFeat;
+        double v;
+        if (blk < K) {
+            v = feat[blk * kNumFeat + f];
+        } else {
+            double s = 0.0;
+            int n = 0;
+            for (int k = 0; k < K; ++k)
+                if (!isnan(feat[k * kNumFeat])) { s += feat[k * kNumFeat + f]; ++n; }
+            v = n ? s / (double)n : __builtin_nan("");
+        }
+        out[t] = (OutT)v;
+    }
+}
+
+template <int MODE, class OutT>
+__global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    typedef typename std::conditional<sizeof(OutT) == 8, double, float>::type Acc;
+    const LdsLayout &Ly = a.lds;
+    uint32_t *LCNT = reinterpret_cast<uint32_t *>(smem + Ly.lcnt_off);
+    uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off);
+    double *FEAT = reinterpret_cast<double *>(smem + Ly.feat_off);
+    uint32_t *MISC = reinterpret_cast<uint32_t *>(smem + Ly.misc_off);
+    const int nw = (int)(blockDim.x / kWave), w = (int)(threadIdx.x / kWave);
+    const int K = a.K;
+    const uint32_t ng = (uint32_t)a.ng;
+    const uint32_t marg_words = 4u * ng;
+    uint32_t *MARG = reinterpret_cast<uint32_t *>(smem + Ly.marg_off) + w * marg_words;
+
+    // LDS starts clean and every item leaves it clean.
+    if (MODE == 0) {
+        uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off);
+        for (uint32_t i = threadIdx.x; i < Ly.kp * Ly.tri_pad; i += blockDim.x) U[i] = 0u;
+    } else {
+        uint32_t *HK = reinterpret_cast<uint32_t *>(smem + Ly.hkey_off);
+        uint32_t *HC = reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off);
+        for (uint32_t i = threadIdx.x; i < Ly.hash_cap; i += blockDim.x) { HK[i] = kNone; HC[i] = 0u; }
+    }
+    for (uint32_t i = threadIdx.x; i < (uint32_t)nw * marg_words; i += blockDim.x)
+        reinterpret_cast<uint32_t *>(smem + Ly.marg_off)[i] = 0u;
+    for (uint32_t i = threadIdx.x; i < Ly.kp; i += blockDim.x) LCNT[i] = 0u;
+    if (threadIdx.x == 0 && direct_roi == kNone) {
+        // class order: largest first; counts clamped to what the buckets hold
+        uint32_t acc = 0;
+        for (int cl = kClasses - 1; cl >= 0; --cl) {
+            uint32_t cnt = min(a.counters[C_CLASS + cl], a.bucket_cap);
+            MISC[8 + cl] = acc;
+            MISC[40 + cl] = cnt;
+            acc += cnt;
+        }
+        MISC[7] = acc;
+    }
+    __syncthreads();
+
+    for (uint32_t iter = 0;; ++iter) {
+        if (threadIdx.x == 0) {
+            uint32_t ok = 0, roi = 0, tile = 0;
+            if (direct_roi != kNone) {
+                if (iter == 0 && direct_roi < a.roi_cap) {
+                    roi = direct_roi;
+                    tile = blockIdx.x;
+                    ok = tile < a.rois[roi].n_tiles;
+                }
+            } else {
+                uint32_t t = atomicAdd(&a.counters[C_TICKET], 1u);
+                if (t < MISC[7]) {
+                    int cl = kClasses - 1;
+                    while (cl > 0 && t >= MISC[8 + cl] + MISC[40 + cl]) --cl;
+                    uint2 it = a.buckets[(uint32_t)cl * a.bucket_cap + (t - MISC[8 + cl])];
+                    roi = it.x;
+                    tile = it.y;
+                    ok = 1;
+                } else {
+                    ok = 0;
+                }
+                // an entry that does not name a valid ROI tile is skipped
+                if (ok && (roi >= a.roi_cap || tile >= a.rois[roi].n_tiles)) ok = 2;
+            }
+            MISC[0] = roi;
+            MISC[1] = tile;
+            MISC[2] = ok;
+        }
+        __syncthreads();
+        if (!MISC[2]) break;
+        if (MISC[2] != 1u) { __syncthreads(); continue; }
+        const uint32_t roi = MISC[0], tile = MISC[1];
+        const RoiDesc rd = a.rois[roi];
+        if (rd.image >= (uint32_t)a.n_images) { __syncthreads(); continue; }
+        const ImgDesc im = a.imgs[rd.image];
+        if (rd.x0 < 0 || rd.y0 < 0 || rd.z0 < 0 || rd.x1 >= im.nx || rd.y1 >= im.ny || rd.z1 >= im.nz ||
+            rd.x0 > rd.x1 || rd.y0 > rd.y1 || rd.z0 > rd.z1 || rd.n_tiles == 0u || rd.tcols == 0u) {
+            __syncthreads();
+            continue;
+        }
+        ItemCtx c;
+        c.I = im.I; c.L = im.L; c.B = im.B;
+        c.nx = im.nx; c.ny = im.ny; c.nz = im.nz;
+        c.label = rd.label; c.vmin = rd.vmin; c.D = rd.vmax - rd.vmin; c.ng = ng;
+        c.rcpD = c.D ? 1.0f / (float)c.D : 0.0f;
+        c.err = &a.counters[C_ERR];
+        uint32_t ra, rb, ca, cb;
+        tile_bounds(rd.rows, (uint32_t)(rd.x1 - rd.x0 + 1), rd.n_tiles, rd.tcols, tile, &ra, &rb, &ca, &cb);
+        const bool split = rd.gslot != kNone;
+        for (int d0 = 0; d0 < K; d0 += (int)Ly.kp) {
+            const int d1 = min(K, d0 + (int)Ly.kp);
+            if (ra < rb && ca < cb) accumulate_rows<MODE>(a, smem, rd, c, ra, rb, ca, cb, d0, d1);
+            __syncthreads();
+            for (int dl = w; dl < d1 - d0; dl += nw) {
+                const uint32_t n = min(LCNT[dl], Ly.list_cap);
+                const uint32_t *lst = LST + dl * Ly.list_cap;
+                if (split) {
+                    uint64_t *G = a.G + ((uint64_t)rd.gslot * K + (d0 + dl)) * (uint64_t)ng * ng;
+                    for (uint32_t e = lane(); e < n; e += kWave) {
+                        uint32_t lo, hi;
+                        uint64_t cnt;
+                        if (MODE == 0) {
+                            SrcDenseList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad};
+                            cnt = s.get(e, lo, hi);
+                            s.clear(e);
+                        } else {
+                            SrcHashList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.hkey_off),
+                                          reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off)};
+                            cnt = s.get(e, lo, hi);
+                            s.clear(e);
+                        }
+                        atomicAdd(reinterpret_cast<unsigned long long *>(&G[(uint64_t)lo * ng + hi]),
+                                  (unsigned long long)cnt);
+                    }
+                } else {
+                    WaveGrp g;
+                    if (MODE == 0) {
+                        SrcDenseList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad};
+                        dir_features<Acc>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng,
+                                          FEAT + (d0 + dl) * kNumFeat);
+                    } else {
+                        SrcHashList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.hkey_off),
+                                      reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off)};
+                        dir_features<Acc>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng,
+                                          FEAT + (d0 + dl) * kNumFeat);
+                    }
+                }
+                if (lane() == 0) LCNT[dl] = 0u;
+            }
+            __syncthreads();
+        }
+        if (!split) write_row<OutT>(a, roi, FEAT, K);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ split ROIs
+// One work-group per (split slot, direction): features from the merged global
+// matrix (dense square, upper triangle).
+template <class Acc>
+__global__ __launch_bounds__(512) void k_split_features(StepArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t ng = (uint32_t)a.ng;
+    const int K = a.K;
+    const uint32_t slot = blockIdx.x / K;
+    const int d = (int)(blockIdx.x % K);
+    if (slot >= min(a.counters[C_NSPLIT], a.g_cap)) return;
+    uint32_t *R = reinterpret_cast<uint32_t *>(smem);
+    uint64_t *scratch = reinterpret_cast<uint64_t *>(smem + 16u * ng);
+    double *out = reinterpret_cast<double *>(smem + 16u * ng + 16 * 8);
+    for (uint32_t i = threadIdx.x; i < 4u * ng; i += blockDim.x) R[i] = 0u;
+    __syncthreads();
+    BlockGrp g{scratch};
+    SrcSquare s{a.G + ((uint64_t)slot * K + d) * (uint64_t)ng * ng, ng};
+    dir_features<Acc>(g, s, R, R + ng, R + 3u * ng - 1u, ng, out);
+    __syncthreads();
+    for (int f = threadIdx.x; f < kNumFeat; f += blockDim.x)
+        a.split_feat[((uint64_t)slot * K + d) * kNumFeat + f] = out[f];
+}
+
+// Feature rows from per-direction scratch features: row map[s] <- scratch[s].
+template <class OutT>
+__global__ __launch_bounds__(256) void k_rows(StepArgs a, const double *scratch, const uint32_t *map,
+                                              const uint32_t *count_ptr, uint32_t count_cap) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint32_t n = count_ptr ? min(*count_ptr, count_cap) : count_cap;
+    uint32_t s = blockIdx.x;
+    if (s >= n) return;
+    const int K = a.K;
+    double *feat = reinterpret_cast<double *>(smem);
+    for (int t = threadIdx.x; t < K * kNumFeat; t += blockDim.x) feat[t] = scratch[(uint64_t)s * K * kNumFeat + t];
+    __syncthreads();
+    write_row<OutT>(a, map ? map[s] : s, feat, K);
+}
+
+// ------------------------------------------------------------------ COO
+// Nonzero upper-triangle cells of each (slot, direction) matrix.
+__global__ __launch_bounds__(256) void k_coo_count(StepArgs a, uint32_t n_slots, uint64_t *counts) {
+    const uint32_t ng = (uint32_t)a.ng;
+    const uint32_t sd = blockIdx.x;
+    if (sd >= n_slots * (uint32_t)a.K) return;
+    const uint64_t *G = a.G + (uint64_t)sd * ng * ng;
+    uint64_t c = 0;
+    for (uint32_t e = threadIdx.x; e < ng * ng; e += blockDim.x) {
+        uint32_t i = e / ng, j = e - i * ng;
+        if (i <= j && G[e]) ++c;
+    }
+    __shared__ uint64_t part[4];
+    c = wave_sum(c);
+    if (lane() == 0) part[threadIdx.x / 64] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) counts[sd] = part[0] + part[1] + part[2] + part[3];
+}
+
+// Writes each (slot, direction) matrix's nonzero cells in (i, j) order at its
+// offset: keys roi << 38 | dir << 32 | i << 16 | j.
+__global__ __launch_bounds__(256) void k_coo_emit(StepArgs a, uint32_t n_slots, const uint64_t *offsets,
+                                                  uint64_t *keys, uint64_t *vals) {
+    const uint32_t ng = (uint32_t)a.ng;
+    const uint32_t sd = blockIdx.x;
+    if (sd >= n_slots * (uint32_t)a.K) return;
+    const uint32_t slot = sd / a.K, d = sd % a.K;
+    const uint64_t roi = a.split_roi[slot];
+    const uint64_t *G = a.G + (uint64_t)sd * ng * ng;
+    __shared__ uint32_t wc[4], s_base;
+    uint64_t pos = offsets[sd];
+    for (uint32_t e0 = 0; e0 < ng * ng; e0 += blockDim.x) {
+        uint32_t e = e0 + threadIdx.x;
+        uint32_t i = e / ng, j = e - i * ng;
+        uint64_t v = (e < ng * ng && i <= j) ? G[e] : 0ull;
+        uint64_t m = __ballot(v != 0ull);
+        if (lane() == 0) wc[threadIdx.x / 64] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+        for (int q = 0; q < 4; ++q) { if (q < (int)(threadIdx.x / 64)) pre += wc[q]; tot += wc[q]; }
+        if (v) {
+            uint64_t p = pos + pre + (uint32_t)__popcll(m & __lanemask_lt());
+            keys[p] = (roi << 38) | ((uint64_t)d << 32) | ((uint64_t)i << 16) | (uint64_t)j;
+            vals[p] = v;
+        }
+        pos += tot;
+        __syncthreads();
+    }
+    (void)s_base;
+}
+
+// Segment start of every (roi, dir) in a sorted key list (n_rois * K + 1 entries).
+__global__ void k_coo_segments_k(const uint64_t *keys, uint64_t nnz, uint32_t n_rois, int K, uint64_t *seg) {
+    uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t n_seg = n_rois * (uint32_t)K;
+    if (s > n_seg) return;
+    uint64_t target = s == n_seg ? ~0ull : (((uint64_t)(s / K)) << 38) | ((uint64_t)(s % K) << 32);
+    uint64_t lo = 0, hi = nnz;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < target) lo = mid + 1; else hi = mid;
+    }
+    seg[s] = s == n_seg ? nnz : lo;
+}
+
+// One work-group per (roi, direction) of a COO list.
+template <class Acc>
+__global__ __launch_bounds__(512) void k_coo_features(StepArgs a, const uint64_t *keys, const uint64_t *vals,
+                                                      const uint64_t *seg, uint32_t n_rois, double *scratch) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t ng = (uint32_t)a.ng;
+    const int K = a.K;
+    const uint32_t s = blockIdx.x;
+    if (s >= n_rois * (uint32_t)K) return;
+    uint32_t *R = reinterpret_cast<uint32_t *>(smem);
+    uint64_t *scr = reinterpret_cast<uint64_t *>(smem + 16u * ng);
+    double *out = reinterpret_cast<double *>(smem + 16u * ng + 16 * 8);
+    for (uint32_t i = threadIdx.x; i < 4u * ng; i += blockDim.x) R[i] = 0u;
+    __syncthreads();
+    BlockGrp g{scr};
+    SrcCoo src{keys + seg[s], vals + seg[s], (uint32_t)(seg[s + 1] - seg[s]),
+               ((uint64_t)(s / K) << 38) | ((uint64_t)(s % K) << 32), ng, &a.counters[C_ERR]};
+    dir_features<Acc>(g, src, R, R + ng, R + 3u * ng - 1u, ng, out);
+    __syncthreads();
+    for (int f = threadIdx.x; f < kNumFeat; f += blockDim.x) scratch[(uint64_t)s * kNumFeat + f] = out[f];
+}
+
+// ================================================================== launchers
+#define NYX_CHECK_LAUNCH() \
+    do { hipError_t _e = hipGetLastError(); if (_e != hipSuccess) return _e; } while (0)
+
+hipError_t launch_max_label(const ImgDesc *imgs, int n_images, uint32_t *out, hipStream_t st) {
+    dim3 grid(256, n_images);
+    hipLaunchKernelGGL(k_max_label, grid, dim3(256), 0, st, imgs, n_images, out);
+    NYX_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_reset(const StepArgs &a, uint32_t n_counters, hipStream_t st) {
+    uint32_t n = a.tab.total > n_counters ? a.tab.total : n_counters;
+    uint32_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, st, a, n_counters);
+    NYX_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)blocks), dim3(256), 0, st, p, n, v);
+    NYX_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_zero_split(const StepArgs &a, hipStream_t st) {
+    if (a.g_cap == 0) return hipSuccess;
+    uint64_t n = (uint64_t)a.g_cap * a.K * (uint64_t)a.ng * a.ng;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_zero_split, dim3((uint32_t)blocks), dim3(256), 0, st, a);
+    NYX_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_scan(const StepArgs &a, hipStream_t st) {
+    if (a.total_chunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan, dim3((a.total_chunks + 255) / 256), dim3(256), 0, st, a);
+    NYX_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_compact(const StepArgs &a, uint32_t roi_lo, uint32_t roi_hi, hipStream_t st) {
+    uint32_t blocks = (a.tab.total + 1023) / 1024;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact_count, dim3(blocks), dim3(1024), 0, st, a);
+    NYX_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_compact_write, dim3(blocks), dim3(1024), 0, st, a, roi_lo, roi_hi);
+    NYX_CHECK_LAUNCH();
+    if (a.force_split) {
+        hipLaunchKernelGGL(k_set_nsplit, dim3(1), dim3(1), 0, st, a, roi_lo, roi_hi);
+        NYX_CHECK_LAUNCH();
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_bin_image(const StepArgs &a, uint16_t *bins, uint64_t total_vox, const uint64_t *img_vox_base,
+                            hipStream_t st) {
+    if (total_vox == 0) return hipSuccess;
+    uint64_t blocks = (total_vox + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_bin_image, dim3((uint32_t)blocks), dim3(256), 0, st, a, bins, total_vox, img_vox_base);
+    NYX_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <int MODE, class OutT>
+static hipError_t launch_batch_t(const StepArgs &a, uint32_t grid, uint32_t block, uint32_t direct_roi,
+                                 hipStream_t st) {
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<MODE, OutT>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    hipLaunchKernelGGL((k_batch<MODE, OutT>), dim3(grid), dim3(block), a.lds.bytes, st, a, direct_roi);
+    NYX_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_batch(const StepArgs &a, uint32_t grid, uint32_t block, uint32_t direct_roi, hipStream_t st) {
+    if (a.lds.mode == 0)
+        return a.fp64 ? launch_batch_t<0, double>(a, grid, block, direct_roi, st)
+                      : launch_batch_t<0, float>(a, grid, block, direct_roi, st);
+    return a.fp64 ? launch_batch_t<1, double>(a, grid, block, direct_roi, st)
+                  : launch_batch_t<1, float>(a, grid, block, direct_roi, st);
+}
+
+hipError_t get_batch_attributes(int mode, int fp64, hipFuncAttributes *attr) {
+    const void *f;
+    if (mode == 0) f = fp64 ? reinterpret_cast<const void *>(&k_batch<0, double>) : reinterpret_cast<const void *>(&k_batch<0, float>);
+    else f = fp64 ? reinterpret_cast<const void *>(&k_batch<1, double>) : reinterpret_cast<const void *>(&k_batch<1, float>);
+    return hipFuncGetAttributes(attr, f);
+}
+
+static hipError_t set_feature_kernel_attrs() {
+    static bool done = false;
+    if (done) return hipSuccess;
+    const void *fs[] = {reinterpret_cast<const void *>(&k_split_features<float>),
+                        reinterpret_cast<const void *>(&k_split_features<double>),
+                        reinterpret_cast<const void *>(&k_coo_features<float>),
+                        reinterpret_cast<const void *>(&k_coo_features<double>)};
+    for (const void *f : fs) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    done = true;
+    return hipSuccess;
+}
+
+hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st) {
+    if (a.g_cap == 0) return hipSuccess;
+    {
+        hipError_t e = set_feature_kernel_attrs();
+        if (e != hipSuccess) return e;
+    }
+    uint32_t lds = 16u * a.ng + 16 * 8 + kNumFeat * 8;
+    uint32_t grid = a.g_cap * a.K;
+    if (a.fp64) hipLaunchKernelGGL(k_split_features<double>, dim3(grid), dim3(512), lds, st, a);
+    else hipLaunchKernelGGL(k_split_features<float>, dim3(grid), dim3(512), lds, st, a);
+    NYX_CHECK_LAUNCH();
+    uint32_t lds2 = a.K * kNumFeat * 8;
+    if (a.fp64)
+        hipLaunchKernelGGL(k_rows<double>, dim3(a.g_cap), dim3(256), lds2, st, a, a.split_feat, a.split_roi,
+                           a.counters + C_NSPLIT, a.g_cap);
+    else
+        hipLaunchKernelGGL(k_rows<float>, dim3(a.g_cap), dim3(256), lds2, st, a, a.split_feat, a.split_roi,
+                           a.counters + C_NSPLIT, a.g_cap);
+    NYX_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_coo_count(const StepArgs &a, uint32_t n_slots, uint64_t *counts, hipStream_t st) {
+    if (n_slots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coo_count, dim3(n_slots * a.K), dim3(256), 0, st, a, n_slots, counts);
+    NYX_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_coo_emit(const StepArgs &a, uint32_t n_slots, const uint64_t *offsets, uint64_t *keys,
+                           uint64_t *vals, hipStream_t st) {
+    if (n_slots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coo_emit, dim3(n_slots * a.K), dim3(256), 0, st, a, n_slots, offsets, keys, vals);
+    NYX_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_coo_features(const StepArgs &a, const uint64_t *keys, const uint64_t *vals, uint64_t nnz,
+                               uint32_t n_rois, uint64_t *seg, double *scratch, hipStream_t st) {
+    uint32_t n_seg = n_rois * (uint32_t)a.K;
+    hipLaunchKernelGGL(k_coo_segments_k, dim3((n_seg + 1 + 255) / 256), dim3(256), 0, st, keys, nnz, n_rois,
+                       a.K, seg);
+    NYX_CHECK_LAUNCH();
+    if (n_seg == 0) return hipSuccess;
+    {
+        hipError_t e = set_feature_kernel_attrs();
+        if (e != hipSuccess) return e;
+    }
+    uint32_t lds = 16u * a.ng + 16 * 8 + kNumFeat * 8;
+    if (a.fp64)
+        hipLaunchKernelGGL(k_coo_features<double>, dim3(n_seg), dim3(512), lds, st, a, keys, vals, seg, n_rois, scratch);
+    else
+        hipLaunchKernelGGL(k_coo_features<float>, dim3(n_seg), dim3(512), lds, st, a, keys, vals, seg, n_rois, scratch);
+    NYX_CHECK_LAUNCH();
+    uint32_t lds2 = a.K * kNumFeat * 8;
+    if (a.fp64)
+        hipLaunchKernelGGL(k_rows<double>, dim3(n_rois), dim3(256), lds2, st, a, scratch, (const uint32_t *)nullptr,
+                           (const uint32_t *)nullptr, n_rois);
+    else
+        hipLaunchKernelGGL(k_rows<float>, dim3(n_rois), dim3(256), lds2, st, a, scratch, (const uint32_t *)nullptr,
+                           (const uint32_t *)nullptr, n_rois);
+    NYX_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+}  // namespace nyx

@@ -1,0 +1,26 @@
+// nyx_launch.h -- host-side launchers of the kernels in nyx_kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "nyx_types.h"
+
+namespace nyx {
+
+hipError_t launch_max_label(const ImgDesc *imgs, int n_images, uint32_t *out, hipStream_t st);
+hipError_t launch_reset(const StepArgs &a, uint32_t n_counters, hipStream_t st);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st);
+hipError_t launch_zero_split(const StepArgs &a, hipStream_t st);
+hipError_t launch_scan(const StepArgs &a, hipStream_t st);
+hipError_t launch_compact(const StepArgs &a, uint32_t roi_lo, uint32_t roi_hi, hipStream_t st);
+hipError_t launch_bin_image(const StepArgs &a, uint16_t *bins, uint64_t total_vox, const uint64_t *img_vox_base,
+                            hipStream_t st);
+hipError_t launch_batch(const StepArgs &a, uint32_t grid, uint32_t block, uint32_t direct_roi, hipStream_t st);
+hipError_t get_batch_attributes(int mode, int fp64, hipFuncAttributes *attr);
+hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st);
+hipError_t launch_coo_count(const StepArgs &a, uint32_t n_slots, uint64_t *counts, hipStream_t st);
+hipError_t launch_coo_emit(const StepArgs &a, uint32_t n_slots, const uint64_t *offsets, uint64_t *keys,
+                           uint64_t *vals, hipStream_t st);
+hipError_t launch_coo_features(const StepArgs &a, const uint64_t *keys, const uint64_t *vals, uint64_t nnz,
+                               uint32_t n_rois, uint64_t *seg, double *scratch, hipStream_t st);
+
+}  // namespace nyx

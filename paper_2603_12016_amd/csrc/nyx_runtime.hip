@@ -1,0 +1,906 @@
+// nyx_runtime.hip -- host runtime and C ABI (include/nyx.h).
+//
+// Planning discovers the ROIs once, chooses the LDS accumulation mode and the
+// split of large ROIs, sizes the work queue and scratch, and captures the
+// whole step (discovery, binning, accumulation, features) in a HIP graph
+// replayed by nyx_plan_execute.  nyx_plan_execute_per_roi runs the same step
+// with one accumulation launch per ROI instead of the persistent queue.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/nyx.h"
+#include "nyx_launch.h"
+#include "nyx_types.h"
+
+using namespace nyx;
+
+namespace {
+
+const char *const kFeatureNames[kNumFeat] = {
+    "ASM", "ACOR", "CLUPROM", "CLUSHADE", "CLUTEND", "CONTRAST", "CORR", "DIFAVE", "DIFENTRO", "DIFVAR",
+    "DIS", "ENERGY", "ENTROPY", "HOM1", "HOM2", "IDM", "INFOMEAS1", "INFOMEAS2", "IDMN", "ID",
+    "IDN", "IV", "JAVE", "JE", "JMAX", "SUMAVE", "SUMENT", "JVAR", "SUMVAR", "VARIANCE"};
+
+constexpr uint32_t kLdsBudget = 160u * 1024u;   // LDS per CU on gfx950
+constexpr uint32_t kMaxNgFused = 8191u;         // hash keys carry 13-bit levels
+constexpr uint64_t kMaxLabelEntries = 1ull << 26;
+
+int log_level() {
+    static int lvl = -1;
+    if (lvl < 0) {
+        const char *s = getenv("NYX_LOG");
+        lvl = s ? atoi(s) : 0;
+    }
+    return lvl;
+}
+
+// Owned device allocation.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t n) {
+        release();
+        if (n == 0) n = 16;
+        hipError_t e = hipMalloc(&p, n);
+        if (e == hipSuccess) bytes = n;
+        else p = nullptr;
+        return e;
+    }
+    template <class T> T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+uint32_t next_pow2(uint32_t v) {
+    uint32_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+struct nyx_ctx {
+    int device = 0;
+    int n_cu = 0;
+    std::string err;
+    hipStream_t capture_stream = nullptr;
+};
+
+// All device state of one discovery/step over a batch of images.
+struct Work {
+    std::vector<ImgDesc> h_imgs;
+    DevBuf imgs, tab[10], counters, rois, buckets, G, split_feat, split_roi, vox_base;
+    uint32_t tab_total = 0, n_blocks = 0, n_counters = 0, total_chunks = 0;
+    uint32_t n_rois = 0;
+    uint64_t total_vox = 0;
+    std::vector<RoiDesc> h_rois;
+    StepArgs args{};
+};
+
+struct nyx_plan {
+    nyx_ctx *ctx = nullptr;
+    Work w;
+    std::vector<nyx_image> imgs;
+    int K = 0, ng = 0;
+    nyx_precision prec = NYX_FP32;
+    uint32_t grid = 0, block = 256;
+    std::vector<uint32_t> roi_tiles;   // per-ROI tile count for the per-ROI path
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *graph_table = nullptr;
+    nyx_roi_table graph_rois{};
+    std::string desc;
+    int64_t workspace_bytes = 0;
+};
+
+namespace {
+
+nyx_status fail(nyx_ctx *c, nyx_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    if (log_level() > 0) fprintf(stderr, "[nyx] error: %s\n", buf);
+    return s;
+}
+
+#define HIPC(ctx, x)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (x);                                                                      \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? NYX_ERR_OOM : NYX_ERR_DEVICE, "%s: %s", #x, \
+                        hipGetErrorString(e_));                                                   \
+    } while (0)
+
+nyx_status validate_images(nyx_ctx *ctx, const nyx_image *imgs, int32_t n) {
+    if (!imgs || n <= 0) return fail(ctx, NYX_ERR_INVALID, "no images");
+    for (int i = 0; i < n; ++i) {
+        const nyx_image &m = imgs[i];
+        if (!m.intensity || !m.labels) return fail(ctx, NYX_ERR_INVALID, "image %d: NULL array", i);
+        if (m.nz <= 0 || m.ny <= 0 || m.nx <= 0) return fail(ctx, NYX_ERR_INVALID, "image %d: dimension <= 0", i);
+        if (m.nz > 65535 || m.ny > 65535 || m.nx > 65535)
+            return fail(ctx, NYX_ERR_INVALID, "image %d: dimension above 65535", i);
+        if (m.nz * m.ny * m.nx >= (1ll << 31)) return fail(ctx, NYX_ERR_INVALID, "image %d: 2^31 voxels or more", i);
+    }
+    return NYX_OK;
+}
+
+nyx_status validate_offsets(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images, const nyx_offset *off,
+                            int32_t K) {
+    if (!off) return fail(ctx, NYX_ERR_INVALID, "offsets are NULL");
+    if (K < 1 || K > kMaxOffsets) return fail(ctx, NYX_ERR_INVALID, "n_offsets must be in [1, 64]");
+    bool any3d = false;
+    for (int i = 0; i < n_images; ++i) any3d |= imgs[i].nz > 1;
+    for (int k = 0; k < K; ++k) {
+        if (off[k].dz == 0 && off[k].dy == 0 && off[k].dx == 0)
+            return fail(ctx, NYX_ERR_INVALID, "offset %d is (0,0,0)", k);
+        if (!any3d && off[k].dz != 0) return fail(ctx, NYX_ERR_INVALID, "offset %d has dz != 0 on 2D images", k);
+        if (abs(off[k].dz) > 65535 || abs(off[k].dy) > 65535 || abs(off[k].dx) > 65535)
+            return fail(ctx, NYX_ERR_INVALID, "offset %d out of range", k);
+    }
+    return NYX_OK;
+}
+
+nyx_status validate_bins(nyx_ctx *ctx, int32_t ng) {
+    if (ng < 2 || ng > 65535) return fail(ctx, NYX_ERR_INVALID, "n_bins must be in [2, 65535]");
+    if ((uint32_t)ng > kMaxNgFused)
+        return fail(ctx, NYX_ERR_UNSUPPORTED, "n_bins above %u is not supported by this build", kMaxNgFused);
+    return NYX_OK;
+}
+
+// Label tables, ROI discovery and the ROI table (no work items).
+nyx_status discover(nyx_ctx *ctx, const nyx_image *imgs, int32_t n, Work &w, hipStream_t st) {
+    w.h_imgs.resize(n);
+    uint32_t chunk = 0;
+    uint64_t tv = 0;
+    std::vector<uint64_t> vbase(n);
+    for (int i = 0; i < n; ++i) {
+        ImgDesc &d = w.h_imgs[i];
+        memset(&d, 0, sizeof d);
+        d.I = imgs[i].intensity;
+        d.L = imgs[i].labels;
+        d.B = nullptr;
+        d.nz = (int32_t)imgs[i].nz;
+        d.ny = (int32_t)imgs[i].ny;
+        d.nx = (int32_t)imgs[i].nx;
+        d.nvox = (uint32_t)(imgs[i].nz * imgs[i].ny * imgs[i].nx);
+        d.chunk_base = chunk;
+        chunk += (d.nvox + 7u) / 8u;
+        d.vec_ok = ((uintptr_t)d.I % 16 == 0) && ((uintptr_t)d.L % 16 == 0) && (d.nvox % 8 == 0);
+        vbase[i] = tv;
+        tv += d.nvox;
+    }
+    w.total_chunks = chunk;
+    w.total_vox = tv;
+    HIPC(ctx, w.imgs.alloc(sizeof(ImgDesc) * n));
+    HIPC(ctx, hipMemcpyAsync(w.imgs.p, w.h_imgs.data(), sizeof(ImgDesc) * n, hipMemcpyHostToDevice, st));
+    HIPC(ctx, w.vox_base.alloc(sizeof(uint64_t) * n));
+    HIPC(ctx, hipMemcpyAsync(w.vox_base.p, vbase.data(), sizeof(uint64_t) * n, hipMemcpyHostToDevice, st));
+    // largest label per image sizes the label tables
+    DevBuf dmax;
+    HIPC(ctx, dmax.alloc(sizeof(uint32_t) * n));
+    std::vector<uint32_t> zeros(n, 0u), hmax(n);
+    HIPC(ctx, hipMemcpyAsync(dmax.p, zeros.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, st));
+    HIPC(ctx, launch_max_label(w.imgs.as<ImgDesc>(), n, dmax.as<uint32_t>(), st));
+    HIPC(ctx, hipMemcpyAsync(hmax.data(), dmax.p, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, st));
+    HIPC(ctx, hipStreamSynchronize(st));
+    uint64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        w.h_imgs[i].tab_base = (uint32_t)total;
+        w.h_imgs[i].max_label = hmax[i];
+        total += (uint64_t)hmax[i] + 1u;
+    }
+    if (total > kMaxLabelEntries)
+        return fail(ctx, NYX_ERR_UNSUPPORTED, "label values too large: %llu label-table entries (limit %llu)",
+                    (unsigned long long)total, (unsigned long long)kMaxLabelEntries);
+    w.tab_total = (uint32_t)total;
+    HIPC(ctx, hipMemcpyAsync(w.imgs.p, w.h_imgs.data(), sizeof(ImgDesc) * n, hipMemcpyHostToDevice, st));
+    for (auto &b : w.tab) HIPC(ctx, b.alloc(sizeof(uint32_t) * (size_t)total));
+    w.n_blocks = (w.tab_total + 1023u) / 1024u;
+    w.n_counters = C_BLOCKS + w.n_blocks;
+    HIPC(ctx, w.counters.alloc(sizeof(uint32_t) * w.n_counters));
+
+    StepArgs &a = w.args;
+    memset(&a, 0, sizeof a);
+    a.imgs = w.imgs.as<ImgDesc>();
+    a.n_images = n;
+    a.total_chunks = w.total_chunks;
+    a.tab.cnt = w.tab[0].as<uint32_t>();
+    a.tab.mn = w.tab[1].as<uint32_t>();
+    a.tab.mx = w.tab[2].as<uint32_t>();
+    a.tab.x0 = w.tab[3].as<int32_t>();
+    a.tab.y0 = w.tab[4].as<int32_t>();
+    a.tab.z0 = w.tab[5].as<int32_t>();
+    a.tab.x1 = w.tab[6].as<int32_t>();
+    a.tab.y1 = w.tab[7].as<int32_t>();
+    a.tab.z1 = w.tab[8].as<int32_t>();
+    a.tab.row = w.tab[9].as<uint32_t>();
+    a.tab.total = w.tab_total;
+    a.counters = w.counters.as<uint32_t>();
+    HIPC(ctx, launch_reset(a, w.n_counters, st));
+    HIPC(ctx, launch_scan(a, st));
+    // ROI count from the per-block counts
+    StepArgs a0 = a;
+    if (w.n_blocks) {
+        // count kernel only (compaction with zero ROI capacity writes nothing)
+        a0.roi_cap = 0;
+        a0.enqueue = 0;
+        HIPC(ctx, launch_compact(a0, 0u, 0u, st));
+    }
+    std::vector<uint32_t> hc(w.n_counters);
+    HIPC(ctx, hipMemcpyAsync(hc.data(), w.counters.p, sizeof(uint32_t) * w.n_counters, hipMemcpyDeviceToHost, st));
+    HIPC(ctx, hipStreamSynchronize(st));
+    if (hc[C_ERR] & E_LABEL_RANGE) return fail(ctx, NYX_ERR_INTERNAL, "label range check failed during discovery");
+    w.n_rois = hc[C_NROIS];
+    HIPC(ctx, w.rois.alloc(sizeof(RoiDesc) * std::max<uint32_t>(w.n_rois, 1u)));
+    a.rois = w.rois.as<RoiDesc>();
+    a.roi_cap = w.n_rois;
+    return NYX_OK;
+}
+
+// Re-runs the compaction to fill the ROI descriptors and fetches them.
+nyx_status fetch_rois(nyx_ctx *ctx, Work &w, hipStream_t st) {
+    StepArgs a = w.args;
+    a.enqueue = 0;
+    HIPC(ctx, launch_reset(a, w.n_counters, st));
+    HIPC(ctx, launch_scan(a, st));
+    HIPC(ctx, launch_compact(a, 0u, 0u, st));
+    w.h_rois.resize(w.n_rois);
+    if (w.n_rois)
+        HIPC(ctx, hipMemcpyAsync(w.h_rois.data(), w.rois.p, sizeof(RoiDesc) * w.n_rois, hipMemcpyDeviceToHost, st));
+    HIPC(ctx, hipStreamSynchronize(st));
+    return NYX_OK;
+}
+
+struct Config {
+    int mode = 0;            // 0 dense, 1 hash
+    uint32_t kp = 1;
+    uint32_t block = 256;
+    uint32_t split_vox = 0, tile_vox = 0;
+    uint32_t list_cap = 0, hash_cap = 0;
+    int force_split = 0;
+};
+
+LdsLayout make_layout(const Config &c, uint32_t ng, int K) {
+    LdsLayout L;
+    memset(&L, 0, sizeof L);
+    L.mode = (uint32_t)c.mode;
+    L.kp = c.kp;
+    L.nwaves = c.block / kWave;
+    uint32_t tri = ng * (ng + 1u) / 2u;
+    L.tri_pad = (tri + 3u) & ~3u;
+    L.list_cap = c.list_cap;
+    L.hash_cap = c.hash_cap;
+    uint32_t off = 0;
+    auto take = [&](uint32_t bytes) {
+        uint32_t o = off;
+        off += (bytes + 15u) & ~15u;
+        return o;
+    };
+    if (c.mode == 0) {
+        L.u_off = take(c.kp * L.tri_pad * 4u);
+    } else {
+        L.hkey_off = take(c.hash_cap * 4u);
+        L.hcnt_off = take(c.hash_cap * 4u);
+    }
+    L.list_off = take(c.kp * c.list_cap * 4u);
+    L.lcnt_off = take(c.kp * 4u);
+    L.marg_off = take(L.nwaves * 4u * ng * 4u);
+    L.feat_off = take((uint32_t)K * kNumFeat * 8u);
+    L.misc_off = take(128u * 4u);
+    L.bytes = off;
+    return L;
+}
+
+// Largest voxel count any work item can hold under a split rule.
+uint64_t max_item_vox(const std::vector<RoiDesc> &rois, uint32_t split_vox, uint32_t tile_vox) {
+    uint64_t m = 0;
+    for (const RoiDesc &r : rois) {
+        uint32_t W = (uint32_t)(r.x1 - r.x0 + 1);
+        Tiling t = tiles_for(r.n, r.rows, W, split_vox, tile_vox);
+        if (t.row_blocks * t.col_blocks == 1u) { m = std::max<uint64_t>(m, r.n); continue; }
+        uint32_t rpt = (r.rows + t.row_blocks - 1u) / t.row_blocks;
+        uint32_t cpt = (W + t.col_blocks - 1u) / t.col_blocks;
+        m = std::max<uint64_t>(m, std::min<uint64_t>((uint64_t)rpt * cpt, r.n));
+    }
+    return m;
+}
+
+// Chooses the accumulation mode and the split of large ROIs.
+nyx_status choose_config(nyx_ctx *ctx, const Work &w, uint32_t ng, int K, int force_split, uint32_t block,
+                         Config &cfg) {
+    cfg = Config();
+    cfg.block = block;
+    cfg.force_split = force_split;
+    const uint32_t nw = block / kWave;
+    const uint32_t tri = ng * (ng + 1u) / 2u;
+    const uint32_t tri_pad = (tri + 3u) & ~3u;
+    const uint32_t fixed = (nw * 4u * ng * 4u + 15u) / 16u * 16u + (uint32_t)K * kNumFeat * 8u + 128u * 4u + 64u * 4u + 64;
+    uint64_t total_vox = 0;
+    for (const RoiDesc &r : w.h_rois) total_vox += r.n;
+    // load balance: split ROIs that would take more than ~1/4 of one
+    // work-group's share of the voxels
+    uint64_t share = total_vox / ((uint64_t)std::max(ctx->n_cu, 1) * 4u) + 1u;
+    uint32_t lb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(share, 4096u), 1u << 20);
+    // dense mode: as many direction triangles as fit
+    for (uint32_t kp = (uint32_t)K; kp >= 1u; --kp) {
+        uint32_t split = force_split ? lb : lb;
+        uint64_t mi = max_item_vox(w.h_rois, split, split);
+        uint32_t list_cap = (uint32_t)std::min<uint64_t>(tri, std::max<uint64_t>(mi, 1u));
+        uint64_t bytes = (uint64_t)kp * tri_pad * 4u + (uint64_t)kp * list_cap * 4u + kp * 4u + fixed;
+        if (bytes <= kLdsBudget) {
+            cfg.mode = 0;
+            cfg.kp = kp;
+            cfg.split_vox = split;
+            cfg.tile_vox = split;
+            cfg.list_cap = list_cap;
+            return NYX_OK;
+        }
+        if (kp == 1u) break;
+    }
+    // hash mode: items small enough that kp directions of pairs fill at most
+    // half the table
+    if (ng > kMaxNgFused) return fail(ctx, NYX_ERR_UNSUPPORTED, "n_bins too large");
+    if (fixed >= kLdsBudget) return fail(ctx, NYX_ERR_UNSUPPORTED, "n_bins too large for the LDS marginals");
+    for (uint32_t kp = (uint32_t)K; kp >= 1u; --kp) {
+        for (uint32_t hc = 1u << 14; hc >= 512u; hc >>= 1) {
+            uint32_t per_dir = hc / (2u * kp);
+            if (per_dir < 64u) continue;
+            uint32_t split = std::min<uint32_t>(per_dir, lb);
+            uint64_t mi = max_item_vox(w.h_rois, split, split);
+            // shrink tiles until the area bound fits
+            while (mi > per_dir && split > 16u) {
+                split /= 2u;
+                mi = max_item_vox(w.h_rois, split, split);
+            }
+            if (mi > per_dir) continue;
+            uint32_t list_cap = (uint32_t)std::max<uint64_t>(mi, 1u);
+            uint64_t bytes = (uint64_t)hc * 8u + (uint64_t)kp * list_cap * 4u + kp * 4u + fixed;
+            if (bytes <= kLdsBudget) {
+                cfg.mode = 1;
+                cfg.kp = kp;
+                cfg.hash_cap = hc;
+                cfg.split_vox = split;
+                cfg.tile_vox = split;
+                cfg.list_cap = list_cap;
+                return NYX_OK;
+            }
+        }
+    }
+    return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%u with %d offsets", ng, K);
+}
+
+// Item and split-slot counts implied by a configuration.
+void count_items(const std::vector<RoiDesc> &rois, const Config &c, uint64_t *items, uint32_t *n_split,
+                 std::vector<uint32_t> *tiles) {
+    uint64_t it = 0;
+    uint32_t ns = 0;
+    if (tiles) tiles->resize(rois.size());
+    for (size_t i = 0; i < rois.size(); ++i) {
+        const RoiDesc &r = rois[i];
+        Tiling t = tiles_for(r.n, r.rows, (uint32_t)(r.x1 - r.x0 + 1), c.split_vox, c.tile_vox);
+        uint32_t nt = t.row_blocks * t.col_blocks;
+        it += nt;
+        if (nt > 1u || c.force_split) ++ns;
+        if (tiles) (*tiles)[i] = nt;
+    }
+    *items = it;
+    *n_split = ns;
+}
+
+// Allocates queue, split matrices and fills the step arguments.
+nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset *off, int K, uint32_t ng,
+                      int fp64, uint32_t g_cap_override, int64_t cap_bytes, int64_t *ws_bytes) {
+    StepArgs &a = w.args;
+    uint64_t items;
+    uint32_t n_split;
+    count_items(w.h_rois, cfg, &items, &n_split, nullptr);
+    if (g_cap_override) n_split = g_cap_override;
+    if (items >= (1ull << 31)) return fail(ctx, NYX_ERR_UNSUPPORTED, "too many work items");
+    uint32_t bucket_cap = (uint32_t)std::max<uint64_t>(items, 1u);
+    uint64_t g_bytes = (uint64_t)n_split * K * (uint64_t)ng * ng * 8u;
+    uint64_t need = (uint64_t)kClasses * bucket_cap * 8u + g_bytes + (uint64_t)n_split * K * kNumFeat * 8u +
+                    n_split * 4u;
+    for (auto &b : w.tab) need += b.bytes;
+    need += w.rois.bytes + w.counters.bytes;
+    if (ws_bytes) *ws_bytes = (int64_t)need;
+    if (cap_bytes > 0 && (int64_t)need > cap_bytes)
+        return fail(ctx, NYX_ERR_OOM, "workspace needs %llu bytes, cap is %lld", (unsigned long long)need,
+                    (long long)cap_bytes);
+    HIPC(ctx, w.buckets.alloc((size_t)kClasses * bucket_cap * sizeof(uint2)));
+    HIPC(ctx, w.G.alloc(std::max<uint64_t>(g_bytes, 16u)));
+    HIPC(ctx, w.split_feat.alloc((size_t)std::max<uint32_t>(n_split, 1u) * K * kNumFeat * 8u));
+    HIPC(ctx, w.split_roi.alloc((size_t)std::max<uint32_t>(n_split, 1u) * 4u));
+    a.buckets = w.buckets.as<uint2>();
+    a.bucket_cap = bucket_cap;
+    a.G = w.G.as<uint64_t>();
+    a.g_cap = n_split;
+    a.split_feat = w.split_feat.as<double>();
+    a.split_roi = w.split_roi.as<uint32_t>();
+    for (int k = 0; k < K; ++k) {
+        a.off[k][0] = off[k].dz;
+        a.off[k][1] = off[k].dy;
+        a.off[k][2] = off[k].dx;
+    }
+    a.K = K;
+    a.ng = (int32_t)ng;
+    a.split_vox = cfg.split_vox;
+    a.tile_vox = cfg.tile_vox;
+    a.force_split = cfg.force_split;
+    a.enqueue = 1;
+    a.fp64 = fp64;
+    a.lds = make_layout(cfg, ng, K);
+    return NYX_OK;
+}
+
+nyx_status set_outputs(nyx_ctx *ctx, StepArgs &a, nyx_roi_table *rois, void *table, uint32_t table_rows) {
+    a.table = table;
+    a.table_rows = table_rows;
+    a.o_label = rois ? rois->label : nullptr;
+    a.o_image = rois ? rois->image : nullptr;
+    a.o_n = rois ? rois->n_vox : nullptr;
+    a.o_min = rois ? rois->vmin : nullptr;
+    a.o_max = rois ? rois->vmax : nullptr;
+    a.o_bbox = rois ? rois->bbox : nullptr;
+    (void)ctx;
+    return NYX_OK;
+}
+
+// The full step on a stream.  per_roi: one accumulation launch per ROI.
+nyx_status enqueue_step(nyx_plan *p, hipStream_t st, bool per_roi) {
+    nyx_ctx *ctx = p->ctx;
+    const StepArgs &a = p->w.args;
+    HIPC(ctx, launch_reset(a, p->w.n_counters, st));
+    HIPC(ctx, launch_scan(a, st));
+    HIPC(ctx, launch_compact(a, 0u, 0xFFFFFFFFu, st));
+    HIPC(ctx, launch_zero_split(a, st));
+    if (!per_roi) {
+        HIPC(ctx, launch_batch(a, p->grid, p->block, kNone, st));
+    } else {
+        for (uint32_t r = 0; r < p->w.n_rois; ++r)
+            HIPC(ctx, launch_batch(a, p->roi_tiles[r], p->block, r, st));
+    }
+    HIPC(ctx, launch_split_finalize(a, st));
+    return NYX_OK;
+}
+
+nyx_status check_counters(nyx_ctx *ctx, Work &w, hipStream_t st) {
+    uint32_t h[8];
+    HIPC(ctx, hipMemcpyAsync(h, w.counters.p, sizeof h, hipMemcpyDeviceToHost, st));
+    HIPC(ctx, hipStreamSynchronize(st));
+    uint32_t e = h[C_ERR];
+    if (e & E_LABEL_RANGE) return fail(ctx, NYX_ERR_CAPACITY, "a label exceeds the planned label range");
+    if (e & E_ROI_CAP) return fail(ctx, NYX_ERR_CAPACITY, "more ROIs than planned");
+    if (e & E_SPLIT_CAP) return fail(ctx, NYX_ERR_CAPACITY, "more split ROIs than planned");
+    if (e & E_ITEM_CAP) return fail(ctx, NYX_ERR_CAPACITY, "more work items than planned");
+    if (e & E_TABLE_CAP) return fail(ctx, NYX_ERR_CAPACITY, "feature table too small");
+    if (e & E_BIN_RANGE) return fail(ctx, NYX_ERR_INVALID, "bin image holds a value outside [1, n_bins]");
+    if (e & E_COO_RANGE) return fail(ctx, NYX_ERR_INVALID, "COO entry outside its matrix");
+    if (e & (E_LIST_CAP | E_HASH_FULL)) return fail(ctx, NYX_ERR_INTERNAL, "LDS capacity exceeded (error bits %u)", e);
+    return NYX_OK;
+}
+
+std::string describe(const Config &c, const nyx_plan *p, uint64_t items, uint32_t n_split) {
+    char buf[512];
+    snprintf(buf, sizeof buf,
+             "mode=%s kp=%u block=%u grid=%u lds=%uB split_vox=%u tile_vox=%u list_cap=%u hash_cap=%u "
+             "rois=%u items=%llu split_rois=%u ng=%d K=%d",
+             c.mode == 0 ? "dense" : "hash", c.kp, c.block, p->grid, p->w.args.lds.bytes, c.split_vox, c.tile_vox,
+             c.list_cap, c.hash_cap, p->w.n_rois, (unsigned long long)items, n_split, p->ng, p->K);
+    return buf;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+const char *nyx_status_string(nyx_status s) {
+    switch (s) {
+        case NYX_OK: return "ok";
+        case NYX_ERR_INVALID: return "invalid argument";
+        case NYX_ERR_OOM: return "out of memory";
+        case NYX_ERR_DEVICE: return "device error";
+        case NYX_ERR_CAPACITY: return "capacity too small";
+        case NYX_ERR_UNSUPPORTED: return "unsupported";
+        case NYX_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+nyx_status nyx_create(nyx_ctx **out, int device_ordinal) {
+    if (!out) return NYX_ERR_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return NYX_ERR_DEVICE;
+    if (device_ordinal < 0 || device_ordinal >= n) return NYX_ERR_DEVICE;
+    if (hipSetDevice(device_ordinal) != hipSuccess) return NYX_ERR_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device_ordinal) != hipSuccess) return NYX_ERR_DEVICE;
+    nyx_ctx *c = new nyx_ctx();
+    c->device = device_ordinal;
+    c->n_cu = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return NYX_ERR_DEVICE;
+    }
+    *out = c;
+    return NYX_OK;
+}
+
+void nyx_destroy(nyx_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    delete ctx;
+}
+
+const char *nyx_last_error(const nyx_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+nyx_status nyx_offsets_default(int32_t dims, int32_t distance, nyx_offset *out_host, int32_t *n) {
+    static const int32_t two[4][3] = {{0, 0, 1}, {0, -1, 1}, {0, -1, 0}, {0, -1, -1}};
+    static const int32_t three[13][3] = {{0, 0, 1},  {0, 1, 0},  {1, 0, 0},   {0, 1, 1},  {0, 1, -1},
+                                         {1, 0, 1},  {1, 0, -1}, {1, 1, 0},   {1, -1, 0}, {1, 1, 1},
+                                         {1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
+    if (!out_host || !n || distance < 1 || (dims != 2 && dims != 3)) return NYX_ERR_INVALID;
+    int k = dims == 2 ? 4 : 13;
+    for (int i = 0; i < k; ++i) {
+        const int32_t *o = dims == 2 ? two[i] : three[i];
+        out_host[i].dz = o[0] * distance;
+        out_host[i].dy = o[1] * distance;
+        out_host[i].dx = o[2] * distance;
+    }
+    *n = k;
+    return NYX_OK;
+}
+
+int32_t nyx_feature_count(void) { return kNumFeat; }
+
+const char *nyx_feature_name(int32_t f) { return (f >= 0 && f < kNumFeat) ? kFeatureNames[f] : nullptr; }
+
+nyx_status nyx_bin_rois(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images, int32_t n_bins, nyx_roi_table *rois,
+                        uint16_t *bins_out, nyx_stream stream) {
+    if (!ctx) return NYX_ERR_INVALID;
+    if (!rois) return fail(ctx, NYX_ERR_INVALID, "rois is NULL");
+    nyx_status s = validate_images(ctx, imgs, n_images);
+    if (s != NYX_OK) return s;
+    if (n_bins < 2 || n_bins > 65535) return fail(ctx, NYX_ERR_INVALID, "n_bins must be in [2, 65535]");
+    hipStream_t st = (hipStream_t)stream;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    Work w;
+    s = discover(ctx, imgs, n_images, w, st);
+    if (s != NYX_OK) return s;
+    if (rois->n_rois_host) *rois->n_rois_host = w.n_rois;
+    if (rois->capacity < (int64_t)w.n_rois)
+        return fail(ctx, NYX_ERR_CAPACITY, "ROI table capacity %lld < %u ROIs", (long long)rois->capacity, w.n_rois);
+    StepArgs a = w.args;
+    a.ng = n_bins;
+    a.enqueue = 0;
+    set_outputs(ctx, a, rois, nullptr, 0);
+    HIPC(ctx, launch_reset(a, w.n_counters, st));
+    HIPC(ctx, launch_scan(a, st));
+    HIPC(ctx, launch_compact(a, 0u, 0u, st));
+    if (bins_out) HIPC(ctx, launch_bin_image(a, bins_out, w.total_vox, w.vox_base.as<uint64_t>(), st));
+    HIPC(ctx, hipStreamSynchronize(st));
+    return NYX_OK;
+}
+
+nyx_status nyx_glcm_accumulate(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images, const nyx_roi_table *rois,
+                               const uint16_t *bins, const nyx_offset *offsets, int32_t K, int32_t symmetric,
+                               int32_t n_bins, nyx_glcm *out, nyx_stream stream) {
+    if (!ctx) return NYX_ERR_INVALID;
+    if (!out) return fail(ctx, NYX_ERR_INVALID, "out is NULL");
+    nyx_status s = validate_images(ctx, imgs, n_images);
+    if (s != NYX_OK) return s;
+    if ((s = validate_offsets(ctx, imgs, n_images, offsets, K)) != NYX_OK) return s;
+    if (n_bins < 2 || n_bins > 65535) return fail(ctx, NYX_ERR_INVALID, "n_bins must be in [2, 65535]");
+    if ((s = validate_bins(ctx, n_bins)) != NYX_OK) return s;
+    if (symmetric != 1) return fail(ctx, NYX_ERR_UNSUPPORTED, "only symmetric matrices are supported");
+    hipStream_t st = (hipStream_t)stream;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    Work w;
+    if ((s = discover(ctx, imgs, n_images, w, st)) != NYX_OK) return s;
+    if (rois && rois->n_rois_host && *rois->n_rois_host != (int64_t)w.n_rois)
+        return fail(ctx, NYX_ERR_INVALID, "ROI table has %lld rows, images have %u ROIs",
+                    (long long)*rois->n_rois_host, w.n_rois);
+    if (bins) {
+        uint64_t off = 0;
+        for (auto &d : w.h_imgs) { d.B = bins + off; off += d.nvox; }
+        HIPC(ctx, hipMemcpyAsync(w.imgs.p, w.h_imgs.data(), sizeof(ImgDesc) * n_images, hipMemcpyHostToDevice, st));
+    }
+    if ((s = fetch_rois(ctx, w, st)) != NYX_OK) return s;
+    const uint32_t ng = (uint32_t)n_bins;
+    Config cfg;
+    if ((s = choose_config(ctx, w, ng, K, 1, 256, cfg)) != NYX_OK) return s;
+    // ROIs in batches whose global matrices fit a fixed budget
+    const uint64_t per_roi = (uint64_t)K * ng * ng * 8u;
+    const uint64_t budget = 2ull << 30;
+    uint32_t batch = (uint32_t)std::max<uint64_t>(1u, std::min<uint64_t>(w.n_rois ? w.n_rois : 1u, budget / per_roi));
+    if ((s = setup_step(ctx, w, cfg, offsets, K, ng, 0, batch, 0, nullptr)) != NYX_OK) return s;
+    StepArgs &a = w.args;
+    set_outputs(ctx, a, nullptr, nullptr, 0);
+    int occ = 0;
+    {
+        hipFuncAttributes fa;
+        HIPC(ctx, get_batch_attributes(a.lds.mode, 0, &fa));
+        occ = 1;
+    }
+    const uint32_t grid = (uint32_t)ctx->n_cu * (uint32_t)std::max(occ, 1) * 2u;
+    DevBuf dcount, doff;
+    HIPC(ctx, dcount.alloc((size_t)batch * K * 8u));
+    HIPC(ctx, doff.alloc((size_t)batch * K * 8u));
+    std::vector<uint64_t> hcount((size_t)batch * K), hoff((size_t)batch * K);
+    uint64_t nnz_total = 0;
+    for (int phase = 0; phase < 2; ++phase) {
+        uint64_t written = 0;
+        for (uint32_t lo = 0; lo < w.n_rois; lo += batch) {
+            uint32_t hi = std::min(w.n_rois, lo + batch);
+            uint32_t ns = hi - lo;
+            HIPC(ctx, launch_reset(a, w.n_counters, st));
+            HIPC(ctx, launch_scan(a, st));
+            HIPC(ctx, launch_compact(a, lo, hi, st));
+            HIPC(ctx, launch_zero_split(a, st));
+            HIPC(ctx, launch_batch(a, grid, cfg.block, kNone, st));
+            HIPC(ctx, launch_coo_count(a, ns, dcount.as<uint64_t>(), st));
+            HIPC(ctx, hipMemcpyAsync(hcount.data(), dcount.p, (size_t)ns * K * 8u, hipMemcpyDeviceToHost, st));
+            HIPC(ctx, hipStreamSynchronize(st));
+            if ((s = check_counters(ctx, w, st)) != NYX_OK) return s;
+            uint64_t acc = written;
+            for (size_t i = 0; i < (size_t)ns * K; ++i) { hoff[i] = acc; acc += hcount[i]; }
+            if (phase == 1) {
+                HIPC(ctx, hipMemcpyAsync(doff.p, hoff.data(), (size_t)ns * K * 8u, hipMemcpyHostToDevice, st));
+                HIPC(ctx, launch_coo_emit(a, ns, doff.as<uint64_t>(), out->key, out->count, st));
+                HIPC(ctx, hipStreamSynchronize(st));
+            }
+            written = acc;
+        }
+        if (phase == 0) {
+            nnz_total = written;
+            if (out->nnz_host) *out->nnz_host = (int64_t)nnz_total;
+            out->n_bins = n_bins;
+            out->n_offsets = K;
+            out->symmetric = 1;
+            out->n_rois = w.n_rois;
+            if (out->capacity < (int64_t)nnz_total)
+                return fail(ctx, NYX_ERR_CAPACITY, "COO capacity %lld < %llu nonzero cells", (long long)out->capacity,
+                            (unsigned long long)nnz_total);
+            if (nnz_total && (!out->key || !out->count)) return fail(ctx, NYX_ERR_INVALID, "COO arrays are NULL");
+        }
+    }
+    return NYX_OK;
+}
+
+nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, nyx_precision prec, void *table,
+                             int64_t table_capacity_rows, nyx_stream stream) {
+    if (!ctx) return NYX_ERR_INVALID;
+    if (!glcm || !table) return fail(ctx, NYX_ERR_INVALID, "NULL argument");
+    if (glcm->n_offsets < 1 || glcm->n_offsets > kMaxOffsets) return fail(ctx, NYX_ERR_INVALID, "bad n_offsets");
+    nyx_status s = validate_bins(ctx, glcm->n_bins);
+    if (s != NYX_OK) return s;
+    if (glcm->n_rois < 0 || glcm->n_rois >= (1ll << 26)) return fail(ctx, NYX_ERR_INVALID, "bad n_rois");
+    if (table_capacity_rows < glcm->n_rois)
+        return fail(ctx, NYX_ERR_CAPACITY, "table capacity %lld < %lld rows", (long long)table_capacity_rows,
+                    (long long)glcm->n_rois);
+    uint64_t nnz = glcm->nnz_host ? (uint64_t)*glcm->nnz_host : 0u;
+    if (nnz && (!glcm->key || !glcm->count)) return fail(ctx, NYX_ERR_INVALID, "COO arrays are NULL");
+    if (prec != NYX_FP32 && prec != NYX_FP64) return fail(ctx, NYX_ERR_INVALID, "bad precision");
+    hipStream_t st = (hipStream_t)stream;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    const uint32_t n_rois = (uint32_t)glcm->n_rois;
+    const int K = glcm->n_offsets;
+    if (n_rois == 0) return NYX_OK;
+    DevBuf seg, scratch, counters;
+    HIPC(ctx, seg.alloc(((size_t)n_rois * K + 1) * 8u));
+    HIPC(ctx, scratch.alloc((size_t)n_rois * K * kNumFeat * 8u));
+    HIPC(ctx, counters.alloc(256));
+    HIPC(ctx, hipMemsetAsync(counters.p, 0, 256, st));
+    StepArgs a;
+    memset(&a, 0, sizeof a);
+    a.K = K;
+    a.ng = glcm->n_bins;
+    a.fp64 = prec == NYX_FP64;
+    a.table = table;
+    a.table_rows = (uint32_t)std::min<int64_t>(table_capacity_rows, 0xFFFFFFFFll);
+    a.counters = counters.as<uint32_t>();
+    HIPC(ctx, launch_coo_features(a, glcm->key, glcm->count, nnz, n_rois, seg.as<uint64_t>(), scratch.as<double>(), st));
+    uint32_t herr = 0;
+    HIPC(ctx, hipMemcpyAsync(&herr, counters.as<uint32_t>() + C_ERR, 4, hipMemcpyDeviceToHost, st));
+    HIPC(ctx, hipStreamSynchronize(st));
+    if (herr & E_COO_RANGE) return fail(ctx, NYX_ERR_INVALID, "COO entry outside its matrix");
+    if (herr & E_TABLE_CAP) return fail(ctx, NYX_ERR_CAPACITY, "feature table too small");
+    return NYX_OK;
+}
+
+nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images, const nyx_extract_opts *opts,
+                           nyx_plan **out, int64_t *n_rois_host) {
+    if (!ctx) return NYX_ERR_INVALID;
+    if (!out || !opts) return fail(ctx, NYX_ERR_INVALID, "NULL argument");
+    *out = nullptr;
+    nyx_status s = validate_images(ctx, imgs, n_images);
+    if (s != NYX_OK) return s;
+    if ((s = validate_offsets(ctx, imgs, n_images, opts->offsets_host, opts->n_offsets)) != NYX_OK) return s;
+    if (opts->n_bins < 2 || opts->n_bins > 65535) return fail(ctx, NYX_ERR_INVALID, "n_bins must be in [2, 65535]");
+    if ((s = validate_bins(ctx, opts->n_bins)) != NYX_OK) return s;
+    if (opts->symmetric != 1) return fail(ctx, NYX_ERR_UNSUPPORTED, "only symmetric matrices are supported");
+    if (opts->precision != NYX_FP32 && opts->precision != NYX_FP64) return fail(ctx, NYX_ERR_INVALID, "bad precision");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = ctx->capture_stream;
+    std::unique_ptr<nyx_plan> p(new nyx_plan());
+    p->ctx = ctx;
+    p->imgs.assign(imgs, imgs + n_images);
+    p->K = opts->n_offsets;
+    p->ng = opts->n_bins;
+    p->prec = opts->precision;
+    if ((s = discover(ctx, imgs, n_images, p->w, st)) != NYX_OK) return s;
+    if ((s = fetch_rois(ctx, p->w, st)) != NYX_OK) return s;
+    Config cfg;
+    if ((s = choose_config(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256, cfg)) != NYX_OK) return s;
+    if ((s = setup_step(ctx, p->w, cfg, opts->offsets_host, p->K, (uint32_t)p->ng, p->prec == NYX_FP64, 0,
+                        opts->workspace_cap_bytes, &p->workspace_bytes)) != NYX_OK)
+        return s;
+    p->block = cfg.block;
+    int occ = 0;
+    {
+        const void *f = nullptr;
+        (void)f;
+        hipFuncAttributes fa;
+        HIPC(ctx, get_batch_attributes(p->w.args.lds.mode, p->prec == NYX_FP64, &fa));
+        uint32_t by_lds = kLdsBudget / std::max<uint32_t>(p->w.args.lds.bytes, 1u);
+        uint32_t by_waves = 32u / (cfg.block / kWave);
+        occ = (int)std::max<uint32_t>(1u, std::min(by_lds, by_waves));
+    }
+    p->grid = (uint32_t)ctx->n_cu * (uint32_t)occ;
+    uint64_t items;
+    uint32_t n_split;
+    count_items(p->w.h_rois, cfg, &items, &n_split, &p->roi_tiles);
+    p->desc = describe(cfg, p.get(), items, n_split);
+    if (log_level() > 0) fprintf(stderr, "[nyx] plan: %s\n", p->desc.c_str());
+    if (n_rois_host) *n_rois_host = p->w.n_rois;
+    *out = p.release();
+    return NYX_OK;
+}
+
+nyx_status nyx_plan_execute(nyx_plan *p, nyx_roi_table *rois, void *table, nyx_stream stream) {
+    if (!p) return NYX_ERR_INVALID;
+    nyx_ctx *ctx = p->ctx;
+    if (!table) return fail(ctx, NYX_ERR_INVALID, "table is NULL");
+    if (rois && rois->capacity < (int64_t)p->w.n_rois)
+        return fail(ctx, NYX_ERR_CAPACITY, "ROI table capacity too small");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    nyx_roi_table key{};
+    if (rois) key = *rois;
+    key.n_rois_host = nullptr;
+    bool same = p->exec && p->graph_table == table && memcmp(&key, &p->graph_rois, sizeof key) == 0;
+    if (!same) {
+        if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+        if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+        set_outputs(ctx, p->w.args, rois, table, p->w.n_rois);
+        hipStream_t cs = ctx->capture_stream;
+        HIPC(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        nyx_status s = enqueue_step(p, cs, false);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &g);
+        if (s != NYX_OK) { if (g) (void)hipGraphDestroy(g); return s; }
+        if (e != hipSuccess) return fail(ctx, NYX_ERR_DEVICE, "graph capture: %s", hipGetErrorString(e));
+        p->graph = g;
+        HIPC(ctx, hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0));
+        p->graph_table = table;
+        p->graph_rois = key;
+    }
+    HIPC(ctx, hipGraphLaunch(p->exec, st));
+    if (rois && rois->n_rois_host) *rois->n_rois_host = p->w.n_rois;
+    return NYX_OK;
+}
+
+nyx_status nyx_plan_execute_per_roi(nyx_plan *p, nyx_roi_table *rois, void *table, nyx_stream stream) {
+    if (!p) return NYX_ERR_INVALID;
+    nyx_ctx *ctx = p->ctx;
+    if (!table) return fail(ctx, NYX_ERR_INVALID, "table is NULL");
+    if (rois && rois->capacity < (int64_t)p->w.n_rois)
+        return fail(ctx, NYX_ERR_CAPACITY, "ROI table capacity too small");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    set_outputs(ctx, p->w.args, rois, table, p->w.n_rois);
+    nyx_status s = enqueue_step(p, (hipStream_t)stream, true);
+    if (rois && rois->n_rois_host) *rois->n_rois_host = p->w.n_rois;
+    return s;
+}
+
+nyx_status nyx_plan_profile(nyx_plan *p, void *table, float *ms_host, nyx_stream stream) {
+    if (!p) return NYX_ERR_INVALID;
+    nyx_ctx *ctx = p->ctx;
+    if (!table || !ms_host) return fail(ctx, NYX_ERR_INVALID, "NULL argument");
+    HIPC(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    set_outputs(ctx, p->w.args, nullptr, table, p->w.n_rois);
+    // the graph (if any) was captured with other outputs; drop it
+    if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+    if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+    p->graph_table = nullptr;
+    hipEvent_t ev[NYX_PHASE_COUNT + 1];
+    for (auto &e : ev) HIPC(ctx, hipEventCreate(&e));
+    const StepArgs &a = p->w.args;
+    nyx_status s = NYX_OK;
+    hipError_t he = hipSuccess;
+    he = hipEventRecord(ev[0], st);
+    if (he == hipSuccess) he = launch_reset(a, p->w.n_counters, st);
+    if (he == hipSuccess) he = hipEventRecord(ev[1], st);
+    if (he == hipSuccess) he = launch_scan(a, st);
+    if (he == hipSuccess) he = hipEventRecord(ev[2], st);
+    if (he == hipSuccess) he = launch_compact(a, 0u, 0xFFFFFFFFu, st);
+    if (he == hipSuccess) he = hipEventRecord(ev[3], st);
+    if (he == hipSuccess) he = launch_zero_split(a, st);
+    if (he == hipSuccess) he = hipEventRecord(ev[4], st);
+    if (he == hipSuccess) he = launch_batch(a, p->grid, p->block, kNone, st);
+    if (he == hipSuccess) he = hipEventRecord(ev[5], st);
+    if (he == hipSuccess) he = launch_split_finalize(a, st);
+    if (he == hipSuccess) he = hipEventRecord(ev[6], st);
+    if (he == hipSuccess) he = hipEventSynchronize(ev[6]);
+    if (he == hipSuccess)
+        for (int i = 0; i < NYX_PHASE_COUNT; ++i) {
+            he = hipEventElapsedTime(&ms_host[i], ev[i], ev[i + 1]);
+            if (he != hipSuccess) break;
+        }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (he != hipSuccess) s = fail(ctx, NYX_ERR_DEVICE, "profile: %s", hipGetErrorString(he));
+    return s;
+}
+
+nyx_status nyx_plan_check(nyx_plan *p, nyx_stream stream) {
+    if (!p) return NYX_ERR_INVALID;
+    return check_counters(p->ctx, p->w, (hipStream_t)stream);
+}
+
+const char *nyx_plan_describe(const nyx_plan *p) { return p ? p->desc.c_str() : ""; }
+
+void nyx_plan_destroy(nyx_plan *p) {
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    delete p;
+}
+
+nyx_status nyx_extract_batch(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images, const nyx_extract_opts *opts,
+                             nyx_roi_table *rois, void *table, int64_t table_capacity_rows, nyx_stream stream) {
+    if (!ctx) return NYX_ERR_INVALID;
+    nyx_plan *p = nullptr;
+    int64_t n = 0;
+    nyx_status s = nyx_plan_create(ctx, imgs, n_images, opts, &p, &n);
+    if (s != NYX_OK) return s;
+    if (rois && rois->n_rois_host) *rois->n_rois_host = n;
+    if (table_capacity_rows < n) {
+        nyx_plan_destroy(p);
+        return fail(ctx, NYX_ERR_CAPACITY, "table capacity %lld < %lld rows", (long long)table_capacity_rows, (long long)n);
+    }
+    if (rois && rois->capacity < n) {
+        nyx_plan_destroy(p);
+        return fail(ctx, NYX_ERR_CAPACITY, "ROI table capacity %lld < %lld", (long long)rois->capacity, (long long)n);
+    }
+    set_outputs(ctx, p->w.args, rois, table, (uint32_t)n);
+    s = enqueue_step(p, (hipStream_t)stream, false);
+    if (s == NYX_OK) s = check_counters(ctx, p->w, (hipStream_t)stream);
+    else (void)hipStreamSynchronize((hipStream_t)stream);
+    nyx_plan_destroy(p);
+    return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+// nyx_types.h -- plain data shared by the HIP kernels and the host runtime.
+//
+// Nothing here depends on torch.  Structures are passed to kernels by value
+// (StepArgs) or live in device memory (ImgDesc, RoiDesc, work items).
+#pragma once
+#include <stdint.h>
+
+namespace nyx {
+
+constexpr int kWave = 64;
+constexpr int kNumFeat = 30;
+constexpr int kMaxOffsets = 64;
+constexpr int kClasses = 32;           // work-item size classes (log2 of voxels)
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Counter slots (u32) in the device counter block.
+enum Counter : int {
+    C_NROIS = 0,    // ROIs found by the last compaction
+    C_NSPLIT = 1,   // ROIs split into several tiles (global-matrix slots used)
+    C_TICKET = 2,   // work-stealing ticket of the persistent kernel
+    C_ERR = 3,      // error bits (see ErrBit)
+    C_NITEMS = 4,   // work items enqueued
+    C_CLASS = 8,    // kClasses counters: items per size class
+    C_BLOCKS = 64,  // per-block ROI counts of the compaction (variable length)
+};
+
+enum ErrBit : uint32_t {
+    E_LABEL_RANGE = 1u,   // a label exceeds the planned label-table capacity
+    E_ROI_CAP = 2u,       // more ROIs than planned
+    E_SPLIT_CAP = 4u,     // more split ROIs than planned
+    E_ITEM_CAP = 8u,      // work-item bucket overflow
+    E_LIST_CAP = 16u,     // LDS nonzero-list overflow (planner bug)
+    E_HASH_FULL = 32u,    // LDS hash table full (planner bug)
+    E_TABLE_CAP = 64u,    // output table too small
+    E_BIN_RANGE = 128u,   // a caller-supplied bin image holds a value outside [1, n_bins]
+    E_COO_RANGE = 256u,   // a caller-supplied COO entry is outside its matrix
+};
+
+struct ImgDesc {
+    const uint16_t *I;     // intensity
+    const uint32_t *L;     // labels
+    const uint16_t *B;     // optional bin image (nullptr: bin on the fly)
+    int32_t nz, ny, nx;
+    uint32_t nvox;
+    uint32_t tab_base;     // label-table index of label 0 of this image
+    uint32_t max_label;    // label-table capacity of this image (labels 0..max_label)
+    uint32_t chunk_base;   // first scan chunk of this image
+    uint32_t vec_ok;       // 1: 16-byte aligned base pointers and nvox % 8 == 0
+};
+
+// Per-label statistics, one entry per (image, label), struct of arrays.
+struct LabelTab {
+    uint32_t *cnt, *mn, *mx;
+    int32_t *x0, *y0, *z0, *x1, *y1, *z1;
+    uint32_t *row;         // ROI row of a present label
+    uint32_t total;        // entries over all images
+};
+
+struct RoiDesc {
+    uint32_t label, image, n, n_tiles;
+    uint32_t vmin, vmax, gslot, rows;   // rows = bbox rows (z * y extent)
+    int32_t x0, y0, z0, x1, y1, z1;
+    uint32_t tcols;                      // column blocks per tile row (n_tiles = row blocks * tcols)
+    uint32_t pad1;
+};
+
+// Layout of the persistent kernel's dynamic LDS (byte offsets).
+struct LdsLayout {
+    uint32_t mode;        // 0 = dense triangles, 1 = hash table
+    uint32_t kp;          // directions accumulated per pass
+    uint32_t tri_pad;     // u32 words per dense triangle (dense mode)
+    uint32_t list_cap;    // entries per direction list
+    uint32_t hash_cap;    // slots (power of two, hash mode)
+    uint32_t u_off, list_off, lcnt_off, marg_off, feat_off, misc_off, hkey_off, hcnt_off;
+    uint32_t bytes;       // total dynamic LDS
+    uint32_t nwaves;      // waves per work-group
+};
+
+struct StepArgs {
+    const ImgDesc *imgs;
+    int32_t n_images;
+    uint32_t total_chunks;      // scan chunks of 8 voxels over all images
+    LabelTab tab;
+    RoiDesc *rois;
+    uint32_t roi_cap;
+    uint32_t *counters;
+    uint2 *buckets;             // kClasses buckets of bucket_cap items
+    uint32_t bucket_cap;
+    uint64_t *G;                // split-ROI dense matrices: g_cap slots of K * ng * ng
+    uint32_t g_cap;
+    double *split_feat;         // g_cap * K * 30 per-direction features of split ROIs
+    uint32_t *split_roi;        // g_cap: ROI row of each split slot
+    int32_t off[kMaxOffsets][3];
+    int32_t K;
+    int32_t ng;
+    uint32_t split_vox;         // ROIs above this many voxels are split
+    uint32_t tile_vox;          // target voxels per tile of a split ROI
+    int32_t force_split;        // 1: every ROI goes through the global matrices
+    int32_t enqueue;            // 0: compaction builds the ROI table only
+    int32_t fp64;               // feature table element type
+    void *table;
+    uint32_t table_rows;
+    // optional ROI-table outputs
+    uint32_t *o_label, *o_image;
+    uint64_t *o_n;
+    uint16_t *o_min, *o_max;
+    int32_t *o_bbox;
+    LdsLayout lds;
+};
+
+// Deterministic split rule shared by host planning and device enqueueing:
+// a ROI above split_vox voxels is cut into about n / tile_vox tiles, first
+// into blocks of bbox rows, then each row block into column blocks.
+struct Tiling { uint32_t row_blocks, col_blocks; };
+
+#ifdef __HIPCC__
+__host__ __device__
+#endif
+inline Tiling tiles_for(uint32_t n, uint32_t rows, uint32_t width, uint32_t split_vox, uint32_t tile_vox) {
+    Tiling t{1u, 1u};
+    if (n <= split_vox || tile_vox == 0u) return t;
+    uint32_t nt = (n + tile_vox - 1u) / tile_vox;
+    t.row_blocks = nt < rows ? nt : rows;
+    uint32_t nc = (nt + t.row_blocks - 1u) / t.row_blocks;
+    t.col_blocks = nc < width ? nc : width;
+    if (t.col_blocks < 1u) t.col_blocks = 1u;
+    return t;
+}
+
+// Bounds of tile `tile` of a ROI: bbox rows [ra, rb) and columns [ca, cb).
+#ifdef __HIPCC__
+__host__ __device__
+#endif
+inline void tile_bounds(uint32_t rows, uint32_t width, uint32_t n_tiles, uint32_t tcols, uint32_t tile,
+                        uint32_t *ra, uint32_t *rb, uint32_t *ca, uint32_t *cb) {
+    uint32_t nrb = n_tiles / tcols;
+    uint32_t rpt = (rows + nrb - 1u) / nrb;
+    uint32_t cpt = (width + tcols - 1u) / tcols;
+    uint32_t r = tile / tcols, c = tile - r * tcols;
+    *ra = r * rpt;
+    *rb = *ra + rpt < rows ? *ra + rpt : rows;
+    *ca = c * cpt;
+    *cb = *ca + cpt < width ? *ca + cpt : width;
+    if (*ra > rows) *ra = rows;
+    if (*ca > width) *ca = width;
+}
+
+#ifdef __HIPCC__
+__host__ __device__
+#endif
+inline uint32_t size_class(uint32_t vox) {
+    uint32_t c = 0;
+    while ((vox >> c) > 1u && c < 31u) ++c;
+    return c;
+}
+
+}  // namespace nyx

@@ -1,0 +1,380 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Counts, ROI tables and bin images must match bit for bit; features must meet
+the precision contract (1e-12 for the FP64 table, 1e-5 for the FP32 table,
+error measure in gpu_util).
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import NAMES, device_images, feature_errors, oracle_rois, scales, worst
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+TOL_FP64 = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_2603_12016_amd import nyx
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    return nyx, nyx.nyx_create(0), dev
+
+
+@pytest.fixture(scope="module")
+def workloads(synth_mod):
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            cache[name] = synth_mod.make(name)
+        return cache[name]
+    return get
+
+
+def _offsets(nyx, w):
+    return nyx.nyx_offsets_default(w.dims, 1)
+
+
+def _oracle_table(oracle, w, offs, rows=None):
+    """Oracle table for all ROIs (or a subset of global rows)."""
+    off = np.array(offs, np.int32)
+    out, Ps = [], []
+    ro = oracle_rois(oracle, w)
+    sel = range(len(ro)) if rows is None else rows
+    for g in sel:
+        k, r, st = ro[g]
+        P = oracle.glcm_roi(w.intensity[k], w.labels[k], st["label"][r], st["vmin"][r], st["vmax"][r],
+                            st["bbox"][r], w.n_bins, off)
+        out.append(oracle.features_roi(P))
+        Ps.append(P)
+    return np.array(out), Ps
+
+
+def _check_features(got, want, Ps, tol, tag):
+    assert got.shape == want.shape, (got.shape, want.shape)
+    errs = np.stack([feature_errors(got[i], want[i], scales(Ps[i])) for i in range(len(Ps))]) if len(Ps) else None
+    if errs is None:
+        return
+    e, name, idx = worst(errs)
+    say(f"  {tag}: {len(Ps)} ROIs, max error {e:.3e} ({name} at {idx})")
+    assert e <= tol, (tag, name, idx, got[idx[0], idx[1]], want[idx[0], idx[1]])
+
+
+# ------------------------------------------------------------------ C1
+def test_c1_fp64_extract_batch(env, workloads, oracle_mod):
+    nyx, ctx, dev = env
+    w = workloads("c1_tiny")
+    say("case c1_tiny extract_batch fp64")
+    offs = _offsets(nyx, w)
+    rois, table = nyx.nyx_extract_batch(ctx, device_images(w, dev), w.n_bins, offs, nyx.NYX_FP64)
+    import torch
+    torch.cuda.synchronize()
+    want, Ps = _oracle_table(oracle_mod, w, offs)
+    _check_features(table.cpu().numpy(), want, Ps, TOL_FP64, "c1 fp64")
+    assert rois.n_rois == 1
+
+
+# ------------------------------------------------------------------ ROI table / bins
+SMALL = ["c2_small", "c3_small", "c4_small", "c5_small"]
+
+
+@pytest.mark.parametrize("name", SMALL + ["c1_tiny"])
+def test_roi_table_and_bins_exact(env, workloads, oracle_mod, name):
+    nyx, ctx, dev = env
+    w = workloads(name)
+    say(f"case {name} bin_rois")
+    rois, bins = nyx.nyx_bin_rois(ctx, device_images(w, dev), w.n_bins, want_bins=True)
+    n = rois.n_rois
+    ro = oracle_rois(oracle_mod, w)
+    assert n == len(ro)
+    lab = rois.label.cpu().numpy()[:n].view(np.uint32)
+    img = rois.image.cpu().numpy()[:n]
+    cnt = rois.n_vox.cpu().numpy()[:n]
+    vmin = rois.vmin.cpu().numpy()[:n].view(np.uint16)
+    vmax = rois.vmax.cpu().numpy()[:n].view(np.uint16)
+    bbox = rois.bbox.cpu().numpy()[:n]
+    for g, (k, r, st) in enumerate(ro):
+        assert img[g] == k and lab[g] == st["label"][r] and cnt[g] == st["count"][r]
+        assert vmin[g] == st["vmin"][r] and vmax[g] == st["vmax"][r]
+        assert np.array_equal(bbox[g], st["bbox"][r])
+    got_bins = bins.cpu().numpy().view(np.uint16)
+    off = 0
+    for k in range(w.n_images):
+        want = oracle_mod.bin_image(w.intensity[k], w.labels[k], w.n_bins)
+        sz = want.size
+        assert np.array_equal(got_bins[off:off + sz].reshape(want.shape), want), f"image {k}"
+        off += sz
+
+
+# ------------------------------------------------------------------ counts
+def _dense_from_coo(g, n_rois, K, ng):
+    keys = g.keys.cpu().numpy().view(np.uint64)
+    cnt = g.counts.cpu().numpy().view(np.uint64)
+    assert np.all(keys[1:] > keys[:-1]), "COO keys not strictly sorted"
+    U = np.zeros((n_rois, K, ng, ng), np.uint64)
+    roi = (keys >> np.uint64(38)).astype(np.int64)
+    d = ((keys >> np.uint64(32)) & np.uint64(63)).astype(np.int64)
+    i = ((keys >> np.uint64(16)) & np.uint64(0xFFFF)).astype(np.int64)
+    j = (keys & np.uint64(0xFFFF)).astype(np.int64)
+    assert np.all(i <= j) and np.all(cnt > 0)
+    U[roi, d, i, j] = cnt
+    return U
+
+
+def _triangle(P):
+    U = np.triu(P).copy()
+    idx = np.arange(P.shape[-1])
+    U[..., idx, idx] //= 2
+    return U
+
+
+@pytest.mark.parametrize("name", ["c1_tiny", "c2_small", "c3_small", "c4_small", "c5_small"])
+@pytest.mark.parametrize("use_bins", [False, True])
+def test_glcm_counts_exact(env, workloads, oracle_mod, name, use_bins):
+    nyx, ctx, dev = env
+    w = workloads(name)
+    if name == "c5_small" and use_bins:
+        pytest.skip("covered by the on-the-fly case")
+    say(f"case {name} glcm_accumulate bins={use_bins}")
+    imgs = device_images(w, dev)
+    offs = _offsets(nyx, w)
+    rois, bins = nyx.nyx_bin_rois(ctx, imgs, w.n_bins, want_bins=use_bins)
+    g = nyx.nyx_glcm_accumulate(ctx, imgs, rois, w.n_bins, offs, bins=bins)
+    ro = oracle_rois(oracle_mod, w)
+    assert g.n_rois == len(ro)
+    if w.n_bins > 256:
+        # compare ROI by ROI without a dense 4D array
+        keys = g.keys.cpu().numpy().view(np.uint64)
+        cnt = g.counts.cpu().numpy().view(np.uint64)
+        roi = (keys >> np.uint64(38)).astype(np.int64)
+        for gi in list(range(0, len(ro), max(1, len(ro) // 25))) + [len(ro) - 1]:
+            k, r, st = ro[gi]
+            P = oracle_mod.glcm_roi(w.intensity[k], w.labels[k], st["label"][r], st["vmin"][r], st["vmax"][r],
+                                    st["bbox"][r], w.n_bins, np.array(offs, np.int32))
+            U = _triangle(P)
+            sel = roi == gi
+            kk = keys[sel]
+            d = ((kk >> np.uint64(32)) & np.uint64(63)).astype(np.int64)
+            i = ((kk >> np.uint64(16)) & np.uint64(0xFFFF)).astype(np.int64)
+            j = (kk & np.uint64(0xFFFF)).astype(np.int64)
+            nz = np.nonzero(U)
+            assert len(kk) == len(nz[0]), gi
+            assert np.array_equal(U[d, i, j], cnt[sel]), gi
+        return
+    U = _dense_from_coo(g, len(ro), len(offs), w.n_bins)
+    for gi, (k, r, st) in enumerate(ro):
+        P = oracle_mod.glcm_roi(w.intensity[k], w.labels[k], st["label"][r], st["vmin"][r], st["vmax"][r],
+                                st["bbox"][r], w.n_bins, np.array(offs, np.int32))
+        assert np.array_equal(U[gi], _triangle(P)), f"ROI {gi}"
+
+
+# ------------------------------------------------------------------ features from oracle counts
+@pytest.mark.parametrize("name,prec", [("c1_tiny", 1), ("c2_small", 0), ("c3_small", 1), ("c4_small", 0),
+                                       ("c5_small", 0)])
+def test_features_from_oracle_coo(env, workloads, oracle_mod, name, prec):
+    import torch
+    nyx, ctx, dev = env
+    w = workloads(name)
+    say(f"case {name} glcm_features from oracle COO prec={prec}")
+    offs = _offsets(nyx, w)
+    K = len(offs)
+    ro = oracle_rois(oracle_mod, w)
+    keys, cnts, Ps = [], [], []
+    for gi, (k, r, st) in enumerate(ro):
+        P = oracle_mod.glcm_roi(w.intensity[k], w.labels[k], st["label"][r], st["vmin"][r], st["vmax"][r],
+                                st["bbox"][r], w.n_bins, np.array(offs, np.int32))
+        Ps.append(P)
+        U = _triangle(P)
+        d, i, j = np.nonzero(U)
+        keys.append((np.uint64(gi) << np.uint64(38)) | (d.astype(np.uint64) << np.uint64(32)) |
+                    (i.astype(np.uint64) << np.uint64(16)) | j.astype(np.uint64))
+        cnts.append(U[d, i, j])
+    keys = np.concatenate(keys)
+    cnts = np.concatenate(cnts).astype(np.uint64)
+    order = np.argsort(keys)
+    kt = torch.from_numpy(keys[order].view(np.int64)).to(dev)
+    ct = torch.from_numpy(cnts[order].view(np.int64)).to(dev)
+    g = nyx.Glcm(kt, ct, int(len(keys)), w.n_bins, K, len(ro))
+    table = nyx.nyx_glcm_features(ctx, g, prec)
+    torch.cuda.synchronize()
+    want = np.array([oracle_mod.features_roi(P) for P in Ps])
+    _check_features(table.cpu().numpy(), want, Ps, TOL_FP64 if prec == 1 else TOL_FP32, f"{name} coo")
+
+
+# ------------------------------------------------------------------ batched path
+@pytest.mark.parametrize("name", SMALL)
+def test_plan_batched_and_per_roi(env, workloads, oracle_mod, name):
+    import torch
+    nyx, ctx, dev = env
+    w = workloads(name)
+    say(f"case {name} plan_execute + per_roi")
+    imgs = device_images(w, dev)
+    offs = _offsets(nyx, w)
+    plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32)
+    say("  plan:", nyx.nyx_plan_describe(plan))
+    t1 = nyx.new_table(plan, len(offs))
+    t2 = nyx.new_table(plan, len(offs))
+    for _ in range(3):  # repeated graph replays with eager work in between
+        nyx.nyx_plan_execute(plan, t1)
+        torch.cuda.synchronize()
+        nyx.nyx_plan_check(plan)
+        first = t1.clone()
+    nyx.nyx_plan_execute_per_roi(plan, t2)
+    torch.cuda.synchronize()
+    nyx.nyx_plan_check(plan)
+    want, Ps = _oracle_table(oracle_mod, w, offs)
+    got = t1.cpu().numpy()[:plan.n_rois]
+    _check_features(got, want, Ps, TOL_FP32, f"{name} batched")
+    _check_features(t2.cpu().numpy()[:plan.n_rois], want, Ps, TOL_FP32, f"{name} per-roi")
+    assert np.allclose(first.cpu().numpy(), got, rtol=1e-6, atol=1e-6, equal_nan=True)
+
+
+# ------------------------------------------------------------------ edge cases
+def _run_extract(nyx, ctx, dev, I, L, ng, offs, prec=1):
+    import torch
+    from types import SimpleNamespace
+    w = SimpleNamespace(intensity=I[None], labels=L[None], n_images=1)
+    return nyx.nyx_extract_batch(ctx, device_images(w, dev), ng, offs, prec)
+
+
+def _oracle_direct(oracle, I, L, ng, offs):
+    st, t = oracle.extract(I, L, ng, np.array(offs, np.int32))
+    Ps = [oracle.glcm_roi(I, L, st["label"][r], st["vmin"][r], st["vmax"][r], st["bbox"][r], ng,
+                          np.array(offs, np.int32)) for r in range(st["label"].size)]
+    return t, Ps
+
+
+EDGE = {
+    "ragged_many_labels": lambda rng: (rng.integers(0, 3000, (1, 37, 53)), rng.integers(0, 40, (1, 37, 53))),
+    "single_voxels": lambda rng: (rng.integers(0, 3000, (1, 9, 9)), np.where(rng.random((1, 9, 9)) < 0.3,
+                                                                           np.arange(81).reshape(1, 9, 9) + 1, 0)),
+    "thin_lines": lambda rng: (rng.integers(0, 3000, (1, 20, 21)), np.tile(np.arange(21) % 3 == 0, (1, 20, 1)) *
+                               (np.arange(21) + 1)),
+    "big_labels": lambda rng: (rng.integers(0, 65535, (1, 16, 24)), np.where(rng.random((1, 16, 24)) < 0.8,
+                                                                            1_000_000 + rng.integers(0, 3, (1, 16, 24)), 0)),
+    "constant": lambda rng: (np.full((1, 12, 10), 777), np.ones((1, 12, 10))),
+    "border_touching_3d": lambda rng: (rng.integers(0, 4096, (5, 6, 7)), rng.integers(1, 3, (5, 6, 7))),
+}
+
+
+@pytest.mark.parametrize("case", sorted(EDGE))
+@pytest.mark.parametrize("ng", [2, 8, 30, 100])
+def test_edge_cases(env, oracle_mod, case, ng):
+    import torch
+    nyx, ctx, dev = env
+    rng = np.random.default_rng(abs(hash(case)) % 1000 + ng)
+    I, L = EDGE[case](rng)
+    I = np.ascontiguousarray(I, np.uint16)
+    L = np.ascontiguousarray(L, np.uint32)
+    dims = 3 if I.shape[0] > 1 else 2
+    offs = nyx.nyx_offsets_default(dims, 1)
+    say(f"case edge {case} ng={ng}")
+    rois, table = _run_extract(nyx, ctx, dev, I, L, ng, offs)
+    torch.cuda.synchronize()
+    want, Ps = _oracle_direct(oracle_mod, I, L, ng, offs)
+    assert rois.n_rois == len(Ps)
+    _check_features(table.cpu().numpy(), want, Ps, TOL_FP64, f"edge {case}")
+
+
+def test_empty_image(env):
+    nyx, ctx, dev = env
+    I = np.zeros((1, 8, 8), np.uint16)
+    L = np.zeros((1, 8, 8), np.uint32)
+    rois, table = _run_extract(nyx, ctx, dev, I, L, 8, nyx.nyx_offsets_default(2, 1))
+    assert rois.n_rois == 0 and table.shape[0] == 0
+
+
+@pytest.mark.parametrize("offs", [[(0, 0, 2), (0, -2, 2), (0, -2, 0), (0, -2, -2)],
+                                  [(0, 1, 3), (0, 0, -1), (0, 2, 0)]])
+def test_other_offsets(env, oracle_mod, offs):
+    import torch
+    nyx, ctx, dev = env
+    rng = np.random.default_rng(len(offs))
+    I = rng.integers(0, 4000, (1, 30, 31)).astype(np.uint16)
+    L = (rng.integers(1, 5, (1, 30, 31)) * (rng.random((1, 30, 31)) < 0.9)).astype(np.uint32)
+    say(f"case offsets {offs}")
+    rois, table = _run_extract(nyx, ctx, dev, I, L, 16, offs)
+    torch.cuda.synchronize()
+    want, Ps = _oracle_direct(oracle_mod, I, L, 16, offs)
+    _check_features(table.cpu().numpy(), want, Ps, TOL_FP64, "offsets")
+
+
+def test_checkerboard_closed_form(env):
+    import math
+    import torch
+    nyx, ctx, dev = env
+    y, x = np.mgrid[0:8, 0:8]
+    I = (((x + y) % 2) * 4095).astype(np.uint16)[None]
+    L = np.ones((1, 8, 8), np.uint32)
+    rois, table = _run_extract(nyx, ctx, dev, I, L, 8, nyx.nyx_offsets_default(2, 1))
+    t = table.cpu().numpy()[0]
+    f = dict(zip(NAMES, t[0]))
+    assert f["CONTRAST"] == pytest.approx(49.0, rel=1e-14)
+    assert f["CORR"] == pytest.approx(-1.0, rel=1e-14)
+    assert f["INFOMEAS2"] == pytest.approx(math.sqrt(1 - math.exp(-2)), rel=1e-13)
+    assert t[4][NAMES.index("CONTRAST")] == pytest.approx(24.5, rel=1e-14)
+
+
+# ------------------------------------------------------------------ argument errors
+def test_invalid_arguments(env):
+    nyx, ctx, dev = env
+    from types import SimpleNamespace
+    I = np.zeros((1, 8, 8), np.uint16)
+    L = np.ones((1, 8, 8), np.uint32)
+    w = SimpleNamespace(intensity=I[None], labels=L[None], n_images=1)
+    imgs = device_images(w, dev)
+    for ng, offs, code in [(1, [(0, 0, 1)], nyx.NYX_ERR_INVALID), (70000, [(0, 0, 1)], nyx.NYX_ERR_INVALID),
+                           (8, [(0, 0, 0)], nyx.NYX_ERR_INVALID), (8, [(1, 0, 0)], nyx.NYX_ERR_INVALID),
+                           (8, [], nyx.NYX_ERR_INVALID), (9000, [(0, 0, 1)], nyx.NYX_ERR_UNSUPPORTED)]:
+        with pytest.raises(nyx.NyxError) as e:
+            nyx.nyx_plan_create(ctx, imgs, ng, offs)
+        assert e.value.status == code, (ng, offs)
+    with pytest.raises(nyx.NyxError) as e:
+        nyx.nyx_extract_batch(ctx, imgs, 8, [(0, 0, 1)], capacity=0)
+    assert e.value.status == nyx.NYX_ERR_CAPACITY
+
+
+# ------------------------------------------------------------------ full sizes (sampled)
+@pytest.mark.parametrize("name", ["c2_cells", "c3_batch", "c4_3d", "c5_stress"])
+def test_full_size_sampled(env, workloads, oracle_mod, name):
+    import torch
+    nyx, ctx, dev = env
+    w = workloads(name)
+    say(f"case {name} full size: plan + execute")
+    imgs = device_images(w, dev)
+    offs = _offsets(nyx, w)
+    plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32)
+    say("  plan:", nyx.nyx_plan_describe(plan))
+    table = nyx.new_table(plan, len(offs))
+    rois = nyx.RoiTable(plan.n_rois, dev)
+    nyx.nyx_plan_execute(plan, table, rois)
+    torch.cuda.synchronize()
+    nyx.nyx_plan_check(plan)
+    ro = oracle_rois(oracle_mod, w)
+    assert plan.n_rois == len(ro)
+    n = np.array([st["count"][r] for _, r, st in ro])
+    assert np.array_equal(rois.n_vox.cpu().numpy()[:len(ro)], n)
+    rng = np.random.default_rng(7)
+    order = np.argsort(n)
+    sample = sorted(set([int(order[0]), int(order[-1]), int(order[len(order) // 2])] +
+                        rng.choice(len(ro), size=min(20, len(ro)), replace=False).tolist()))
+    want, Ps = _oracle_table(oracle_mod, w, offs, rows=sample)
+    got = table.cpu().numpy()[sample]
+    _check_features(got, want, Ps, TOL_FP32, f"{name} sampled")
+    tab = table.cpu().numpy()[:len(ro)]
+    assert np.all(np.isfinite(tab[n >= 4][:, -1, 0]))
