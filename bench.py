@@ -60,6 +60,7 @@ def main() -> int:
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures a single GPU; multi-GPU runs are not part of this build (use --gpus 1)",
@@ -86,7 +87,7 @@ def main() -> int:
     prec = nyx.NYX_FP64 if w.precision == "fp64" else nyx.NYX_FP32
     ctx = nyx.nyx_create(0)
     t0 = time.perf_counter()
-    plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, prec)
+    plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, prec, autotune=not args.no_autotune)
     plan_s = time.perf_counter() - t0
     log(f"plan in {plan_s:.2f} s: {nyx.nyx_plan_describe(plan)}")
     n_rois = plan.n_rois

@@ -115,6 +115,11 @@ typedef struct nyx_extract_opts {
     int32_t symmetric;           /* must be 1 */
     nyx_precision precision;     /* feature output type */
     int32_t autotune;            /* 1: time candidate kernel configurations at plan time */
+    int32_t accum_mode;          /* -1 = automatic; else force one accumulation mode:
+                                    0 LDS triangle + nonzero list built by returning atomics,
+                                    1 LDS hash table, 2 LDS triangle + ordered scan,
+                                    3 LDS triangle of 16-bit counters + ordered scan
+                                    (NYX_ERR_UNSUPPORTED when it does not fit) */
     int64_t workspace_cap_bytes; /* 0 = no cap; exceeding it gives NYX_ERR_OOM */
 } nyx_extract_opts;
 

@@ -28,24 +28,68 @@ __device__ __forceinline__ uint32_t fbn_level(uint32_t I, uint32_t vmin, uint32_
 }
 
 // ------------------------------------------------------------ wave ops
+// Wave-wide reductions with DPP: four in-row steps (quad_perm [1,0,3,2],
+// quad_perm [2,3,0,1], row_half_mirror, row_mirror) leave every lane of each
+// 16-lane row holding its row's total; the four row totals are then combined
+// from lanes 0, 16, 32 and 48 with readlane.  The result is wave-uniform.
+constexpr int kDppQuad1032 = 0xB1;
+constexpr int kDppQuad2301 = 0x4E;
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL, class T>
+__device__ __forceinline__ T dpp_move(T v) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32/64-bit only");
+    if constexpr (sizeof(T) == 4) {
+        uint32_t u = __builtin_bit_cast(uint32_t, v);
+        return __builtin_bit_cast(T, dpp32<CTRL>(u));
+    } else {
+        uint64_t u = __builtin_bit_cast(uint64_t, v);
+        uint32_t lo = dpp32<CTRL>((uint32_t)u), hi = dpp32<CTRL>((uint32_t)(u >> 32));
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+
 template <class T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+__device__ __forceinline__ T readlane_(T v, int l) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, (uint32_t)__builtin_amdgcn_readlane((int)__builtin_bit_cast(uint32_t, v), l));
+    } else {
+        uint64_t u = __builtin_bit_cast(uint64_t, v);
+        uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+        uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+// Row (16-lane) reduction: every lane ends with its row's combination.
+template <class T, class Op>
+__device__ __forceinline__ T row_reduce(T v, Op op) {
+    v = op(v, dpp_move<kDppQuad1032>(v));
+    v = op(v, dpp_move<kDppQuad2301>(v));
+    v = op(v, dpp_move<kDppRowHalfMirror>(v));
+    v = op(v, dpp_move<kDppRowMirror>(v));
     return v;
 }
-template <class T>
-__device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) { T u = __shfl_xor(v, o); v = u > v ? u : v; }
-    return v;
+
+template <class T, class Op>
+__device__ __forceinline__ T wave_reduce(T v, Op op) {
+    v = row_reduce(v, op);
+    return op(op(readlane_(v, 0), readlane_(v, 16)), op(readlane_(v, 32), readlane_(v, 48)));
 }
-template <class T>
-__device__ __forceinline__ T wave_min(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) { T u = __shfl_xor(v, o); v = u < v ? u : v; }
-    return v;
-}
+
+struct OpAdd { template <class T> __device__ __forceinline__ T operator()(T a, T b) const { return a + b; } };
+struct OpMax { template <class T> __device__ __forceinline__ T operator()(T a, T b) const { return a > b ? a : b; } };
+struct OpMin { template <class T> __device__ __forceinline__ T operator()(T a, T b) const { return a < b ? a : b; } };
+
+template <class T> __device__ __forceinline__ T wave_sum(T v) { return wave_reduce(v, OpAdd()); }
+template <class T> __device__ __forceinline__ T wave_max(T v) { return wave_reduce(v, OpMax()); }
+template <class T> __device__ __forceinline__ T wave_min(T v) { return wave_reduce(v, OpMin()); }
 
 // Compensated (Kahan-Babuska / Neumaier) accumulator.
 template <class F>
@@ -61,21 +105,35 @@ struct Comp {
     __device__ __forceinline__ F value() const { return s + c; }
 };
 
-// Sum of compensated accumulators across the wave: the partial sums are
-// combined with an error-free two-sum, the compensations added.
+// Sum of compensated accumulators across the wave: partial sums are combined
+// with an error-free two-sum at each step, the compensations added.
+template <class F>
+struct CompPair { F s, c; };
+
+template <class F>
+__device__ __forceinline__ CompPair<F> comp_combine(CompPair<F> a, CompPair<F> b) {
+    F t = a.s + b.s;
+    F bp = t - a.s;
+    F err = (a.s - (t - bp)) + (b.s - bp);
+    return CompPair<F>{t, a.c + b.c + err};
+}
+
+template <int CTRL, class F>
+__device__ __forceinline__ CompPair<F> dpp_move_pair(CompPair<F> v) {
+    return CompPair<F>{dpp_move<CTRL>(v.s), dpp_move<CTRL>(v.c)};
+}
+
 template <class F>
 __device__ __forceinline__ F wave_sum_comp(Comp<F> a) {
-    F s = a.s, c = a.c;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        F s2 = __shfl_xor(s, o), c2 = __shfl_xor(c, o);
-        F t = s + s2;
-        F bp = t - s;
-        F err = (s - (t - bp)) + (s2 - bp);
-        s = t;
-        c = c + c2 + err;
-    }
-    return s + c;
+    CompPair<F> v{a.s, a.c};
+    v = comp_combine(v, dpp_move_pair<kDppQuad1032>(v));
+    v = comp_combine(v, dpp_move_pair<kDppQuad2301>(v));
+    v = comp_combine(v, dpp_move_pair<kDppRowHalfMirror>(v));
+    v = comp_combine(v, dpp_move_pair<kDppRowMirror>(v));
+    CompPair<F> r0{readlane_(v.s, 0), readlane_(v.c, 0)}, r1{readlane_(v.s, 16), readlane_(v.c, 16)};
+    CompPair<F> r2{readlane_(v.s, 32), readlane_(v.c, 32)}, r3{readlane_(v.s, 48), readlane_(v.c, 48)};
+    CompPair<F> t = comp_combine(comp_combine(r0, r1), comp_combine(r2, r3));
+    return t.s + t.c;
 }
 
 // ------------------------------------------------------------ 128-bit

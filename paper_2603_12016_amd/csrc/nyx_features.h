@@ -80,20 +80,24 @@ struct BlockGrp {
 // A source enumerates candidate cells e in [0, size()); get() returns the
 // 0-based levels lo <= hi and the triangle count (0 = skip the cell).
 
+template <bool PACKED>
 struct SrcDenseList {     // fused dense mode: LDS triangle + list of touched cells
     const uint32_t *list;
     uint32_t n;
-    uint32_t *U;
+    uint32_t *U;             // u32 counts, or u16 counts packed two per word
     __device__ __forceinline__ uint32_t size() const { return n; }
     __device__ __forceinline__ uint64_t get(uint32_t e, uint32_t &lo, uint32_t &hi) const {
         uint32_t p = list[e];
         lo = p & 0xFFFFu;
         hi = p >> 16;
-        return U[tri_idx(lo, hi)];
+        const uint32_t i = tri_idx(lo, hi);
+        return PACKED ? (uint64_t)reinterpret_cast<const uint16_t *>(U)[i] : (uint64_t)U[i];
     }
     __device__ __forceinline__ void clear(uint32_t e) const {
         uint32_t p = list[e];
-        U[tri_idx(p & 0xFFFFu, p >> 16)] = 0u;
+        const uint32_t i = tri_idx(p & 0xFFFFu, p >> 16);
+        if (PACKED) reinterpret_cast<uint16_t *>(U)[i] = 0u;
+        else U[i] = 0u;
     }
 };
 
@@ -153,6 +157,55 @@ struct SrcCoo {           // sorted COO segment of one ROI-direction
     __device__ __forceinline__ void clear(uint32_t) const {}
 };
 
+// Reduced per-direction sums (wave-uniform), input of finalize_dir.
+struct DirSums {
+    uint64_t T, S1, S2, Sm1, S11, sumP2, maxP, pad;
+    double HX, DENT, HOM1, HOM2, IDMN, IDN, IV, SENT, JE, CSHADE, CPROM, MI;
+};
+
+// The 30 features of one direction from its reduced sums (one lane).
+__device__ __noinline__ void finalize_dir(const DirSums &s, double *out) {
+    if (s.T == 0) {
+        for (int f = 0; f < kNumFeat; ++f) out[f] = __builtin_nan("");
+        return;
+    }
+    const uint64_t T = s.T, S1 = s.S1, S2 = s.S2, S11 = s.S11, Sm1 = s.Sm1;
+    const double Td = (double)T;
+    const double T2 = Td * Td;
+    const u128 Tq = (u128)T;
+    const u128 s1sq = (u128)S1 * (u128)S1;
+    const u128 nvar = Tq * (u128)S2 - s1sq;
+    const i128 ncov = (i128)(Tq * (u128)S11) - (i128)s1sq;
+    const u128 sm2 = 2 * (u128)S2 - 2 * (u128)S11;     // sum (i - j)^2 P
+    const u128 ndv = Tq * sm2 - (u128)Sm1 * (u128)Sm1;
+    const bool single = nvar == 0;
+    const double var = u128_to_double(nvar) / T2;
+    out[F_ASM] = out[F_ENERGY] = (double)s.sumP2 / T2;
+    out[F_ACOR] = (double)S11 / Td;
+    out[F_CLUPROM] = s.CPROM;
+    out[F_CLUSHADE] = s.CSHADE;
+    out[F_CLUTEND] = out[F_SUMVAR] = i128_to_double(2 * (i128)nvar + 2 * ncov) / T2;
+    out[F_CONTRAST] = u128_to_double(sm2) / Td;
+    out[F_CORR] = single ? 1.0 : i128_to_double(ncov) / u128_to_double(nvar);
+    out[F_DIFAVE] = out[F_DIS] = (double)Sm1 / Td;
+    out[F_DIFENTRO] = s.DENT;
+    out[F_DIFVAR] = u128_to_double(ndv) / T2;
+    out[F_ENTROPY] = out[F_JE] = s.JE;
+    out[F_HOM1] = out[F_ID] = s.HOM1;
+    out[F_HOM2] = out[F_IDM] = s.HOM2;
+    const double mi = s.MI > 0.0 ? s.MI : 0.0;
+    out[F_INFOMEAS1] = single ? 0.0 : -s.MI / s.HX;
+    out[F_INFOMEAS2] = sqrt(1.0 - exp(-2.0 * mi));
+    out[F_IDMN] = s.IDMN;
+    out[F_IDN] = s.IDN;
+    out[F_IV] = s.IV;
+    out[F_JAVE] = (double)S1 / Td;
+    out[F_JMAX] = (double)s.maxP / Td;
+    out[F_SUMAVE] = 2.0 * (double)S1 / Td;
+    out[F_SUMENT] = s.SENT;
+    out[F_JVAR] = out[F_VARIANCE] = var;
+}
+
 template <class F> __device__ __forceinline__ F log2_(F x);
 template <> __device__ __forceinline__ float log2_<float>(float x) { return log2f(x); }
 template <> __device__ __forceinline__ double log2_<double>(double x) { return log2(x); }
@@ -160,13 +213,13 @@ template <class F> __device__ __forceinline__ F log1p_(F x);
 template <> __device__ __forceinline__ float log1p_<float>(float x) { return log1pf(x); }
 template <> __device__ __forceinline__ double log1p_<double>(double x) { return log1p(x); }
 
-// Features of one direction.  R, Sp, Sm are zeroed LDS arrays of ng, 2 ng - 1
-// and ng u32 (row, sum and difference marginals of the symmetric matrix);
-// they are zeroed again on return, and the source cells are cleared.
-// out[30] (LDS) is written by rank 0.  Returns T (0: direction empty, all NaN).
+// Reduced sums of one direction.  R, Sp, Sm are zeroed LDS arrays of ng,
+// 2 ng - 1 and ng u32 (row, sum and difference marginals of the symmetric
+// matrix); they are zeroed again on return, and the source cells are cleared.
+// *out (LDS) is written by rank 0.  Returns T (0: direction empty).
 template <class Acc, class Grp, class Src>
-__device__ uint64_t dir_features(const Grp &g, const Src &src, uint32_t *R, uint32_t *Sp,
-                                 uint32_t *Sm, uint32_t ng, double *out) {
+__device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t *Sp,
+                             uint32_t *Sm, uint32_t ng, DirSums *out) {
     const uint32_t n = src.size();
     const int r0 = g.rank(), gs = g.size();
     // Sweep 1: marginals.  An off-diagonal triangle cell (lo < hi) with count
@@ -186,8 +239,7 @@ __device__ uint64_t dir_features(const Grp &g, const Src &src, uint32_t *R, uint
     const uint64_t T = g.sum(Tl);
     g.sync();
     if (T == 0) {
-        if (r0 == 0)
-            for (int f = 0; f < kNumFeat; ++f) out[f] = __builtin_nan("");
+        if (r0 == 0) out->T = 0;
         g.sync();
         return 0;
     }
@@ -291,38 +343,11 @@ __device__ uint64_t dir_features(const Grp &g, const Src &src, uint32_t *R, uint
         MI = (double)g.csum(m);
     }
     if (r0 == 0) {
-        const u128 Tq = (u128)T;
-        const u128 nvar = Tq * (u128)S2 - (u128)S1 * (u128)S1;
-        const i128 ncov = (i128)(Tq * (u128)S11) - (i128)((u128)S1 * (u128)S1);
-        const double T2 = Td * Td;
-        const u128 sm2 = 2 * (u128)S2 - 2 * (u128)S11;     // sum (i - j)^2 P
-        const u128 ndv = Tq * sm2 - (u128)Sm1 * (u128)Sm1;
-        const bool single = nvar == 0;
-        const double var = u128_to_double(nvar) / T2;
-        out[F_ASM] = out[F_ENERGY] = (double)sumP2 / T2;
-        out[F_ACOR] = (double)S11 / Td;
-        out[F_CLUPROM] = CPROM;
-        out[F_CLUSHADE] = CSHADE;
-        out[F_CLUTEND] = out[F_SUMVAR] = i128_to_double(2 * (i128)nvar + 2 * ncov) / T2;
-        out[F_CONTRAST] = u128_to_double(sm2) / Td;
-        out[F_CORR] = single ? 1.0 : i128_to_double(ncov) / u128_to_double(nvar);
-        out[F_DIFAVE] = out[F_DIS] = (double)Sm1 / Td;
-        out[F_DIFENTRO] = DENT;
-        out[F_DIFVAR] = u128_to_double(ndv) / T2;
-        out[F_ENTROPY] = out[F_JE] = JE;
-        out[F_HOM1] = out[F_ID] = HOM1;
-        out[F_HOM2] = out[F_IDM] = HOM2;
-        double mi = MI > 0.0 ? MI : 0.0;
-        out[F_INFOMEAS1] = single ? 0.0 : -MI / HX;
-        out[F_INFOMEAS2] = sqrt(1.0 - exp(-2.0 * mi));
-        out[F_IDMN] = IDMN;
-        out[F_IDN] = IDN;
-        out[F_IV] = IV;
-        out[F_JAVE] = (double)S1 / Td;
-        out[F_JMAX] = (double)maxP / Td;
-        out[F_SUMAVE] = 2.0 * (double)S1 / Td;
-        out[F_SUMENT] = SENT;
-        out[F_JVAR] = out[F_VARIANCE] = var;
+        out->T = T; out->S1 = S1; out->S2 = S2; out->Sm1 = Sm1; out->S11 = S11;
+        out->sumP2 = sumP2; out->maxP = maxP;
+        out->HX = HX; out->DENT = DENT; out->HOM1 = HOM1; out->HOM2 = HOM2; out->IDMN = IDMN;
+        out->IDN = IDN; out->IV = IV; out->SENT = SENT; out->JE = JE; out->CSHADE = CSHADE;
+        out->CPROM = CPROM; out->MI = MI;
     }
     // Clean up for the next direction / item.
     g.sync();

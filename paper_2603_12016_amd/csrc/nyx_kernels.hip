@@ -85,91 +85,123 @@ __global__ void k_zero_split(StepArgs a) {
 }
 
 // ------------------------------------------------------------------ scan
-// Each lane takes 8 consecutive voxels; a wavefront then folds the statistics
-// of each distinct label present in its 512 voxels and one lane per label
-// updates the global per-label entry.
+// ROI discovery.  A work-group covers a tile of kScanRows image rows (rows
+// of all z-planes, flattened) by kScanCols columns; each lane walks one row
+// segment, cutting it into runs of equal label.  Each run's statistics are
+// folded into an LDS table keyed by label, and the table is flushed to the
+// global per-label entries once per tile.  A label that finds no free LDS
+// slot goes straight to the global entry.
+constexpr int kScanRows = 256;
+constexpr int kScanCols = 32;
+constexpr int kScanSlots = 256;
+
+struct ScanLds {
+    uint32_t key[kScanSlots], cnt[kScanSlots], mn[kScanSlots], mx[kScanSlots];
+    int32_t x0[kScanSlots], x1[kScanSlots], y0[kScanSlots], y1[kScanSlots], z0[kScanSlots], z1[kScanSlots];
+};
+
+__device__ __forceinline__ void scan_flush_global(const StepArgs &a, uint32_t K, uint32_t c, uint32_t mn, uint32_t mx,
+                                                  int32_t x0, int32_t x1, int32_t y0, int32_t y1, int32_t z0,
+                                                  int32_t z1) {
+    atomicAdd(&a.tab.cnt[K], c);
+    atomicMin(&a.tab.mn[K], mn);
+    atomicMax(&a.tab.mx[K], mx);
+    atomicMin(&a.tab.x0[K], x0); atomicMax(&a.tab.x1[K], x1);
+    atomicMin(&a.tab.y0[K], y0); atomicMax(&a.tab.y1[K], y1);
+    atomicMin(&a.tab.z0[K], z0); atomicMax(&a.tab.z1[K], z1);
+}
+
+__device__ __forceinline__ void scan_flush_run(const StepArgs &a, ScanLds &S, uint32_t K, uint32_t c, uint32_t mn,
+                                               uint32_t mx, int32_t x0, int32_t x1, int32_t y, int32_t z) {
+    uint32_t h = hash_u32(K) & (kScanSlots - 1);
+    for (int probe = 0; probe < 8; ++probe) {
+        uint32_t cur = atomicCAS(&S.key[h], kNone, K);
+        if (cur == kNone || cur == K) {
+            atomicAdd(&S.cnt[h], c);
+            atomicMin(&S.mn[h], mn);
+            atomicMax(&S.mx[h], mx);
+            atomicMin(&S.x0[h], x0); atomicMax(&S.x1[h], x1);
+            atomicMin(&S.y0[h], y); atomicMax(&S.y1[h], y);
+            atomicMin(&S.z0[h], z); atomicMax(&S.z1[h], z);
+            return;
+        }
+        h = (h + 1u) & (kScanSlots - 1);
+    }
+    scan_flush_global(a, K, c, mn, mx, x0, x1, y, y, z, z);
+}
+
 __global__ __launch_bounds__(256) void k_scan(StepArgs a) {
-    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = c < a.total_chunks;
-    const int im = find_image_chunk(a.imgs, a.n_images, in ? c : 0u);
+    __shared__ ScanLds S;
+    for (int i = threadIdx.x; i < kScanSlots; i += blockDim.x) {
+        S.key[i] = kNone; S.cnt[i] = 0u; S.mn[i] = 0xFFFFFFFFu; S.mx[i] = 0u;
+        S.x0[i] = INT_MAX; S.y0[i] = INT_MAX; S.z0[i] = INT_MAX;
+        S.x1[i] = -1; S.y1[i] = -1; S.z1[i] = -1;
+    }
+    const uint32_t tile = blockIdx.x;
+    const int im = find_image_chunk(a.imgs, a.n_images, tile);
     const ImgDesc d = a.imgs[im];
-    const uint32_t v0 = (c - d.chunk_base) * 8u;
-    uint32_t lab[8], val[8];
+    const uint32_t nxc = ((uint32_t)d.nx + kScanCols - 1u) / kScanCols;
+    const uint32_t t = tile - d.chunk_base;
+    const uint32_t rblk = t / nxc, cblk = t - rblk * nxc;
+    const uint32_t rows = (uint32_t)d.nz * (uint32_t)d.ny;
+    const uint32_t row = rblk * kScanRows + threadIdx.x;
+    const int32_t xs = (int32_t)(cblk * kScanCols);
+    const int32_t ncol = min(kScanCols, d.nx - xs);
+    __syncthreads();
+    if (row < rows && im < a.n_images) {
+        const int32_t z = (int32_t)(row / (uint32_t)d.ny), y = (int32_t)(row - (uint32_t)z * (uint32_t)d.ny);
+        const uint64_t base = (uint64_t)row * (uint32_t)d.nx + (uint32_t)xs;
+        uint32_t lab[kScanCols], val[kScanCols];
+        if (d.vec_ok && ncol == kScanCols) {
+            const uint4 *pl = reinterpret_cast<const uint4 *>(d.L + base);
+            const uint4 *pi = reinterpret_cast<const uint4 *>(d.I + base);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) { lab[j] = 0u; val[j] = 0u; }
-    if (in && v0 < d.nvox) {
-        if (d.vec_ok) {
-            uint4 l0 = *reinterpret_cast<const uint4 *>(d.L + v0);
-            uint4 l1 = *reinterpret_cast<const uint4 *>(d.L + v0 + 4);
-            uint4 iv = *reinterpret_cast<const uint4 *>(d.I + v0);
-            lab[0] = l0.x; lab[1] = l0.y; lab[2] = l0.z; lab[3] = l0.w;
-            lab[4] = l1.x; lab[5] = l1.y; lab[6] = l1.z; lab[7] = l1.w;
-            val[0] = iv.x & 0xFFFFu; val[1] = iv.x >> 16; val[2] = iv.y & 0xFFFFu; val[3] = iv.y >> 16;
-            val[4] = iv.z & 0xFFFFu; val[5] = iv.z >> 16; val[6] = iv.w & 0xFFFFu; val[7] = iv.w >> 16;
+            for (int q = 0; q < kScanCols / 4; ++q) {
+                uint4 v = pl[q];
+                lab[4 * q] = v.x; lab[4 * q + 1] = v.y; lab[4 * q + 2] = v.z; lab[4 * q + 3] = v.w;
+            }
+#pragma unroll
+            for (int q = 0; q < kScanCols / 8; ++q) {
+                uint4 v = pi[q];
+                val[8 * q + 0] = v.x & 0xFFFFu; val[8 * q + 1] = v.x >> 16;
+                val[8 * q + 2] = v.y & 0xFFFFu; val[8 * q + 3] = v.y >> 16;
+                val[8 * q + 4] = v.z & 0xFFFFu; val[8 * q + 5] = v.z >> 16;
+                val[8 * q + 6] = v.w & 0xFFFFu; val[8 * q + 7] = v.w >> 16;
+            }
         } else {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                uint32_t v = v0 + j;
-                if (v < d.nvox) { lab[j] = d.L[v]; val[j] = d.I[v]; }
+            for (int j = 0; j < kScanCols; ++j) {
+                bool ok = j < ncol;
+                lab[j] = ok ? d.L[base + j] : 0u;
+                val[j] = ok ? (uint32_t)d.I[base + j] : 0u;
             }
         }
-    }
-    uint32_t key[8];
-    uint32_t pend = 0u, bad = 0u;
+        uint32_t bad = 0u;
+        uint32_t cur = 0u, c = 0u, mn = 0xFFFFu, mx = 0u;
+        int32_t rx0 = 0, rx1 = 0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        uint32_t l = lab[j];
-        key[j] = kNone;
-        if (l != 0u) {
-            if (l > d.max_label) bad = 1u;
-            else { key[j] = d.tab_base + l; pend |= 1u << j; }
-        }
-    }
-    if (bad) atomicOr(&a.counters[C_ERR], (uint32_t)E_LABEL_RANGE);
-    const uint32_t nx = (uint32_t)d.nx, ny = (uint32_t)d.ny;
-    uint32_t rowi = v0 / nx;
-    int32_t x = (int32_t)(v0 - rowi * nx);
-    uint32_t zz = rowi / ny;
-    int32_t y = (int32_t)(rowi - zz * ny), z = (int32_t)zz;
-    int32_t xs[8], ys[8], zs[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        xs[j] = x; ys[j] = y; zs[j] = z;
-        if (++x == (int32_t)nx) { x = 0; if (++y == (int32_t)ny) { y = 0; ++z; } }
-    }
-    while (true) {
-        uint64_t act = __ballot(pend != 0u);
-        if (act == 0ull) break;
-        int leader = __ffsll((unsigned long long)act) - 1;
-        uint32_t mine = kNone;
-#pragma unroll
-        for (int j = 7; j >= 0; --j)
-            if ((pend >> j) & 1u) mine = key[j];
-        uint32_t K = __shfl(mine, leader);
-        uint32_t cnt = 0u, mn = 0xFFFFu, mx = 0u;
-        int32_t bx0 = INT_MAX, by0 = INT_MAX, bz0 = INT_MAX, bx1 = -1, by1 = -1, bz1 = -1;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (((pend >> j) & 1u) && key[j] == K) {
-                ++cnt;
-                mn = min(mn, val[j]); mx = max(mx, val[j]);
-                bx0 = min(bx0, xs[j]); bx1 = max(bx1, xs[j]);
-                by0 = min(by0, ys[j]); by1 = max(by1, ys[j]);
-                bz0 = min(bz0, zs[j]); bz1 = max(bz1, zs[j]);
-                pend &= ~(1u << j);
+        for (int j = 0; j < kScanCols; ++j) {
+            uint32_t l = lab[j];
+            if (l > d.max_label) { bad = 1u; l = 0u; }
+            if (l != cur) {
+                if (cur) scan_flush_run(a, S, d.tab_base + cur, c, mn, mx, rx0, rx1, y, z);
+                cur = l; c = 0u; mn = 0xFFFFu; mx = 0u; rx0 = xs + j;
+            }
+            if (l) {
+                ++c;
+                mn = min(mn, val[j]);
+                mx = max(mx, val[j]);
+                rx1 = xs + j;
             }
         }
-        cnt = wave_sum(cnt);
-        mn = wave_min(mn); mx = wave_max(mx);
-        bx0 = wave_min(bx0); by0 = wave_min(by0); bz0 = wave_min(bz0);
-        bx1 = wave_max(bx1); by1 = wave_max(by1); bz1 = wave_max(bz1);
-        if (lane() == leader) {
-            atomicAdd(&a.tab.cnt[K], cnt);
-            atomicMin(&a.tab.mn[K], mn);
-            atomicMax(&a.tab.mx[K], mx);
-            atomicMin(&a.tab.x0[K], bx0); atomicMin(&a.tab.y0[K], by0); atomicMin(&a.tab.z0[K], bz0);
-            atomicMax(&a.tab.x1[K], bx1); atomicMax(&a.tab.y1[K], by1); atomicMax(&a.tab.z1[K], bz1);
-        }
+        if (cur) scan_flush_run(a, S, d.tab_base + cur, c, mn, mx, rx0, rx1, y, z);
+        if (bad) atomicOr(&a.counters[C_ERR], (uint32_t)E_LABEL_RANGE);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kScanSlots; i += blockDim.x) {
+        uint32_t K = S.key[i];
+        if (K != kNone)
+            scan_flush_global(a, K, S.cnt[i], S.mn[i], S.mx[i], S.x0[i], S.x1[i], S.y0[i], S.y1[i], S.z0[i], S.z1[i]);
     }
 }
 
@@ -193,6 +225,8 @@ __global__ __launch_bounds__(1024) void k_compact_count(StepArgs a) {
 // class, so the persistent kernel can drain the largest work first.
 __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi_lo, uint32_t roi_hi) {
     __shared__ uint32_t wc[16], wpre[16], s_part[16], s_prefix;
+    __shared__ uint32_t cls_cnt[kClasses], cls_base[kClasses];
+    if (threadIdx.x < kClasses) cls_cnt[threadIdx.x] = 0u;
     uint32_t part = 0;
     for (uint32_t b = threadIdx.x; b < blockIdx.x; b += 1024u) part += a.counters[C_BLOCKS + b];
     part = wave_sum(part);
@@ -210,13 +244,17 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
         if (blockIdx.x == gridDim.x - 1) a.counters[C_NROIS] = s + acc;
     }
     __syncthreads();
-    if (!p) return;
+    // Every thread reaches the block-level class aggregation below.
     const uint32_t rank = (uint32_t)__popcll(m & __lanemask_lt());
     const uint32_t row = s_prefix + wpre[threadIdx.x / 64] + rank;
-    if (row >= a.roi_cap) { atomicOr(&a.counters[C_ERR], (uint32_t)E_ROI_CAP); return; }
+    bool live = p;
+    if (live && row >= a.roi_cap) { atomicOr(&a.counters[C_ERR], (uint32_t)E_ROI_CAP); live = false; }
+    RoiDesc rd;
+    bool enq = false;
+    uint32_t cls = 0u, nt = 1u, local = 0u;
+    if (live) {
     const int im = find_image_entry(a.imgs, a.n_images, e);
     const uint32_t label = e - a.imgs[im].tab_base;
-    RoiDesc rd;
     rd.label = label;
     rd.image = (uint32_t)im;
     rd.n = a.tab.cnt[e];
@@ -229,7 +267,7 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
     a.tab.row[e] = row;
     const bool take = a.enqueue && row >= roi_lo && row < roi_hi;
     const Tiling tl = tiles_for(rd.n, rd.rows, (uint32_t)(rd.x1 - rd.x0 + 1), a.split_vox, a.tile_vox);
-    const uint32_t nt = tl.row_blocks * tl.col_blocks;
+    nt = tl.row_blocks * tl.col_blocks;
     rd.n_tiles = nt;
     rd.tcols = tl.col_blocks;
     rd.gslot = kNone;
@@ -244,13 +282,9 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
     }
     a.rois[row] = rd;
     if (take && (rd.gslot != kNone || nt == 1u)) {
-        uint32_t cls = size_class((rd.n + nt - 1u) / nt);
-        uint32_t pos = atomicAdd(&a.counters[C_CLASS + cls], nt);
-        if (pos + nt > a.bucket_cap) {
-            atomicOr(&a.counters[C_ERR], (uint32_t)E_ITEM_CAP);
-        } else {
-            for (uint32_t t = 0; t < nt; ++t) a.buckets[cls * a.bucket_cap + pos + t] = make_uint2(row, t);
-        }
+        enq = true;
+        cls = size_class((rd.n + nt - 1u) / nt);
+        local = atomicAdd(&cls_cnt[cls], nt);
     }
     if (a.o_label) a.o_label[row] = label;
     if (a.o_image) a.o_image[row] = (uint32_t)im;
@@ -260,6 +294,19 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
     if (a.o_bbox) {
         int32_t *b = a.o_bbox + 6ull * row;
         b[0] = rd.x0; b[1] = rd.y0; b[2] = rd.z0; b[3] = rd.x1; b[4] = rd.y1; b[5] = rd.z1;
+    }
+    }  // live
+    __syncthreads();
+    if (threadIdx.x < kClasses && cls_cnt[threadIdx.x])
+        cls_base[threadIdx.x] = atomicAdd(&a.counters[C_CLASS + threadIdx.x], cls_cnt[threadIdx.x]);
+    __syncthreads();
+    if (enq) {
+        uint32_t pos = cls_base[cls] + local;
+        if (pos + nt > a.bucket_cap) {
+            atomicOr(&a.counters[C_ERR], (uint32_t)E_ITEM_CAP);
+        } else {
+            for (uint32_t t = 0; t < nt; ++t) a.buckets[cls * a.bucket_cap + pos + t] = make_uint2(row, t);
+        }
     }
 }
 
@@ -336,7 +383,14 @@ __device__ __forceinline__ void add_pair(const StepArgs &a, uint8_t *smem, uint3
     uint32_t lo = (la < lb ? la : lb) - 1u, hi = (la < lb ? lb : la) - 1u;
     uint32_t *LCNT = reinterpret_cast<uint32_t *>(smem + Ly.lcnt_off);
     uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off) + dl * Ly.list_cap;
-    if (MODE == 0) {
+    if (MODE == 2) {
+        uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
+        __hip_atomic_fetch_add(&U[tri_idx(lo, hi)], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else if (MODE == 3) {
+        uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
+        const uint32_t i = tri_idx(lo, hi);
+        __hip_atomic_fetch_add(&U[i >> 1], 1u << ((i & 1u) << 4), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else if (MODE == 0) {
         uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
         uint32_t old = atomicAdd(&U[tri_idx(lo, hi)], 1u);
         bool fresh = old == 0u;
@@ -430,6 +484,102 @@ __device__ void write_row(const StepArgs &a, uint32_t row, const double *feat, i
     }
 }
 
+// 2D distance-1 accumulation by row sweep.  A wavefront covers 64 adjacent
+// columns of one row at a time (lanes 0..62 own their column, lane 63 only
+// supplies the right neighbour) and walks down a chunk of rows keeping the
+// previous row's levels in registers; the right neighbours come from the next
+// lane by a DPP wave shift.  Owned pairs per lane (column x, row y):
+//   H    (y, x)-(y, x+1)      V    (y, x)-(y-1, x)
+//   D45  (y, x)-(y-1, x+1)    D135 (y-1, x)-(y, x+1)
+// h, v, d45, d135 are the local direction slots of the four classes (-1: not
+// in this pass).
+__device__ __forceinline__ uint32_t lane_next(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false);  // wave_shl1
+}
+
+template <int MODE>
+__device__ void accumulate_sweep2d(const StepArgs &a, uint8_t *smem, const RoiDesc &rd, const ItemCtx &c,
+                                   uint32_t ra, uint32_t rb, uint32_t ca, uint32_t cb, int h, int v, int d45,
+                                   int d135) {
+    const int nw = (int)(blockDim.x / kWave), w = (int)(threadIdx.x / kWave), ln = lane();
+    const uint32_t Wt = cb - ca;
+    const uint32_t nstrip = (Wt + 62u) / 63u;
+    const uint32_t nrows = rb - ra;
+    uint32_t want = (2u * (uint32_t)nw + nstrip - 1u) / nstrip;     // chunks per strip
+    uint32_t CH = (nrows + want - 1u) / want;
+    CH = CH < 4u ? 4u : (CH > 64u ? 64u : CH);
+    const uint32_t nchunk = (nrows + CH - 1u) / CH;
+    const uint32_t units = nstrip * nchunk;
+    const int32_t xt0 = rd.x0 + (int32_t)ca, xt1 = rd.x0 + (int32_t)cb;   // owned columns [xt0, xt1)
+    for (uint32_t u = (uint32_t)w; u < units; u += (uint32_t)nw) {
+        const uint32_t s = u % nstrip, ch = u / nstrip;
+        const int32_t x = xt0 + 63 * (int32_t)s + ln;
+        const bool xin = x < c.nx;
+        const bool owner = ln < 63 && x < xt1;
+        const uint32_t r0 = ra + ch * CH, r1 = min(rb, r0 + CH);
+        const int32_t ybase = rd.y0 + (int32_t)r0;
+        uint32_t prev = 0u;
+        if (xin && ybase - 1 >= rd.y0) {
+            int64_t idx = (int64_t)(ybase - 1) * c.nx + x;
+            if (c.L[idx] == c.label) prev = c.level((uint32_t)idx);
+        }
+        // rows in groups of 8: all loads of a group are issued before use
+        for (uint32_t g0 = r0; g0 < r1; g0 += 8u) {
+            uint32_t lab[8], lev[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                lab[j] = 0u;
+                if (xin && g0 + j < r1) lab[j] = c.L[(int64_t)(rd.y0 + (int32_t)(g0 + j)) * c.nx + x];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                lev[j] = 0u;
+                if (lab[j] == c.label && xin && g0 + j < r1)
+                    lev[j] = c.level((uint32_t)((int64_t)(rd.y0 + (int32_t)(g0 + j)) * c.nx + x));
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (g0 + j >= r1) break;
+                const uint32_t cur = lev[j];
+                const uint32_t cur_r = lane_next(cur), prev_r = lane_next(prev);
+                if (owner && cur) {
+                    if (h >= 0 && cur_r) add_pair<MODE>(a, smem, (uint32_t)h, cur, cur_r);
+                    if (v >= 0 && prev) add_pair<MODE>(a, smem, (uint32_t)v, cur, prev);
+                    if (d45 >= 0 && prev_r) add_pair<MODE>(a, smem, (uint32_t)d45, cur, prev_r);
+                }
+                if (owner && prev && cur_r && d135 >= 0) add_pair<MODE>(a, smem, (uint32_t)d135, prev, cur_r);
+                prev = cur;
+            }
+        }
+    }
+}
+
+// Builds the nonzero list of one direction's triangle (scan modes) in
+// triangle-index order, i.e. (hi, lo) ascending; one wavefront.
+template <bool PACKED>
+__device__ __forceinline__ uint32_t build_list(const uint32_t *U, uint32_t tri, uint32_t *list, uint32_t cap,
+                                               uint32_t *err) {
+    uint32_t n = 0;
+    for (uint32_t base = 0; base < tri; base += kWave) {
+        const uint32_t i = base + (uint32_t)lane();
+        uint32_t c = 0u;
+        if (i < tri) c = PACKED ? (uint32_t)reinterpret_cast<const uint16_t *>(U)[i] : U[i];
+        const uint64_t m = __ballot(c != 0u);
+        if (c) {
+            // decode i = hi (hi + 1) / 2 + lo
+            uint32_t hi = (uint32_t)((sqrtf(8.0f * (float)i + 1.0f) - 1.0f) * 0.5f);
+            if (((hi * (hi + 1u)) >> 1) > i) --hi;
+            else if ((((hi + 1u) * (hi + 2u)) >> 1) <= i) ++hi;
+            const uint32_t lo = i - ((hi * (hi + 1u)) >> 1);
+            const uint32_t pos = n + (uint32_t)__popcll(m & __lanemask_lt());
+            if (pos < cap) list[pos] = lo | (hi << 16);
+            else atomicOr(err, (uint32_t)E_LIST_CAP);
+        }
+        n += (uint32_t)__popcll(m);
+    }
+    return n < cap ? n : cap;
+}
+
 template <int MODE, class OutT>
 __global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -438,6 +588,7 @@ __global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) 
     uint32_t *LCNT = reinterpret_cast<uint32_t *>(smem + Ly.lcnt_off);
     uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off);
     double *FEAT = reinterpret_cast<double *>(smem + Ly.feat_off);
+    DirSums *SUMS = reinterpret_cast<DirSums *>(smem + Ly.sums_off);
     uint32_t *MISC = reinterpret_cast<uint32_t *>(smem + Ly.misc_off);
     const int nw = (int)(blockDim.x / kWave), w = (int)(threadIdx.x / kWave);
     const int K = a.K;
@@ -446,7 +597,7 @@ __global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) 
     uint32_t *MARG = reinterpret_cast<uint32_t *>(smem + Ly.marg_off) + w * marg_words;
 
     // LDS starts clean and every item leaves it clean.
-    if (MODE == 0) {
+    if (MODE != 1) {
         uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off);
         for (uint32_t i = threadIdx.x; i < Ly.kp * Ly.tri_pad; i += blockDim.x) U[i] = 0u;
     } else {
@@ -462,106 +613,123 @@ __global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) 
         uint32_t acc = 0;
         for (int cl = kClasses - 1; cl >= 0; --cl) {
             uint32_t cnt = min(a.counters[C_CLASS + cl], a.bucket_cap);
-            MISC[8 + cl] = acc;
-            MISC[40 + cl] = cnt;
+            MISC[64 + cl] = acc;
+            MISC[96 + cl] = cnt;
             acc += cnt;
         }
-        MISC[7] = acc;
+        MISC[63] = acc;
     }
     __syncthreads();
 
     for (uint32_t iter = 0;; ++iter) {
+        // A chunk of up to kTicketChunk consecutive queue entries per ticket.
         if (threadIdx.x == 0) {
-            uint32_t ok = 0, roi = 0, tile = 0;
+            uint32_t n = 0;
             if (direct_roi != kNone) {
-                if (iter == 0 && direct_roi < a.roi_cap) {
-                    roi = direct_roi;
-                    tile = blockIdx.x;
-                    ok = tile < a.rois[roi].n_tiles;
+                if (iter == 0 && direct_roi < a.roi_cap && blockIdx.x < a.rois[direct_roi].n_tiles) {
+                    MISC[0] = direct_roi;
+                    MISC[1] = blockIdx.x;
+                    n = 1;
                 }
             } else {
-                uint32_t t = atomicAdd(&a.counters[C_TICKET], 1u);
-                if (t < MISC[7]) {
+                const uint32_t total = MISC[63];
+                uint32_t t = atomicAdd(&a.counters[C_TICKET], (uint32_t)kTicketChunk);
+                for (uint32_t q = 0; q < (uint32_t)kTicketChunk && t + q < total; ++q) {
+                    uint32_t tt = t + q;
                     int cl = kClasses - 1;
-                    while (cl > 0 && t >= MISC[8 + cl] + MISC[40 + cl]) --cl;
-                    uint2 it = a.buckets[(uint32_t)cl * a.bucket_cap + (t - MISC[8 + cl])];
-                    roi = it.x;
-                    tile = it.y;
-                    ok = 1;
-                } else {
-                    ok = 0;
+                    while (cl > 0 && tt >= MISC[64 + cl] + MISC[96 + cl]) --cl;
+                    uint2 it = a.buckets[(uint32_t)cl * a.bucket_cap + (tt - MISC[64 + cl])];
+                    MISC[2 * n] = it.x;
+                    MISC[2 * n + 1] = it.y;
+                    ++n;
                 }
-                // an entry that does not name a valid ROI tile is skipped
-                if (ok && (roi >= a.roi_cap || tile >= a.rois[roi].n_tiles)) ok = 2;
             }
-            MISC[0] = roi;
-            MISC[1] = tile;
-            MISC[2] = ok;
+            MISC[32] = n;
         }
         __syncthreads();
-        if (!MISC[2]) break;
-        if (MISC[2] != 1u) { __syncthreads(); continue; }
-        const uint32_t roi = MISC[0], tile = MISC[1];
-        const RoiDesc rd = a.rois[roi];
-        if (rd.image >= (uint32_t)a.n_images) { __syncthreads(); continue; }
-        const ImgDesc im = a.imgs[rd.image];
-        if (rd.x0 < 0 || rd.y0 < 0 || rd.z0 < 0 || rd.x1 >= im.nx || rd.y1 >= im.ny || rd.z1 >= im.nz ||
-            rd.x0 > rd.x1 || rd.y0 > rd.y1 || rd.z0 > rd.z1 || rd.n_tiles == 0u || rd.tcols == 0u) {
-            __syncthreads();
-            continue;
-        }
-        ItemCtx c;
-        c.I = im.I; c.L = im.L; c.B = im.B;
-        c.nx = im.nx; c.ny = im.ny; c.nz = im.nz;
-        c.label = rd.label; c.vmin = rd.vmin; c.D = rd.vmax - rd.vmin; c.ng = ng;
-        c.rcpD = c.D ? 1.0f / (float)c.D : 0.0f;
-        c.err = &a.counters[C_ERR];
-        uint32_t ra, rb, ca, cb;
-        tile_bounds(rd.rows, (uint32_t)(rd.x1 - rd.x0 + 1), rd.n_tiles, rd.tcols, tile, &ra, &rb, &ca, &cb);
-        const bool split = rd.gslot != kNone;
-        for (int d0 = 0; d0 < K; d0 += (int)Ly.kp) {
-            const int d1 = min(K, d0 + (int)Ly.kp);
-            if (ra < rb && ca < cb) accumulate_rows<MODE>(a, smem, rd, c, ra, rb, ca, cb, d0, d1);
-            __syncthreads();
-            for (int dl = w; dl < d1 - d0; dl += nw) {
-                const uint32_t n = min(LCNT[dl], Ly.list_cap);
-                const uint32_t *lst = LST + dl * Ly.list_cap;
-                if (split) {
-                    uint64_t *G = a.G + ((uint64_t)rd.gslot * K + (d0 + dl)) * (uint64_t)ng * ng;
-                    for (uint32_t e = lane(); e < n; e += kWave) {
-                        uint32_t lo, hi;
-                        uint64_t cnt;
-                        if (MODE == 0) {
-                            SrcDenseList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad};
-                            cnt = s.get(e, lo, hi);
-                            s.clear(e);
+        const uint32_t n_items = MISC[32];
+        if (n_items == 0u) break;
+        for (uint32_t q = 0; q < n_items; ++q) {
+            const uint32_t roi = MISC[2 * q], tile = MISC[2 * q + 1];
+            // an entry that does not name a valid ROI tile is skipped
+            if (roi >= a.roi_cap) continue;
+            const RoiDesc rd = a.rois[roi];
+            if (tile >= rd.n_tiles || rd.image >= (uint32_t)a.n_images) continue;
+            const ImgDesc im = a.imgs[rd.image];
+            if (rd.x0 < 0 || rd.y0 < 0 || rd.z0 < 0 || rd.x1 >= im.nx || rd.y1 >= im.ny || rd.z1 >= im.nz ||
+                rd.x0 > rd.x1 || rd.y0 > rd.y1 || rd.z0 > rd.z1 || rd.tcols == 0u)
+                continue;
+            ItemCtx c;
+            c.I = im.I; c.L = im.L; c.B = im.B;
+            c.nx = im.nx; c.ny = im.ny; c.nz = im.nz;
+            c.label = rd.label; c.vmin = rd.vmin; c.D = rd.vmax - rd.vmin; c.ng = ng;
+            c.rcpD = c.D ? 1.0f / (float)c.D : 0.0f;
+            c.err = &a.counters[C_ERR];
+            uint32_t ra, rb, ca, cb;
+            tile_bounds(rd.rows, (uint32_t)(rd.x1 - rd.x0 + 1), rd.n_tiles, rd.tcols, tile, &ra, &rb, &ca, &cb);
+            const bool split = rd.gslot != kNone;
+            for (int d0 = 0, pass = 0; d0 < K; d0 += (int)Ly.kp, ++pass) {
+                const int d1 = min(K, d0 + (int)Ly.kp);
+                if (ra < rb && ca < cb) {
+                    if (a.sweep_ok && pass < kMaxSweepPasses)
+                        accumulate_sweep2d<MODE>(a, smem, rd, c, ra, rb, ca, cb, a.sweep[pass][0], a.sweep[pass][1],
+                                                 a.sweep[pass][2], a.sweep[pass][3]);
+                    else
+                        accumulate_rows<MODE>(a, smem, rd, c, ra, rb, ca, cb, d0, d1);
+                }
+                __syncthreads();
+                for (int dl = w; dl < d1 - d0; dl += nw) {
+                    uint32_t *Ud = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
+                    if (MODE == 2 || MODE == 3) {
+                        const uint32_t nn = build_list<MODE == 3>(Ud, (ng * (ng + 1u)) >> 1, LST + dl * Ly.list_cap,
+                                                                  Ly.list_cap, &a.counters[C_ERR]);
+                        if (lane() == 0) LCNT[dl] = nn;
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                    const uint32_t n = min(LCNT[dl], Ly.list_cap);
+                    const uint32_t *lst = LST + dl * Ly.list_cap;
+                    if (split) {
+                        uint64_t *G = a.G + ((uint64_t)rd.gslot * K + (d0 + dl)) * (uint64_t)ng * ng;
+                        for (uint32_t e = lane(); e < n; e += kWave) {
+                            uint32_t lo, hi;
+                            uint64_t cnt;
+                            if (MODE != 1) {
+                                SrcDenseList<MODE == 3> s{lst, n, Ud};
+                                cnt = s.get(e, lo, hi);
+                                s.clear(e);
+                            } else {
+                                SrcHashList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.hkey_off),
+                                              reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off)};
+                                cnt = s.get(e, lo, hi);
+                                s.clear(e);
+                            }
+                            atomicAdd(reinterpret_cast<unsigned long long *>(&G[(uint64_t)lo * ng + hi]),
+                                      (unsigned long long)cnt);
+                        }
+                    } else {
+                        WaveGrp g;
+                        if (MODE != 1) {
+                            SrcDenseList<MODE == 3> s{lst, n, Ud};
+                            dir_sums<Acc>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng, SUMS + d0 + dl);
                         } else {
                             SrcHashList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.hkey_off),
                                           reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off)};
-                            cnt = s.get(e, lo, hi);
-                            s.clear(e);
+                            dir_sums<Acc>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng, SUMS + d0 + dl);
                         }
-                        atomicAdd(reinterpret_cast<unsigned long long *>(&G[(uint64_t)lo * ng + hi]),
-                                  (unsigned long long)cnt);
                     }
-                } else {
-                    WaveGrp g;
-                    if (MODE == 0) {
-                        SrcDenseList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad};
-                        dir_features<Acc>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng,
-                                          FEAT + (d0 + dl) * kNumFeat);
-                    } else {
-                        SrcHashList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.hkey_off),
-                                      reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off)};
-                        dir_features<Acc>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng,
-                                          FEAT + (d0 + dl) * kNumFeat);
-                    }
+                    if (lane() == 0) LCNT[dl] = 0u;
                 }
-                if (lane() == 0) LCNT[dl] = 0u;
+                __syncthreads();
             }
-            __syncthreads();
+            if (!split) {
+                // the 30 features of every direction at once: one lane per direction
+                for (int d = threadIdx.x; d < K; d += blockDim.x) finalize_dir(SUMS[d], FEAT + d * kNumFeat);
+                __syncthreads();
+                write_row<OutT>(a, roi, FEAT, K);
+                __syncthreads();
+            }
         }
-        if (!split) write_row<OutT>(a, roi, FEAT, K);
         __syncthreads();
     }
 }
@@ -584,7 +752,10 @@ __global__ __launch_bounds__(512) void k_split_features(StepArgs a) {
     __syncthreads();
     BlockGrp g{scratch};
     SrcSquare s{a.G + ((uint64_t)slot * K + d) * (uint64_t)ng * ng, ng};
-    dir_features<Acc>(g, s, R, R + ng, R + 3u * ng - 1u, ng, out);
+    DirSums *sums = reinterpret_cast<DirSums *>(out + kNumFeat);
+    dir_sums<Acc>(g, s, R, R + ng, R + 3u * ng - 1u, ng, sums);
+    __syncthreads();
+    if (threadIdx.x == 0) finalize_dir(*sums, out);
     __syncthreads();
     for (int f = threadIdx.x; f < kNumFeat; f += blockDim.x)
         a.split_feat[((uint64_t)slot * K + d) * kNumFeat + f] = out[f];
@@ -687,7 +858,10 @@ __global__ __launch_bounds__(512) void k_coo_features(StepArgs a, const uint64_t
     BlockGrp g{scr};
     SrcCoo src{keys + seg[s], vals + seg[s], (uint32_t)(seg[s + 1] - seg[s]),
                ((uint64_t)(s / K) << 38) | ((uint64_t)(s % K) << 32), ng, &a.counters[C_ERR]};
-    dir_features<Acc>(g, src, R, R + ng, R + 3u * ng - 1u, ng, out);
+    DirSums *sums = reinterpret_cast<DirSums *>(out + kNumFeat);
+    dir_sums<Acc>(g, src, R, R + ng, R + 3u * ng - 1u, ng, sums);
+    __syncthreads();
+    if (threadIdx.x == 0) finalize_dir(*sums, out);
     __syncthreads();
     for (int f = threadIdx.x; f < kNumFeat; f += blockDim.x) scratch[(uint64_t)s * kNumFeat + f] = out[f];
 }
@@ -734,7 +908,7 @@ hipError_t launch_zero_split(const StepArgs &a, hipStream_t st) {
 
 hipError_t launch_scan(const StepArgs &a, hipStream_t st) {
     if (a.total_chunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scan, dim3((a.total_chunks + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_scan, dim3(a.total_chunks), dim3(256), 0, st, a);
     NYX_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -779,17 +953,42 @@ static hipError_t launch_batch_t(const StepArgs &a, uint32_t grid, uint32_t bloc
 }
 
 hipError_t launch_batch(const StepArgs &a, uint32_t grid, uint32_t block, uint32_t direct_roi, hipStream_t st) {
-    if (a.lds.mode == 0)
-        return a.fp64 ? launch_batch_t<0, double>(a, grid, block, direct_roi, st)
-                      : launch_batch_t<0, float>(a, grid, block, direct_roi, st);
-    return a.fp64 ? launch_batch_t<1, double>(a, grid, block, direct_roi, st)
-                  : launch_batch_t<1, float>(a, grid, block, direct_roi, st);
+    switch (a.lds.mode) {
+        case 0: return a.fp64 ? launch_batch_t<0, double>(a, grid, block, direct_roi, st)
+                              : launch_batch_t<0, float>(a, grid, block, direct_roi, st);
+        case 1: return a.fp64 ? launch_batch_t<1, double>(a, grid, block, direct_roi, st)
+                              : launch_batch_t<1, float>(a, grid, block, direct_roi, st);
+        case 2: return a.fp64 ? launch_batch_t<2, double>(a, grid, block, direct_roi, st)
+                              : launch_batch_t<2, float>(a, grid, block, direct_roi, st);
+        default: return a.fp64 ? launch_batch_t<3, double>(a, grid, block, direct_roi, st)
+                               : launch_batch_t<3, float>(a, grid, block, direct_roi, st);
+    }
+}
+
+static const void *batch_kernel(int mode, int fp64) {
+    switch (mode) {
+        case 0: return fp64 ? reinterpret_cast<const void *>(&k_batch<0, double>) : reinterpret_cast<const void *>(&k_batch<0, float>);
+        case 1: return fp64 ? reinterpret_cast<const void *>(&k_batch<1, double>) : reinterpret_cast<const void *>(&k_batch<1, float>);
+        case 2: return fp64 ? reinterpret_cast<const void *>(&k_batch<2, double>) : reinterpret_cast<const void *>(&k_batch<2, float>);
+        default: return fp64 ? reinterpret_cast<const void *>(&k_batch<3, double>) : reinterpret_cast<const void *>(&k_batch<3, float>);
+    }
+}
+
+hipError_t batch_occupancy(int mode, int fp64, uint32_t block, uint32_t lds_bytes, int *blocks_per_cu) {
+    const void *f = batch_kernel(mode, fp64);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, (int)block, (size_t)lds_bytes);
 }
 
 hipError_t get_batch_attributes(int mode, int fp64, hipFuncAttributes *attr) {
     const void *f;
-    if (mode == 0) f = fp64 ? reinterpret_cast<const void *>(&k_batch<0, double>) : reinterpret_cast<const void *>(&k_batch<0, float>);
-    else f = fp64 ? reinterpret_cast<const void *>(&k_batch<1, double>) : reinterpret_cast<const void *>(&k_batch<1, float>);
+    switch (mode) {
+        case 0: f = fp64 ? reinterpret_cast<const void *>(&k_batch<0, double>) : reinterpret_cast<const void *>(&k_batch<0, float>); break;
+        case 1: f = fp64 ? reinterpret_cast<const void *>(&k_batch<1, double>) : reinterpret_cast<const void *>(&k_batch<1, float>); break;
+        case 2: f = fp64 ? reinterpret_cast<const void *>(&k_batch<2, double>) : reinterpret_cast<const void *>(&k_batch<2, float>); break;
+        default: f = fp64 ? reinterpret_cast<const void *>(&k_batch<3, double>) : reinterpret_cast<const void *>(&k_batch<3, float>); break;
+    }
     return hipFuncGetAttributes(attr, f);
 }
 
@@ -814,7 +1013,7 @@ hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st) {
         hipError_t e = set_feature_kernel_attrs();
         if (e != hipSuccess) return e;
     }
-    uint32_t lds = 16u * a.ng + 16 * 8 + kNumFeat * 8;
+    uint32_t lds = 16u * a.ng + 16 * 8 + kNumFeat * 8 + (uint32_t)sizeof(DirSums);
     uint32_t grid = a.g_cap * a.K;
     if (a.fp64) hipLaunchKernelGGL(k_split_features<double>, dim3(grid), dim3(512), lds, st, a);
     else hipLaunchKernelGGL(k_split_features<float>, dim3(grid), dim3(512), lds, st, a);
@@ -856,7 +1055,7 @@ hipError_t launch_coo_features(const StepArgs &a, const uint64_t *keys, const ui
         hipError_t e = set_feature_kernel_attrs();
         if (e != hipSuccess) return e;
     }
-    uint32_t lds = 16u * a.ng + 16 * 8 + kNumFeat * 8;
+    uint32_t lds = 16u * a.ng + 16 * 8 + kNumFeat * 8 + (uint32_t)sizeof(DirSums);
     if (a.fp64)
         hipLaunchKernelGGL(k_coo_features<double>, dim3(n_seg), dim3(512), lds, st, a, keys, vals, seg, n_rois, scratch);
     else

@@ -16,6 +16,7 @@ hipError_t launch_bin_image(const StepArgs &a, uint16_t *bins, uint64_t total_vo
                             hipStream_t st);
 hipError_t launch_batch(const StepArgs &a, uint32_t grid, uint32_t block, uint32_t direct_roi, hipStream_t st);
 hipError_t get_batch_attributes(int mode, int fp64, hipFuncAttributes *attr);
+hipError_t batch_occupancy(int mode, int fp64, uint32_t block, uint32_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st);
 hipError_t launch_coo_count(const StepArgs &a, uint32_t n_slots, uint64_t *counts, hipStream_t st);
 hipError_t launch_coo_emit(const StepArgs &a, uint32_t n_slots, const uint64_t *offsets, uint64_t *keys,

@@ -68,6 +68,9 @@ struct DevBuf {
     template <class T> T *as() const { return reinterpret_cast<T *>(p); }
 };
 
+// Size of the device DirSums record (8 u64 + 12 double).
+struct DirSumsHost { uint64_t u[8]; double d[12]; };
+
 uint32_t next_pow2(uint32_t v) {
     uint32_t p = 1;
     while (p < v) p <<= 1;
@@ -108,6 +111,9 @@ struct nyx_plan {
     nyx_roi_table graph_rois{};
     std::string desc;
     int64_t workspace_bytes = 0;
+    float tuned_ms = 0.f;
+    struct Cfg { int mode; uint32_t kp, block, split_vox, tile_vox, list_cap, hash_cap; int force_split; };
+    Cfg cfg{};
 };
 
 namespace {
@@ -184,8 +190,12 @@ nyx_status discover(nyx_ctx *ctx, const nyx_image *imgs, int32_t n, Work &w, hip
         d.nx = (int32_t)imgs[i].nx;
         d.nvox = (uint32_t)(imgs[i].nz * imgs[i].ny * imgs[i].nx);
         d.chunk_base = chunk;
-        chunk += (d.nvox + 7u) / 8u;
-        d.vec_ok = ((uintptr_t)d.I % 16 == 0) && ((uintptr_t)d.L % 16 == 0) && (d.nvox % 8 == 0);
+        {
+            // scan tiles: 256 rows (all planes flattened) by 32 columns
+            uint64_t rows = (uint64_t)d.nz * (uint64_t)d.ny;
+            chunk += (uint32_t)(((rows + 255u) / 256u) * (((uint64_t)d.nx + 31u) / 32u));
+        }
+        d.vec_ok = ((uintptr_t)d.I % 16 == 0) && ((uintptr_t)d.L % 16 == 0) && (d.nx % 8 == 0);
         vbase[i] = tv;
         tv += d.nvox;
     }
@@ -272,7 +282,7 @@ nyx_status fetch_rois(nyx_ctx *ctx, Work &w, hipStream_t st) {
 }
 
 struct Config {
-    int mode = 0;            // 0 dense, 1 hash
+    int mode = 0;            // 0 dense + list, 1 hash, 2 dense + scan, 3 packed dense + scan
     uint32_t kp = 1;
     uint32_t block = 256;
     uint32_t split_vox = 0, tile_vox = 0;
@@ -280,14 +290,28 @@ struct Config {
     int force_split = 0;
 };
 
+const char *mode_name(int m) {
+    switch (m) {
+        case 0: return "dense-list";
+        case 1: return "hash";
+        case 2: return "dense-scan";
+        default: return "dense16-scan";
+    }
+}
+
+uint32_t u_words(int mode, uint32_t ng) {
+    uint32_t tri = ng * (ng + 1u) / 2u;
+    uint32_t w = mode == 3 ? (tri + 1u) / 2u : tri;
+    return (w + 3u) & ~3u;
+}
+
 LdsLayout make_layout(const Config &c, uint32_t ng, int K) {
     LdsLayout L;
     memset(&L, 0, sizeof L);
     L.mode = (uint32_t)c.mode;
     L.kp = c.kp;
     L.nwaves = c.block / kWave;
-    uint32_t tri = ng * (ng + 1u) / 2u;
-    L.tri_pad = (tri + 3u) & ~3u;
+    L.tri_pad = u_words(c.mode, ng);
     L.list_cap = c.list_cap;
     L.hash_cap = c.hash_cap;
     uint32_t off = 0;
@@ -296,7 +320,7 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K) {
         off += (bytes + 15u) & ~15u;
         return o;
     };
-    if (c.mode == 0) {
+    if (c.mode != 1) {
         L.u_off = take(c.kp * L.tri_pad * 4u);
     } else {
         L.hkey_off = take(c.hash_cap * 4u);
@@ -306,6 +330,7 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K) {
     L.lcnt_off = take(c.kp * 4u);
     L.marg_off = take(L.nwaves * 4u * ng * 4u);
     L.feat_off = take((uint32_t)K * kNumFeat * 8u);
+    L.sums_off = take((uint32_t)K * (uint32_t)sizeof(DirSumsHost));
     L.misc_off = take(128u * 4u);
     L.bytes = off;
     return L;
@@ -325,49 +350,51 @@ uint64_t max_item_vox(const std::vector<RoiDesc> &rois, uint32_t split_vox, uint
     return m;
 }
 
-// Chooses the accumulation mode and the split of large ROIs.
-nyx_status choose_config(nyx_ctx *ctx, const Work &w, uint32_t ng, int K, int force_split, uint32_t block,
-                         Config &cfg) {
-    cfg = Config();
-    cfg.block = block;
-    cfg.force_split = force_split;
+// Feasible LDS configurations for this workload, one per accumulation mode,
+// each with as many directions per pass as fit.  Dense triangles first; the
+// hash table only when no dense triangle fits.
+std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_t ng, int K, int force_split,
+                                      uint32_t block) {
+    std::vector<Config> out;
     const uint32_t nw = block / kWave;
     const uint32_t tri = ng * (ng + 1u) / 2u;
-    const uint32_t tri_pad = (tri + 3u) & ~3u;
-    const uint32_t fixed = (nw * 4u * ng * 4u + 15u) / 16u * 16u + (uint32_t)K * kNumFeat * 8u + 128u * 4u + 64u * 4u + 64;
+    const uint32_t fixed = (nw * 4u * ng * 4u + 15u) / 16u * 16u + (uint32_t)K * kNumFeat * 8u +
+                           (uint32_t)K * (uint32_t)sizeof(DirSumsHost) + 128u * 4u + 64u * 4u + 64;
     uint64_t total_vox = 0;
     for (const RoiDesc &r : w.h_rois) total_vox += r.n;
     // load balance: split ROIs that would take more than ~1/4 of one
     // work-group's share of the voxels
     uint64_t share = total_vox / ((uint64_t)std::max(ctx->n_cu, 1) * 4u) + 1u;
-    uint32_t lb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(share, 4096u), 1u << 20);
-    // dense mode: as many direction triangles as fit
-    for (uint32_t kp = (uint32_t)K; kp >= 1u; --kp) {
-        uint32_t split = force_split ? lb : lb;
+    const uint32_t lb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(share, 4096u), 1u << 20);
+    for (int mode : {3, 2, 0}) {
+        uint32_t split = mode == 3 ? std::min<uint32_t>(lb, 65535u) : lb;
         uint64_t mi = max_item_vox(w.h_rois, split, split);
-        uint32_t list_cap = (uint32_t)std::min<uint64_t>(tri, std::max<uint64_t>(mi, 1u));
-        uint64_t bytes = (uint64_t)kp * tri_pad * 4u + (uint64_t)kp * list_cap * 4u + kp * 4u + fixed;
-        if (bytes <= kLdsBudget) {
-            cfg.mode = 0;
-            cfg.kp = kp;
-            cfg.split_vox = split;
-            cfg.tile_vox = split;
-            cfg.list_cap = list_cap;
-            return NYX_OK;
+        while (mode == 3 && mi > 65535u && split > 64u) {
+            split /= 2u;
+            mi = max_item_vox(w.h_rois, split, split);
         }
-        if (kp == 1u) break;
+        if (mode == 3 && mi > 65535u) continue;
+        const uint32_t list_cap = (uint32_t)std::min<uint64_t>(tri, std::max<uint64_t>(mi, 1u));
+        for (uint32_t kp = (uint32_t)K; kp >= 1u; --kp) {
+            uint64_t bytes = (uint64_t)kp * u_words(mode, ng) * 4u + (uint64_t)kp * list_cap * 4u + kp * 4u + fixed;
+            if (bytes <= kLdsBudget) {
+                Config c;
+                c.mode = mode; c.kp = kp; c.block = block; c.split_vox = split; c.tile_vox = split;
+                c.list_cap = list_cap; c.force_split = force_split;
+                out.push_back(c);
+                break;
+            }
+        }
     }
+    if (!out.empty() || fixed >= kLdsBudget) return out;
     // hash mode: items small enough that kp directions of pairs fill at most
     // half the table
-    if (ng > kMaxNgFused) return fail(ctx, NYX_ERR_UNSUPPORTED, "n_bins too large");
-    if (fixed >= kLdsBudget) return fail(ctx, NYX_ERR_UNSUPPORTED, "n_bins too large for the LDS marginals");
     for (uint32_t kp = (uint32_t)K; kp >= 1u; --kp) {
         for (uint32_t hc = 1u << 14; hc >= 512u; hc >>= 1) {
             uint32_t per_dir = hc / (2u * kp);
             if (per_dir < 64u) continue;
             uint32_t split = std::min<uint32_t>(per_dir, lb);
             uint64_t mi = max_item_vox(w.h_rois, split, split);
-            // shrink tiles until the area bound fits
             while (mi > per_dir && split > 16u) {
                 split /= 2u;
                 mi = max_item_vox(w.h_rois, split, split);
@@ -376,17 +403,40 @@ nyx_status choose_config(nyx_ctx *ctx, const Work &w, uint32_t ng, int K, int fo
             uint32_t list_cap = (uint32_t)std::max<uint64_t>(mi, 1u);
             uint64_t bytes = (uint64_t)hc * 8u + (uint64_t)kp * list_cap * 4u + kp * 4u + fixed;
             if (bytes <= kLdsBudget) {
-                cfg.mode = 1;
-                cfg.kp = kp;
-                cfg.hash_cap = hc;
-                cfg.split_vox = split;
-                cfg.tile_vox = split;
-                cfg.list_cap = list_cap;
-                return NYX_OK;
+                Config c;
+                c.mode = 1; c.kp = kp; c.block = block; c.hash_cap = hc; c.split_vox = split; c.tile_vox = split;
+                c.list_cap = list_cap; c.force_split = force_split;
+                out.push_back(c);
+                return out;
             }
         }
     }
-    return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%u with %d offsets", ng, K);
+    return out;
+}
+
+// Default choice without timing: an ordered scan of the triangle costs
+// O(Ng^2) per direction and item, a returning-atomic list costs O(pairs);
+// scan while the triangle is small next to the average item.
+Config default_config(const std::vector<Config> &cands, const Work &w, uint32_t ng) {
+    uint64_t total_vox = 0;
+    for (const RoiDesc &r : w.h_rois) total_vox += r.n;
+    const uint64_t avg = w.h_rois.empty() ? 1u : std::max<uint64_t>(1u, total_vox / w.h_rois.size());
+    const uint64_t tri = (uint64_t)ng * (ng + 1u) / 2u;
+    const bool prefer_scan = tri <= 8u * avg;
+    const Config *best = nullptr;
+    for (const Config &c : cands) {
+        bool scan = c.mode == 2 || c.mode == 3;
+        if (prefer_scan == scan || c.mode == 1) { best = &c; break; }
+    }
+    return best ? *best : cands.front();
+}
+
+nyx_status choose_config(nyx_ctx *ctx, const Work &w, uint32_t ng, int K, int force_split, uint32_t block,
+                         Config &cfg) {
+    std::vector<Config> c = candidate_configs(ctx, w, ng, K, force_split, block);
+    if (c.empty()) return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%u with %d offsets", ng, K);
+    cfg = default_config(c, w, ng);
+    return NYX_OK;
 }
 
 // Item and split-slot counts implied by a configuration.
@@ -405,6 +455,31 @@ void count_items(const std::vector<RoiDesc> &rois, const Config &c, uint64_t *it
     }
     *items = it;
     *n_split = ns;
+}
+
+// Row-sweep eligibility: all images 2D and every offset of each pass one of
+// the four distance-1 in-plane classes, each class at most once per pass.
+void set_sweep(StepArgs &a, const std::vector<ImgDesc> &imgs, const nyx_offset *off, int K, uint32_t kp) {
+    a.sweep_ok = 0;
+    memset(a.sweep, -1, sizeof a.sweep);
+    for (const ImgDesc &d : imgs)
+        if (d.nz != 1) return;
+    int pass = 0;
+    for (int d0 = 0; d0 < K; d0 += (int)kp, ++pass) {
+        if (pass >= kMaxSweepPasses) return;
+        for (int d = d0; d < std::min(K, d0 + (int)kp); ++d) {
+            const nyx_offset &o = off[d];
+            if (o.dz != 0 || abs(o.dy) > 1 || abs(o.dx) > 1) return;
+            int cls;
+            if (o.dy == 0) cls = 0;
+            else if (o.dx == 0) cls = 1;
+            else if (o.dy * o.dx < 0) cls = 2;   // (-1, +1) or (+1, -1)
+            else cls = 3;                        // (-1, -1) or (+1, +1)
+            if (a.sweep[pass][cls] >= 0) return; // the same class twice in a pass
+            a.sweep[pass][cls] = (int8_t)(d - d0);
+        }
+    }
+    a.sweep_ok = 1;
 }
 
 // Allocates queue, split matrices and fills the step arguments.
@@ -449,6 +524,7 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     a.enqueue = 1;
     a.fp64 = fp64;
     a.lds = make_layout(cfg, ng, K);
+    set_sweep(a, w.h_imgs, off, K, cfg.kp);
     return NYX_OK;
 }
 
@@ -504,9 +580,28 @@ std::string describe(const Config &c, const nyx_plan *p, uint64_t items, uint32_
     snprintf(buf, sizeof buf,
              "mode=%s kp=%u block=%u grid=%u lds=%uB split_vox=%u tile_vox=%u list_cap=%u hash_cap=%u "
              "rois=%u items=%llu split_rois=%u ng=%d K=%d",
-             c.mode == 0 ? "dense" : "hash", c.kp, c.block, p->grid, p->w.args.lds.bytes, c.split_vox, c.tile_vox,
+             mode_name(c.mode), c.kp, c.block, p->grid, p->w.args.lds.bytes, c.split_vox, c.tile_vox,
              c.list_cap, c.hash_cap, p->w.n_rois, (unsigned long long)items, n_split, p->ng, p->K);
     return buf;
+}
+
+// Applies a configuration to a plan: scratch, step arguments, grid.
+nyx_status configure(nyx_plan *p, const Config &cfg, const nyx_extract_opts *opts) {
+    nyx_ctx *ctx = p->ctx;
+    nyx_status s = setup_step(ctx, p->w, cfg, opts->offsets_host, p->K, (uint32_t)p->ng, p->prec == NYX_FP64, 0,
+                              opts->workspace_cap_bytes, &p->workspace_bytes);
+    if (s != NYX_OK) return s;
+    p->block = cfg.block;
+    int occ = 0;
+    HIPC(ctx, batch_occupancy(cfg.mode, p->prec == NYX_FP64, cfg.block, p->w.args.lds.bytes, &occ));
+    p->grid = (uint32_t)ctx->n_cu * (uint32_t)std::max(occ, 1);
+    uint64_t items;
+    uint32_t n_split;
+    count_items(p->w.h_rois, cfg, &items, &n_split, &p->roi_tiles);
+    p->cfg = nyx_plan::Cfg{cfg.mode, cfg.kp, cfg.block, cfg.split_vox, cfg.tile_vox, cfg.list_cap, cfg.hash_cap,
+                           cfg.force_split};
+    p->desc = describe(cfg, p, items, n_split);
+    return NYX_OK;
 }
 
 }  // namespace
@@ -751,27 +846,43 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
     p->prec = opts->precision;
     if ((s = discover(ctx, imgs, n_images, p->w, st)) != NYX_OK) return s;
     if ((s = fetch_rois(ctx, p->w, st)) != NYX_OK) return s;
-    Config cfg;
-    if ((s = choose_config(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256, cfg)) != NYX_OK) return s;
-    if ((s = setup_step(ctx, p->w, cfg, opts->offsets_host, p->K, (uint32_t)p->ng, p->prec == NYX_FP64, 0,
-                        opts->workspace_cap_bytes, &p->workspace_bytes)) != NYX_OK)
-        return s;
-    p->block = cfg.block;
-    int occ = 0;
-    {
-        const void *f = nullptr;
-        (void)f;
-        hipFuncAttributes fa;
-        HIPC(ctx, get_batch_attributes(p->w.args.lds.mode, p->prec == NYX_FP64, &fa));
-        uint32_t by_lds = kLdsBudget / std::max<uint32_t>(p->w.args.lds.bytes, 1u);
-        uint32_t by_waves = 32u / (cfg.block / kWave);
-        occ = (int)std::max<uint32_t>(1u, std::min(by_lds, by_waves));
+    std::vector<Config> cands = candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256);
+    if (cands.empty())
+        return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%d with %d offsets", p->ng, p->K);
+    Config cfg = default_config(cands, p->w, (uint32_t)p->ng);
+    if (opts->accum_mode >= 0) {
+        bool found = false;
+        for (const Config &c : cands)
+            if (c.mode == opts->accum_mode) { cfg = c; found = true; break; }
+        if (!found) return fail(ctx, NYX_ERR_UNSUPPORTED, "accumulation mode %d does not fit this workload", opts->accum_mode);
+    } else if (opts->autotune && cands.size() > 1) {
+        // time one step of every candidate and keep the fastest
+        DevBuf tmp;
+        size_t row_bytes = (size_t)(p->K + 1) * kNumFeat * (p->prec == NYX_FP64 ? 8u : 4u);
+        HIPC(ctx, tmp.alloc(std::max<size_t>(p->w.n_rois, 1u) * row_bytes));
+        hipEvent_t e0, e1;
+        HIPC(ctx, hipEventCreate(&e0));
+        HIPC(ctx, hipEventCreate(&e1));
+        float best = 1e30f;
+        for (const Config &c : cands) {
+            if ((s = configure(p.get(), c, opts)) != NYX_OK) continue;
+            set_outputs(ctx, p->w.args, nullptr, tmp.p, p->w.n_rois);
+            if ((s = enqueue_step(p.get(), st, false)) != NYX_OK) break;
+            HIPC(ctx, hipEventRecord(e0, st));
+            if ((s = enqueue_step(p.get(), st, false)) != NYX_OK) break;
+            HIPC(ctx, hipEventRecord(e1, st));
+            HIPC(ctx, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPC(ctx, hipEventElapsedTime(&ms, e0, e1));
+            if (log_level() > 0) fprintf(stderr, "[nyx] autotune %s kp=%u: %.3f ms\n", mode_name(c.mode), c.kp, ms);
+            if (ms < best) { best = ms; cfg = c; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (s != NYX_OK) return s;
+        p->tuned_ms = best;
     }
-    p->grid = (uint32_t)ctx->n_cu * (uint32_t)occ;
-    uint64_t items;
-    uint32_t n_split;
-    count_items(p->w.h_rois, cfg, &items, &n_split, &p->roi_tiles);
-    p->desc = describe(cfg, p.get(), items, n_split);
+    if ((s = configure(p.get(), cfg, opts)) != NYX_OK) return s;
     if (log_level() > 0) fprintf(stderr, "[nyx] plan: %s\n", p->desc.c_str());
     if (n_rois_host) *n_rois_host = p->w.n_rois;
     *out = p.release();

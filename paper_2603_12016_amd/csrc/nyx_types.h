@@ -12,6 +12,8 @@ constexpr int kNumFeat = 30;
 constexpr int kMaxOffsets = 64;
 constexpr int kClasses = 32;           // work-item size classes (log2 of voxels)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kTicketChunk = 8;        // queue entries taken per work ticket
+constexpr int kMaxSweepPasses = 16;    // passes with a precomputed 2D sweep map
 
 // Counter slots (u32) in the device counter block.
 enum Counter : int {
@@ -44,8 +46,8 @@ struct ImgDesc {
     uint32_t nvox;
     uint32_t tab_base;     // label-table index of label 0 of this image
     uint32_t max_label;    // label-table capacity of this image (labels 0..max_label)
-    uint32_t chunk_base;   // first scan chunk of this image
-    uint32_t vec_ok;       // 1: 16-byte aligned base pointers and nvox % 8 == 0
+    uint32_t chunk_base;   // first scan tile of this image
+    uint32_t vec_ok;       // 1: 16-byte aligned base pointers and nx % 8 == 0
 };
 
 // Per-label statistics, one entry per (image, label), struct of arrays.
@@ -71,7 +73,7 @@ struct LdsLayout {
     uint32_t tri_pad;     // u32 words per dense triangle (dense mode)
     uint32_t list_cap;    // entries per direction list
     uint32_t hash_cap;    // slots (power of two, hash mode)
-    uint32_t u_off, list_off, lcnt_off, marg_off, feat_off, misc_off, hkey_off, hcnt_off;
+    uint32_t u_off, list_off, lcnt_off, marg_off, feat_off, sums_off, misc_off, hkey_off, hcnt_off;
     uint32_t bytes;       // total dynamic LDS
     uint32_t nwaves;      // waves per work-group
 };
@@ -79,7 +81,7 @@ struct LdsLayout {
 struct StepArgs {
     const ImgDesc *imgs;
     int32_t n_images;
-    uint32_t total_chunks;      // scan chunks of 8 voxels over all images
+    uint32_t total_chunks;      // scan tiles over all images
     LabelTab tab;
     RoiDesc *rois;
     uint32_t roi_cap;
@@ -106,6 +108,10 @@ struct StepArgs {
     uint16_t *o_min, *o_max;
     int32_t *o_bbox;
     LdsLayout lds;
+    // 2D distance-1 row-sweep accumulation: per pass, the local direction slot
+    // of the H, V, D45, D135 neighbour classes (-1 = absent)
+    int32_t sweep_ok;
+    int8_t sweep[kMaxSweepPasses][4];
 };
 
 // Deterministic split rule shared by host planning and device enqueueing:

@@ -50,7 +50,7 @@ class nyx_glcm(ctypes.Structure):
 
 class nyx_extract_opts(ctypes.Structure):
     _fields_ = [("n_bins", c_int32), ("offsets_host", POINTER(nyx_offset)), ("n_offsets", c_int32),
-                ("symmetric", c_int32), ("precision", c_int), ("autotune", c_int32),
+                ("symmetric", c_int32), ("precision", c_int), ("autotune", c_int32), ("accum_mode", c_int32),
                 ("workspace_cap_bytes", c_int64)]
 
 
@@ -155,10 +155,13 @@ def _offsets(offsets):
     return arr, len(offs)
 
 
-def _opts(n_bins, offsets, precision, autotune=0, workspace_cap=0):
+MODES = {"auto": -1, "dense-list": 0, "hash": 1, "dense-scan": 2, "dense16-scan": 3}
+
+
+def _opts(n_bins, offsets, precision, autotune=0, workspace_cap=0, mode="auto"):
     arr, K = _offsets(offsets)
     o = nyx_extract_opts(int(n_bins), ctypes.cast(arr, POINTER(nyx_offset)), K, 1, int(precision),
-                         int(autotune), int(workspace_cap))
+                         int(autotune), int(MODES[mode] if isinstance(mode, str) else mode), int(workspace_cap))
     return o, arr
 
 
@@ -325,9 +328,9 @@ def nyx_extract_batch(ctx: Ctx, images, n_bins: int, offsets, precision: int = N
 
 
 def nyx_plan_create(ctx: Ctx, images, n_bins: int, offsets, precision: int = NYX_FP32, autotune: bool = False,
-                    workspace_cap: int = 0) -> Plan:
+                    workspace_cap: int = 0, mode="auto") -> Plan:
     imgs = _images(images)
-    opts, keep = _opts(n_bins, offsets, precision, int(autotune), workspace_cap)
+    opts, keep = _opts(n_bins, offsets, precision, int(autotune), workspace_cap, mode)
     h = c_void_p()
     n = c_int64(0)
     _check(lib().nyx_plan_create(ctx.handle, imgs, len(images), byref(opts), byref(h), byref(n)), ctx)

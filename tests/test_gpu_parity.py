@@ -217,15 +217,22 @@ def test_features_from_oracle_coo(env, workloads, oracle_mod, name, prec):
 
 
 # ------------------------------------------------------------------ batched path
-@pytest.mark.parametrize("name", SMALL)
-def test_plan_batched_and_per_roi(env, workloads, oracle_mod, name):
+MODE_CASES = [(n, m) for n in SMALL for m in ("auto", "dense-list", "dense-scan", "dense16-scan")
+              if not (n == "c5_small" and m != "auto")] + [("c3_small", "autotune")]
+
+
+@pytest.mark.parametrize("name,mode", MODE_CASES)
+def test_plan_batched_and_per_roi(env, workloads, oracle_mod, name, mode):
     import torch
     nyx, ctx, dev = env
     w = workloads(name)
-    say(f"case {name} plan_execute + per_roi")
+    say(f"case {name} plan_execute + per_roi, mode {mode}")
     imgs = device_images(w, dev)
     offs = _offsets(nyx, w)
-    plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32)
+    if mode == "autotune":
+        plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32, autotune=True)
+    else:
+        plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32, mode=mode)
     say("  plan:", nyx.nyx_plan_describe(plan))
     t1 = nyx.new_table(plan, len(offs))
     t2 = nyx.new_table(plan, len(offs))
@@ -242,6 +249,10 @@ def test_plan_batched_and_per_roi(env, workloads, oracle_mod, name):
     _check_features(got, want, Ps, TOL_FP32, f"{name} batched")
     _check_features(t2.cpu().numpy()[:plan.n_rois], want, Ps, TOL_FP32, f"{name} per-roi")
     assert np.allclose(first.cpu().numpy(), got, rtol=1e-6, atol=1e-6, equal_nan=True)
+    if "scan" in nyx.nyx_plan_describe(plan):
+        # ordered nonzero lists: replays and the per-ROI path agree bit for bit
+        assert np.array_equal(first.cpu().numpy(), got, equal_nan=True)
+        assert np.array_equal(t2.cpu().numpy()[:plan.n_rois], got, equal_nan=True)
 
 
 # ------------------------------------------------------------------ edge cases
