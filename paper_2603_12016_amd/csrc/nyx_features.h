@@ -1,23 +1,28 @@
 // nyx_features.h -- GLCM normalisation, marginals and the 30 features of one
-// direction, computed by a cooperating group of lanes (one wavefront, or a
-// whole work-group) from the nonzero cells of the upper triangle.
+// direction, computed by a cooperating group of lanes (a 16-lane DPP row, one
+// wavefront, or a whole work-group) from the nonzero cells of the upper
+// triangle of the symmetric co-occurrence matrix.
 //
 // Definitions: the GLCM rows of the paper's Supplementary Table S3 (NY column)
 // with the standard IBSI formulas the paper defers to.  The arithmetic is
 // arranged for exactness on integers where that is cheap:
-//   T      = sum P                         (exact, 64-bit)
+//   T      = sum P                         (exact)
 //   S1     = sum_i i R(i), S2 = sum_i i^2 R(i), S11 = sum i j P(i, j)
 //   Nvar   = T S2 - S1^2,  Ncov = T S11 - S1^2   (exact, 128-bit)
 //   mean = S1 / T, variance = Nvar / T^2, correlation = Ncov / Nvar,
 //   sum-average = 2 S1 / T, sum-variance = cluster tendency = 2(Nvar+Ncov)/T^2,
 //   contrast = (2 S2 - 2 S11) / T, difference variance from exact moments,
 //   ASM = sum P^2 / T^2, maximum probability = max P / T.
-// Entropies, homogeneities and inverse variance are compensated sums of
-// positive terms in the accumulation precision Acc (float or double); the
-// cluster shade / prominence moments are centred double sums.  The mutual
-// information (HX + HY - HXY) is taken as 2 HX - JE, and re-summed cell by
-// cell as sum p log(p / (px py)) when small, where the subtraction would
-// lose the digits the information measure of correlation needs.
+// Entropies use H = log2 T - (sum n log2 n) / T over the integer counts n of
+// the matrix or marginal, so every cell is visited once before T is known;
+// homogeneities and inverse variance are weighted sums of the difference
+// marginal divided by T.  Per-lane partial sums of floating terms are
+// compensated in the accumulation precision Acc (float or double) and
+// combined across lanes in double.  Cluster shade / prominence are centred
+// double sums over the sum marginal.  The mutual information HX + HY - HXY is
+// taken as 2 HX - JE and, when it is small (where the subtraction would lose
+// the digits the information measure of correlation needs), re-summed cell
+// by cell as sum p log(p / (px py)) with an exactly formed ratio.
 #pragma once
 #include "nyx_device.h"
 
@@ -32,6 +37,10 @@ enum Feat : int {
 };
 
 // ------------------------------------------------------------- groups
+// Interface: rank()/size(), sync() (LDS visibility inside the group), sum/max
+// (result in every lane of the group), ballot(pred) (group-local bit mask,
+// bit r = rank r) and below() (mask of ranks lower than the caller's).
+
 // One wavefront.
 struct WaveGrp {
     __device__ __forceinline__ int rank() const { return lane(); }
@@ -42,7 +51,24 @@ struct WaveGrp {
     }
     template <class T> __device__ __forceinline__ T sum(T v) const { return wave_sum(v); }
     template <class T> __device__ __forceinline__ T max(T v) const { return wave_max(v); }
-    template <class F> __device__ __forceinline__ F csum(const Comp<F> &c) const { return wave_sum_comp(c); }
+    __device__ __forceinline__ uint64_t ballot(bool p) const { return __ballot(p); }
+    __device__ __forceinline__ uint64_t below() const { return __lanemask_lt(); }
+};
+
+// One 16-lane DPP row of a wavefront: four independent groups per wavefront,
+// reduced together by the same DPP instructions.
+struct RowGrp {
+    __device__ __forceinline__ int rank() const { return lane() & 15; }
+    __device__ __forceinline__ int size() const { return 16; }
+    __device__ __forceinline__ int row() const { return lane() >> 4; }
+    __device__ __forceinline__ void sync() const {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    template <class T> __device__ __forceinline__ T sum(T v) const { return row_reduce(v, OpAdd()); }
+    template <class T> __device__ __forceinline__ T max(T v) const { return row_reduce(v, OpMax()); }
+    __device__ __forceinline__ uint64_t ballot(bool p) const { return (__ballot(p) >> (16 * row())) & 0xFFFFull; }
+    __device__ __forceinline__ uint64_t below() const { return (__lanemask_lt() >> (16 * row())) & 0xFFFFull; }
 };
 
 // The whole work-group; `scratch` is LDS room for one 8-byte value per wave.
@@ -71,93 +97,159 @@ struct BlockGrp {
         for (int w = 1; w < nw(); ++w) { T u = reinterpret_cast<T *>(scratch)[w]; r = u > r ? u : r; }
         return r;
     }
-    template <class F> __device__ __forceinline__ F csum(const Comp<F> &c) const {
-        return sum_of_waves<F>(wave_sum_comp(c));
-    }
 };
 
 // ------------------------------------------------------------- sources
-// A source enumerates candidate cells e in [0, size()); get() returns the
-// 0-based levels lo <= hi and the triangle count (0 = skip the cell).
+// A source hands every nonzero cell of one direction's upper triangle to
+// fn(lo, hi, c) (0-based levels lo <= hi, triangle count c), spread over the
+// lanes of a group, and can leave its storage zeroed for the next item.
 
 template <bool PACKED>
-struct SrcDenseList {     // fused dense mode: LDS triangle + list of touched cells
-    const uint32_t *list;
-    uint32_t n;
-    uint32_t *U;             // u32 counts, or u16 counts packed two per word
-    __device__ __forceinline__ uint32_t size() const { return n; }
-    __device__ __forceinline__ uint64_t get(uint32_t e, uint32_t &lo, uint32_t &hi) const {
-        uint32_t p = list[e];
-        lo = p & 0xFFFFu;
-        hi = p >> 16;
-        const uint32_t i = tri_idx(lo, hi);
-        return PACKED ? (uint64_t)reinterpret_cast<const uint16_t *>(U)[i] : (uint64_t)U[i];
+__device__ __forceinline__ uint32_t tri_count(const uint32_t *U, uint32_t i) {
+    return PACKED ? (uint32_t)reinterpret_cast<const uint16_t *>(U)[i] : U[i];
+}
+
+// Inverse of tri_idx: the pair (lo, hi) of triangle index i.
+__device__ __forceinline__ void tri_decode(uint32_t i, uint32_t &lo, uint32_t &hi) {
+    uint32_t h = (uint32_t)((sqrtf(8.0f * (float)i + 1.0f) - 1.0f) * 0.5f);
+    if (((h * (h + 1u)) >> 1) > i) --h;
+    else if ((((h + 1u) * (h + 2u)) >> 1) <= i) ++h;
+    hi = h;
+    lo = i - ((h * (h + 1u)) >> 1);
+}
+
+// LDS triangle of one direction, scanned in index order; the nonzero cells of
+// each chunk are compacted into `buf` (room for size() * kScanPerLane
+// entries) before fn runs, so lanes stay busy on sparse triangles and the
+// order of every floating sum is fixed.
+constexpr int kScanPerLane = 4;
+
+template <bool PACKED>
+struct SrcTriScan {
+    uint32_t *U;
+    uint32_t tri;
+    uint2 *buf;
+    template <class Grp, class Fn>
+    __device__ __forceinline__ void for_each(const Grp &g, Fn &&fn) const {
+        const uint32_t gs = (uint32_t)g.size(), r = (uint32_t)g.rank();
+        for (uint32_t base = 0; base < tri; base += gs * kScanPerLane) {
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int v = 0; v < kScanPerLane; ++v) {
+                const uint32_t i = base + (uint32_t)v * gs + r;
+                const uint32_t c = i < tri ? tri_count<PACKED>(U, i) : 0u;
+                const uint64_t m = g.ballot(c != 0u);
+                if (c) buf[cnt + (uint32_t)__popcll(m & g.below())] = make_uint2(i, c);
+                cnt += (uint32_t)__popcll(m);
+            }
+            g.sync();
+            for (uint32_t e = r; e < cnt; e += gs) {
+                const uint2 q = buf[e];
+                uint32_t lo, hi;
+                tri_decode(q.x, lo, hi);
+                fn(lo, hi, q.y);
+            }
+            g.sync();
+        }
     }
-    __device__ __forceinline__ void clear(uint32_t e) const {
-        uint32_t p = list[e];
-        const uint32_t i = tri_idx(p & 0xFFFFu, p >> 16);
-        if (PACKED) reinterpret_cast<uint16_t *>(U)[i] = 0u;
-        else U[i] = 0u;
+    template <class Grp>
+    __device__ __forceinline__ void clear(const Grp &g) const {
+        const uint32_t words = PACKED ? (tri + 1u) >> 1 : tri;
+        for (uint32_t i = (uint32_t)g.rank(); i < words; i += (uint32_t)g.size()) U[i] = 0u;
     }
 };
 
-struct SrcHashList {      // hash mode: LDS hash slots listed per direction
+// LDS triangle plus a list of its touched cells (returning-atomic mode).
+struct SrcDenseList {
+    const uint32_t *list;
+    uint32_t n;
+    uint32_t *U;
+    template <class Grp, class Fn>
+    __device__ __forceinline__ void for_each(const Grp &g, Fn &&fn) const {
+        for (uint32_t e = g.rank(); e < n; e += g.size()) {
+            const uint32_t p = list[e];
+            const uint32_t lo = p & 0xFFFFu, hi = p >> 16;
+            const uint32_t c = U[tri_idx(lo, hi)];
+            if (c) fn(lo, hi, c);
+        }
+    }
+    template <class Grp>
+    __device__ __forceinline__ void clear(const Grp &g) const {
+        for (uint32_t e = g.rank(); e < n; e += g.size()) {
+            const uint32_t p = list[e];
+            U[tri_idx(p & 0xFFFFu, p >> 16)] = 0u;
+        }
+    }
+};
+
+// LDS hash slots listed per direction.
+struct SrcHashList {
     const uint32_t *list;
     uint32_t n;
     uint32_t *keys;
     uint32_t *cnts;
-    __device__ __forceinline__ uint32_t size() const { return n; }
-    __device__ __forceinline__ uint64_t get(uint32_t e, uint32_t &lo, uint32_t &hi) const {
-        uint32_t s = list[e];
-        uint32_t k = keys[s];
-        lo = k & 0x1FFFu;
-        hi = (k >> 13) & 0x1FFFu;
-        return cnts[s];
+    template <class Grp, class Fn>
+    __device__ __forceinline__ void for_each(const Grp &g, Fn &&fn) const {
+        for (uint32_t e = g.rank(); e < n; e += g.size()) {
+            const uint32_t s = list[e];
+            const uint32_t k = keys[s];
+            const uint32_t c = cnts[s];
+            if (c) fn(k & 0x1FFFu, (k >> 13) & 0x1FFFu, c);
+        }
     }
-    __device__ __forceinline__ void clear(uint32_t e) const {
-        uint32_t s = list[e];
-        keys[s] = kNone;
-        cnts[s] = 0u;
+    template <class Grp>
+    __device__ __forceinline__ void clear(const Grp &g) const {
+        for (uint32_t e = g.rank(); e < n; e += g.size()) {
+            const uint32_t s = list[e];
+            keys[s] = kNone;
+            cnts[s] = 0u;
+        }
     }
 };
 
-struct SrcSquare {        // global dense square (upper triangle used)
+// Global dense square (upper triangle used) of a merged split ROI.
+struct SrcSquare {
     const uint64_t *G;
     uint32_t ng;
-    __device__ __forceinline__ uint32_t size() const { return ng * ng; }
-    __device__ __forceinline__ uint64_t get(uint32_t e, uint32_t &lo, uint32_t &hi) const {
-        lo = e / ng;
-        hi = e - lo * ng;
-        return lo <= hi ? G[e] : 0ull;
+    template <class Grp, class Fn>
+    __device__ __forceinline__ void for_each(const Grp &g, Fn &&fn) const {
+        for (uint32_t e = g.rank(); e < ng * ng; e += g.size()) {
+            const uint32_t lo = e / ng, hi = e - lo * ng;
+            if (lo > hi) continue;
+            const uint64_t c = G[e];
+            if (c) fn(lo, hi, (uint32_t)c);
+        }
     }
-    __device__ __forceinline__ void clear(uint32_t) const {}
+    template <class Grp> __device__ __forceinline__ void clear(const Grp &) const {}
 };
 
-struct SrcCoo {           // sorted COO segment of one ROI-direction
+// Sorted COO segment of one ROI-direction; entries outside the matrix or of
+// another (roi, dir) are skipped and flagged.
+struct SrcCoo {
     const uint64_t *key;
     const uint64_t *cnt;
     uint32_t n;
     uint64_t prefix;         // expected roi << 38 | dir << 32
     uint32_t ng;
     uint32_t *err;
-    __device__ __forceinline__ uint32_t size() const { return n; }
-    // Cells outside the matrix or of another (roi, dir) are skipped and flagged.
-    __device__ __forceinline__ uint64_t get(uint32_t e, uint32_t &lo, uint32_t &hi) const {
-        uint64_t k = key[e];
-        lo = (uint32_t)(k >> 16) & 0xFFFFu;
-        hi = (uint32_t)k & 0xFFFFu;
-        uint64_t c = cnt[e];
-        if ((k & ~0xFFFFFFFFull) != prefix || lo > hi || hi >= ng || c >= (1ull << 32)) {
-            if (c) atomicOr(err, (uint32_t)E_COO_RANGE);
-            lo = hi = 0;
-            return 0ull;
+    template <class Grp, class Fn>
+    __device__ __forceinline__ void for_each(const Grp &g, Fn &&fn) const {
+        for (uint32_t e = g.rank(); e < n; e += g.size()) {
+            const uint64_t k = key[e];
+            const uint32_t lo = (uint32_t)(k >> 16) & 0xFFFFu, hi = (uint32_t)k & 0xFFFFu;
+            const uint64_t c = cnt[e];
+            if ((k & ~0xFFFFFFFFull) != prefix || lo > hi || hi >= ng || c >= (1ull << 31)) {
+                if (c) atomicOr(err, (uint32_t)E_COO_RANGE);
+                continue;
+            }
+            if (c) fn(lo, hi, (uint32_t)c);
         }
-        return c;
     }
-    __device__ __forceinline__ void clear(uint32_t) const {}
+    template <class Grp> __device__ __forceinline__ void clear(const Grp &) const {}
 };
 
-// Reduced per-direction sums (wave-uniform), input of finalize_dir.
+// ------------------------------------------------------------- sums
+// Reduced per-direction sums (group-uniform), input of finalize_dir.
 struct DirSums {
     uint64_t T, S1, S2, Sm1, S11, sumP2, maxP, pad;
     double HX, DENT, HOM1, HOM2, IDMN, IDN, IV, SENT, JE, CSHADE, CPROM, MI;
@@ -213,138 +305,131 @@ template <class F> __device__ __forceinline__ F log1p_(F x);
 template <> __device__ __forceinline__ float log1p_<float>(float x) { return log1pf(x); }
 template <> __device__ __forceinline__ double log1p_<double>(double x) { return log1p(x); }
 
+template <class F>
+__device__ __forceinline__ double comp_value(const Comp<F> &c) { return (double)c.s + (double)c.c; }
+
+// Below this many bits of mutual information the difference 2 HX - JE is
+// re-summed cell by cell.
+template <class Acc> __device__ __forceinline__ double mi_resum_threshold();
+template <> __device__ __forceinline__ double mi_resum_threshold<float>() { return 0.25; }
+template <> __device__ __forceinline__ double mi_resum_threshold<double>() { return 1e-3; }
+
 // Reduced sums of one direction.  R, Sp, Sm are zeroed LDS arrays of ng,
 // 2 ng - 1 and ng u32 (row, sum and difference marginals of the symmetric
-// matrix); they are zeroed again on return, and the source cells are cleared.
-// *out (LDS) is written by rank 0.  Returns T (0: direction empty).
-template <class Acc, class Grp, class Src>
-__device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t *Sp,
-                             uint32_t *Sm, uint32_t ng, DirSums *out) {
-    const uint32_t n = src.size();
+// matrix); they are zeroed again on return, and the source is cleared.
+// *out (LDS) is written by rank 0.  ISum is the type of the per-lane integer
+// sums: double where every partial and total stays below 2^53 (small work
+// items), uint64_t otherwise.  Returns T (0: direction empty).
+template <class Acc, class ISum, class Grp, class Src>
+__device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t *Sp, uint32_t *Sm,
+                             uint32_t ng, DirSums *out) {
     const int r0 = g.rank(), gs = g.size();
-    // Sweep 1: marginals.  An off-diagonal triangle cell (lo < hi) with count
-    // c stands for P(lo, hi) = P(hi, lo) = c, a diagonal one for P = 2c.
-    uint64_t Tl = 0;
-    for (uint32_t e = r0; e < n; e += gs) {
-        uint32_t lo, hi;
-        uint64_t c = src.get(e, lo, hi);
-        if (c == 0) continue;
-        uint32_t c32 = (uint32_t)c;
-        atomicAdd(&R[lo], c32);
-        atomicAdd(&R[hi], c32);
-        atomicAdd(&Sp[lo + hi], 2u * c32);
-        atomicAdd(&Sm[hi - lo], 2u * c32);
-        Tl += 2ull * c;
-    }
-    const uint64_t T = g.sum(Tl);
+    // One sweep over the nonzero cells: marginals and cell terms.  A cell
+    // (lo < hi) with count c stands for P(lo, hi) = P(hi, lo) = c, a diagonal
+    // one for P = 2c.
+    ISum Tl = 0, sumP2 = 0, S11 = 0;
+    uint32_t maxP = 0;
+    Comp<Acc> plp;
+    src.for_each(g, [&](uint32_t lo, uint32_t hi, uint32_t c) {
+        atomicAdd(&R[lo], c);
+        atomicAdd(&R[hi], c);
+        atomicAdd(&Sp[lo + hi], 2u * c);
+        atomicAdd(&Sm[hi - lo], 2u * c);
+        const bool diag = lo == hi;
+        const uint32_t P = diag ? 2u * c : c;
+        const ISum Pm = diag ? (ISum)P : (ISum)(2ull * P);    // P summed over both orders
+        Tl += (ISum)(2ull * c);
+        sumP2 += Pm * (ISum)P;
+        maxP = P > maxP ? P : maxP;
+        S11 += Pm * (ISum)((uint64_t)(lo + 1u) * (hi + 1u));
+        plp.add((Acc)Pm * log2_<Acc>((Acc)P));
+    });
     g.sync();
+    // Level sweeps over the marginals (unnormalised).
+    ISum S1 = 0, S2 = 0, Sm1 = 0;
+    Comp<Acc> rlr, slp, hom1, hom2, idmn, idn, iv, plps;
+    const Acc ngf = (Acc)ng;
+    for (uint32_t i = r0; i < ng; i += gs) {
+        const uint32_t r = R[i];
+        if (r) {
+            const ISum lv = (ISum)(i + 1u);
+            S1 += lv * (ISum)r;
+            S2 += lv * lv * (ISum)r;
+            rlr.add((Acc)r * log2_<Acc>((Acc)r));
+        }
+        const uint32_t s = Sm[i];
+        if (s) {
+            Sm1 += (ISum)i * (ISum)s;
+            const Acc sf = (Acc)s, k = (Acc)i;
+            slp.add(sf * log2_<Acc>(sf));
+            hom1.add(sf / ((Acc)1 + k));
+            hom2.add(sf / ((Acc)1 + k * k));
+            idmn.add(sf / ((Acc)1 + (k * k) / (ngf * ngf)));
+            idn.add(sf / ((Acc)1 + k / ngf));
+            if (i > 0) iv.add(sf / (k * k));
+        }
+    }
+    for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) {
+        const uint32_t s = Sp[k];
+        if (s) plps.add((Acc)s * log2_<Acc>((Acc)s));
+    }
+    const uint64_t T = (uint64_t)g.sum(Tl);
     if (T == 0) {
+        g.sync();
         if (r0 == 0) out->T = 0;
+        for (uint32_t i = r0; i < ng; i += gs) { R[i] = 0u; Sm[i] = 0u; }
+        for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) Sp[k] = 0u;
+        src.clear(g);
         g.sync();
         return 0;
     }
-    const double Td = (double)T;
-    const Acc invT = (Acc)(1.0 / Td);
-    // Level sweeps over the marginals.
-    uint64_t S1 = 0, S2 = 0, Sm1 = 0;
-    Comp<Acc> hx, dent, hom1, hom2, idmn, idn, iv, sent, je, mi;
-    const Acc ngf = (Acc)ng;
-    for (uint32_t i = r0; i < ng; i += gs) {
-        uint32_t r = R[i];
-        if (r) {
-            uint64_t lv = i + 1u;
-            S1 += lv * r;
-            S2 += lv * lv * r;
-            Acc p = (Acc)r * invT;
-            hx.add(-p * log2_<Acc>(p));
-        }
-        uint32_t s = Sm[i];
-        if (s) {
-            Sm1 += (uint64_t)i * s;
-            Acc p = (Acc)s * invT;
-            Acc k = (Acc)i;
-            dent.add(-p * log2_<Acc>(p));
-            hom1.add(p / ((Acc)1 + k));
-            hom2.add(p / ((Acc)1 + k * k));
-            idmn.add(p / ((Acc)1 + (k * k) / (ngf * ngf)));
-            idn.add(p / ((Acc)1 + k / ngf));
-            if (i > 0) iv.add(p / (k * k));
-        }
-    }
-    for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) {
-        uint32_t s = Sp[k];
-        if (s) {
-            Acc p = (Acc)s * invT;
-            sent.add(-p * log2_<Acc>(p));
-        }
-    }
-    // Sweep 2: cell terms.
-    uint64_t sumP2 = 0, maxP = 0, S11 = 0;
-    for (uint32_t e = r0; e < n; e += gs) {
-        uint32_t lo, hi;
-        uint64_t c = src.get(e, lo, hi);
-        if (c == 0) continue;
-        bool diag = lo == hi;
-        uint64_t P = diag ? 2ull * c : c;
-        uint64_t mult = diag ? 1ull : 2ull;
-        sumP2 += mult * P * P;
-        maxP = P > maxP ? P : maxP;
-        S11 += mult * (uint64_t)(lo + 1u) * (uint64_t)(hi + 1u) * P;
-        Acc p = (Acc)P * invT;
-        je.add(-(Acc)mult * p * log2_<Acc>(p));
-    }
-    S1 = g.sum(S1);
-    S2 = g.sum(S2);
-    Sm1 = g.sum(Sm1);
-    sumP2 = g.sum(sumP2);
-    maxP = g.max(maxP);
-    S11 = g.sum(S11);
-    const double HX = (double)g.csum(hx);
-    const double DENT = (double)g.csum(dent);
-    const double HOM1 = (double)g.csum(hom1);
-    const double HOM2 = (double)g.csum(hom2);
-    const double IDMN = (double)g.csum(idmn);
-    const double IDN = (double)g.csum(idn);
-    const double IV = (double)g.csum(iv);
-    const double SENT = (double)g.csum(sent);
-    const double JE = (double)g.csum(je);
+    const double Td = (double)T, invT = 1.0 / Td, lgT = log2(Td);
+    const uint64_t S1t = (uint64_t)g.sum(S1), S2t = (uint64_t)g.sum(S2), Sm1t = (uint64_t)g.sum(Sm1);
+    const uint64_t S11t = (uint64_t)g.sum(S11), sumP2t = (uint64_t)g.sum(sumP2);
+    const uint32_t maxPt = g.max(maxP);
+    const double JE = lgT - g.sum(comp_value(plp)) * invT;
+    const double HX = lgT - g.sum(comp_value(rlr)) * invT;
+    const double DENT = lgT - g.sum(comp_value(slp)) * invT;
+    const double SENT = lgT - g.sum(comp_value(plps)) * invT;
+    const double HOM1 = g.sum(comp_value(hom1)) * invT;
+    const double HOM2 = g.sum(comp_value(hom2)) * invT;
+    const double IDMN = g.sum(comp_value(idmn)) * invT;
+    const double IDN = g.sum(comp_value(idn)) * invT;
+    const double IV = g.sum(comp_value(iv)) * invT;
     // Cluster shade / prominence: moments of the sum marginal about 2 mu.
-    const double two_mu = 2.0 * (double)S1 / Td;
-    Comp<double> cs, cp;
+    const double two_mu = 2.0 * (double)S1t * invT;
+    double cs = 0.0, cp = 0.0;
     for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) {
-        uint32_t s = Sp[k];
+        const uint32_t s = Sp[k];
         if (s) {
-            double p = (double)s / Td;
-            double d = (double)(k + 2u) - two_mu;
-            double d3 = d * d * d;
-            cs.add(d3 * p);
-            cp.add(d3 * d * p);
+            const double p = (double)s * invT;
+            const double d = (double)(k + 2u) - two_mu;
+            const double d3 = d * d * d;
+            cs += d3 * p;
+            cp += d3 * d * p;
         }
     }
-    const double CSHADE = g.csum(cs);
-    const double CPROM = g.csum(cp);
+    const double CSHADE = g.sum(cs), CPROM = g.sum(cp);
     // Mutual information HX + HY - HXY (HX = HY for a symmetric matrix).
     double MI = 2.0 * HX - JE;
-    if (MI < 0.25) {
+    if (MI < mi_resum_threshold<Acc>()) {
         Comp<Acc> m;
-        for (uint32_t e = r0; e < n; e += gs) {
-            uint32_t lo, hi;
-            uint64_t c = src.get(e, lo, hi);
-            if (c == 0) continue;
-            bool diag = lo == hi;
-            uint64_t P = diag ? 2ull * c : c;
-            Acc mult = diag ? (Acc)1 : (Acc)2;
-            uint64_t A = P * T;                               // P T < 2^64
-            uint64_t B = (uint64_t)R[lo] * (uint64_t)R[hi];   // px py T^2
-            Acc delta = A >= B ? (Acc)(A - B) / (Acc)B : -((Acc)(B - A) / (Acc)B);
-            Acc p = (Acc)P * invT;
+        const Acc invTa = (Acc)invT;
+        src.for_each(g, [&](uint32_t lo, uint32_t hi, uint32_t c) {
+            const bool diag = lo == hi;
+            const uint64_t P = diag ? 2ull * c : (uint64_t)c;
+            const Acc mult = diag ? (Acc)1 : (Acc)2;
+            const uint64_t A = P * T;                               // P T < 2^64
+            const uint64_t B = (uint64_t)R[lo] * (uint64_t)R[hi];   // px py T^2
+            const Acc delta = A >= B ? (Acc)(A - B) / (Acc)B : -((Acc)(B - A) / (Acc)B);
+            const Acc p = (Acc)P * invTa;
             m.add(mult * p * log1p_<Acc>(delta) * (Acc)1.4426950408889634);
-        }
-        MI = (double)g.csum(m);
+        });
+        MI = g.sum(comp_value(m));
     }
     if (r0 == 0) {
-        out->T = T; out->S1 = S1; out->S2 = S2; out->Sm1 = Sm1; out->S11 = S11;
-        out->sumP2 = sumP2; out->maxP = maxP;
+        out->T = T; out->S1 = S1t; out->S2 = S2t; out->Sm1 = Sm1t; out->S11 = S11t;
+        out->sumP2 = sumP2t; out->maxP = maxPt;
         out->HX = HX; out->DENT = DENT; out->HOM1 = HOM1; out->HOM2 = HOM2; out->IDMN = IDMN;
         out->IDN = IDN; out->IV = IV; out->SENT = SENT; out->JE = JE; out->CSHADE = CSHADE;
         out->CPROM = CPROM; out->MI = MI;
@@ -353,7 +438,7 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
     g.sync();
     for (uint32_t i = r0; i < ng; i += gs) { R[i] = 0u; Sm[i] = 0u; }
     for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) Sp[k] = 0u;
-    for (uint32_t e = r0; e < n; e += gs) src.clear(e);
+    src.clear(g);
     g.sync();
     return T;
 }

@@ -554,30 +554,23 @@ __device__ void accumulate_sweep2d(const StepArgs &a, uint8_t *smem, const RoiDe
     }
 }
 
-// Builds the nonzero list of one direction's triangle (scan modes) in
-// triangle-index order, i.e. (hi, lo) ascending; one wavefront.
-template <bool PACKED>
-__device__ __forceinline__ uint32_t build_list(const uint32_t *U, uint32_t tri, uint32_t *list, uint32_t cap,
-                                               uint32_t *err) {
-    uint32_t n = 0;
-    for (uint32_t base = 0; base < tri; base += kWave) {
-        const uint32_t i = base + (uint32_t)lane();
-        uint32_t c = 0u;
-        if (i < tri) c = PACKED ? (uint32_t)reinterpret_cast<const uint16_t *>(U)[i] : U[i];
-        const uint64_t m = __ballot(c != 0u);
-        if (c) {
-            // decode i = hi (hi + 1) / 2 + lo
-            uint32_t hi = (uint32_t)((sqrtf(8.0f * (float)i + 1.0f) - 1.0f) * 0.5f);
-            if (((hi * (hi + 1u)) >> 1) > i) --hi;
-            else if ((((hi + 1u) * (hi + 2u)) >> 1) <= i) ++hi;
-            const uint32_t lo = i - ((hi * (hi + 1u)) >> 1);
-            const uint32_t pos = n + (uint32_t)__popcll(m & __lanemask_lt());
-            if (pos < cap) list[pos] = lo | (hi << 16);
-            else atomicOr(err, (uint32_t)E_LIST_CAP);
-        }
-        n += (uint32_t)__popcll(m);
+// One direction of a finished item: features (unsplit ROI) or a 64-bit
+// atomic merge into the ROI's global matrix (tile of a split ROI).
+template <class Acc, class Src>
+__device__ __forceinline__ void dir_or_flush(const StepArgs &a, const WaveGrp &g, const Src &s, bool split,
+                                             const RoiDesc &rd, int d, uint32_t *MARG, uint32_t ng,
+                                             DirSums *SUMS) {
+    if (split) {
+        uint64_t *G = a.G + ((uint64_t)rd.gslot * a.K + d) * (uint64_t)ng * ng;
+        s.for_each(g, [&](uint32_t lo, uint32_t hi, uint32_t c) {
+            atomicAdd(reinterpret_cast<unsigned long long *>(&G[(uint64_t)lo * ng + hi]), (unsigned long long)c);
+        });
+        g.sync();
+        s.clear(g);
+        g.sync();
+    } else {
+        dir_sums<Acc, double>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng, SUMS + d);
     }
-    return n < cap ? n : cap;
 }
 
 template <int MODE, class OutT>
@@ -589,6 +582,7 @@ __global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) 
     uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off);
     double *FEAT = reinterpret_cast<double *>(smem + Ly.feat_off);
     DirSums *SUMS = reinterpret_cast<DirSums *>(smem + Ly.sums_off);
+    uint2 *BUF = reinterpret_cast<uint2 *>(smem + Ly.buf_off);
     uint32_t *MISC = reinterpret_cast<uint32_t *>(smem + Ly.misc_off);
     const int nw = (int)(blockDim.x / kWave), w = (int)(threadIdx.x / kWave);
     const int K = a.K;
@@ -605,7 +599,8 @@ __global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) 
         uint32_t *HC = reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off);
         for (uint32_t i = threadIdx.x; i < Ly.hash_cap; i += blockDim.x) { HK[i] = kNone; HC[i] = 0u; }
     }
-    for (uint32_t i = threadIdx.x; i < (uint32_t)nw * marg_words; i += blockDim.x)
+    // marginal sets exist for the waves that reduce a direction (w < kp)
+    for (uint32_t i = threadIdx.x; i < min((uint32_t)nw, Ly.kp) * marg_words; i += blockDim.x)
         reinterpret_cast<uint32_t *>(smem + Ly.marg_off)[i] = 0u;
     for (uint32_t i = threadIdx.x; i < Ly.kp; i += blockDim.x) LCNT[i] = 0u;
     if (threadIdx.x == 0 && direct_roi == kNone) {
@@ -680,43 +675,19 @@ __global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) 
                 __syncthreads();
                 for (int dl = w; dl < d1 - d0; dl += nw) {
                     uint32_t *Ud = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
-                    if (MODE == 2 || MODE == 3) {
-                        const uint32_t nn = build_list<MODE == 3>(Ud, (ng * (ng + 1u)) >> 1, LST + dl * Ly.list_cap,
-                                                                  Ly.list_cap, &a.counters[C_ERR]);
-                        if (lane() == 0) LCNT[dl] = nn;
-                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                    }
                     const uint32_t n = min(LCNT[dl], Ly.list_cap);
                     const uint32_t *lst = LST + dl * Ly.list_cap;
-                    if (split) {
-                        uint64_t *G = a.G + ((uint64_t)rd.gslot * K + (d0 + dl)) * (uint64_t)ng * ng;
-                        for (uint32_t e = lane(); e < n; e += kWave) {
-                            uint32_t lo, hi;
-                            uint64_t cnt;
-                            if (MODE != 1) {
-                                SrcDenseList<MODE == 3> s{lst, n, Ud};
-                                cnt = s.get(e, lo, hi);
-                                s.clear(e);
-                            } else {
-                                SrcHashList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.hkey_off),
-                                              reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off)};
-                                cnt = s.get(e, lo, hi);
-                                s.clear(e);
-                            }
-                            atomicAdd(reinterpret_cast<unsigned long long *>(&G[(uint64_t)lo * ng + hi]),
-                                      (unsigned long long)cnt);
-                        }
+                    WaveGrp g;
+                    if (MODE == 2 || MODE == 3) {
+                        SrcTriScan<MODE == 3> s{Ud, (ng * (ng + 1u)) >> 1, BUF + (uint32_t)w * kWave * kScanPerLane};
+                        dir_or_flush<Acc>(a, g, s, split, rd, d0 + dl, MARG, ng, SUMS);
+                    } else if (MODE == 0) {
+                        SrcDenseList s{lst, n, Ud};
+                        dir_or_flush<Acc>(a, g, s, split, rd, d0 + dl, MARG, ng, SUMS);
                     } else {
-                        WaveGrp g;
-                        if (MODE != 1) {
-                            SrcDenseList<MODE == 3> s{lst, n, Ud};
-                            dir_sums<Acc>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng, SUMS + d0 + dl);
-                        } else {
-                            SrcHashList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.hkey_off),
-                                          reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off)};
-                            dir_sums<Acc>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng, SUMS + d0 + dl);
-                        }
+                        SrcHashList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.hkey_off),
+                                      reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off)};
+                        dir_or_flush<Acc>(a, g, s, split, rd, d0 + dl, MARG, ng, SUMS);
                     }
                     if (lane() == 0) LCNT[dl] = 0u;
                 }
@@ -753,7 +724,7 @@ __global__ __launch_bounds__(512) void k_split_features(StepArgs a) {
     BlockGrp g{scratch};
     SrcSquare s{a.G + ((uint64_t)slot * K + d) * (uint64_t)ng * ng, ng};
     DirSums *sums = reinterpret_cast<DirSums *>(out + kNumFeat);
-    dir_sums<Acc>(g, s, R, R + ng, R + 3u * ng - 1u, ng, sums);
+    dir_sums<Acc, uint64_t>(g, s, R, R + ng, R + 3u * ng - 1u, ng, sums);
     __syncthreads();
     if (threadIdx.x == 0) finalize_dir(*sums, out);
     __syncthreads();
@@ -859,7 +830,7 @@ __global__ __launch_bounds__(512) void k_coo_features(StepArgs a, const uint64_t
     SrcCoo src{keys + seg[s], vals + seg[s], (uint32_t)(seg[s + 1] - seg[s]),
                ((uint64_t)(s / K) << 38) | ((uint64_t)(s % K) << 32), ng, &a.counters[C_ERR]};
     DirSums *sums = reinterpret_cast<DirSums *>(out + kNumFeat);
-    dir_sums<Acc>(g, src, R, R + ng, R + 3u * ng - 1u, ng, sums);
+    dir_sums<Acc, uint64_t>(g, src, R, R + ng, R + 3u * ng - 1u, ng, sums);
     __syncthreads();
     if (threadIdx.x == 0) finalize_dir(*sums, out);
     __syncthreads();

@@ -328,7 +328,8 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K) {
     }
     L.list_off = take(c.kp * c.list_cap * 4u);
     L.lcnt_off = take(c.kp * 4u);
-    L.marg_off = take(L.nwaves * 4u * ng * 4u);
+    L.buf_off = take((c.mode == 2 || c.mode == 3) ? L.nwaves * kWave * 4u * 8u : 0u);
+    L.marg_off = take(std::min(L.nwaves, c.kp) * 4u * ng * 4u);   // one set per wave that reduces a direction
     L.feat_off = take((uint32_t)K * kNumFeat * 8u);
     L.sums_off = take((uint32_t)K * (uint32_t)sizeof(DirSumsHost));
     L.misc_off = take(128u * 4u);
@@ -358,8 +359,13 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
     std::vector<Config> out;
     const uint32_t nw = block / kWave;
     const uint32_t tri = ng * (ng + 1u) / 2u;
-    const uint32_t fixed = (nw * 4u * ng * 4u + 15u) / 16u * 16u + (uint32_t)K * kNumFeat * 8u +
-                           (uint32_t)K * (uint32_t)sizeof(DirSumsHost) + 128u * 4u + 64u * 4u + 64;
+    // LDS besides triangles / hash / lists: marginals for up to nw directions
+    // at a time, feature staging, sums, misc, alignment slack
+    auto fixed_for = [&](uint32_t kp) {
+        return (std::min(nw, kp) * 4u * ng * 4u + 15u) / 16u * 16u + (uint32_t)K * kNumFeat * 8u +
+               (uint32_t)K * (uint32_t)sizeof(DirSumsHost) + 128u * 4u + 64u * 4u + 64;
+    };
+    const uint32_t fixed = fixed_for(1u);
     uint64_t total_vox = 0;
     for (const RoiDesc &r : w.h_rois) total_vox += r.n;
     // load balance: split ROIs that would take more than ~1/4 of one
@@ -374,9 +380,12 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
             mi = max_item_vox(w.h_rois, split, split);
         }
         if (mode == 3 && mi > 65535u) continue;
-        const uint32_t list_cap = (uint32_t)std::min<uint64_t>(tri, std::max<uint64_t>(mi, 1u));
+        const bool scan = mode == 2 || mode == 3;
+        const uint32_t list_cap = scan ? 0u : (uint32_t)std::min<uint64_t>(tri, std::max<uint64_t>(mi, 1u));
+        const uint64_t scan_buf = scan ? (uint64_t)nw * kWave * 4u * 8u : 0u;
         for (uint32_t kp = (uint32_t)K; kp >= 1u; --kp) {
-            uint64_t bytes = (uint64_t)kp * u_words(mode, ng) * 4u + (uint64_t)kp * list_cap * 4u + kp * 4u + fixed;
+            uint64_t bytes = (uint64_t)kp * u_words(mode, ng) * 4u + (uint64_t)kp * list_cap * 4u + kp * 4u +
+                             fixed_for(kp) + scan_buf;
             if (bytes <= kLdsBudget) {
                 Config c;
                 c.mode = mode; c.kp = kp; c.block = block; c.split_vox = split; c.tile_vox = split;
@@ -401,7 +410,7 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
             }
             if (mi > per_dir) continue;
             uint32_t list_cap = (uint32_t)std::max<uint64_t>(mi, 1u);
-            uint64_t bytes = (uint64_t)hc * 8u + (uint64_t)kp * list_cap * 4u + kp * 4u + fixed;
+            uint64_t bytes = (uint64_t)hc * 8u + (uint64_t)kp * list_cap * 4u + kp * 4u + fixed_for(kp);
             if (bytes <= kLdsBudget) {
                 Config c;
                 c.mode = 1; c.kp = kp; c.block = block; c.hash_cap = hc; c.split_vox = split; c.tile_vox = split;

@@ -73,7 +73,7 @@ struct LdsLayout {
     uint32_t tri_pad;     // u32 words per dense triangle (dense mode)
     uint32_t list_cap;    // entries per direction list
     uint32_t hash_cap;    // slots (power of two, hash mode)
-    uint32_t u_off, list_off, lcnt_off, marg_off, feat_off, sums_off, misc_off, hkey_off, hcnt_off;
+    uint32_t u_off, list_off, lcnt_off, marg_off, feat_off, sums_off, misc_off, hkey_off, hcnt_off, buf_off;
     uint32_t bytes;       // total dynamic LDS
     uint32_t nwaves;      // waves per work-group
 };
