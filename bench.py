@@ -32,11 +32,21 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, offs, seconds: float) -> dict:
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(w, offs, seconds: float, threads: int) -> tuple:
     """The oracle, as it stands, on whole images of the workload until about
-    `seconds` of wall time; all host threads."""
+    `seconds` of wall time."""
     import oracle
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     off = np.array(offs, np.int32)
     vox, t0, n_img = 0, time.perf_counter(), 0
     for k in range(w.n_images):
@@ -46,8 +56,27 @@ def cpu_baseline(w, offs, seconds: float) -> dict:
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
-    return {"value": vox / dt, "unit": "ROI-voxels/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n_img} of {w.n_images} images ({vox} ROI voxels), FP64 oracle, {dt:.1f} s"}
+    return vox / dt, n_img, vox, dt
+
+
+def cpu_baseline(w, offs, seconds: float) -> dict:
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    rate, n_img, vox, dt = oracle_rate(w, offs, seconds, threads)
+    rate1, n1, vox1, dt1 = oracle_rate(w, offs, seconds / 3.0, 1)
+    return {"value": rate, "unit": "ROI-voxels/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_img} of {w.n_images} images ({vox} ROI voxels), FP64 oracle, {dt:.1f} s",
+            "single_thread": {"value": rate1, "sample": f"{n1} images ({vox1} ROI voxels), {dt1:.1f} s"},
+            "cpu_model": cpu_model()}
+
+
+def same_label_pairs(lab, off) -> int:
+    """Voxel pairs (v, v + off) inside one ROI (equal nonzero labels); lab is
+    a (nz, ny, nx) device tensor."""
+    def cut(d, n):
+        return (slice(0, max(n - d, 0)), slice(d, n)) if d >= 0 else (slice(-d, n), slice(0, max(n + d, 0)))
+    (za, zb), (ya, yb), (xa, xb) = (cut(d, n) for d, n in zip(off, lab.shape))
+    a, b = lab[za, ya, xa], lab[zb, yb, xb]
+    return int(((a == b) & (a != 0)).sum().item())
 
 
 def main() -> int:
@@ -77,11 +106,20 @@ def main() -> int:
     t0 = time.perf_counter()
     w = synth.make(args.workload)
     log(f"generated {args.workload} in {time.perf_counter() - t0:.1f} s")
-    imgs = []
-    for k in range(w.n_images):
-        imgs.append((torch.from_numpy(w.intensity[k].view(np.int16)).to(dev),
-                     torch.from_numpy(w.labels[k].view(np.int32)).to(dev)))
+    # inputs to HBM from pinned host memory, timed apart from the step
+    host = [(torch.from_numpy(w.intensity[k].view(np.int16)).pin_memory(),
+             torch.from_numpy(w.labels[k].view(np.int32)).pin_memory()) for k in range(w.n_images)]
+    imgs = [(torch.empty_like(i, device=dev), torch.empty_like(l, device=dev)) for i, l in host]
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (di, dl), (hi, hl) in zip(imgs, host):
+        di.copy_(hi, non_blocking=True)
+        dl.copy_(hl, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d_s = time.perf_counter() - t0
+    in_bytes = sum(i.numel() * 2 + l.numel() * 4 for i, l in host)
+    del host
+    log(f"inputs to device: {in_bytes / 1e9:.2f} GB in {h2d_s * 1e3:.1f} ms")
     offs = nyx.nyx_offsets_default(w.dims, 1)
     K = len(offs)
     prec = nyx.NYX_FP64 if w.precision == "fp64" else nyx.NYX_FP32
@@ -100,16 +138,22 @@ def main() -> int:
     torch.cuda.synchronize()
     nyx.nyx_plan_check(plan)
     log(f"warmup done ({args.warmup} steps)")
+    # events between replays, on the stream the graph is launched on
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    evs[0].record()
+    for k in range(args.steps):
         nyx.nyx_plan_execute(plan, table)
+        evs[k + 1].record()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     nyx.nyx_plan_check(plan)
+    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
     ms = dt * 1e3 / args.steps
     value = roi_vox / (dt / args.steps)
-    log(f"batched: {ms:.3f} ms/step, {value / 1e9:.2f} G ROI-voxels/s")
+    log(f"batched: {ms:.3f} ms/step (median {np.median(step_ms):.3f}, min {min(step_ms):.3f}), "
+        f"{value / 1e9:.2f} G ROI-voxels/s")
 
     # phase times of the same step, eager, with HIP events between phases
     prof = {p: 0.0 for p in nyx.PHASES}
@@ -133,14 +177,32 @@ def main() -> int:
         same = bool(torch.allclose(table, t2, rtol=1e-5, atol=1e-6, equal_nan=True))
         log(f"per-ROI launches: {dt_roi * 1e3:.1f} ms/step, tables agree: {same}")
 
-    # algorithmic bytes: scan reads 4 B label + 2 B intensity
-    # per image voxel; the accumulate/feature kernel reads 4 B label + 2 B
-    # intensity per ROI voxel and writes the feature rows.
-    out_bytes = n_rois * (K + 1) * 30 * (8 if prec == nyx.NYX_FP64 else 4)
-    alg = {"scan": img_vox * 6.0, "batch": roi_vox * 6.0 + out_bytes}
-    dom = max(("scan", "batch"), key=lambda p: prof[p])
+    # algorithmic bytes: the scan reads 4 B label + 2 B intensity per image
+    # voxel; each accumulate/feature kernel reads 4 B label + 2 B intensity per
+    # voxel of the ROIs it owns and writes their feature rows.
+    desc = nyx.nyx_plan_describe(plan)
+    fields = dict(kv.split("=", 1) for kv in desc.split() if "=" in kv)
+    wave_rois, wave_vox = int(fields.get("wave_rois", 0)), int(fields.get("wave_roi_voxels", 0))
+    row_bytes = (K + 1) * 30 * (8 if prec == nyx.NYX_FP64 else 4)
+    out_bytes = n_rois * row_bytes
+    alg = {"scan": img_vox * 6.0,
+           "batch": (roi_vox - wave_vox) * 6.0 + (n_rois - wave_rois) * row_bytes,
+           "wave": wave_vox * 6.0 + wave_rois * row_bytes}
+    kernel_names = {"scan": "k_scan", "batch": "k_batch", "wave": "k_wave"}
+    dom = max(("scan", "batch", "wave"), key=lambda p: prof[p])
     achieved = alg[dom] / (prof[dom] * 1e-3) / 1e9
     step_alg = img_vox * 4.0 + roi_vox * 2.0 + out_bytes
+
+    # same-ROI neighbour pairs = LDS atomics of the accumulation
+    pairs = sum(same_label_pairs(lab, o) for _, lab in imgs for o in offs)
+    machine = {}
+    try:
+        from paper_2603_12016_amd import micro
+        machine = {"copy_GBps": micro.copy_bandwidth()["GBps"], "read_GBps": micro.read_bandwidth()["GBps"],
+                   "lds_atomics_per_s": micro.lds_atomic_rate()["per_second"]}
+        log("machine: " + ", ".join(f"{k}={v:.4g}" for k, v in machine.items()))
+    except (ImportError, OSError, RuntimeError) as e:
+        log(f"machine ceilings not measured: {e}")
 
     rec = {
         "metric": "ROI-voxels/s for GLCM+features, batched vs per-ROI launch; % HBM peak",
@@ -162,8 +224,15 @@ def main() -> int:
                                                        "steps": args.per_roi_steps, "tables_agree": same},
         "speedup_vs_per_roi": None if dt_roi is None else dt_roi * 1e3 / ms,
         "step_hbm_frac_alg": step_alg / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "ms_median": float(np.median(step_ms)),
+        "ms_min": float(min(step_ms)),
         "phases_ms": prof,
-        "roofline": {"kernel": "k_batch" if dom == "batch" else "k_scan", "bound": "hbm", "achieved": achieved,
+        "inputs_h2d": {"bytes": in_bytes, "seconds": h2d_s, "GBps": in_bytes / h2d_s / 1e9,
+                       "value_incl_h2d": roi_vox / (h2d_s + dt / args.steps)},
+        "lds_atomics": {"pairs_per_step": pairs,
+                        "achieved_per_s": pairs / (sum(prof[p] for p in ("batch", "wave", "split")) * 1e-3)},
+        "machine": machine,
+        "roofline": {"kernel": kernel_names[dom], "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "plan_seconds": plan_s,
     }

@@ -120,6 +120,10 @@ typedef struct nyx_extract_opts {
                                     1 LDS hash table, 2 LDS triangle + ordered scan,
                                     3 LDS triangle of 16-bit counters + ordered scan
                                     (NYX_ERR_UNSUPPORTED when it does not fit) */
+    int32_t wave_max_vox;        /* -1 = automatic; 0 = every ROI on the work-group kernel;
+                                    n > 0 = unsplit ROIs of at most n voxels (n <= 65535) are
+                                    processed one wavefront each when there are at most 4
+                                    offsets and their LDS fits (else ignored) */
     int64_t workspace_cap_bytes; /* 0 = no cap; exceeding it gives NYX_ERR_OOM */
 } nyx_extract_opts;
 
@@ -189,9 +193,11 @@ typedef enum nyx_phase {
     NYX_PHASE_SCAN = 1,      /* ROI discovery: count, min, max, bbox per label */
     NYX_PHASE_COMPACT = 2,   /* ROI table and size-sorted work queue */
     NYX_PHASE_ZERO = 3,      /* clear the global matrices of split ROIs */
-    NYX_PHASE_BATCH = 4,     /* binning, co-occurrence counts, features */
-    NYX_PHASE_FINALIZE = 5,  /* features of split ROIs from global matrices */
-    NYX_PHASE_COUNT = 6
+    NYX_PHASE_BATCH = 4,     /* binning, co-occurrence counts, reduced sums (work-group per item) */
+    NYX_PHASE_WAVE = 5,      /* the same for small ROIs, one wavefront per ROI */
+    NYX_PHASE_SPLIT = 6,     /* reduced sums of split ROIs from their merged global matrices */
+    NYX_PHASE_FEATURES = 7,  /* the 30 features per direction and their mean, every ROI */
+    NYX_PHASE_COUNT = 8
 } nyx_phase;
 
 /* Runs one step eagerly (no graph) on `stream` with HIP events between its

@@ -9,6 +9,8 @@ ROOT = os.path.dirname(HERE)
 SOURCES = ["csrc/nyx_kernels.hip", "csrc/nyx_runtime.hip"]
 HEADERS = ["csrc/nyx_types.h", "csrc/nyx_device.h", "csrc/nyx_features.h", "csrc/nyx_launch.h"]
 LIB = os.path.join(HERE, "libnyx.so")
+MICRO_SOURCES = ["csrc/nyx_micro.hip"]
+MICRO_LIB = os.path.join(HERE, "libnyx_micro.so")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -24,18 +26,23 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    """Compile libnyx.so (always recompiles)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _compile(sources, lib, verbose):
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [hipcc(), *HIPCC_FLAGS, "-I" + os.path.join(HERE, "csrc"), "-I" + os.path.join(ROOT, "include"),
-           "-o", tmp, *[os.path.join(HERE, s) for s in SOURCES]]
+           "-o", tmp, *[os.path.join(HERE, s) for s in sources]]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libnyx.so and the measurement kernels libnyx_micro.so (always recompiles)."""
+    _compile(MICRO_SOURCES, MICRO_LIB, verbose)
+    return _compile(SOURCES, LIB, verbose)
 
 
 if __name__ == "__main__":

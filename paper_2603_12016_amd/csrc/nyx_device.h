@@ -83,6 +83,43 @@ __device__ __forceinline__ T wave_reduce(T v, Op op) {
     return op(op(readlane_(v, 0), readlane_(v, 16)), op(readlane_(v, 32), readlane_(v, 48)));
 }
 
+// Batched row reduction of kSumSlots doubles by recursive halving.  Each of
+// four exchange steps (row_mirror, row_half_mirror, quad_perm [2,3,0,1],
+// quad_perm [1,0,3,2]) pairs lanes that hold the same set of slots; one keeps
+// the lower half of the set and its partner the upper half, each adding the
+// partner's copy of the half it keeps.  Afterwards the lane of row-rank r
+// holds the row total of slot r: 15 exchanges instead of 16 x 4.
+template <int CTRL, int N>
+__device__ __forceinline__ void halve_step(double *v, bool keep_low) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const double send = keep_low ? v[N + j] : v[j];
+        const double mine = keep_low ? v[j] : v[N + j];
+        v[j] = mine + dpp_move<CTRL>(send);
+    }
+}
+
+__device__ __forceinline__ double row_reduce_slots(double (&v)[kSumSlots]) {
+    static_assert(kSumSlots == 16, "four halving steps");
+    const int r = lane() & 15;
+    halve_step<kDppRowMirror, 8>(v, r < 8);
+    halve_step<kDppRowHalfMirror, 4>(v, (r & 4) == 0);
+    halve_step<kDppQuad2301, 2>(v, (r & 2) == 0);
+    halve_step<kDppQuad1032, 1>(v, (r & 1) == 0);
+    return v[0];
+}
+
+// Two values: one halving step (row_mirror), then plain row sums; lanes of
+// row-rank < 8 end with the total of a, the others with that of b.
+__device__ __forceinline__ double row_reduce_pair(double a, double b) {
+    const bool lo = (lane() & 15) < 8;
+    double v = (lo ? a : b) + dpp_move<kDppRowMirror>(lo ? b : a);
+    v += dpp_move<kDppRowHalfMirror>(v);
+    v += dpp_move<kDppQuad2301>(v);
+    v += dpp_move<kDppQuad1032>(v);
+    return v;
+}
+
 struct OpAdd { template <class T> __device__ __forceinline__ T operator()(T a, T b) const { return a + b; } };
 struct OpMax { template <class T> __device__ __forceinline__ T operator()(T a, T b) const { return a > b ? a : b; } };
 struct OpMin { template <class T> __device__ __forceinline__ T operator()(T a, T b) const { return a < b ? a : b; } };

@@ -41,10 +41,29 @@ enum Feat : int {
 // (result in every lane of the group), ballot(pred) (group-local bit mask,
 // bit r = rank r) and below() (mask of ranks lower than the caller's).
 
+// Groups that are one wavefront or one 16-lane row also offer the batched
+// reduction (kBatched): reduce_slots leaves the group total of slot r in the
+// lane of rank r < kSumSlots, reduce_pair the totals of two values (rank 0 holds
+// the first, rank 8 the second), bcast reads a lane's value into every lane.
+
 // One wavefront.
 struct WaveGrp {
+    static constexpr bool kBatched = true;
     __device__ __forceinline__ int rank() const { return lane(); }
     __device__ __forceinline__ int size() const { return kWave; }
+    __device__ __forceinline__ double reduce_slots(double (&v)[kSumSlots]) const {
+        double s = row_reduce_slots(v);
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        return s;
+    }
+    __device__ __forceinline__ double reduce_pair(double a, double b) const {
+        double s = row_reduce_pair(a, b);
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        return s;
+    }
+    __device__ __forceinline__ double bcast(double v, int r) const { return readlane_(v, r); }
     __device__ __forceinline__ void sync() const {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -58,8 +77,12 @@ struct WaveGrp {
 // One 16-lane DPP row of a wavefront: four independent groups per wavefront,
 // reduced together by the same DPP instructions.
 struct RowGrp {
+    static constexpr bool kBatched = true;
     __device__ __forceinline__ int rank() const { return lane() & 15; }
     __device__ __forceinline__ int size() const { return 16; }
+    __device__ __forceinline__ double reduce_slots(double (&v)[kSumSlots]) const { return row_reduce_slots(v); }
+    __device__ __forceinline__ double reduce_pair(double a, double b) const { return row_reduce_pair(a, b); }
+    __device__ __forceinline__ double bcast(double v, int r) const { return __shfl(v, r, 16); }
     __device__ __forceinline__ int row() const { return lane() >> 4; }
     __device__ __forceinline__ void sync() const {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -73,6 +96,7 @@ struct RowGrp {
 
 // The whole work-group; `scratch` is LDS room for one 8-byte value per wave.
 struct BlockGrp {
+    static constexpr bool kBatched = false;
     uint64_t *scratch;
     __device__ __forceinline__ int rank() const { return (int)threadIdx.x; }
     __device__ __forceinline__ int size() const { return (int)blockDim.x; }
@@ -249,20 +273,15 @@ struct SrcCoo {
 };
 
 // ------------------------------------------------------------- sums
-// Reduced per-direction sums (group-uniform), input of finalize_dir.
-struct DirSums {
-    uint64_t T, S1, S2, Sm1, S11, sumP2, maxP, pad;
-    double HX, DENT, HOM1, HOM2, IDMN, IDN, IV, SENT, JE, CSHADE, CPROM, MI;
-};
-
 // The 30 features of one direction from its reduced sums (one lane).
 __device__ __noinline__ void finalize_dir(const DirSums &s, double *out) {
-    if (s.T == 0) {
+    const uint64_t T = s.T;
+    if (T == 0) {
         for (int f = 0; f < kNumFeat; ++f) out[f] = __builtin_nan("");
         return;
     }
-    const uint64_t T = s.T, S1 = s.S1, S2 = s.S2, S11 = s.S11, Sm1 = s.Sm1;
-    const double Td = (double)T;
+    const uint64_t S1 = s.S1, S2 = s.S2, S11 = s.S11, Sm1 = s.Sm1;
+    const double Td = (double)T, invT = 1.0 / Td, lgT = log2(Td);
     const double T2 = Td * Td;
     const u128 Tq = (u128)T;
     const u128 s1sq = (u128)S1 * (u128)S1;
@@ -272,6 +291,10 @@ __device__ __noinline__ void finalize_dir(const DirSums &s, double *out) {
     const u128 ndv = Tq * sm2 - (u128)Sm1 * (u128)Sm1;
     const bool single = nvar == 0;
     const double var = u128_to_double(nvar) / T2;
+    // entropies H = log2 T - (sum n log2 n) / T
+    const double JE = lgT - s.plp * invT;
+    const double HX = lgT - s.rlr * invT;
+    const double MI = isnan(s.MI) ? 2.0 * HX - JE : s.MI;
     out[F_ASM] = out[F_ENERGY] = (double)s.sumP2 / T2;
     out[F_ACOR] = (double)S11 / Td;
     out[F_CLUPROM] = s.CPROM;
@@ -280,21 +303,21 @@ __device__ __noinline__ void finalize_dir(const DirSums &s, double *out) {
     out[F_CONTRAST] = u128_to_double(sm2) / Td;
     out[F_CORR] = single ? 1.0 : i128_to_double(ncov) / u128_to_double(nvar);
     out[F_DIFAVE] = out[F_DIS] = (double)Sm1 / Td;
-    out[F_DIFENTRO] = s.DENT;
+    out[F_DIFENTRO] = lgT - s.slp * invT;
     out[F_DIFVAR] = u128_to_double(ndv) / T2;
-    out[F_ENTROPY] = out[F_JE] = s.JE;
-    out[F_HOM1] = out[F_ID] = s.HOM1;
-    out[F_HOM2] = out[F_IDM] = s.HOM2;
-    const double mi = s.MI > 0.0 ? s.MI : 0.0;
-    out[F_INFOMEAS1] = single ? 0.0 : -s.MI / s.HX;
+    out[F_ENTROPY] = out[F_JE] = JE;
+    out[F_HOM1] = out[F_ID] = s.hom1 * invT;
+    out[F_HOM2] = out[F_IDM] = s.hom2 * invT;
+    const double mi = MI > 0.0 ? MI : 0.0;
+    out[F_INFOMEAS1] = single ? 0.0 : -MI / HX;
     out[F_INFOMEAS2] = sqrt(1.0 - exp(-2.0 * mi));
-    out[F_IDMN] = s.IDMN;
-    out[F_IDN] = s.IDN;
-    out[F_IV] = s.IV;
+    out[F_IDMN] = s.idmn * invT;
+    out[F_IDN] = s.idn * invT;
+    out[F_IV] = s.iv * invT;
     out[F_JAVE] = (double)S1 / Td;
     out[F_JMAX] = (double)s.maxP / Td;
     out[F_SUMAVE] = 2.0 * (double)S1 / Td;
-    out[F_SUMENT] = s.SENT;
+    out[F_SUMENT] = lgT - s.plps * invT;
     out[F_JVAR] = out[F_VARIANCE] = var;
 }
 
@@ -317,12 +340,14 @@ template <> __device__ __forceinline__ double mi_resum_threshold<double>() { ret
 // Reduced sums of one direction.  R, Sp, Sm are zeroed LDS arrays of ng,
 // 2 ng - 1 and ng u32 (row, sum and difference marginals of the symmetric
 // matrix); they are zeroed again on return, and the source is cleared.
-// *out (LDS) is written by rank 0.  ISum is the type of the per-lane integer
-// sums: double where every partial and total stays below 2^53 (small work
-// items), uint64_t otherwise.  Returns T (0: direction empty).
+// *out (LDS or global) is written by the group.  ISum is the type of the
+// per-lane integer sums: double where every partial and total stays below
+// 2^53 (small work items; required by the batched reduction), uint64_t
+// otherwise.  Returns T (0: direction empty).
 template <class Acc, class ISum, class Grp, class Src>
 __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t *Sp, uint32_t *Sm,
                              uint32_t ng, DirSums *out) {
+    static_assert(!Grp::kBatched || std::is_same<ISum, double>::value, "batched sums are exact doubles");
     const int r0 = g.rank(), gs = g.size();
     // One sweep over the nonzero cells: marginals and cell terms.  A cell
     // (lo < hi) with count c stands for P(lo, hi) = P(hi, lo) = c, a diagonal
@@ -373,7 +398,36 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
         const uint32_t s = Sp[k];
         if (s) plps.add((Acc)s * log2_<Acc>((Acc)s));
     }
-    const uint64_t T = (uint64_t)g.sum(Tl);
+    // Group totals.  Batched groups reduce the sixteen slots of DirSums at
+    // once (rank r < 16 ends with slot r); the others reduce value by value.
+    uint64_t T, S1t;
+    double slot = 0.0, plp_t, rlr_t;
+    const int rk = r0;
+    uint64_t tot_u[6];
+    double tot_d[10];
+    if constexpr (Grp::kBatched) {
+        double v[kSumSlots] = {(double)Tl, (double)S1, (double)S2, (double)Sm1, (double)S11, (double)sumP2,
+                               comp_value(plp), comp_value(rlr), comp_value(slp), comp_value(plps),
+                               comp_value(hom1), comp_value(hom2), comp_value(idmn), comp_value(idn),
+                               comp_value(iv), 0.0};
+        slot = g.reduce_slots(v);
+        T = (uint64_t)g.bcast(slot, 0);
+        S1t = (uint64_t)g.bcast(slot, 1);
+        plp_t = g.bcast(slot, 6);
+        rlr_t = g.bcast(slot, 7);
+    } else {
+        tot_u[0] = (uint64_t)g.sum(Tl); tot_u[1] = (uint64_t)g.sum(S1); tot_u[2] = (uint64_t)g.sum(S2);
+        tot_u[3] = (uint64_t)g.sum(Sm1); tot_u[4] = (uint64_t)g.sum(S11); tot_u[5] = (uint64_t)g.sum(sumP2);
+        tot_d[0] = g.sum(comp_value(plp)); tot_d[1] = g.sum(comp_value(rlr)); tot_d[2] = g.sum(comp_value(slp));
+        tot_d[3] = g.sum(comp_value(plps)); tot_d[4] = g.sum(comp_value(hom1)); tot_d[5] = g.sum(comp_value(hom2));
+        tot_d[6] = g.sum(comp_value(idmn)); tot_d[7] = g.sum(comp_value(idn)); tot_d[8] = g.sum(comp_value(iv));
+        tot_d[9] = 0.0;
+        T = tot_u[0];
+        S1t = tot_u[1];
+        plp_t = tot_d[0];
+        rlr_t = tot_d[1];
+    }
+    const uint32_t maxPt = g.max(maxP);
     if (T == 0) {
         g.sync();
         if (r0 == 0) out->T = 0;
@@ -384,18 +438,6 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
         return 0;
     }
     const double Td = (double)T, invT = 1.0 / Td, lgT = log2(Td);
-    const uint64_t S1t = (uint64_t)g.sum(S1), S2t = (uint64_t)g.sum(S2), Sm1t = (uint64_t)g.sum(Sm1);
-    const uint64_t S11t = (uint64_t)g.sum(S11), sumP2t = (uint64_t)g.sum(sumP2);
-    const uint32_t maxPt = g.max(maxP);
-    const double JE = lgT - g.sum(comp_value(plp)) * invT;
-    const double HX = lgT - g.sum(comp_value(rlr)) * invT;
-    const double DENT = lgT - g.sum(comp_value(slp)) * invT;
-    const double SENT = lgT - g.sum(comp_value(plps)) * invT;
-    const double HOM1 = g.sum(comp_value(hom1)) * invT;
-    const double HOM2 = g.sum(comp_value(hom2)) * invT;
-    const double IDMN = g.sum(comp_value(idmn)) * invT;
-    const double IDN = g.sum(comp_value(idn)) * invT;
-    const double IV = g.sum(comp_value(iv)) * invT;
     // Cluster shade / prominence: moments of the sum marginal about 2 mu.
     const double two_mu = 2.0 * (double)S1t * invT;
     double cs = 0.0, cp = 0.0;
@@ -409,10 +451,20 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
             cp += d3 * d * p;
         }
     }
-    const double CSHADE = g.sum(cs), CPROM = g.sum(cp);
-    // Mutual information HX + HY - HXY (HX = HY for a symmetric matrix).
-    double MI = 2.0 * HX - JE;
-    if (MI < mi_resum_threshold<Acc>()) {
+    double CSHADE, CPROM;
+    if constexpr (Grp::kBatched) {
+        const double pr = g.reduce_pair(cs, cp);
+        CSHADE = g.bcast(pr, 0);
+        CPROM = g.bcast(pr, 8);
+    } else {
+        CSHADE = g.sum(cs);
+        CPROM = g.sum(cp);
+    }
+    // Mutual information HX + HY - HXY (HX = HY for a symmetric matrix),
+    // re-summed cell by cell where the closed form loses digits.
+    const double JE = lgT - plp_t * invT, HX = lgT - rlr_t * invT;
+    double MI = __builtin_nan("");
+    if (2.0 * HX - JE < mi_resum_threshold<Acc>()) {
         Comp<Acc> m;
         const Acc invTa = (Acc)invT;
         src.for_each(g, [&](uint32_t lo, uint32_t hi, uint32_t c) {
@@ -427,12 +479,23 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
         });
         MI = g.sum(comp_value(m));
     }
+    if constexpr (Grp::kBatched) {
+        if (rk < kSumSlots) {
+            const uint64_t bits = rk < 6 ? (uint64_t)slot : __builtin_bit_cast(uint64_t, slot);
+            reinterpret_cast<uint64_t *>(out)[rk] = bits;
+        }
+    } else if (r0 == 0) {
+        out->T = tot_u[0]; out->S1 = tot_u[1]; out->S2 = tot_u[2]; out->Sm1 = tot_u[3]; out->S11 = tot_u[4];
+        out->sumP2 = tot_u[5];
+        out->plp = tot_d[0]; out->rlr = tot_d[1]; out->slp = tot_d[2]; out->plps = tot_d[3];
+        out->hom1 = tot_d[4]; out->hom2 = tot_d[5]; out->idmn = tot_d[6]; out->idn = tot_d[7]; out->iv = tot_d[8];
+        out->spare = 0.0;
+    }
     if (r0 == 0) {
-        out->T = T; out->S1 = S1t; out->S2 = S2t; out->Sm1 = Sm1t; out->S11 = S11t;
-        out->sumP2 = sumP2t; out->maxP = maxPt;
-        out->HX = HX; out->DENT = DENT; out->HOM1 = HOM1; out->HOM2 = HOM2; out->IDMN = IDMN;
-        out->IDN = IDN; out->IV = IV; out->SENT = SENT; out->JE = JE; out->CSHADE = CSHADE;
-        out->CPROM = CPROM; out->MI = MI;
+        out->maxP = maxPt;
+        out->CSHADE = CSHADE;
+        out->CPROM = CPROM;
+        out->MI = MI;
     }
     // Clean up for the next direction / item.
     g.sync();

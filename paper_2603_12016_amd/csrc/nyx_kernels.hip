@@ -5,9 +5,10 @@
 //   k_scan             ROI discovery: per-label count, min, max, bbox
 //   k_compact_*        ROI table in (image, label) order + size-sorted work queue
 //   k_bin_image        per-voxel grey levels (explicit binning output)
-//   k_batch            persistent work-stealing accumulation + features
-//   k_split_features   features of ROIs whose matrices were merged in global memory
-//   k_rows             feature rows (direction blocks + mean) from a scratch table
+//   k_batch            persistent work-stealing accumulation + reduced sums per direction
+//   k_wave             the same for small ROIs, one wavefront per ROI
+//   k_split_features   reduced sums of ROIs whose matrices were merged in global memory
+//   k_features         the 30 features per direction and their mean, one lane per direction
 //   k_coo_*            sorted COO export / import of the co-occurrence counts
 //
 // The method: the paper's regional texture extraction (one row per unique
@@ -225,8 +226,8 @@ __global__ __launch_bounds__(1024) void k_compact_count(StepArgs a) {
 // class, so the persistent kernel can drain the largest work first.
 __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi_lo, uint32_t roi_hi) {
     __shared__ uint32_t wc[16], wpre[16], s_part[16], s_prefix;
-    __shared__ uint32_t cls_cnt[kClasses], cls_base[kClasses];
-    if (threadIdx.x < kClasses) cls_cnt[threadIdx.x] = 0u;
+    __shared__ uint32_t cls_cnt[2 * kClasses], cls_base[2 * kClasses];   // work-group queue, then wave queue
+    if (threadIdx.x < 2 * kClasses) cls_cnt[threadIdx.x] = 0u;
     uint32_t part = 0;
     for (uint32_t b = threadIdx.x; b < blockIdx.x; b += 1024u) part += a.counters[C_BLOCKS + b];
     part = wave_sum(part);
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
     bool live = p;
     if (live && row >= a.roi_cap) { atomicOr(&a.counters[C_ERR], (uint32_t)E_ROI_CAP); live = false; }
     RoiDesc rd;
-    bool enq = false;
+    bool enq = false, wave_item = false;
     uint32_t cls = 0u, nt = 1u, local = 0u;
     if (live) {
     const int im = find_image_entry(a.imgs, a.n_images, e);
@@ -283,8 +284,9 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
     a.rois[row] = rd;
     if (take && (rd.gslot != kNone || nt == 1u)) {
         enq = true;
+        wave_item = a.wave_ok && rd.gslot == kNone && nt == 1u && rd.n <= a.wave_max_vox;
         cls = size_class((rd.n + nt - 1u) / nt);
-        local = atomicAdd(&cls_cnt[cls], nt);
+        local = atomicAdd(&cls_cnt[(wave_item ? kClasses : 0) + cls], nt);
     }
     if (a.o_label) a.o_label[row] = label;
     if (a.o_image) a.o_image[row] = (uint32_t)im;
@@ -297,15 +299,18 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
     }
     }  // live
     __syncthreads();
-    if (threadIdx.x < kClasses && cls_cnt[threadIdx.x])
-        cls_base[threadIdx.x] = atomicAdd(&a.counters[C_CLASS + threadIdx.x], cls_cnt[threadIdx.x]);
+    if (threadIdx.x < 2 * kClasses && cls_cnt[threadIdx.x]) {
+        const uint32_t slot = threadIdx.x < kClasses ? C_CLASS + threadIdx.x : C_CLASS_W + threadIdx.x - kClasses;
+        cls_base[threadIdx.x] = atomicAdd(&a.counters[slot], cls_cnt[threadIdx.x]);
+    }
     __syncthreads();
     if (enq) {
-        uint32_t pos = cls_base[cls] + local;
+        uint32_t pos = cls_base[(wave_item ? kClasses : 0) + cls] + local;
+        uint2 *bk = wave_item ? a.buckets_w : a.buckets;
         if (pos + nt > a.bucket_cap) {
             atomicOr(&a.counters[C_ERR], (uint32_t)E_ITEM_CAP);
         } else {
-            for (uint32_t t = 0; t < nt; ++t) a.buckets[cls * a.bucket_cap + pos + t] = make_uint2(row, t);
+            for (uint32_t t = 0; t < nt; ++t) bk[cls * a.bucket_cap + pos + t] = make_uint2(row, t);
         }
     }
 }
@@ -433,14 +438,14 @@ __device__ __forceinline__ void add_pair(const StepArgs &a, uint8_t *smem, uint3
 
 // Accumulate the pairs owned by the voxels of bbox rows [ra, rb) for the
 // directions [d0, d1): each voxel owns the pair (v, v + d) of each offset.
-template <int MODE>
-__device__ void accumulate_rows(const StepArgs &a, uint8_t *smem, const RoiDesc &rd, const ItemCtx &c,
-                                uint32_t ra, uint32_t rb, uint32_t ca, uint32_t cb, int d0, int d1) {
+template <class Add>
+__device__ void accumulate_rows(const StepArgs &a, const RoiDesc &rd, const ItemCtx &c, uint32_t ra, uint32_t rb,
+                                uint32_t ca, uint32_t cb, int d0, int d1, uint32_t t0, uint32_t ts, Add &&add) {
     const uint32_t W = cb - ca, H = (uint32_t)(rd.y1 - rd.y0 + 1);
     const double rcpW = 1.0 / (double)W, rcpH = 1.0 / (double)H;
     const uint32_t nv = (rb - ra) * W;
     const int64_t plane = (int64_t)c.ny * c.nx;
-    for (uint32_t f = threadIdx.x; f < nv; f += blockDim.x) {
+    for (uint32_t f = t0; f < nv; f += ts) {
         uint32_t q = udiv_exact(f, W, rcpW);
         int32_t x = rd.x0 + (int32_t)ca + (int32_t)(f - q * W);
         uint32_t rr = ra + q;
@@ -456,31 +461,8 @@ __device__ void accumulate_rows(const StepArgs &a, uint8_t *smem, const RoiDesc 
             if (wz < 0 || wz >= c.nz || wy < 0 || wy >= c.ny || wx < 0 || wx >= c.nx) continue;
             int64_t w = v + (int64_t)dz * plane + (int64_t)dy * c.nx + dx;
             if (c.L[w] != c.label) continue;
-            add_pair<MODE>(a, smem, (uint32_t)(d - d0), bv, c.level((uint32_t)w));
+            add((uint32_t)(d - d0), bv, c.level((uint32_t)w));
         }
-    }
-}
-
-template <class OutT>
-__device__ void write_row(const StepArgs &a, uint32_t row, const double *feat, int K) {
-    if (row >= a.table_rows) {
-        if (threadIdx.x == 0) atomicOr(&a.counters[C_ERR], (uint32_t)E_TABLE_CAP);
-        return;
-    }
-    OutT *out = reinterpret_cast<OutT *>(a.table) + (uint64_t)row * (K + 1) * kNumFeat;
-    for (int t = threadIdx.x; t < (K + 1) * kNumFeat; t += blockDim.x) {
-        int blk = t / kNumFeat, f = t - blk * kNumFeat;
-        double v;
-        if (blk < K) {
-            v = feat[blk * kNumFeat + f];
-        } else {
-            double s = 0.0;
-            int n = 0;
-            for (int k = 0; k < K; ++k)
-                if (!isnan(feat[k * kNumFeat])) { s += feat[k * kNumFeat + f]; ++n; }
-            v = n ? s / (double)n : __builtin_nan("");
-        }
-        out[t] = (OutT)v;
     }
 }
 
@@ -497,11 +479,10 @@ __device__ __forceinline__ uint32_t lane_next(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false);  // wave_shl1
 }
 
-template <int MODE>
-__device__ void accumulate_sweep2d(const StepArgs &a, uint8_t *smem, const RoiDesc &rd, const ItemCtx &c,
-                                   uint32_t ra, uint32_t rb, uint32_t ca, uint32_t cb, int h, int v, int d45,
-                                   int d135) {
-    const int nw = (int)(blockDim.x / kWave), w = (int)(threadIdx.x / kWave), ln = lane();
+template <class Add>
+__device__ void accumulate_sweep2d(const RoiDesc &rd, const ItemCtx &c, uint32_t ra, uint32_t rb, uint32_t ca,
+                                   uint32_t cb, int h, int v, int d45, int d135, int w, int nw, Add &&add) {
+    const int ln = lane();
     const uint32_t Wt = cb - ca;
     const uint32_t nstrip = (Wt + 62u) / 63u;
     const uint32_t nrows = rb - ra;
@@ -543,11 +524,11 @@ __device__ void accumulate_sweep2d(const StepArgs &a, uint8_t *smem, const RoiDe
                 const uint32_t cur = lev[j];
                 const uint32_t cur_r = lane_next(cur), prev_r = lane_next(prev);
                 if (owner && cur) {
-                    if (h >= 0 && cur_r) add_pair<MODE>(a, smem, (uint32_t)h, cur, cur_r);
-                    if (v >= 0 && prev) add_pair<MODE>(a, smem, (uint32_t)v, cur, prev);
-                    if (d45 >= 0 && prev_r) add_pair<MODE>(a, smem, (uint32_t)d45, cur, prev_r);
+                    if (h >= 0 && cur_r) add((uint32_t)h, cur, cur_r);
+                    if (v >= 0 && prev) add((uint32_t)v, cur, prev);
+                    if (d45 >= 0 && prev_r) add((uint32_t)d45, cur, prev_r);
                 }
-                if (owner && prev && cur_r && d135 >= 0) add_pair<MODE>(a, smem, (uint32_t)d135, prev, cur_r);
+                if (owner && prev && cur_r && d135 >= 0) add((uint32_t)d135, prev, cur_r);
                 prev = cur;
             }
         }
@@ -558,8 +539,7 @@ __device__ void accumulate_sweep2d(const StepArgs &a, uint8_t *smem, const RoiDe
 // atomic merge into the ROI's global matrix (tile of a split ROI).
 template <class Acc, class Src>
 __device__ __forceinline__ void dir_or_flush(const StepArgs &a, const WaveGrp &g, const Src &s, bool split,
-                                             const RoiDesc &rd, int d, uint32_t *MARG, uint32_t ng,
-                                             DirSums *SUMS) {
+                                             const RoiDesc &rd, uint32_t roi, int d, uint32_t *MARG, uint32_t ng) {
     if (split) {
         uint64_t *G = a.G + ((uint64_t)rd.gslot * a.K + d) * (uint64_t)ng * ng;
         s.for_each(g, [&](uint32_t lo, uint32_t hi, uint32_t c) {
@@ -569,7 +549,7 @@ __device__ __forceinline__ void dir_or_flush(const StepArgs &a, const WaveGrp &g
         s.clear(g);
         g.sync();
     } else {
-        dir_sums<Acc, double>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng, SUMS + d);
+        dir_sums<Acc, double>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng, a.dsums + (uint64_t)roi * a.K + d);
     }
 }
 
@@ -580,8 +560,6 @@ __global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) 
     const LdsLayout &Ly = a.lds;
     uint32_t *LCNT = reinterpret_cast<uint32_t *>(smem + Ly.lcnt_off);
     uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off);
-    double *FEAT = reinterpret_cast<double *>(smem + Ly.feat_off);
-    DirSums *SUMS = reinterpret_cast<DirSums *>(smem + Ly.sums_off);
     uint2 *BUF = reinterpret_cast<uint2 *>(smem + Ly.buf_off);
     uint32_t *MISC = reinterpret_cast<uint32_t *>(smem + Ly.misc_off);
     const int nw = (int)(blockDim.x / kWave), w = (int)(threadIdx.x / kWave);
@@ -666,11 +644,12 @@ __global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) 
             for (int d0 = 0, pass = 0; d0 < K; d0 += (int)Ly.kp, ++pass) {
                 const int d1 = min(K, d0 + (int)Ly.kp);
                 if (ra < rb && ca < cb) {
+                    auto add = [&](uint32_t dl, uint32_t la, uint32_t lb) { add_pair<MODE>(a, smem, dl, la, lb); };
                     if (a.sweep_ok && pass < kMaxSweepPasses)
-                        accumulate_sweep2d<MODE>(a, smem, rd, c, ra, rb, ca, cb, a.sweep[pass][0], a.sweep[pass][1],
-                                                 a.sweep[pass][2], a.sweep[pass][3]);
+                        accumulate_sweep2d(rd, c, ra, rb, ca, cb, a.sweep[pass][0], a.sweep[pass][1], a.sweep[pass][2],
+                                           a.sweep[pass][3], w, nw, add);
                     else
-                        accumulate_rows<MODE>(a, smem, rd, c, ra, rb, ca, cb, d0, d1);
+                        accumulate_rows(a, rd, c, ra, rb, ca, cb, d0, d1, threadIdx.x, blockDim.x, add);
                 }
                 __syncthreads();
                 for (int dl = w; dl < d1 - d0; dl += nw) {
@@ -680,28 +659,121 @@ __global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) 
                     WaveGrp g;
                     if (MODE == 2 || MODE == 3) {
                         SrcTriScan<MODE == 3> s{Ud, (ng * (ng + 1u)) >> 1, BUF + (uint32_t)w * kWave * kScanPerLane};
-                        dir_or_flush<Acc>(a, g, s, split, rd, d0 + dl, MARG, ng, SUMS);
+                        dir_or_flush<Acc>(a, g, s, split, rd, roi, d0 + dl, MARG, ng);
                     } else if (MODE == 0) {
                         SrcDenseList s{lst, n, Ud};
-                        dir_or_flush<Acc>(a, g, s, split, rd, d0 + dl, MARG, ng, SUMS);
+                        dir_or_flush<Acc>(a, g, s, split, rd, roi, d0 + dl, MARG, ng);
                     } else {
                         SrcHashList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.hkey_off),
                                       reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off)};
-                        dir_or_flush<Acc>(a, g, s, split, rd, d0 + dl, MARG, ng, SUMS);
+                        dir_or_flush<Acc>(a, g, s, split, rd, roi, d0 + dl, MARG, ng);
                     }
                     if (lane() == 0) LCNT[dl] = 0u;
                 }
                 __syncthreads();
             }
-            if (!split) {
-                // the 30 features of every direction at once: one lane per direction
-                for (int d = threadIdx.x; d < K; d += blockDim.x) finalize_dir(SUMS[d], FEAT + d * kNumFeat);
-                __syncthreads();
-                write_row<OutT>(a, roi, FEAT, K);
-                __syncthreads();
-            }
         }
         __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ wave per ROI
+// Small unsplit ROIs of images with at most four offsets: one wavefront owns a
+// whole ROI.  It accumulates the ROI's voxels alone (row sweep or gather) into
+// its own LDS triangles, then each 16-lane DPP row reduces one direction, so
+// the four directions share every reduction instruction and no work-group
+// barrier is ever needed.  One wavefront per work-group.
+template <bool PACKED, class OutT>
+__global__ __launch_bounds__(64) void k_wave(StepArgs a, uint32_t direct_roi) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    typedef typename std::conditional<sizeof(OutT) == 8, double, float>::type Acc;
+    const LdsLayout &Ly = a.wlds;
+    uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off);
+    uint2 *BUF = reinterpret_cast<uint2 *>(smem + Ly.buf_off);
+    uint32_t *MARG = reinterpret_cast<uint32_t *>(smem + Ly.marg_off);
+    uint32_t *MISC = reinterpret_cast<uint32_t *>(smem + Ly.misc_off);
+    const int K = a.K;
+    const uint32_t ng = (uint32_t)a.ng, tri = (ng * (ng + 1u)) >> 1;
+    const uint32_t ln = (uint32_t)lane();
+    const WaveGrp wg;
+    for (uint32_t i = ln; i < (uint32_t)K * Ly.tri_pad; i += kWave) U[i] = 0u;
+    for (uint32_t i = ln; i < (uint32_t)K * 4u * ng; i += kWave) MARG[i] = 0u;
+    if (ln == 0 && direct_roi == kNone) {
+        uint32_t acc = 0;
+        for (int cl = kClasses - 1; cl >= 0; --cl) {
+            uint32_t cnt = min(a.counters[C_CLASS_W + cl], a.bucket_cap);
+            MISC[64 + cl] = acc;
+            MISC[96 + cl] = cnt;
+            acc += cnt;
+        }
+        MISC[63] = acc;
+    }
+    wg.sync();
+    for (uint32_t iter = 0;; ++iter) {
+        if (ln == 0) {
+            uint32_t n = 0;
+            if (direct_roi != kNone) {
+                if (iter == 0 && direct_roi < a.roi_cap) { MISC[0] = direct_roi; MISC[1] = 0u; n = 1; }
+            } else {
+                const uint32_t total = MISC[63];
+                uint32_t t = atomicAdd(&a.counters[C_TICKET_W], (uint32_t)kTicketChunk);
+                for (uint32_t q = 0; q < (uint32_t)kTicketChunk && t + q < total; ++q) {
+                    uint32_t tt = t + q;
+                    int cl = kClasses - 1;
+                    while (cl > 0 && tt >= MISC[64 + cl] + MISC[96 + cl]) --cl;
+                    uint2 it = a.buckets_w[(uint32_t)cl * a.bucket_cap + (tt - MISC[64 + cl])];
+                    MISC[2 * n] = it.x;
+                    MISC[2 * n + 1] = it.y;
+                    ++n;
+                }
+            }
+            MISC[32] = n;
+        }
+        wg.sync();
+        const uint32_t n_items = __builtin_amdgcn_readfirstlane(MISC[32]);
+        if (n_items == 0u) break;
+        for (uint32_t q = 0; q < n_items; ++q) {
+            const uint32_t roi = __builtin_amdgcn_readfirstlane(MISC[2 * q]);
+            if (roi >= a.roi_cap) continue;
+            const RoiDesc rd = a.rois[roi];
+            if (rd.n_tiles != 1u || rd.gslot != kNone || rd.image >= (uint32_t)a.n_images) continue;
+            const ImgDesc im = a.imgs[rd.image];
+            if (rd.x0 < 0 || rd.y0 < 0 || rd.z0 < 0 || rd.x1 >= im.nx || rd.y1 >= im.ny || rd.z1 >= im.nz ||
+                rd.x0 > rd.x1 || rd.y0 > rd.y1 || rd.z0 > rd.z1)
+                continue;
+            ItemCtx c;
+            c.I = im.I; c.L = im.L; c.B = im.B;
+            c.nx = im.nx; c.ny = im.ny; c.nz = im.nz;
+            c.label = rd.label; c.vmin = rd.vmin; c.D = rd.vmax - rd.vmin; c.ng = ng;
+            c.rcpD = c.D ? 1.0f / (float)c.D : 0.0f;
+            c.err = &a.counters[C_ERR];
+            const uint32_t W = (uint32_t)(rd.x1 - rd.x0 + 1);
+            auto add = [&](uint32_t dl, uint32_t la, uint32_t lb) {
+                const uint32_t lo = (la < lb ? la : lb) - 1u, hi = (la < lb ? lb : la) - 1u;
+                const uint32_t i = tri_idx(lo, hi);
+                uint32_t *Ud = U + dl * Ly.tri_pad;
+                if (PACKED)
+                    __hip_atomic_fetch_add(&Ud[i >> 1], 1u << ((i & 1u) << 4), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                else
+                    __hip_atomic_fetch_add(&Ud[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            };
+            if (a.wsweep_ok)
+                accumulate_sweep2d(rd, c, 0u, rd.rows, 0u, W, a.wsweep[0], a.wsweep[1], a.wsweep[2], a.wsweep[3], 0,
+                                   1, add);
+            else
+                accumulate_rows(a, rd, c, 0u, rd.rows, 0u, W, 0, K, ln, (uint32_t)kWave, add);
+            wg.sync();
+            // one 16-lane row per direction
+            const RowGrp g;
+            const int r = g.row();
+            if (r < K) {
+                SrcTriScan<PACKED> s{U + (uint32_t)r * Ly.tri_pad, tri, BUF + (uint32_t)r * 16u * kScanPerLane};
+                uint32_t *M = MARG + (uint32_t)r * 4u * ng;
+                dir_sums<Acc, double>(g, s, M, M + ng, M + 3u * ng - 1u, ng, a.dsums + (uint64_t)roi * K + r);
+            }
+            wg.sync();
+        }
     }
 }
 
@@ -716,35 +788,56 @@ __global__ __launch_bounds__(512) void k_split_features(StepArgs a) {
     const uint32_t slot = blockIdx.x / K;
     const int d = (int)(blockIdx.x % K);
     if (slot >= min(a.counters[C_NSPLIT], a.g_cap)) return;
+    const uint32_t roi = a.split_roi[slot];
+    if (roi >= a.roi_cap) return;
     uint32_t *R = reinterpret_cast<uint32_t *>(smem);
     uint64_t *scratch = reinterpret_cast<uint64_t *>(smem + 16u * ng);
-    double *out = reinterpret_cast<double *>(smem + 16u * ng + 16 * 8);
     for (uint32_t i = threadIdx.x; i < 4u * ng; i += blockDim.x) R[i] = 0u;
     __syncthreads();
     BlockGrp g{scratch};
     SrcSquare s{a.G + ((uint64_t)slot * K + d) * (uint64_t)ng * ng, ng};
-    DirSums *sums = reinterpret_cast<DirSums *>(out + kNumFeat);
-    dir_sums<Acc, uint64_t>(g, s, R, R + ng, R + 3u * ng - 1u, ng, sums);
-    __syncthreads();
-    if (threadIdx.x == 0) finalize_dir(*sums, out);
-    __syncthreads();
-    for (int f = threadIdx.x; f < kNumFeat; f += blockDim.x)
-        a.split_feat[((uint64_t)slot * K + d) * kNumFeat + f] = out[f];
+    dir_sums<Acc, uint64_t>(g, s, R, R + ng, R + 3u * ng - 1u, ng, a.dsums + (uint64_t)roi * K + d);
 }
 
-// Feature rows from per-direction scratch features: row map[s] <- scratch[s].
+// ------------------------------------------------------------------ features
+// The 30 features of every (ROI, direction) from its reduced sums, one lane
+// each, then the ROI's table row: the K direction blocks and their mean over
+// the non-empty directions, written as one contiguous run of the table.
+// Rows [0, n) with n = min(*n_ptr, n_cap) (n_cap without n_ptr).
 template <class OutT>
-__global__ __launch_bounds__(256) void k_rows(StepArgs a, const double *scratch, const uint32_t *map,
-                                              const uint32_t *count_ptr, uint32_t count_cap) {
+__global__ __launch_bounds__(128) void k_features(StepArgs a, const DirSums *ds, uint32_t n_cap,
+                                                  const uint32_t *n_ptr) {
     extern __shared__ __align__(16) uint8_t smem[];
-    uint32_t n = count_ptr ? min(*count_ptr, count_cap) : count_cap;
-    uint32_t s = blockIdx.x;
-    if (s >= n) return;
-    const int K = a.K;
     double *feat = reinterpret_cast<double *>(smem);
-    for (int t = threadIdx.x; t < K * kNumFeat; t += blockDim.x) feat[t] = scratch[(uint64_t)s * K * kNumFeat + t];
+    const uint32_t K = (uint32_t)a.K;
+    const uint32_t rpb = blockDim.x / K;
+    const uint32_t n = n_ptr ? min(*n_ptr, n_cap) : n_cap;
+    const uint32_t row0 = blockIdx.x * rpb;
+    if (row0 >= n) return;
+    uint32_t rows = min(rpb, n - row0);
+    if (threadIdx.x < rows * K) finalize_dir(ds[(uint64_t)row0 * K + threadIdx.x], feat + threadIdx.x * kNumFeat);
     __syncthreads();
-    write_row<OutT>(a, map ? map[s] : s, feat, K);
+    if (row0 + rows > a.table_rows) {
+        if (threadIdx.x == 0) atomicOr(&a.counters[C_ERR], (uint32_t)E_TABLE_CAP);
+        rows = a.table_rows > row0 ? a.table_rows - row0 : 0u;
+    }
+    const uint32_t per = (K + 1u) * kNumFeat;
+    OutT *out = reinterpret_cast<OutT *>(a.table) + (uint64_t)row0 * per;
+    for (uint32_t i = threadIdx.x; i < rows * per; i += blockDim.x) {
+        const uint32_t rr = i / per, q = i - rr * per, blk = q / kNumFeat, f = q - blk * kNumFeat;
+        const double *fr = feat + rr * K * kNumFeat;
+        double v;
+        if (blk < K) {
+            v = fr[blk * kNumFeat + f];
+        } else {
+            double s = 0.0;
+            int m = 0;
+            for (uint32_t k = 0; k < K; ++k)
+                if (!isnan(fr[k * kNumFeat])) { s += fr[k * kNumFeat + f]; ++m; }
+            v = m ? s / (double)m : __builtin_nan("");
+        }
+        out[i] = (OutT)v;
+    }
 }
 
 // ------------------------------------------------------------------ COO
@@ -815,7 +908,7 @@ __global__ void k_coo_segments_k(const uint64_t *keys, uint64_t nnz, uint32_t n_
 // One work-group per (roi, direction) of a COO list.
 template <class Acc>
 __global__ __launch_bounds__(512) void k_coo_features(StepArgs a, const uint64_t *keys, const uint64_t *vals,
-                                                      const uint64_t *seg, uint32_t n_rois, double *scratch) {
+                                                      const uint64_t *seg, uint32_t n_rois, DirSums *sums) {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t ng = (uint32_t)a.ng;
     const int K = a.K;
@@ -823,18 +916,12 @@ __global__ __launch_bounds__(512) void k_coo_features(StepArgs a, const uint64_t
     if (s >= n_rois * (uint32_t)K) return;
     uint32_t *R = reinterpret_cast<uint32_t *>(smem);
     uint64_t *scr = reinterpret_cast<uint64_t *>(smem + 16u * ng);
-    double *out = reinterpret_cast<double *>(smem + 16u * ng + 16 * 8);
     for (uint32_t i = threadIdx.x; i < 4u * ng; i += blockDim.x) R[i] = 0u;
     __syncthreads();
     BlockGrp g{scr};
     SrcCoo src{keys + seg[s], vals + seg[s], (uint32_t)(seg[s + 1] - seg[s]),
                ((uint64_t)(s / K) << 38) | ((uint64_t)(s % K) << 32), ng, &a.counters[C_ERR]};
-    DirSums *sums = reinterpret_cast<DirSums *>(out + kNumFeat);
-    dir_sums<Acc, uint64_t>(g, src, R, R + ng, R + 3u * ng - 1u, ng, sums);
-    __syncthreads();
-    if (threadIdx.x == 0) finalize_dir(*sums, out);
-    __syncthreads();
-    for (int f = threadIdx.x; f < kNumFeat; f += blockDim.x) scratch[(uint64_t)s * kNumFeat + f] = out[f];
+    dir_sums<Acc, uint64_t>(g, src, R, R + ng, R + 3u * ng - 1u, ng, sums + s);
 }
 
 // ================================================================== launchers
@@ -936,6 +1023,41 @@ hipError_t launch_batch(const StepArgs &a, uint32_t grid, uint32_t block, uint32
     }
 }
 
+static const void *wave_kernel(int packed, int fp64) {
+    if (packed) return fp64 ? reinterpret_cast<const void *>(&k_wave<true, double>) : reinterpret_cast<const void *>(&k_wave<true, float>);
+    return fp64 ? reinterpret_cast<const void *>(&k_wave<false, double>) : reinterpret_cast<const void *>(&k_wave<false, float>);
+}
+
+hipError_t launch_wave(const StepArgs &a, uint32_t grid, uint32_t direct_roi, hipStream_t st) {
+    if (!a.wave_ok) return hipSuccess;
+    static bool attr_done = false;
+    if (!attr_done) {
+        for (int p = 0; p < 2; ++p)
+            for (int f = 0; f < 2; ++f) {
+                hipError_t e = hipFuncSetAttribute(wave_kernel(p, f), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                if (e != hipSuccess) return e;
+            }
+        attr_done = true;
+    }
+    const bool packed = a.wlds.mode == 3;
+    if (packed) {
+        if (a.fp64) hipLaunchKernelGGL((k_wave<true, double>), dim3(grid), dim3(64), a.wlds.bytes, st, a, direct_roi);
+        else hipLaunchKernelGGL((k_wave<true, float>), dim3(grid), dim3(64), a.wlds.bytes, st, a, direct_roi);
+    } else {
+        if (a.fp64) hipLaunchKernelGGL((k_wave<false, double>), dim3(grid), dim3(64), a.wlds.bytes, st, a, direct_roi);
+        else hipLaunchKernelGGL((k_wave<false, float>), dim3(grid), dim3(64), a.wlds.bytes, st, a, direct_roi);
+    }
+    NYX_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t wave_occupancy(int packed, int fp64, uint32_t lds_bytes, int *blocks_per_cu) {
+    const void *f = wave_kernel(packed, fp64);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, 64, (size_t)lds_bytes);
+}
+
 static const void *batch_kernel(int mode, int fp64) {
     switch (mode) {
         case 0: return fp64 ? reinterpret_cast<const void *>(&k_batch<0, double>) : reinterpret_cast<const void *>(&k_batch<0, float>);
@@ -984,18 +1106,22 @@ hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st) {
         hipError_t e = set_feature_kernel_attrs();
         if (e != hipSuccess) return e;
     }
-    uint32_t lds = 16u * a.ng + 16 * 8 + kNumFeat * 8 + (uint32_t)sizeof(DirSums);
+    uint32_t lds = 16u * a.ng + 16 * 8;
     uint32_t grid = a.g_cap * a.K;
     if (a.fp64) hipLaunchKernelGGL(k_split_features<double>, dim3(grid), dim3(512), lds, st, a);
     else hipLaunchKernelGGL(k_split_features<float>, dim3(grid), dim3(512), lds, st, a);
     NYX_CHECK_LAUNCH();
-    uint32_t lds2 = a.K * kNumFeat * 8;
-    if (a.fp64)
-        hipLaunchKernelGGL(k_rows<double>, dim3(a.g_cap), dim3(256), lds2, st, a, a.split_feat, a.split_roi,
-                           a.counters + C_NSPLIT, a.g_cap);
-    else
-        hipLaunchKernelGGL(k_rows<float>, dim3(a.g_cap), dim3(256), lds2, st, a, a.split_feat, a.split_roi,
-                           a.counters + C_NSPLIT, a.g_cap);
+    return hipSuccess;
+}
+
+hipError_t launch_features(const StepArgs &a, const DirSums *ds, uint32_t n_cap, const uint32_t *n_ptr,
+                           hipStream_t st) {
+    if (n_cap == 0) return hipSuccess;
+    const uint32_t block = 128u, rpb = block / (uint32_t)a.K;
+    const uint32_t grid = (n_cap + rpb - 1u) / rpb;
+    const uint32_t lds = rpb * (uint32_t)a.K * kNumFeat * 8u;
+    if (a.fp64) hipLaunchKernelGGL(k_features<double>, dim3(grid), dim3(block), lds, st, a, ds, n_cap, n_ptr);
+    else hipLaunchKernelGGL(k_features<float>, dim3(grid), dim3(block), lds, st, a, ds, n_cap, n_ptr);
     NYX_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1016,7 +1142,7 @@ hipError_t launch_coo_emit(const StepArgs &a, uint32_t n_slots, const uint64_t *
 }
 
 hipError_t launch_coo_features(const StepArgs &a, const uint64_t *keys, const uint64_t *vals, uint64_t nnz,
-                               uint32_t n_rois, uint64_t *seg, double *scratch, hipStream_t st) {
+                               uint32_t n_rois, uint64_t *seg, DirSums *sums, hipStream_t st) {
     uint32_t n_seg = n_rois * (uint32_t)a.K;
     hipLaunchKernelGGL(k_coo_segments_k, dim3((n_seg + 1 + 255) / 256), dim3(256), 0, st, keys, nnz, n_rois,
                        a.K, seg);
@@ -1026,21 +1152,13 @@ hipError_t launch_coo_features(const StepArgs &a, const uint64_t *keys, const ui
         hipError_t e = set_feature_kernel_attrs();
         if (e != hipSuccess) return e;
     }
-    uint32_t lds = 16u * a.ng + 16 * 8 + kNumFeat * 8 + (uint32_t)sizeof(DirSums);
+    uint32_t lds = 16u * a.ng + 16 * 8;
     if (a.fp64)
-        hipLaunchKernelGGL(k_coo_features<double>, dim3(n_seg), dim3(512), lds, st, a, keys, vals, seg, n_rois, scratch);
+        hipLaunchKernelGGL(k_coo_features<double>, dim3(n_seg), dim3(512), lds, st, a, keys, vals, seg, n_rois, sums);
     else
-        hipLaunchKernelGGL(k_coo_features<float>, dim3(n_seg), dim3(512), lds, st, a, keys, vals, seg, n_rois, scratch);
+        hipLaunchKernelGGL(k_coo_features<float>, dim3(n_seg), dim3(512), lds, st, a, keys, vals, seg, n_rois, sums);
     NYX_CHECK_LAUNCH();
-    uint32_t lds2 = a.K * kNumFeat * 8;
-    if (a.fp64)
-        hipLaunchKernelGGL(k_rows<double>, dim3(n_rois), dim3(256), lds2, st, a, scratch, (const uint32_t *)nullptr,
-                           (const uint32_t *)nullptr, n_rois);
-    else
-        hipLaunchKernelGGL(k_rows<float>, dim3(n_rois), dim3(256), lds2, st, a, scratch, (const uint32_t *)nullptr,
-                           (const uint32_t *)nullptr, n_rois);
-    NYX_CHECK_LAUNCH();
-    return hipSuccess;
+    return launch_features(a, sums, n_rois, nullptr, st);
 }
 
 }  // namespace nyx

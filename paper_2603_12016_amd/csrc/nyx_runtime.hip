@@ -68,8 +68,6 @@ struct DevBuf {
     template <class T> T *as() const { return reinterpret_cast<T *>(p); }
 };
 
-// Size of the device DirSums record (8 u64 + 12 double).
-struct DirSumsHost { uint64_t u[8]; double d[12]; };
 
 uint32_t next_pow2(uint32_t v) {
     uint32_t p = 1;
@@ -89,7 +87,7 @@ struct nyx_ctx {
 // All device state of one discovery/step over a batch of images.
 struct Work {
     std::vector<ImgDesc> h_imgs;
-    DevBuf imgs, tab[10], counters, rois, buckets, G, split_feat, split_roi, vox_base;
+    DevBuf imgs, tab[10], counters, rois, buckets, buckets_w, G, dsums, split_roi, vox_base;
     uint32_t tab_total = 0, n_blocks = 0, n_counters = 0, total_chunks = 0;
     uint32_t n_rois = 0;
     uint64_t total_vox = 0;
@@ -103,8 +101,9 @@ struct nyx_plan {
     std::vector<nyx_image> imgs;
     int K = 0, ng = 0;
     nyx_precision prec = NYX_FP32;
-    uint32_t grid = 0, block = 256;
+    uint32_t grid = 0, block = 256, wgrid = 0;
     std::vector<uint32_t> roi_tiles;   // per-ROI tile count for the per-ROI path
+    std::vector<uint8_t> roi_wave;     // per-ROI: processed by the wavefront kernel
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     void *graph_table = nullptr;
@@ -112,7 +111,7 @@ struct nyx_plan {
     std::string desc;
     int64_t workspace_bytes = 0;
     float tuned_ms = 0.f;
-    struct Cfg { int mode; uint32_t kp, block, split_vox, tile_vox, list_cap, hash_cap; int force_split; };
+    struct Cfg { int mode; uint32_t kp, block, split_vox, tile_vox, list_cap, hash_cap; int force_split; uint32_t wave_vox; };
     Cfg cfg{};
 };
 
@@ -288,6 +287,7 @@ struct Config {
     uint32_t split_vox = 0, tile_vox = 0;
     uint32_t list_cap = 0, hash_cap = 0;
     int force_split = 0;
+    uint32_t wave_vox = 0;   // unsplit ROIs up to this many voxels go to the wavefront kernel (0: none)
 };
 
 const char *mode_name(int m) {
@@ -330,12 +330,40 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K) {
     L.lcnt_off = take(c.kp * 4u);
     L.buf_off = take((c.mode == 2 || c.mode == 3) ? L.nwaves * kWave * 4u * 8u : 0u);
     L.marg_off = take(std::min(L.nwaves, c.kp) * 4u * ng * 4u);   // one set per wave that reduces a direction
-    L.feat_off = take((uint32_t)K * kNumFeat * 8u);
-    L.sums_off = take((uint32_t)K * (uint32_t)sizeof(DirSumsHost));
     L.misc_off = take(128u * 4u);
     L.bytes = off;
     return L;
 }
+
+// LDS of one wavefront of the wave-per-ROI kernel: K packed triangles, the
+// compaction buffer of four 16-lane rows, K marginal sets, sums, features,
+// misc.  The triangles hold 16-bit counters, so items stay below 65536 voxels.
+LdsLayout make_wave_layout(uint32_t ng, int K) {
+    LdsLayout L;
+    memset(&L, 0, sizeof L);
+    L.mode = 3;
+    L.kp = (uint32_t)K;
+    L.nwaves = 1;
+    L.tri_pad = u_words(3, ng);
+    uint32_t off = 0;
+    auto take = [&](uint32_t bytes) {
+        uint32_t o = off;
+        off += (bytes + 15u) & ~15u;
+        return o;
+    };
+    L.u_off = take((uint32_t)K * L.tri_pad * 4u);
+    L.buf_off = take(kWave * 4u * 8u);
+    L.marg_off = take((uint32_t)K * 4u * ng * 4u);
+    L.misc_off = take(128u * 4u);
+    L.bytes = off;
+    return L;
+}
+
+// Wavefront path: at most four offsets and a per-wave LDS footprint that
+// leaves room for several waves per CU.
+constexpr uint32_t kWaveLdsMax = 40u * 1024u;
+constexpr uint32_t kWaveVoxDefault = 4096u;
+bool wave_feasible(uint32_t ng, int K) { return K <= 4 && make_wave_layout(ng, K).bytes <= kWaveLdsMax; }
 
 // Largest voxel count any work item can hold under a split rule.
 uint64_t max_item_vox(const std::vector<RoiDesc> &rois, uint32_t split_vox, uint32_t tile_vox) {
@@ -360,10 +388,9 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
     const uint32_t nw = block / kWave;
     const uint32_t tri = ng * (ng + 1u) / 2u;
     // LDS besides triangles / hash / lists: marginals for up to nw directions
-    // at a time, feature staging, sums, misc, alignment slack
+    // at a time, misc, alignment slack
     auto fixed_for = [&](uint32_t kp) {
-        return (std::min(nw, kp) * 4u * ng * 4u + 15u) / 16u * 16u + (uint32_t)K * kNumFeat * 8u +
-               (uint32_t)K * (uint32_t)sizeof(DirSumsHost) + 128u * 4u + 64u * 4u + 64;
+        return (std::min(nw, kp) * 4u * ng * 4u + 15u) / 16u * 16u + 128u * 4u + 64u * 4u + 64;
     };
     const uint32_t fixed = fixed_for(1u);
     uint64_t total_vox = 0;
@@ -468,27 +495,32 @@ void count_items(const std::vector<RoiDesc> &rois, const Config &c, uint64_t *it
 
 // Row-sweep eligibility: all images 2D and every offset of each pass one of
 // the four distance-1 in-plane classes, each class at most once per pass.
-void set_sweep(StepArgs &a, const std::vector<ImgDesc> &imgs, const nyx_offset *off, int K, uint32_t kp) {
-    a.sweep_ok = 0;
-    memset(a.sweep, -1, sizeof a.sweep);
+bool sweep_table(const std::vector<ImgDesc> &imgs, const nyx_offset *off, int K, uint32_t kp,
+                 int8_t (*sweep)[4], int max_passes) {
+    memset(sweep, -1, sizeof(int8_t[4]) * max_passes);
     for (const ImgDesc &d : imgs)
-        if (d.nz != 1) return;
+        if (d.nz != 1) return false;
     int pass = 0;
     for (int d0 = 0; d0 < K; d0 += (int)kp, ++pass) {
-        if (pass >= kMaxSweepPasses) return;
+        if (pass >= max_passes) return false;
         for (int d = d0; d < std::min(K, d0 + (int)kp); ++d) {
             const nyx_offset &o = off[d];
-            if (o.dz != 0 || abs(o.dy) > 1 || abs(o.dx) > 1) return;
+            if (o.dz != 0 || abs(o.dy) > 1 || abs(o.dx) > 1) return false;
             int cls;
             if (o.dy == 0) cls = 0;
             else if (o.dx == 0) cls = 1;
             else if (o.dy * o.dx < 0) cls = 2;   // (-1, +1) or (+1, -1)
             else cls = 3;                        // (-1, -1) or (+1, +1)
-            if (a.sweep[pass][cls] >= 0) return; // the same class twice in a pass
-            a.sweep[pass][cls] = (int8_t)(d - d0);
+            if (sweep[pass][cls] >= 0) return false; // the same class twice in a pass
+            sweep[pass][cls] = (int8_t)(d - d0);
         }
     }
-    a.sweep_ok = 1;
+    return true;
+}
+
+void set_sweep(StepArgs &a, const std::vector<ImgDesc> &imgs, const nyx_offset *off, int K, uint32_t kp) {
+    a.sweep_ok = sweep_table(imgs, off, K, kp, a.sweep, kMaxSweepPasses) ? 1 : 0;
+    a.wsweep_ok = K <= 4 && sweep_table(imgs, off, K, (uint32_t)K, &a.wsweep, 1) ? 1 : 0;
 }
 
 // Allocates queue, split matrices and fills the step arguments.
@@ -502,8 +534,9 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     if (items >= (1ull << 31)) return fail(ctx, NYX_ERR_UNSUPPORTED, "too many work items");
     uint32_t bucket_cap = (uint32_t)std::max<uint64_t>(items, 1u);
     uint64_t g_bytes = (uint64_t)n_split * K * (uint64_t)ng * ng * 8u;
-    uint64_t need = (uint64_t)kClasses * bucket_cap * 8u + g_bytes + (uint64_t)n_split * K * kNumFeat * 8u +
-                    n_split * 4u;
+    const bool wave = cfg.wave_vox > 0u && wave_feasible(ng, K);
+    const uint64_t sums_bytes = (uint64_t)std::max<uint32_t>(w.n_rois, 1u) * K * sizeof(DirSums);
+    uint64_t need = (uint64_t)kClasses * bucket_cap * 8u * (wave ? 2u : 1u) + g_bytes + sums_bytes + n_split * 4u;
     for (auto &b : w.tab) need += b.bytes;
     need += w.rois.bytes + w.counters.bytes;
     if (ws_bytes) *ws_bytes = (int64_t)need;
@@ -511,14 +544,16 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
         return fail(ctx, NYX_ERR_OOM, "workspace needs %llu bytes, cap is %lld", (unsigned long long)need,
                     (long long)cap_bytes);
     HIPC(ctx, w.buckets.alloc((size_t)kClasses * bucket_cap * sizeof(uint2)));
+    if (wave) HIPC(ctx, w.buckets_w.alloc((size_t)kClasses * bucket_cap * sizeof(uint2)));
+    else w.buckets_w.release();
     HIPC(ctx, w.G.alloc(std::max<uint64_t>(g_bytes, 16u)));
-    HIPC(ctx, w.split_feat.alloc((size_t)std::max<uint32_t>(n_split, 1u) * K * kNumFeat * 8u));
+    HIPC(ctx, w.dsums.alloc(sums_bytes));
     HIPC(ctx, w.split_roi.alloc((size_t)std::max<uint32_t>(n_split, 1u) * 4u));
     a.buckets = w.buckets.as<uint2>();
     a.bucket_cap = bucket_cap;
     a.G = w.G.as<uint64_t>();
     a.g_cap = n_split;
-    a.split_feat = w.split_feat.as<double>();
+    a.dsums = w.dsums.as<DirSums>();
     a.split_roi = w.split_roi.as<uint32_t>();
     for (int k = 0; k < K; ++k) {
         a.off[k][0] = off[k].dz;
@@ -534,6 +569,10 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     a.fp64 = fp64;
     a.lds = make_layout(cfg, ng, K);
     set_sweep(a, w.h_imgs, off, K, cfg.kp);
+    a.wave_ok = wave ? 1 : 0;
+    a.wave_max_vox = wave ? std::min<uint32_t>(cfg.wave_vox, 65535u) : 0u;
+    a.buckets_w = wave ? w.buckets_w.as<uint2>() : nullptr;
+    a.wlds = wave ? make_wave_layout(ng, K) : LdsLayout{};
     return NYX_OK;
 }
 
@@ -560,11 +599,15 @@ nyx_status enqueue_step(nyx_plan *p, hipStream_t st, bool per_roi) {
     HIPC(ctx, launch_zero_split(a, st));
     if (!per_roi) {
         HIPC(ctx, launch_batch(a, p->grid, p->block, kNone, st));
+        if (a.wave_ok) HIPC(ctx, launch_wave(a, p->wgrid, kNone, st));
     } else {
-        for (uint32_t r = 0; r < p->w.n_rois; ++r)
-            HIPC(ctx, launch_batch(a, p->roi_tiles[r], p->block, r, st));
+        for (uint32_t r = 0; r < p->w.n_rois; ++r) {
+            if (p->roi_wave[r]) HIPC(ctx, launch_wave(a, 1u, r, st));
+            else HIPC(ctx, launch_batch(a, p->roi_tiles[r], p->block, r, st));
+        }
     }
     HIPC(ctx, launch_split_finalize(a, st));
+    HIPC(ctx, launch_features(a, a.dsums, a.roi_cap, a.counters + C_NROIS, st));
     return NYX_OK;
 }
 
@@ -584,13 +627,16 @@ nyx_status check_counters(nyx_ctx *ctx, Work &w, hipStream_t st) {
     return NYX_OK;
 }
 
-std::string describe(const Config &c, const nyx_plan *p, uint64_t items, uint32_t n_split) {
+std::string describe(const Config &c, const nyx_plan *p, uint64_t items, uint32_t n_split, uint32_t wave_rois,
+                     uint64_t wave_voxels) {
     char buf[512];
     snprintf(buf, sizeof buf,
              "mode=%s kp=%u block=%u grid=%u lds=%uB split_vox=%u tile_vox=%u list_cap=%u hash_cap=%u "
-             "rois=%u items=%llu split_rois=%u ng=%d K=%d",
+             "wave_vox=%u wave_grid=%u wave_lds=%uB wave_rois=%u wave_roi_voxels=%llu rois=%u items=%llu "
+             "split_rois=%u ng=%d K=%d",
              mode_name(c.mode), c.kp, c.block, p->grid, p->w.args.lds.bytes, c.split_vox, c.tile_vox,
-             c.list_cap, c.hash_cap, p->w.n_rois, (unsigned long long)items, n_split, p->ng, p->K);
+             c.list_cap, c.hash_cap, p->w.args.wave_max_vox, p->wgrid, p->w.args.wlds.bytes, wave_rois,
+             (unsigned long long)wave_voxels, p->w.n_rois, (unsigned long long)items, n_split, p->ng, p->K);
     return buf;
 }
 
@@ -607,9 +653,26 @@ nyx_status configure(nyx_plan *p, const Config &cfg, const nyx_extract_opts *opt
     uint64_t items;
     uint32_t n_split;
     count_items(p->w.h_rois, cfg, &items, &n_split, &p->roi_tiles);
+    // the wavefront kernel's share, decided as the compaction decides it
+    const StepArgs &a = p->w.args;
+    p->roi_wave.assign(p->w.n_rois, 0);
+    uint32_t wave_rois = 0;
+    uint64_t wave_voxels = 0;
+    p->wgrid = 0;
+    if (a.wave_ok) {
+        for (uint32_t r = 0; r < p->w.n_rois; ++r)
+            if (p->roi_tiles[r] == 1u && !cfg.force_split && p->w.h_rois[r].n <= a.wave_max_vox) {
+                p->roi_wave[r] = 1;
+                ++wave_rois;
+                wave_voxels += p->w.h_rois[r].n;
+            }
+        int wocc = 0;
+        HIPC(ctx, wave_occupancy(1, p->prec == NYX_FP64, a.wlds.bytes, &wocc));
+        p->wgrid = (uint32_t)ctx->n_cu * (uint32_t)std::max(wocc, 1);
+    }
     p->cfg = nyx_plan::Cfg{cfg.mode, cfg.kp, cfg.block, cfg.split_vox, cfg.tile_vox, cfg.list_cap, cfg.hash_cap,
-                           cfg.force_split};
-    p->desc = describe(cfg, p, items, n_split);
+                           cfg.force_split, a.wave_max_vox};
+    p->desc = describe(cfg, p, items, n_split, wave_rois, wave_voxels);
     return NYX_OK;
 }
 
@@ -813,7 +876,7 @@ nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, nyx_precision p
     if (n_rois == 0) return NYX_OK;
     DevBuf seg, scratch, counters;
     HIPC(ctx, seg.alloc(((size_t)n_rois * K + 1) * 8u));
-    HIPC(ctx, scratch.alloc((size_t)n_rois * K * kNumFeat * 8u));
+    HIPC(ctx, scratch.alloc((size_t)n_rois * K * sizeof(DirSums)));
     HIPC(ctx, counters.alloc(256));
     HIPC(ctx, hipMemsetAsync(counters.p, 0, 256, st));
     StepArgs a;
@@ -824,7 +887,7 @@ nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, nyx_precision p
     a.table = table;
     a.table_rows = (uint32_t)std::min<int64_t>(table_capacity_rows, 0xFFFFFFFFll);
     a.counters = counters.as<uint32_t>();
-    HIPC(ctx, launch_coo_features(a, glcm->key, glcm->count, nnz, n_rois, seg.as<uint64_t>(), scratch.as<double>(), st));
+    HIPC(ctx, launch_coo_features(a, glcm->key, glcm->count, nnz, n_rois, seg.as<uint64_t>(), scratch.as<DirSums>(), st));
     uint32_t herr = 0;
     HIPC(ctx, hipMemcpyAsync(&herr, counters.as<uint32_t>() + C_ERR, 4, hipMemcpyDeviceToHost, st));
     HIPC(ctx, hipStreamSynchronize(st));
@@ -858,13 +921,30 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
     std::vector<Config> cands = candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256);
     if (cands.empty())
         return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%d with %d offsets", p->ng, p->K);
+    // wavefront-per-ROI share: automatic, off, or a given ROI size limit
+    const bool wave_ok = wave_feasible((uint32_t)p->ng, p->K);
+    const uint32_t wave_vox = !wave_ok || opts->wave_max_vox == 0 ? 0u
+                              : opts->wave_max_vox < 0 ? kWaveVoxDefault
+                                                       : (uint32_t)std::min(opts->wave_max_vox, 65535);
+    for (Config &c : cands) c.wave_vox = wave_vox;
+    if (opts->autotune && opts->wave_max_vox < 0 && wave_ok) {
+        // also time other wavefront shares of each candidate
+        const size_t n0 = cands.size();
+        for (size_t i = 0; i < n0; ++i)
+            for (uint32_t v : {0u, 1024u, 16384u}) {
+                Config c = cands[i];
+                c.wave_vox = v;
+                cands.push_back(c);
+            }
+    }
     Config cfg = default_config(cands, p->w, (uint32_t)p->ng);
     if (opts->accum_mode >= 0) {
         bool found = false;
         for (const Config &c : cands)
             if (c.mode == opts->accum_mode) { cfg = c; found = true; break; }
         if (!found) return fail(ctx, NYX_ERR_UNSUPPORTED, "accumulation mode %d does not fit this workload", opts->accum_mode);
-    } else if (opts->autotune && cands.size() > 1) {
+    }
+    if (opts->autotune && cands.size() > 1) {
         // time one step of every candidate and keep the fastest
         DevBuf tmp;
         size_t row_bytes = (size_t)(p->K + 1) * kNumFeat * (p->prec == NYX_FP64 ? 8u : 4u);
@@ -874,6 +954,7 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
         HIPC(ctx, hipEventCreate(&e1));
         float best = 1e30f;
         for (const Config &c : cands) {
+            if (opts->accum_mode >= 0 && c.mode != opts->accum_mode) continue;
             if ((s = configure(p.get(), c, opts)) != NYX_OK) continue;
             set_outputs(ctx, p->w.args, nullptr, tmp.p, p->w.n_rois);
             if ((s = enqueue_step(p.get(), st, false)) != NYX_OK) break;
@@ -883,7 +964,8 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
             HIPC(ctx, hipEventSynchronize(e1));
             float ms = 0.f;
             HIPC(ctx, hipEventElapsedTime(&ms, e0, e1));
-            if (log_level() > 0) fprintf(stderr, "[nyx] autotune %s kp=%u: %.3f ms\n", mode_name(c.mode), c.kp, ms);
+            if (log_level() > 0)
+                fprintf(stderr, "[nyx] autotune %s kp=%u wave_vox=%u: %.3f ms\n", mode_name(c.mode), c.kp, c.wave_vox, ms);
             if (ms < best) { best = ms; cfg = c; }
         }
         (void)hipEventDestroy(e0);
@@ -971,9 +1053,13 @@ nyx_status nyx_plan_profile(nyx_plan *p, void *table, float *ms_host, nyx_stream
     if (he == hipSuccess) he = hipEventRecord(ev[4], st);
     if (he == hipSuccess) he = launch_batch(a, p->grid, p->block, kNone, st);
     if (he == hipSuccess) he = hipEventRecord(ev[5], st);
-    if (he == hipSuccess) he = launch_split_finalize(a, st);
+    if (he == hipSuccess && a.wave_ok) he = launch_wave(a, p->wgrid, kNone, st);
     if (he == hipSuccess) he = hipEventRecord(ev[6], st);
-    if (he == hipSuccess) he = hipEventSynchronize(ev[6]);
+    if (he == hipSuccess) he = launch_split_finalize(a, st);
+    if (he == hipSuccess) he = hipEventRecord(ev[7], st);
+    if (he == hipSuccess) he = launch_features(a, a.dsums, a.roi_cap, a.counters + C_NROIS, st);
+    if (he == hipSuccess) he = hipEventRecord(ev[8], st);
+    if (he == hipSuccess) he = hipEventSynchronize(ev[8]);
     if (he == hipSuccess)
         for (int i = 0; i < NYX_PHASE_COUNT; ++i) {
             he = hipEventElapsedTime(&ms_host[i], ev[i], ev[i + 1]);

@@ -22,8 +22,10 @@ enum Counter : int {
     C_TICKET = 2,   // work-stealing ticket of the persistent kernel
     C_ERR = 3,      // error bits (see ErrBit)
     C_NITEMS = 4,   // work items enqueued
-    C_CLASS = 8,    // kClasses counters: items per size class
-    C_BLOCKS = 64,  // per-block ROI counts of the compaction (variable length)
+    C_TICKET_W = 5, // work-stealing ticket of the wave-per-ROI kernel
+    C_CLASS = 8,    // kClasses counters: work-group items per size class
+    C_CLASS_W = 64, // kClasses counters: wave-per-ROI items per size class
+    C_BLOCKS = 128, // per-block ROI counts of the compaction (variable length)
 };
 
 enum ErrBit : uint32_t {
@@ -67,6 +69,26 @@ struct RoiDesc {
 };
 
 // Layout of the persistent kernel's dynamic LDS (byte offsets).
+// Reduced sums of one (ROI, direction), written by the accumulation kernels
+// and turned into the 30 features by the feature kernel.  Slots 0..15 come
+// out of one batched reduction (slot i = 8-byte word i); the integer sums are
+// exact.  The floating sums are raw (unnormalised) totals over the counts:
+//   plp  = sum over both orders of P log2 P     rlr  = sum_i R(i) log2 R(i)
+//   slp  = sum_k Sm(k) log2 Sm(k)               plps = sum_k Sp(k) log2 Sp(k)
+//   hom1, hom2, idmn, idn, iv = sum_k Sm(k) w(k) with the feature's weight w
+// with R, Sp, Sm the row, sum and difference marginals of P (Sm over |i-j|
+// counting both orders).  CSHADE / CPROM are already normalised; MI is the
+// cell-by-cell re-summed mutual information (bits) or NaN when the closed
+// form 2 HX - JE is accurate enough.
+struct DirSums {
+    uint64_t T, S1, S2, Sm1, S11, sumP2;                              // slots 0-5
+    double plp, rlr, slp, plps, hom1, hom2, idmn, idn, iv, spare;     // slots 6-15
+    uint64_t maxP;
+    double CSHADE, CPROM, MI;
+};
+static_assert(sizeof(DirSums) == 160, "DirSums layout");
+constexpr int kSumSlots = 16;
+
 struct LdsLayout {
     uint32_t mode;        // 0 = dense triangles, 1 = hash table
     uint32_t kp;          // directions accumulated per pass
@@ -90,7 +112,7 @@ struct StepArgs {
     uint32_t bucket_cap;
     uint64_t *G;                // split-ROI dense matrices: g_cap slots of K * ng * ng
     uint32_t g_cap;
-    double *split_feat;         // g_cap * K * 30 per-direction features of split ROIs
+    DirSums *dsums;             // roi_cap * K reduced sums, row-major by ROI
     uint32_t *split_roi;        // g_cap: ROI row of each split slot
     int32_t off[kMaxOffsets][3];
     int32_t K;
@@ -112,6 +134,14 @@ struct StepArgs {
     // of the H, V, D45, D135 neighbour classes (-1 = absent)
     int32_t sweep_ok;
     int8_t sweep[kMaxSweepPasses][4];
+    // wave-per-ROI path: unsplit ROIs up to wave_max_vox voxels (wave_ok = 1)
+    // go to their own queue, one wavefront per ROI, LDS layout wlds per wave
+    int32_t wave_ok;
+    uint32_t wave_max_vox;
+    uint2 *buckets_w;
+    LdsLayout wlds;
+    int32_t wsweep_ok;   // row sweep with all K directions in one pass
+    int8_t wsweep[4];
 };
 
 // Deterministic split rule shared by host planning and device enqueueing:

@@ -51,7 +51,7 @@ class nyx_glcm(ctypes.Structure):
 class nyx_extract_opts(ctypes.Structure):
     _fields_ = [("n_bins", c_int32), ("offsets_host", POINTER(nyx_offset)), ("n_offsets", c_int32),
                 ("symmetric", c_int32), ("precision", c_int), ("autotune", c_int32), ("accum_mode", c_int32),
-                ("workspace_cap_bytes", c_int64)]
+                ("wave_max_vox", c_int32), ("workspace_cap_bytes", c_int64)]
 
 
 _lib = None
@@ -62,7 +62,7 @@ EXPORTS = ("nyx_create", "nyx_destroy", "nyx_last_error", "nyx_status_string", "
            "nyx_extract_batch", "nyx_plan_create", "nyx_plan_execute", "nyx_plan_execute_per_roi",
            "nyx_plan_check", "nyx_plan_describe", "nyx_plan_destroy", "nyx_plan_profile")
 
-PHASES = ("reset", "scan", "compact", "zero", "batch", "finalize")
+PHASES = ("reset", "scan", "compact", "zero", "batch", "wave", "split", "features")
 
 
 def lib():
@@ -158,10 +158,11 @@ def _offsets(offsets):
 MODES = {"auto": -1, "dense-list": 0, "hash": 1, "dense-scan": 2, "dense16-scan": 3}
 
 
-def _opts(n_bins, offsets, precision, autotune=0, workspace_cap=0, mode="auto"):
+def _opts(n_bins, offsets, precision, autotune=0, workspace_cap=0, mode="auto", wave=-1):
     arr, K = _offsets(offsets)
     o = nyx_extract_opts(int(n_bins), ctypes.cast(arr, POINTER(nyx_offset)), K, 1, int(precision),
-                         int(autotune), int(MODES[mode] if isinstance(mode, str) else mode), int(workspace_cap))
+                         int(autotune), int(MODES[mode] if isinstance(mode, str) else mode), int(wave),
+                         int(workspace_cap))
     return o, arr
 
 
@@ -305,10 +306,10 @@ def nyx_glcm_features(ctx: Ctx, glcm: Glcm, precision: int = NYX_FP32, stream=No
 
 
 def nyx_extract_batch(ctx: Ctx, images, n_bins: int, offsets, precision: int = NYX_FP32, stream=None,
-                      capacity=None):
+                      capacity=None, mode="auto", wave: int = -1):
     """One-shot extraction: returns (RoiTable, table (n, K + 1, 30))."""
     imgs = _images(images)
-    opts, keep = _opts(n_bins, offsets, precision)
+    opts, keep = _opts(n_bins, offsets, precision, mode=mode, wave=wave)
     dev = _dev()
     if capacity is None:
         probe = RoiTable(0, dev)
@@ -328,9 +329,11 @@ def nyx_extract_batch(ctx: Ctx, images, n_bins: int, offsets, precision: int = N
 
 
 def nyx_plan_create(ctx: Ctx, images, n_bins: int, offsets, precision: int = NYX_FP32, autotune: bool = False,
-                    workspace_cap: int = 0, mode="auto") -> Plan:
+                    workspace_cap: int = 0, mode="auto", wave: int = -1) -> Plan:
+    """mode: accumulation mode name (MODES) or -1/auto; wave: -1 automatic, 0 off, n > 0 the largest
+    ROI (voxels) processed one wavefront per ROI."""
     imgs = _images(images)
-    opts, keep = _opts(n_bins, offsets, precision, int(autotune), workspace_cap, mode)
+    opts, keep = _opts(n_bins, offsets, precision, int(autotune), workspace_cap, mode, wave)
     h = c_void_p()
     n = c_int64(0)
     _check(lib().nyx_plan_create(ctx.handle, imgs, len(images), byref(opts), byref(h), byref(n)), ctx)

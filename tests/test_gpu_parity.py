@@ -217,28 +217,35 @@ def test_features_from_oracle_coo(env, workloads, oracle_mod, name, prec):
 
 
 # ------------------------------------------------------------------ batched path
-MODE_CASES = [(n, m) for n in SMALL for m in ("auto", "dense-list", "dense-scan", "dense16-scan")
-              if not (n == "c5_small" and m != "auto")] + [("c3_small", "autotune")]
+# (workload, accumulation mode, wavefront share: -1 automatic, 0 none, 65535 every unsplit ROI)
+MODE_CASES = ([(n, m, 0) for n in SMALL for m in ("auto", "dense-list", "dense-scan", "dense16-scan")
+               if not (n == "c5_small" and m != "auto")] +
+              [(n, "auto", v) for n in SMALL for v in (-1, 65535)] + [("c3_small", "autotune", -1)])
 
 
-@pytest.mark.parametrize("name,mode", MODE_CASES)
-def test_plan_batched_and_per_roi(env, workloads, oracle_mod, name, mode):
+@pytest.mark.parametrize("name,mode,wave", MODE_CASES)
+def test_plan_batched_and_per_roi(env, workloads, oracle_mod, name, mode, wave):
     import torch
     nyx, ctx, dev = env
     w = workloads(name)
-    say(f"case {name} plan_execute + per_roi, mode {mode}")
+    say(f"case {name} plan_execute + per_roi, mode {mode}, wave {wave}")
     imgs = device_images(w, dev)
     offs = _offsets(nyx, w)
     if mode == "autotune":
         plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32, autotune=True)
     else:
         try:
-            plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32, mode=mode)
+            plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32, mode=mode, wave=wave)
         except nyx.NyxError as e:
             if e.status == nyx.NYX_ERR_UNSUPPORTED:
                 pytest.skip(f"{mode} does not fit LDS for {name}")
             raise
-    say("  plan:", nyx.nyx_plan_describe(plan))
+    desc = nyx.nyx_plan_describe(plan)
+    say("  plan:", desc)
+    if wave == 0:
+        assert "wave_rois=0 " in desc
+    elif wave == 65535 and "wave_lds=0B" not in desc:
+        assert "wave_rois=0 " not in desc
     t1 = nyx.new_table(plan, len(offs))
     t2 = nyx.new_table(plan, len(offs))
     for _ in range(3):  # repeated graph replays with eager work in between
@@ -254,18 +261,18 @@ def test_plan_batched_and_per_roi(env, workloads, oracle_mod, name, mode):
     _check_features(got, want, Ps, TOL_FP32, f"{name} batched")
     _check_features(t2.cpu().numpy()[:plan.n_rois], want, Ps, TOL_FP32, f"{name} per-roi")
     assert np.allclose(first.cpu().numpy(), got, rtol=1e-6, atol=1e-6, equal_nan=True)
-    if "scan" in nyx.nyx_plan_describe(plan):
+    if "scan" in desc:
         # ordered nonzero lists: replays and the per-ROI path agree bit for bit
         assert np.array_equal(first.cpu().numpy(), got, equal_nan=True)
         assert np.array_equal(t2.cpu().numpy()[:plan.n_rois], got, equal_nan=True)
 
 
 # ------------------------------------------------------------------ edge cases
-def _run_extract(nyx, ctx, dev, I, L, ng, offs, prec=1):
+def _run_extract(nyx, ctx, dev, I, L, ng, offs, prec=1, wave=-1):
     import torch
     from types import SimpleNamespace
     w = SimpleNamespace(intensity=I[None], labels=L[None], n_images=1)
-    return nyx.nyx_extract_batch(ctx, device_images(w, dev), ng, offs, prec)
+    return nyx.nyx_extract_batch(ctx, device_images(w, dev), ng, offs, prec, wave=wave)
 
 
 def _oracle_direct(oracle, I, L, ng, offs):
@@ -288,19 +295,20 @@ EDGE = {
 }
 
 
+@pytest.mark.parametrize("wave", [-1, 0])
 @pytest.mark.parametrize("case", sorted(EDGE))
 @pytest.mark.parametrize("ng", [2, 8, 30, 100])
-def test_edge_cases(env, oracle_mod, case, ng):
+def test_edge_cases(env, oracle_mod, case, ng, wave):
     import torch
     nyx, ctx, dev = env
-    rng = np.random.default_rng(abs(hash(case)) % 1000 + ng)
+    rng = np.random.default_rng(sum(map(ord, case)) % 1000 + ng)
     I, L = EDGE[case](rng)
     I = np.ascontiguousarray(I, np.uint16)
     L = np.ascontiguousarray(L, np.uint32)
     dims = 3 if I.shape[0] > 1 else 2
     offs = nyx.nyx_offsets_default(dims, 1)
-    say(f"case edge {case} ng={ng}")
-    rois, table = _run_extract(nyx, ctx, dev, I, L, ng, offs)
+    say(f"case edge {case} ng={ng} wave={wave}")
+    rois, table = _run_extract(nyx, ctx, dev, I, L, ng, offs, wave=wave)
     torch.cuda.synchronize()
     want, Ps = _oracle_direct(oracle_mod, I, L, ng, offs)
     assert rois.n_rois == len(Ps)
