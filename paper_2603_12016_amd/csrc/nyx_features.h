@@ -142,36 +142,61 @@ __device__ __forceinline__ void tri_decode(uint32_t i, uint32_t &lo, uint32_t &h
     lo = i - ((h * (h + 1u)) >> 1);
 }
 
-// LDS triangle of one direction, scanned in index order; the nonzero cells of
-// each chunk are compacted into `buf` (room for size() * kScanPerLane
-// entries) before fn runs, so lanes stay busy on sparse triangles and the
-// order of every floating sum is fixed.
-constexpr int kScanPerLane = 4;
-
+// LDS triangle of one direction, scanned in index order.  Each lane reads
+// one 16-byte run of the triangle per chunk (8 packed 16-bit or 4 32-bit
+// counters), decodes the run's cell indices incrementally, and writes its
+// nonzero cells, packed as (lo | hi << 16, count), into `buf` at its prefix
+// offset within the group (room for size() * kScanCells entries, kScanCells
+// from the shared types header).  fn then
+// runs over the compacted entries, so lanes stay busy on sparse triangles and
+// the order of every floating sum is fixed.  U must be 16-byte aligned and
+// padded with zero words to a multiple of 4 words.
 template <bool PACKED>
 struct SrcTriScan {
     uint32_t *U;
     uint32_t tri;
     uint2 *buf;
+    static constexpr uint32_t kPerRead = PACKED ? 8u : 4u;   // cells per 16-byte read
     template <class Grp, class Fn>
     __device__ __forceinline__ void for_each(const Grp &g, Fn &&fn) const {
         const uint32_t gs = (uint32_t)g.size(), r = (uint32_t)g.rank();
-        for (uint32_t base = 0; base < tri; base += gs * kScanPerLane) {
-            uint32_t cnt = 0;
+        const uint32_t words = PACKED ? (tri + 1u) >> 1 : tri;
+        for (uint32_t wbase = 0; wbase < words; wbase += 4u * gs) {
+            const uint32_t w0 = wbase + 4u * r;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (w0 < words) v = *reinterpret_cast<const uint4 *>(U + w0);
+            uint32_t c[kPerRead];
+            if (PACKED) {
+                c[0] = v.x & 0xFFFFu; c[1] = v.x >> 16; c[2] = v.y & 0xFFFFu; c[3] = v.y >> 16;
+                c[4] = v.z & 0xFFFFu; c[5] = v.z >> 16; c[6] = v.w & 0xFFFFu; c[7] = v.w >> 16;
+            } else {
+                c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+            }
+            const uint32_t i0 = PACKED ? 2u * w0 : w0;   // first cell of the run
+            uint32_t n = 0;
 #pragma unroll
-            for (int v = 0; v < kScanPerLane; ++v) {
-                const uint32_t i = base + (uint32_t)v * gs + r;
-                const uint32_t c = i < tri ? tri_count<PACKED>(U, i) : 0u;
-                const uint64_t m = g.ballot(c != 0u);
-                if (c) buf[cnt + (uint32_t)__popcll(m & g.below())] = make_uint2(i, c);
-                cnt += (uint32_t)__popcll(m);
+            for (uint32_t k = 0; k < kPerRead; ++k) n += (c[k] != 0u && i0 + k < tri) ? 1u : 0u;
+            // exclusive prefix of n over the group and its total, bit by bit
+            uint32_t pos = 0, cnt = 0;
+#pragma unroll
+            for (uint32_t b = 0; b < 4u; ++b) {
+                const uint64_t m = g.ballot(((n >> b) & 1u) != 0u);
+                pos += (uint32_t)__popcll(m & g.below()) << b;
+                cnt += (uint32_t)__popcll(m) << b;
+            }
+            if (n) {
+                uint32_t lo, hi;
+                tri_decode(i0 < tri ? i0 : 0u, lo, hi);
+#pragma unroll
+                for (uint32_t k = 0; k < kPerRead; ++k) {
+                    if (c[k] != 0u && i0 + k < tri) buf[pos++] = make_uint2(lo | (hi << 16), c[k]);
+                    if (++lo > hi) { ++hi; lo = 0u; }
+                }
             }
             g.sync();
             for (uint32_t e = r; e < cnt; e += gs) {
                 const uint2 q = buf[e];
-                uint32_t lo, hi;
-                tri_decode(q.x, lo, hi);
-                fn(lo, hi, q.y);
+                fn(q.x & 0xFFFFu, q.x >> 16, q.y);
             }
             g.sync();
         }
@@ -179,7 +204,8 @@ struct SrcTriScan {
     template <class Grp>
     __device__ __forceinline__ void clear(const Grp &g) const {
         const uint32_t words = PACKED ? (tri + 1u) >> 1 : tri;
-        for (uint32_t i = (uint32_t)g.rank(); i < words; i += (uint32_t)g.size()) U[i] = 0u;
+        for (uint32_t w = 4u * (uint32_t)g.rank(); w < words; w += 4u * (uint32_t)g.size())
+            *reinterpret_cast<uint4 *>(U + w) = make_uint4(0u, 0u, 0u, 0u);
     }
 };
 
@@ -437,7 +463,7 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
         g.sync();
         return 0;
     }
-    const double Td = (double)T, invT = 1.0 / Td, lgT = log2(Td);
+    const double Td = (double)T, invT = 1.0 / Td;
     // Cluster shade / prominence: moments of the sum marginal about 2 mu.
     const double two_mu = 2.0 * (double)S1t * invT;
     double cs = 0.0, cp = 0.0;
@@ -461,10 +487,12 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
         CPROM = g.sum(cp);
     }
     // Mutual information HX + HY - HXY (HX = HY for a symmetric matrix),
-    // re-summed cell by cell where the closed form loses digits.
-    const double JE = lgT - plp_t * invT, HX = lgT - rlr_t * invT;
+    // re-summed cell by cell where the closed form 2 HX - JE loses digits.
+    // Only the decision is taken here (log2 T in single precision is ample
+    // for it); the closed form itself is evaluated with the features.
+    const double mi_cf = (double)__log2f((float)Td) - (2.0 * rlr_t - plp_t) * invT;
     double MI = __builtin_nan("");
-    if (2.0 * HX - JE < mi_resum_threshold<Acc>()) {
+    if (mi_cf < mi_resum_threshold<Acc>()) {
         Comp<Acc> m;
         const Acc invTa = (Acc)invT;
         src.for_each(g, [&](uint32_t lo, uint32_t hi, uint32_t c) {

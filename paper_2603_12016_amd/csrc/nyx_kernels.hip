@@ -553,8 +553,10 @@ __device__ __forceinline__ void dir_or_flush(const StepArgs &a, const WaveGrp &g
     }
 }
 
+// Single precision: at most 128 VGPRs, four waves per SIMD (the compiler would
+// otherwise take ~150 and leave three); double precision keeps its registers.
 template <int MODE, class OutT>
-__global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) {
+__global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 4 : 1)) void k_batch(StepArgs a, uint32_t direct_roi) {
     extern __shared__ __align__(16) uint8_t smem[];
     typedef typename std::conditional<sizeof(OutT) == 8, double, float>::type Acc;
     const LdsLayout &Ly = a.lds;
@@ -620,10 +622,13 @@ __global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) 
             MISC[32] = n;
         }
         __syncthreads();
-        const uint32_t n_items = MISC[32];
+        // queue entries are work-group uniform: keep them (and every descriptor
+        // field loaded through them) in scalar registers
+        const uint32_t n_items = __builtin_amdgcn_readfirstlane(MISC[32]);
         if (n_items == 0u) break;
         for (uint32_t q = 0; q < n_items; ++q) {
-            const uint32_t roi = MISC[2 * q], tile = MISC[2 * q + 1];
+            const uint32_t roi = __builtin_amdgcn_readfirstlane(MISC[2 * q]);
+            const uint32_t tile = __builtin_amdgcn_readfirstlane(MISC[2 * q + 1]);
             // an entry that does not name a valid ROI tile is skipped
             if (roi >= a.roi_cap) continue;
             const RoiDesc rd = a.rois[roi];
@@ -658,7 +663,7 @@ __global__ __launch_bounds__(256) void k_batch(StepArgs a, uint32_t direct_roi) 
                     const uint32_t *lst = LST + dl * Ly.list_cap;
                     WaveGrp g;
                     if (MODE == 2 || MODE == 3) {
-                        SrcTriScan<MODE == 3> s{Ud, (ng * (ng + 1u)) >> 1, BUF + (uint32_t)w * kWave * kScanPerLane};
+                        SrcTriScan<MODE == 3> s{Ud, (ng * (ng + 1u)) >> 1, BUF + (uint32_t)w * kWave * SrcTriScan<MODE == 3>::kPerRead};
                         dir_or_flush<Acc>(a, g, s, split, rd, roi, d0 + dl, MARG, ng);
                     } else if (MODE == 0) {
                         SrcDenseList s{lst, n, Ud};
@@ -768,7 +773,7 @@ __global__ __launch_bounds__(64) void k_wave(StepArgs a, uint32_t direct_roi) {
             const RowGrp g;
             const int r = g.row();
             if (r < K) {
-                SrcTriScan<PACKED> s{U + (uint32_t)r * Ly.tri_pad, tri, BUF + (uint32_t)r * 16u * kScanPerLane};
+                SrcTriScan<PACKED> s{U + (uint32_t)r * Ly.tri_pad, tri, BUF + (uint32_t)r * 16u * kScanCells};
                 uint32_t *M = MARG + (uint32_t)r * 4u * ng;
                 dir_sums<Acc, double>(g, s, M, M + ng, M + 3u * ng - 1u, ng, a.dsums + (uint64_t)roi * K + r);
             }

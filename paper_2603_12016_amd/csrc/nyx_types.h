@@ -88,6 +88,9 @@ struct DirSums {
 };
 static_assert(sizeof(DirSums) == 160, "DirSums layout");
 constexpr int kSumSlots = 16;
+// Compaction buffer entries per lane of an ordered triangle scan (one
+// 16-byte read: at most 8 packed counters).
+constexpr int kScanCells = 8;
 
 struct LdsLayout {
     uint32_t mode;        // 0 = dense triangles, 1 = hash table
