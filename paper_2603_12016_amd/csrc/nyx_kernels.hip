@@ -367,16 +367,18 @@ struct ItemCtx {
     uint32_t label, vmin, D, ng;
     float rcpD;
     uint32_t *err;
-    // Level of voxel v; a caller-supplied bin image is clamped to [1, ng]
-    // (flagging the error) so no LDS address can leave its triangle.
-    __device__ __forceinline__ uint32_t level(uint32_t v) const {
-        if (!B) return fbn_level(I[v], vmin, D, rcpD, ng);
-        uint32_t b = B[v];
-        if (b == 0u || b > ng) {
+    // The stored value under voxel v (bin or intensity) and its level, split
+    // so a caller can issue many loads before converting any of them.  A
+    // caller-supplied bin image is clamped to [1, ng] (flagging the error) so
+    // no LDS address can leave its triangle.
+    __device__ __forceinline__ uint32_t raw(uint32_t v) const { return B ? (uint32_t)B[v] : (uint32_t)I[v]; }
+    __device__ __forceinline__ uint32_t level_of(uint32_t r) const {
+        if (!B) return fbn_level(r, vmin, D, rcpD, ng);
+        if (r == 0u || r > ng) {
             atomicOr(err, (uint32_t)E_BIN_RANGE);
-            b = b == 0u ? 1u : ng;
+            r = r == 0u ? 1u : ng;
         }
-        return b;
+        return r;
     }
 };
 
@@ -436,45 +438,68 @@ __device__ __forceinline__ void add_pair(const StepArgs &a, uint8_t *smem, uint3
     }
 }
 
-// Accumulate the pairs owned by the voxels of bbox rows [ra, rb) for the
-// directions [d0, d1): each voxel owns the pair (v, v + d) of each offset.
+// Accumulate the pairs owned by the voxels of bbox rows [ra, rb) (rows of
+// all planes, flattened) and columns [ca, cb) for the directions [d0, d1):
+// each voxel owns the pair (v, v + d) of each offset.  Lanes take voxels
+// t0, t0 + ts, ...; for each voxel the label and value of the voxel and of up
+// to kGatherDirs neighbours are loaded in one batch before any is used.
+constexpr int kGatherDirs = 8;
+
 template <class Add>
 __device__ void accumulate_rows(const StepArgs &a, const RoiDesc &rd, const ItemCtx &c, uint32_t ra, uint32_t rb,
                                 uint32_t ca, uint32_t cb, int d0, int d1, uint32_t t0, uint32_t ts, Add &&add) {
     const uint32_t W = cb - ca, H = (uint32_t)(rd.y1 - rd.y0 + 1);
     const double rcpW = 1.0 / (double)W, rcpH = 1.0 / (double)H;
     const uint32_t nv = (rb - ra) * W;
-    const int64_t plane = (int64_t)c.ny * c.nx;
+    const uint32_t plane = (uint32_t)c.ny * (uint32_t)c.nx;
     for (uint32_t f = t0; f < nv; f += ts) {
-        uint32_t q = udiv_exact(f, W, rcpW);
-        int32_t x = rd.x0 + (int32_t)ca + (int32_t)(f - q * W);
-        uint32_t rr = ra + q;
-        uint32_t zq = udiv_exact(rr, H, rcpH);
-        int32_t y = rd.y0 + (int32_t)(rr - zq * H);
-        int32_t z = rd.z0 + (int32_t)zq;
-        int64_t v = (int64_t)z * plane + (int64_t)y * c.nx + x;
-        if (c.L[v] != c.label) continue;
-        uint32_t bv = c.level((uint32_t)v);
-        for (int d = d0; d < d1; ++d) {
-            int32_t dz = a.off[d][0], dy = a.off[d][1], dx = a.off[d][2];
-            int32_t wz = z + dz, wy = y + dy, wx = x + dx;
-            if (wz < 0 || wz >= c.nz || wy < 0 || wy >= c.ny || wx < 0 || wx >= c.nx) continue;
-            int64_t w = v + (int64_t)dz * plane + (int64_t)dy * c.nx + dx;
-            if (c.L[w] != c.label) continue;
-            add((uint32_t)(d - d0), bv, c.level((uint32_t)w));
+        const uint32_t q = udiv_exact(f, W, rcpW);
+        const int32_t x = rd.x0 + (int32_t)ca + (int32_t)(f - q * W);
+        const uint32_t rr = ra + q;
+        const uint32_t zq = udiv_exact(rr, H, rcpH);
+        const int32_t y = rd.y0 + (int32_t)(rr - zq * H);
+        const int32_t z = rd.z0 + (int32_t)zq;
+        const uint32_t v = (uint32_t)z * plane + (uint32_t)y * (uint32_t)c.nx + (uint32_t)x;
+        const uint32_t lv = c.L[v], rv = c.raw(v);
+        for (int db = d0; db < d1; db += kGatherDirs) {
+            uint32_t nl[kGatherDirs], nr[kGatherDirs];
+#pragma unroll
+            for (int k = 0; k < kGatherDirs; ++k) {
+                nl[k] = 0u;
+                nr[k] = 0u;
+                const int d = db + k;
+                if (d < d1) {
+                    const int32_t wz = z + a.off[d][0], wy = y + a.off[d][1], wx = x + a.off[d][2];
+                    if (wz >= 0 && wz < c.nz && wy >= 0 && wy < c.ny && wx >= 0 && wx < c.nx) {
+                        const uint32_t wv = (uint32_t)wz * plane + (uint32_t)wy * (uint32_t)c.nx + (uint32_t)wx;
+                        nl[k] = c.L[wv];
+                        nr[k] = c.raw(wv);
+                    }
+                }
+            }
+            if (lv != c.label) continue;
+            const uint32_t bv = c.level_of(rv);
+#pragma unroll
+            for (int k = 0; k < kGatherDirs; ++k)
+                if (db + k < d1 && nl[k] == c.label) add((uint32_t)(db + k - d0), bv, c.level_of(nr[k]));
         }
     }
 }
 
 // 2D distance-1 accumulation by row sweep.  A wavefront covers 64 adjacent
-// columns of one row at a time (lanes 0..62 own their column, lane 63 only
-// supplies the right neighbour) and walks down a chunk of rows keeping the
-// previous row's levels in registers; the right neighbours come from the next
-// lane by a DPP wave shift.  Owned pairs per lane (column x, row y):
+// columns (lanes 0..62 own their column, lane 63 only supplies the right
+// neighbour) of a unit of up to kSweepRows rows, and loads the labels and
+// values of all those rows and of the row above in one batch, so a unit costs
+// a single round trip to memory; it then walks down the unit keeping the
+// previous row's levels in registers, with right neighbours taken from the
+// next lane by a DPP wave shift.  Owned pairs per lane (column x, row y):
 //   H    (y, x)-(y, x+1)      V    (y, x)-(y-1, x)
 //   D45  (y, x)-(y-1, x+1)    D135 (y-1, x)-(y, x+1)
 // h, v, d45, d135 are the local direction slots of the four classes (-1: not
-// in this pass).
+// in this pass).  Units (63-column strip x row block) are dealt to the nw
+// wavefronts round robin; w is the caller's index among them.
+constexpr uint32_t kSweepRows = 8;
+
 __device__ __forceinline__ uint32_t lane_next(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false);  // wave_shl1
 }
@@ -485,52 +510,45 @@ __device__ void accumulate_sweep2d(const RoiDesc &rd, const ItemCtx &c, uint32_t
     const int ln = lane();
     const uint32_t Wt = cb - ca;
     const uint32_t nstrip = (Wt + 62u) / 63u;
-    const uint32_t nrows = rb - ra;
-    uint32_t want = (2u * (uint32_t)nw + nstrip - 1u) / nstrip;     // chunks per strip
-    uint32_t CH = (nrows + want - 1u) / want;
-    CH = CH < 4u ? 4u : (CH > 64u ? 64u : CH);
-    const uint32_t nchunk = (nrows + CH - 1u) / CH;
+    const uint32_t nchunk = (rb - ra + kSweepRows - 1u) / kSweepRows;
     const uint32_t units = nstrip * nchunk;
     const int32_t xt0 = rd.x0 + (int32_t)ca, xt1 = rd.x0 + (int32_t)cb;   // owned columns [xt0, xt1)
+    const uint32_t nx = (uint32_t)c.nx;
     for (uint32_t u = (uint32_t)w; u < units; u += (uint32_t)nw) {
         const uint32_t s = u % nstrip, ch = u / nstrip;
         const int32_t x = xt0 + 63 * (int32_t)s + ln;
         const bool xin = x < c.nx;
         const bool owner = ln < 63 && x < xt1;
-        const uint32_t r0 = ra + ch * CH, r1 = min(rb, r0 + CH);
-        const int32_t ybase = rd.y0 + (int32_t)r0;
-        uint32_t prev = 0u;
-        if (xin && ybase - 1 >= rd.y0) {
-            int64_t idx = (int64_t)(ybase - 1) * c.nx + x;
-            if (c.L[idx] == c.label) prev = c.level((uint32_t)idx);
+        const uint32_t r0 = ra + ch * kSweepRows, nr = min(rb - r0, kSweepRows);
+        const int32_t y0 = rd.y0 + (int32_t)r0;
+        // batch row j is image row y0 - 1 + j; row 0 (above the unit) only
+        // inside the bounding box
+        uint32_t lab[kSweepRows + 1], val[kSweepRows + 1];
+        const uint32_t base = (uint32_t)(y0 - 1) * nx + (uint32_t)x;
+#pragma unroll
+        for (uint32_t j = 0; j <= kSweepRows; ++j) {
+            lab[j] = 0u;
+            val[j] = 0u;
+            const bool ok = xin && (j == 0 ? y0 > rd.y0 : j <= nr);
+            if (ok) {
+                const uint32_t idx = base + j * nx;
+                lab[j] = c.L[idx];
+                val[j] = c.raw(idx);
+            }
         }
-        // rows in groups of 8: all loads of a group are issued before use
-        for (uint32_t g0 = r0; g0 < r1; g0 += 8u) {
-            uint32_t lab[8], lev[8];
+        uint32_t prev = lab[0] == c.label ? c.level_of(val[0]) : 0u;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                lab[j] = 0u;
-                if (xin && g0 + j < r1) lab[j] = c.L[(int64_t)(rd.y0 + (int32_t)(g0 + j)) * c.nx + x];
+        for (uint32_t j = 1; j <= kSweepRows; ++j) {
+            if (j > nr) break;
+            const uint32_t cur = lab[j] == c.label ? c.level_of(val[j]) : 0u;
+            const uint32_t cur_r = lane_next(cur), prev_r = lane_next(prev);
+            if (owner && cur) {
+                if (h >= 0 && cur_r) add((uint32_t)h, cur, cur_r);
+                if (v >= 0 && prev) add((uint32_t)v, cur, prev);
+                if (d45 >= 0 && prev_r) add((uint32_t)d45, cur, prev_r);
             }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                lev[j] = 0u;
-                if (lab[j] == c.label && xin && g0 + j < r1)
-                    lev[j] = c.level((uint32_t)((int64_t)(rd.y0 + (int32_t)(g0 + j)) * c.nx + x));
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (g0 + j >= r1) break;
-                const uint32_t cur = lev[j];
-                const uint32_t cur_r = lane_next(cur), prev_r = lane_next(prev);
-                if (owner && cur) {
-                    if (h >= 0 && cur_r) add((uint32_t)h, cur, cur_r);
-                    if (v >= 0 && prev) add((uint32_t)v, cur, prev);
-                    if (d45 >= 0 && prev_r) add((uint32_t)d45, cur, prev_r);
-                }
-                if (owner && prev && cur_r && d135 >= 0) add((uint32_t)d135, prev, cur_r);
-                prev = cur;
-            }
+            if (owner && prev && cur_r && d135 >= 0) add((uint32_t)d135, prev, cur_r);
+            prev = cur;
         }
     }
 }
