@@ -120,7 +120,8 @@ typedef struct nyx_extract_opts {
                                     1 LDS hash table, 2 LDS triangle + ordered scan,
                                     3 LDS triangle of 16-bit counters + ordered scan
                                     (NYX_ERR_UNSUPPORTED when it does not fit) */
-    int32_t wave_max_vox;        /* -1 = automatic; 0 = every ROI on the work-group kernel;
+    int32_t wave_max_vox;        /* -1 = automatic (none, unless autotune times a share that
+                                    pays); 0 = every ROI on the work-group kernel;
                                     n > 0 = unsplit ROIs of at most n voxels (n <= 65535) are
                                     processed one wavefront each when there are at most 4
                                     offsets and their LDS fits (else ignored) */

@@ -9,6 +9,14 @@ namespace nyx {
 
 __device__ __forceinline__ int lane() { return (int)__lane_id(); }
 
+// Load through a global-address-space view of a device pointer: compiles to
+// global_load (SGPR base + VGPR offset where possible) instead of the flat
+// form, which also waits on the LDS counter.
+template <class T>
+__device__ __forceinline__ T ldg(const T *p, uint32_t i) {
+    return ((const __attribute__((address_space(1))) T *)p)[i];
+}
+
 // ------------------------------------------------------------ binning
 // Fixed-bin-number level (paper: "number of bins" / grey depth, Materials and
 // methods, "Feature Control and Tunability"): 1 + floor(ng (I - vmin) / D),
@@ -18,9 +26,10 @@ __device__ __forceinline__ int lane() { return (int)__lane_id(); }
 __device__ __forceinline__ uint32_t fbn_level(uint32_t I, uint32_t vmin, uint32_t D, float rcpD,
                                               uint32_t ng) {
     if (D == 0u) return 1u;
-    uint32_t num = ng * (I - vmin);
+    // 16-bit operands: 24-bit multiplies (full rate) are exact here
+    uint32_t num = __umul24(ng, I - vmin);
     uint32_t q = (uint32_t)((float)num * rcpD);
-    uint32_t qd = q * D;
+    uint32_t qd = __umul24(q, D);
     if (qd > num) q -= 1u;
     else if (num - qd >= D) q += 1u;
     uint32_t b = q + 1u;
@@ -187,8 +196,9 @@ __device__ __forceinline__ double i128_to_double(i128 v) {
 
 // ------------------------------------------------------------ triangles
 // Compact upper-triangle index of the unordered level pair (lo <= hi), 0-based.
+// Levels are below 2^16, so the 24-bit multiply is exact.
 __device__ __forceinline__ uint32_t tri_idx(uint32_t lo, uint32_t hi) {
-    return ((hi * (hi + 1u)) >> 1) + lo;
+    return (__umul24(hi, hi + 1u) >> 1) + lo;
 }
 
 __device__ __forceinline__ uint32_t hash_u32(uint32_t k) {

@@ -136,10 +136,10 @@ __device__ __forceinline__ uint32_t tri_count(const uint32_t *U, uint32_t i) {
 // Inverse of tri_idx: the pair (lo, hi) of triangle index i.
 __device__ __forceinline__ void tri_decode(uint32_t i, uint32_t &lo, uint32_t &hi) {
     uint32_t h = (uint32_t)((sqrtf(8.0f * (float)i + 1.0f) - 1.0f) * 0.5f);
-    if (((h * (h + 1u)) >> 1) > i) --h;
-    else if ((((h + 1u) * (h + 2u)) >> 1) <= i) ++h;
+    if ((__umul24(h, h + 1u) >> 1) > i) --h;
+    else if ((__umul24(h + 1u, h + 2u) >> 1) <= i) ++h;
     hi = h;
-    lo = i - ((h * (h + 1u)) >> 1);
+    lo = i - (__umul24(h, h + 1u) >> 1);
 }
 
 // LDS triangle of one direction, scanned in index order.  Each lane reads
@@ -347,15 +347,32 @@ __device__ __noinline__ void finalize_dir(const DirSums &s, double *out) {
     out[F_JVAR] = out[F_VARIANCE] = var;
 }
 
-template <class F> __device__ __forceinline__ F log2_(F x);
-template <> __device__ __forceinline__ float log2_<float>(float x) { return log2f(x); }
-template <> __device__ __forceinline__ double log2_<double>(double x) { return log2(x); }
 template <class F> __device__ __forceinline__ F log1p_(F x);
 template <> __device__ __forceinline__ float log1p_<float>(float x) { return log1pf(x); }
 template <> __device__ __forceinline__ double log1p_<double>(double x) { return log1p(x); }
 
 template <class F>
 __device__ __forceinline__ double comp_value(const Comp<F> &c) { return (double)c.s + (double)c.c; }
+
+// Per-lane sum of floating terms.  Double precision path: compensated double
+// sums.  Single precision path: the terms are formed in single precision with
+// the hardware log2 and reciprocal (inputs are integers >= 1, so no denormal
+// handling is needed) and summed in double, so the sum adds no error beyond
+// the terms' own rounding (~1e-7 relative each).
+template <class Acc> struct LaneSum;
+template <> struct LaneSum<double> : Comp<double> {};
+template <> struct LaneSum<float> {
+    double s = 0.0;
+    __device__ __forceinline__ void add(float x) { s += (double)x; }
+};
+__device__ __forceinline__ double comp_value(const LaneSum<float> &c) { return c.s; }
+
+template <class Acc> __device__ __forceinline__ Acc term_log2(Acc x);
+template <> __device__ __forceinline__ float term_log2<float>(float x) { return __log2f(x); }
+template <> __device__ __forceinline__ double term_log2<double>(double x) { return log2(x); }
+template <class Acc> __device__ __forceinline__ Acc term_div(Acc a, Acc b);
+template <> __device__ __forceinline__ float term_div<float>(float a, float b) { return __fdividef(a, b); }
+template <> __device__ __forceinline__ double term_div<double>(double a, double b) { return a / b; }
 
 // Below this many bits of mutual information the difference 2 HX - JE is
 // re-summed cell by cell.
@@ -380,7 +397,7 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
     // one for P = 2c.
     ISum Tl = 0, sumP2 = 0, S11 = 0;
     uint32_t maxP = 0;
-    Comp<Acc> plp;
+    LaneSum<Acc> plp;
     src.for_each(g, [&](uint32_t lo, uint32_t hi, uint32_t c) {
         atomicAdd(&R[lo], c);
         atomicAdd(&R[hi], c);
@@ -392,13 +409,13 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
         Tl += (ISum)(2ull * c);
         sumP2 += Pm * (ISum)P;
         maxP = P > maxP ? P : maxP;
-        S11 += Pm * (ISum)((uint64_t)(lo + 1u) * (hi + 1u));
-        plp.add((Acc)Pm * log2_<Acc>((Acc)P));
+        S11 += Pm * (ISum)__umul24(lo + 1u, hi + 1u);   // levels < 2^16: exact
+        plp.add((Acc)Pm * term_log2<Acc>((Acc)P));
     });
     g.sync();
     // Level sweeps over the marginals (unnormalised).
     ISum S1 = 0, S2 = 0, Sm1 = 0;
-    Comp<Acc> rlr, slp, hom1, hom2, idmn, idn, iv, plps;
+    LaneSum<Acc> rlr, slp, hom1, hom2, idmn, idn, iv, plps;
     const Acc ngf = (Acc)ng;
     for (uint32_t i = r0; i < ng; i += gs) {
         const uint32_t r = R[i];
@@ -406,23 +423,23 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
             const ISum lv = (ISum)(i + 1u);
             S1 += lv * (ISum)r;
             S2 += lv * lv * (ISum)r;
-            rlr.add((Acc)r * log2_<Acc>((Acc)r));
+            rlr.add((Acc)r * term_log2<Acc>((Acc)r));
         }
         const uint32_t s = Sm[i];
         if (s) {
             Sm1 += (ISum)i * (ISum)s;
             const Acc sf = (Acc)s, k = (Acc)i;
-            slp.add(sf * log2_<Acc>(sf));
-            hom1.add(sf / ((Acc)1 + k));
-            hom2.add(sf / ((Acc)1 + k * k));
-            idmn.add(sf / ((Acc)1 + (k * k) / (ngf * ngf)));
-            idn.add(sf / ((Acc)1 + k / ngf));
-            if (i > 0) iv.add(sf / (k * k));
+            slp.add(sf * term_log2<Acc>(sf));
+            hom1.add(term_div<Acc>(sf, (Acc)1 + k));
+            hom2.add(term_div<Acc>(sf, (Acc)1 + k * k));
+            idmn.add(term_div<Acc>(sf, (Acc)1 + (k * k) / (ngf * ngf)));
+            idn.add(term_div<Acc>(sf, (Acc)1 + k / ngf));
+            if (i > 0) iv.add(term_div<Acc>(sf, k * k));
         }
     }
     for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) {
         const uint32_t s = Sp[k];
-        if (s) plps.add((Acc)s * log2_<Acc>((Acc)s));
+        if (s) plps.add((Acc)s * term_log2<Acc>((Acc)s));
     }
     // Group totals.  Batched groups reduce the sixteen slots of DirSums at
     // once (rank r < 16 ends with slot r); the others reduce value by value.

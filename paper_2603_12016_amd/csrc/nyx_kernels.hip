@@ -371,7 +371,10 @@ struct ItemCtx {
     // so a caller can issue many loads before converting any of them.  A
     // caller-supplied bin image is clamped to [1, ng] (flagging the error) so
     // no LDS address can leave its triangle.
-    __device__ __forceinline__ uint32_t raw(uint32_t v) const { return B ? (uint32_t)B[v] : (uint32_t)I[v]; }
+    __device__ __forceinline__ uint32_t raw(uint32_t v) const {
+        return B ? (uint32_t)ldg(B, v) : (uint32_t)ldg(I, v);
+    }
+    __device__ __forceinline__ uint32_t lab(uint32_t v) const { return ldg(L, v); }
     __device__ __forceinline__ uint32_t level_of(uint32_t r) const {
         if (!B) return fbn_level(r, vmin, D, rcpD, ng);
         if (r == 0u || r > ng) {
@@ -460,19 +463,20 @@ __device__ void accumulate_rows(const StepArgs &a, const RoiDesc &rd, const Item
         const int32_t y = rd.y0 + (int32_t)(rr - zq * H);
         const int32_t z = rd.z0 + (int32_t)zq;
         const uint32_t v = (uint32_t)z * plane + (uint32_t)y * (uint32_t)c.nx + (uint32_t)x;
-        const uint32_t lv = c.L[v], rv = c.raw(v);
+        const uint32_t lv = c.lab(v), rv = c.raw(v);
         for (int db = d0; db < d1; db += kGatherDirs) {
             uint32_t nl[kGatherDirs], nr[kGatherDirs];
 #pragma unroll
             for (int k = 0; k < kGatherDirs; ++k) {
                 nl[k] = 0u;
                 nr[k] = 0u;
-                const int d = db + k;
+                // a uniform index keeps the offset table reads scalar
+                const int d = __builtin_amdgcn_readfirstlane(db + k);
                 if (d < d1) {
                     const int32_t wz = z + a.off[d][0], wy = y + a.off[d][1], wx = x + a.off[d][2];
                     if (wz >= 0 && wz < c.nz && wy >= 0 && wy < c.ny && wx >= 0 && wx < c.nx) {
                         const uint32_t wv = (uint32_t)wz * plane + (uint32_t)wy * (uint32_t)c.nx + (uint32_t)wx;
-                        nl[k] = c.L[wv];
+                        nl[k] = c.lab(wv);
                         nr[k] = c.raw(wv);
                     }
                 }
@@ -524,15 +528,14 @@ __device__ void accumulate_sweep2d(const RoiDesc &rd, const ItemCtx &c, uint32_t
         // batch row j is image row y0 - 1 + j; row 0 (above the unit) only
         // inside the bounding box
         uint32_t lab[kSweepRows + 1], val[kSweepRows + 1];
-        const uint32_t base = (uint32_t)(y0 - 1) * nx + (uint32_t)x;
+        uint32_t idx = (uint32_t)(y0 - 1) * nx + (uint32_t)x;   // wraps for y0 = 0; row 0 is then unused
 #pragma unroll
-        for (uint32_t j = 0; j <= kSweepRows; ++j) {
+        for (uint32_t j = 0; j <= kSweepRows; ++j, idx += nx) {
             lab[j] = 0u;
             val[j] = 0u;
             const bool ok = xin && (j == 0 ? y0 > rd.y0 : j <= nr);
             if (ok) {
-                const uint32_t idx = base + j * nx;
-                lab[j] = c.L[idx];
+                lab[j] = c.lab(idx);
                 val[j] = c.raw(idx);
             }
         }
@@ -582,7 +585,8 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 4 : 1)) void k_batch(Step
     uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off);
     uint2 *BUF = reinterpret_cast<uint2 *>(smem + Ly.buf_off);
     uint32_t *MISC = reinterpret_cast<uint32_t *>(smem + Ly.misc_off);
-    const int nw = (int)(blockDim.x / kWave), w = (int)(threadIdx.x / kWave);
+    const int nw = (int)(blockDim.x / kWave);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));   // wave index: uniform
     const int K = a.K;
     const uint32_t ng = (uint32_t)a.ng;
     const uint32_t marg_words = 4u * ng;

@@ -366,7 +366,6 @@ LdsLayout make_wave_layout(uint32_t ng, int K) {
 // Wavefront path: at most four offsets and a per-wave LDS footprint that
 // leaves room for several waves per CU.
 constexpr uint32_t kWaveLdsMax = 40u * 1024u;
-constexpr uint32_t kWaveVoxDefault = 4096u;
 bool wave_feasible(uint32_t ng, int K) { return K <= 4 && make_wave_layout(ng, K).bytes <= kWaveLdsMax; }
 
 // Largest voxel count any work item can hold under a split rule.
@@ -925,17 +924,16 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
     std::vector<Config> cands = candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256);
     if (cands.empty())
         return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%d with %d offsets", p->ng, p->K);
-    // wavefront-per-ROI share: automatic, off, or a given ROI size limit
+    // wavefront-per-ROI share: automatic (off unless timing finds a share
+    // that pays), off, or a given ROI size limit
     const bool wave_ok = wave_feasible((uint32_t)p->ng, p->K);
-    const uint32_t wave_vox = !wave_ok || opts->wave_max_vox == 0 ? 0u
-                              : opts->wave_max_vox < 0 ? kWaveVoxDefault
-                                                       : (uint32_t)std::min(opts->wave_max_vox, 65535);
+    const uint32_t wave_vox = !wave_ok || opts->wave_max_vox <= 0 ? 0u : (uint32_t)std::min(opts->wave_max_vox, 65535);
     for (Config &c : cands) c.wave_vox = wave_vox;
     if (opts->autotune && opts->wave_max_vox < 0 && wave_ok) {
-        // also time other wavefront shares of each candidate
+        // also time wavefront shares of each candidate
         const size_t n0 = cands.size();
         for (size_t i = 0; i < n0; ++i)
-            for (uint32_t v : {0u, 1024u, 16384u}) {
+            for (uint32_t v : {1024u, 4096u}) {
                 Config c = cands[i];
                 c.wave_vox = v;
                 cands.push_back(c);

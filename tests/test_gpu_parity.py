@@ -217,10 +217,10 @@ def test_features_from_oracle_coo(env, workloads, oracle_mod, name, prec):
 
 
 # ------------------------------------------------------------------ batched path
-# (workload, accumulation mode, wavefront share: -1 automatic, 0 none, 65535 every unsplit ROI)
+# (workload, accumulation mode, wavefront share: 0 none, n > 0 unsplit ROIs up to n voxels)
 MODE_CASES = ([(n, m, 0) for n in SMALL for m in ("auto", "dense-list", "dense-scan", "dense16-scan")
                if not (n == "c5_small" and m != "auto")] +
-              [(n, "auto", v) for n in SMALL for v in (-1, 65535)] + [("c3_small", "autotune", -1)])
+              [(n, "auto", v) for n in SMALL for v in (1024, 65535)] + [("c3_small", "autotune", -1)])
 
 
 @pytest.mark.parametrize("name,mode,wave", MODE_CASES)
@@ -295,7 +295,7 @@ EDGE = {
 }
 
 
-@pytest.mark.parametrize("wave", [-1, 0])
+@pytest.mark.parametrize("wave", [65535, 0])
 @pytest.mark.parametrize("case", sorted(EDGE))
 @pytest.mark.parametrize("ng", [2, 8, 30, 100])
 def test_edge_cases(env, oracle_mod, case, ng, wave):
