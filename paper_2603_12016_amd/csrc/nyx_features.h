@@ -64,6 +64,7 @@ struct WaveGrp {
         return s;
     }
     __device__ __forceinline__ double bcast(double v, int r) const { return readlane_(v, r); }
+    __device__ __forceinline__ uint32_t bcast_u32(uint32_t v, int r) const { return readlane_(v, r); }
     __device__ __forceinline__ void sync() const {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -83,6 +84,7 @@ struct RowGrp {
     __device__ __forceinline__ double reduce_slots(double (&v)[kSumSlots]) const { return row_reduce_slots(v); }
     __device__ __forceinline__ double reduce_pair(double a, double b) const { return row_reduce_pair(a, b); }
     __device__ __forceinline__ double bcast(double v, int r) const { return __shfl(v, r, 16); }
+    __device__ __forceinline__ uint32_t bcast_u32(uint32_t v, int r) const { return __shfl(v, r, 16); }
     __device__ __forceinline__ int row() const { return lane() >> 4; }
     __device__ __forceinline__ void sync() const {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -135,28 +137,32 @@ __device__ __forceinline__ uint32_t tri_count(const uint32_t *U, uint32_t i) {
 
 // Inverse of tri_idx: the pair (lo, hi) of triangle index i.
 __device__ __forceinline__ void tri_decode(uint32_t i, uint32_t &lo, uint32_t &hi) {
-    uint32_t h = (uint32_t)((sqrtf(8.0f * (float)i + 1.0f) - 1.0f) * 0.5f);
+    // hardware square root: the estimate is corrected to the exact row below
+    uint32_t h = (uint32_t)((__builtin_amdgcn_sqrtf(8.0f * (float)i + 1.0f) - 1.0f) * 0.5f);
     if ((__umul24(h, h + 1u) >> 1) > i) --h;
     else if ((__umul24(h + 1u, h + 2u) >> 1) <= i) ++h;
     hi = h;
     lo = i - (__umul24(h, h + 1u) >> 1);
 }
 
-// LDS triangle of one direction, scanned in index order.  Each lane reads
-// one 16-byte run of the triangle per chunk (8 packed 16-bit or 4 32-bit
-// counters), decodes the run's cell indices incrementally, and writes its
-// nonzero cells, packed as (lo | hi << 16, count), into `buf` at its prefix
-// offset within the group (room for size() * kScanCells entries, kScanCells
-// from the shared types header).  fn then
-// runs over the compacted entries, so lanes stay busy on sparse triangles and
-// the order of every floating sum is fixed.  U must be 16-byte aligned and
-// padded with zero words to a multiple of 4 words.
+// LDS triangle of one direction, visited in index order.  Per chunk each
+// lane reads one 16-byte run of the triangle (8 packed 16-bit or 4 32-bit
+// counters) and turns it into a mask of its nonzero cells; the group forms
+// the exclusive prefix of the masks' popcounts and each lane expands its set
+// bits, as cell indices, into `buf` (room for size() * kPerRead entries) at
+// its offset.  fn then runs over the compacted entries (count re-read from
+// the triangle, index decoded to (lo, hi)), so lanes stay busy however sparse
+// the triangle is and the order of every floating sum is fixed.  U must be
+// 16-byte aligned and padded with zero words to a multiple of 4 words.
 template <bool PACKED>
 struct SrcTriScan {
     uint32_t *U;
     uint32_t tri;
-    uint2 *buf;
+    uint32_t *buf;
     static constexpr uint32_t kPerRead = PACKED ? 8u : 4u;   // cells per 16-byte read
+    __device__ __forceinline__ uint32_t count(uint32_t i) const {
+        return PACKED ? (uint32_t)reinterpret_cast<const uint16_t *>(U)[i] : U[i];
+    }
     template <class Grp, class Fn>
     __device__ __forceinline__ void for_each(const Grp &g, Fn &&fn) const {
         const uint32_t gs = (uint32_t)g.size(), r = (uint32_t)g.rank();
@@ -165,18 +171,16 @@ struct SrcTriScan {
             const uint32_t w0 = wbase + 4u * r;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             if (w0 < words) v = *reinterpret_cast<const uint4 *>(U + w0);
-            uint32_t c[kPerRead];
+            uint32_t mask;   // bit k: cell i0 + k is nonzero (cells past tri are zero padding)
             if (PACKED) {
-                c[0] = v.x & 0xFFFFu; c[1] = v.x >> 16; c[2] = v.y & 0xFFFFu; c[3] = v.y >> 16;
-                c[4] = v.z & 0xFFFFu; c[5] = v.z >> 16; c[6] = v.w & 0xFFFFu; c[7] = v.w >> 16;
+                mask = ((v.x & 0xFFFFu) ? 1u : 0u) | ((v.x >> 16) ? 2u : 0u) | ((v.y & 0xFFFFu) ? 4u : 0u) |
+                       ((v.y >> 16) ? 8u : 0u) | ((v.z & 0xFFFFu) ? 16u : 0u) | ((v.z >> 16) ? 32u : 0u) |
+                       ((v.w & 0xFFFFu) ? 64u : 0u) | ((v.w >> 16) ? 128u : 0u);
             } else {
-                c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+                mask = (v.x ? 1u : 0u) | (v.y ? 2u : 0u) | (v.z ? 4u : 0u) | (v.w ? 8u : 0u);
             }
-            const uint32_t i0 = PACKED ? 2u * w0 : w0;   // first cell of the run
-            uint32_t n = 0;
-#pragma unroll
-            for (uint32_t k = 0; k < kPerRead; ++k) n += (c[k] != 0u && i0 + k < tri) ? 1u : 0u;
-            // exclusive prefix of n over the group and its total, bit by bit
+            const uint32_t n = (uint32_t)__popc(mask);
+            // exclusive prefix of n (<= 8) over the group and its total
             uint32_t pos = 0, cnt = 0;
 #pragma unroll
             for (uint32_t b = 0; b < 4u; ++b) {
@@ -184,19 +188,17 @@ struct SrcTriScan {
                 pos += (uint32_t)__popcll(m & g.below()) << b;
                 cnt += (uint32_t)__popcll(m) << b;
             }
-            if (n) {
-                uint32_t lo, hi;
-                tri_decode(i0 < tri ? i0 : 0u, lo, hi);
-#pragma unroll
-                for (uint32_t k = 0; k < kPerRead; ++k) {
-                    if (c[k] != 0u && i0 + k < tri) buf[pos++] = make_uint2(lo | (hi << 16), c[k]);
-                    if (++lo > hi) { ++hi; lo = 0u; }
-                }
+            const uint32_t i0 = PACKED ? 2u * w0 : w0;   // first cell of the run
+            while (mask) {
+                buf[pos++] = i0 + (uint32_t)__builtin_ctz(mask);
+                mask &= mask - 1u;
             }
             g.sync();
             for (uint32_t e = r; e < cnt; e += gs) {
-                const uint2 q = buf[e];
-                fn(q.x & 0xFFFFu, q.x >> 16, q.y);
+                const uint32_t i = buf[e];
+                uint32_t lo, hi;
+                tri_decode(i, lo, hi);
+                fn(lo, hi, count(i));
             }
             g.sync();
         }

@@ -393,13 +393,13 @@ __device__ __forceinline__ void add_pair(const StepArgs &a, uint8_t *smem, uint3
     uint32_t lo = (la < lb ? la : lb) - 1u, hi = (la < lb ? lb : la) - 1u;
     uint32_t *LCNT = reinterpret_cast<uint32_t *>(smem + Ly.lcnt_off);
     uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off) + dl * Ly.list_cap;
-    if (MODE == 2) {
-        uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
-        __hip_atomic_fetch_add(&U[tri_idx(lo, hi)], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    } else if (MODE == 3) {
+    if (MODE == 2 || MODE == 3) {
         uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
         const uint32_t i = tri_idx(lo, hi);
-        __hip_atomic_fetch_add(&U[i >> 1], 1u << ((i & 1u) << 4), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (MODE == 2)
+            __hip_atomic_fetch_add(&U[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            __hip_atomic_fetch_add(&U[i >> 1], 1u << ((i & 1u) << 4), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     } else if (MODE == 0) {
         uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
         uint32_t old = atomicAdd(&U[tri_idx(lo, hi)], 1u);
@@ -574,16 +574,18 @@ __device__ __forceinline__ void dir_or_flush(const StepArgs &a, const WaveGrp &g
     }
 }
 
-// Single precision: at most 128 VGPRs, four waves per SIMD (the compiler would
-// otherwise take ~150 and leave three); double precision keeps its registers.
+// Single precision: at most 102 VGPRs, five waves per SIMD (a few bytes of
+// spill at item level; measured faster than four), which with ~30 KB of LDS
+// per work-group at 64 levels keeps five work-groups on a CU; double
+// precision keeps its registers.
 template <int MODE, class OutT>
-__global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 4 : 1)) void k_batch(StepArgs a, uint32_t direct_roi) {
+__global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(StepArgs a, uint32_t direct_roi) {
     extern __shared__ __align__(16) uint8_t smem[];
     typedef typename std::conditional<sizeof(OutT) == 8, double, float>::type Acc;
     const LdsLayout &Ly = a.lds;
     uint32_t *LCNT = reinterpret_cast<uint32_t *>(smem + Ly.lcnt_off);
     uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off);
-    uint2 *BUF = reinterpret_cast<uint2 *>(smem + Ly.buf_off);
+    uint32_t *BUF = reinterpret_cast<uint32_t *>(smem + Ly.buf_off);
     uint32_t *MISC = reinterpret_cast<uint32_t *>(smem + Ly.misc_off);
     const int nw = (int)(blockDim.x / kWave);
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));   // wave index: uniform
@@ -685,7 +687,8 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 4 : 1)) void k_batch(Step
                     const uint32_t *lst = LST + dl * Ly.list_cap;
                     WaveGrp g;
                     if (MODE == 2 || MODE == 3) {
-                        SrcTriScan<MODE == 3> s{Ud, (ng * (ng + 1u)) >> 1, BUF + (uint32_t)w * kWave * SrcTriScan<MODE == 3>::kPerRead};
+                        SrcTriScan<MODE == 3> s{Ud, (ng * (ng + 1u)) >> 1,
+                                                BUF + (uint32_t)w * kWave * SrcTriScan<MODE == 3>::kPerRead};
                         dir_or_flush<Acc>(a, g, s, split, rd, roi, d0 + dl, MARG, ng);
                     } else if (MODE == 0) {
                         SrcDenseList s{lst, n, Ud};
@@ -716,7 +719,7 @@ __global__ __launch_bounds__(64) void k_wave(StepArgs a, uint32_t direct_roi) {
     typedef typename std::conditional<sizeof(OutT) == 8, double, float>::type Acc;
     const LdsLayout &Ly = a.wlds;
     uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off);
-    uint2 *BUF = reinterpret_cast<uint2 *>(smem + Ly.buf_off);
+    uint32_t *BUF = reinterpret_cast<uint32_t *>(smem + Ly.buf_off);
     uint32_t *MARG = reinterpret_cast<uint32_t *>(smem + Ly.marg_off);
     uint32_t *MISC = reinterpret_cast<uint32_t *>(smem + Ly.misc_off);
     const int K = a.K;
@@ -795,7 +798,8 @@ __global__ __launch_bounds__(64) void k_wave(StepArgs a, uint32_t direct_roi) {
             const RowGrp g;
             const int r = g.row();
             if (r < K) {
-                SrcTriScan<PACKED> s{U + (uint32_t)r * Ly.tri_pad, tri, BUF + (uint32_t)r * 16u * kScanCells};
+                SrcTriScan<PACKED> s{U + (uint32_t)r * Ly.tri_pad, tri,
+                                     BUF + (uint32_t)r * 16u * kScanCells};
                 uint32_t *M = MARG + (uint32_t)r * 4u * ng;
                 dir_sums<Acc, double>(g, s, M, M + ng, M + 3u * ng - 1u, ng, a.dsums + (uint64_t)roi * K + r);
             }

@@ -299,8 +299,8 @@ const char *mode_name(int m) {
     }
 }
 
-// Compaction entries per lane of a scan chunk: one 16-byte read holds 8
-// packed 16-bit or 4 32-bit counters.
+// Compaction entries (u32 cell indices) per lane of a scan chunk: one
+// 16-byte read holds 8 packed 16-bit or 4 32-bit counters.
 uint32_t scan_cells(int mode) { return mode == 3 ? (uint32_t)kScanCells : (uint32_t)kScanCells / 2u; }
 
 uint32_t u_words(int mode, uint32_t ng) {
@@ -332,7 +332,7 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K) {
     }
     L.list_off = take(c.kp * c.list_cap * 4u);
     L.lcnt_off = take(c.kp * 4u);
-    L.buf_off = take((c.mode == 2 || c.mode == 3) ? L.nwaves * kWave * scan_cells(c.mode) * 8u : 0u);
+    L.buf_off = take((c.mode == 2 || c.mode == 3) ? L.nwaves * kWave * scan_cells(c.mode) * 4u : 0u);
     L.marg_off = take(std::min(L.nwaves, c.kp) * 4u * ng * 4u);   // one set per wave that reduces a direction
     L.misc_off = take(128u * 4u);
     L.bytes = off;
@@ -356,7 +356,7 @@ LdsLayout make_wave_layout(uint32_t ng, int K) {
         return o;
     };
     L.u_off = take((uint32_t)K * L.tri_pad * 4u);
-    L.buf_off = take(kWave * (uint32_t)kScanCells * 8u);
+    L.buf_off = take(kWave * (uint32_t)kScanCells * 4u);
     L.marg_off = take((uint32_t)K * 4u * ng * 4u);
     L.misc_off = take(128u * 4u);
     L.bytes = off;
@@ -412,7 +412,7 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
         if (mode == 3 && mi > 65535u) continue;
         const bool scan = mode == 2 || mode == 3;
         const uint32_t list_cap = scan ? 0u : (uint32_t)std::min<uint64_t>(tri, std::max<uint64_t>(mi, 1u));
-        const uint64_t scan_buf = scan ? (uint64_t)nw * kWave * scan_cells(mode) * 8u : 0u;
+        const uint64_t scan_buf = scan ? (uint64_t)nw * kWave * scan_cells(mode) * 4u : 0u;
         for (uint32_t kp = (uint32_t)K; kp >= 1u; --kp) {
             uint64_t bytes = (uint64_t)kp * u_words(mode, ng) * 4u + (uint64_t)kp * list_cap * 4u + kp * 4u +
                              fixed_for(kp) + scan_buf;

@@ -88,8 +88,8 @@ struct DirSums {
 };
 static_assert(sizeof(DirSums) == 160, "DirSums layout");
 constexpr int kSumSlots = 16;
-// Compaction buffer entries per lane of an ordered triangle scan (one
-// 16-byte read: at most 8 packed counters).
+// Compaction buffer entries (u32 cell indices) per lane of an ordered
+// triangle scan (one 16-byte read: at most 8 packed counters).
 constexpr int kScanCells = 8;
 
 struct LdsLayout {
