@@ -147,12 +147,12 @@ __device__ __forceinline__ void tri_decode(uint32_t i, uint32_t &lo, uint32_t &h
 
 // LDS triangle of one direction, visited in index order.  Per chunk each
 // lane reads one 16-byte run of the triangle (8 packed 16-bit or 4 32-bit
-// counters) and turns it into a mask of its nonzero cells; the group forms
-// the exclusive prefix of the masks' popcounts and each lane expands its set
-// bits, as cell indices, into `buf` (room for size() * kPerRead entries) at
-// its offset.  fn then runs over the compacted entries (count re-read from
-// the triangle, index decoded to (lo, hi)), so lanes stay busy however sparse
-// the triangle is and the order of every floating sum is fixed.  U must be
+// counters); the group forms the exclusive prefix of the runs' nonzero-cell
+// counts and each lane appends its nonzero cells, as cell indices, to `buf`
+// (room for size() * kPerRead entries).  fn runs over the buffered entries
+// (count re-read from the triangle, index decoded to (lo, hi)) whenever the
+// next chunk might not fit, and at the end: lanes stay busy however sparse
+// the triangle is, and the order of every floating sum is fixed.  U must be
 // 16-byte aligned and padded with zero words to a multiple of 4 words.
 template <bool PACKED>
 struct SrcTriScan {
@@ -164,22 +164,36 @@ struct SrcTriScan {
         return PACKED ? (uint32_t)reinterpret_cast<const uint16_t *>(U)[i] : U[i];
     }
     template <class Grp, class Fn>
+    __device__ __forceinline__ void flush(const Grp &g, uint32_t n, Fn &&fn) const {
+        g.sync();
+        for (uint32_t e = (uint32_t)g.rank(); e < n; e += (uint32_t)g.size()) {
+            const uint32_t i = buf[e];
+            uint32_t lo, hi;
+            tri_decode(i, lo, hi);
+            fn(lo, hi, count(i));
+        }
+        g.sync();
+    }
+    template <class Grp, class Fn>
     __device__ __forceinline__ void for_each(const Grp &g, Fn &&fn) const {
         const uint32_t gs = (uint32_t)g.size(), r = (uint32_t)g.rank();
         const uint32_t words = PACKED ? (tri + 1u) >> 1 : tri;
+        const uint32_t cap = gs * kPerRead;
+        uint32_t held = 0;   // entries waiting in buf (group-uniform)
         for (uint32_t wbase = 0; wbase < words; wbase += 4u * gs) {
             const uint32_t w0 = wbase + 4u * r;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             if (w0 < words) v = *reinterpret_cast<const uint4 *>(U + w0);
-            uint32_t mask;   // bit k: cell i0 + k is nonzero (cells past tri are zero padding)
+            uint32_t c[kPerRead];   // counters of the run (cells past tri are zero padding)
             if (PACKED) {
-                mask = ((v.x & 0xFFFFu) ? 1u : 0u) | ((v.x >> 16) ? 2u : 0u) | ((v.y & 0xFFFFu) ? 4u : 0u) |
-                       ((v.y >> 16) ? 8u : 0u) | ((v.z & 0xFFFFu) ? 16u : 0u) | ((v.z >> 16) ? 32u : 0u) |
-                       ((v.w & 0xFFFFu) ? 64u : 0u) | ((v.w >> 16) ? 128u : 0u);
+                c[0] = v.x & 0xFFFFu; c[1] = v.x >> 16; c[2] = v.y & 0xFFFFu; c[3] = v.y >> 16;
+                c[4] = v.z & 0xFFFFu; c[5] = v.z >> 16; c[6] = v.w & 0xFFFFu; c[7] = v.w >> 16;
             } else {
-                mask = (v.x ? 1u : 0u) | (v.y ? 2u : 0u) | (v.z ? 4u : 0u) | (v.w ? 8u : 0u);
+                c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
             }
-            const uint32_t n = (uint32_t)__popc(mask);
+            uint32_t n = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < kPerRead; ++k) n += c[k] != 0u ? 1u : 0u;
             // exclusive prefix of n (<= 8) over the group and its total
             uint32_t pos = 0, cnt = 0;
 #pragma unroll
@@ -188,20 +202,18 @@ struct SrcTriScan {
                 pos += (uint32_t)__popcll(m & g.below()) << b;
                 cnt += (uint32_t)__popcll(m) << b;
             }
+            if (held + cnt > cap) {
+                flush(g, held, fn);
+                held = 0;
+            }
+            pos += held;
             const uint32_t i0 = PACKED ? 2u * w0 : w0;   // first cell of the run
-            while (mask) {
-                buf[pos++] = i0 + (uint32_t)__builtin_ctz(mask);
-                mask &= mask - 1u;
-            }
-            g.sync();
-            for (uint32_t e = r; e < cnt; e += gs) {
-                const uint32_t i = buf[e];
-                uint32_t lo, hi;
-                tri_decode(i, lo, hi);
-                fn(lo, hi, count(i));
-            }
-            g.sync();
+#pragma unroll
+            for (uint32_t k = 0; k < kPerRead; ++k)
+                if (c[k] != 0u) buf[pos++] = i0 + k;
+            held += cnt;
         }
+        if (held) flush(g, held, fn);
     }
     template <class Grp>
     __device__ __forceinline__ void clear(const Grp &g) const {

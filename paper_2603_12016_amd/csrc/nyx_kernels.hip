@@ -521,7 +521,7 @@ __device__ void accumulate_sweep2d(const RoiDesc &rd, const ItemCtx &c, uint32_t
     for (uint32_t u = (uint32_t)w; u < units; u += (uint32_t)nw) {
         const uint32_t s = u % nstrip, ch = u / nstrip;
         const int32_t x = xt0 + 63 * (int32_t)s + ln;
-        const bool xin = x < c.nx;
+        const bool xin = x < c.nx && x <= xt1;   // owned columns and the right neighbour of the last
         const bool owner = ln < 63 && x < xt1;
         const uint32_t r0 = ra + ch * kSweepRows, nr = min(rb - r0, kSweepRows);
         const int32_t y0 = rd.y0 + (int32_t)r0;

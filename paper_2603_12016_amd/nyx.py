@@ -174,10 +174,11 @@ def _dev():
 class Ctx:
     def __init__(self, handle):
         self.handle = handle
+        self._destroy = lib().nyx_destroy   # kept: module globals may be gone at interpreter exit
 
     def __del__(self):
         if getattr(self, "handle", None):
-            lib().nyx_destroy(self.handle)
+            self._destroy(self.handle)
             self.handle = None
 
 
@@ -220,9 +221,12 @@ class Glcm:
 class Plan:
     def __init__(self, ctx, handle, n_rois, keep):
         self.ctx, self.handle, self.n_rois, self._keep = ctx, handle, n_rois, keep
+        self._destroy = lib().nyx_plan_destroy
 
     def __del__(self):
-        nyx_plan_destroy(self)
+        if getattr(self, "handle", None):
+            self._destroy(self.handle)
+            self.handle = None
 
 
 # ------------------------------------------------------------------ API
@@ -369,7 +373,7 @@ def nyx_plan_describe(plan: Plan) -> str:
 
 def nyx_plan_destroy(plan: Plan):
     if getattr(plan, "handle", None):
-        lib().nyx_plan_destroy(plan.handle)
+        plan._destroy(plan.handle)
         plan.handle = None
 
 
