@@ -48,7 +48,9 @@ constexpr int kDppRowMirror = 0x140;
 
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp32(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)0, (int)v, CTRL, 0xF, 0xF, false);
+    // bound_ctrl: a lane whose source is outside the wave reads 0 (no register
+    // has to hold an "old" value)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
 }
 
 template <int CTRL, class T>

@@ -385,17 +385,22 @@ struct ItemCtx {
     }
 };
 
-// Add one unordered level pair (1-based a, b) to local direction dl.
+// Triangle offset of a 1-based level x: the index of cell (lo, hi = x - 1)
+// is row_off(x) + lo + 1, so a pair (a <= b) lands at row_off(b) + a.
+__device__ __forceinline__ uint32_t row_off(uint32_t x) { return (__umul24(x - 1u, x) >> 1) - 1u; }
+
+// Add one unordered level pair (1-based la, lb, with their row offsets ta,
+// tb) to local direction dl.
 template <int MODE>
-__device__ __forceinline__ void add_pair(const StepArgs &a, uint8_t *smem, uint32_t dl, uint32_t la,
-                                         uint32_t lb) {
+__device__ __forceinline__ void add_pair(const StepArgs &a, uint8_t *smem, uint32_t dl, uint32_t la, uint32_t ta,
+                                         uint32_t lb, uint32_t tb) {
     const LdsLayout &Ly = a.lds;
     uint32_t lo = (la < lb ? la : lb) - 1u, hi = (la < lb ? lb : la) - 1u;
     uint32_t *LCNT = reinterpret_cast<uint32_t *>(smem + Ly.lcnt_off);
     uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off) + dl * Ly.list_cap;
     if (MODE == 2 || MODE == 3) {
         uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
-        const uint32_t i = tri_idx(lo, hi);
+        const uint32_t i = la <= lb ? tb + la : ta + lb;
         if (MODE == 2)
             __hip_atomic_fetch_add(&U[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         else
@@ -485,72 +490,100 @@ __device__ void accumulate_rows(const StepArgs &a, const RoiDesc &rd, const Item
             const uint32_t bv = c.level_of(rv);
 #pragma unroll
             for (int k = 0; k < kGatherDirs; ++k)
-                if (db + k < d1 && nl[k] == c.label) add((uint32_t)(db + k - d0), bv, c.level_of(nr[k]));
+                if (db + k < d1 && nl[k] == c.label) {
+                    const uint32_t bw = c.level_of(nr[k]);
+                    add((uint32_t)(db + k - d0), bv, row_off(bv), bw, row_off(bw));
+                }
         }
     }
 }
 
-// 2D distance-1 accumulation by row sweep.  A wavefront covers 64 adjacent
-// columns (lanes 0..62 own their column, lane 63 only supplies the right
-// neighbour) of a unit of up to kSweepRows rows, and loads the labels and
-// values of all those rows and of the row above in one batch, so a unit costs
-// a single round trip to memory; it then walks down the unit keeping the
-// previous row's levels in registers, with right neighbours taken from the
-// next lane by a DPP wave shift.  Owned pairs per lane (column x, row y):
+// 2D distance-1 accumulation by row sweep.  A wavefront is split into S
+// sub-rows of Wl = 64/S lanes (S = 1, 2 or 4, chosen per item to need the
+// fewest steps for the tile's width); each step covers S consecutive image
+// rows of a strip of Wl - 1 owned columns (the last lane of a sub-row only
+// supplies the right neighbour).  A unit of kSweepSteps steps loads the labels
+// and values of all its rows, and of the row above it, in one batch, so it
+// costs a single round trip to memory; levels of the row above come from the
+// sub-row above in the same step (one lane permute), or from the last
+// sub-row's previous step, and right neighbours from the next lane by a DPP
+// wave shift.  Owned pairs per lane (column x, row y):
 //   H    (y, x)-(y, x+1)      V    (y, x)-(y-1, x)
 //   D45  (y, x)-(y-1, x+1)    D135 (y-1, x)-(y, x+1)
 // h, v, d45, d135 are the local direction slots of the four classes (-1: not
-// in this pass).  Units (63-column strip x row block) are dealt to the nw
+// in this pass).  Units (strip x block of rows) are dealt to the nw
 // wavefronts round robin; w is the caller's index among them.
-constexpr uint32_t kSweepRows = 8;
+constexpr uint32_t kSweepSteps = 8;
 
 __device__ __forceinline__ uint32_t lane_next(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false);  // wave_shl1
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true);  // wave_shl1; lane 63 reads 0
 }
 
 template <class Add>
 __device__ void accumulate_sweep2d(const RoiDesc &rd, const ItemCtx &c, uint32_t ra, uint32_t rb, uint32_t ca,
                                    uint32_t cb, int h, int v, int d45, int d135, int w, int nw, Add &&add) {
-    const int ln = lane();
-    const uint32_t Wt = cb - ca;
-    const uint32_t nstrip = (Wt + 62u) / 63u;
-    const uint32_t nchunk = (rb - ra + kSweepRows - 1u) / kSweepRows;
-    const uint32_t units = nstrip * nchunk;
+    const uint32_t ln = (uint32_t)lane();
+    const uint32_t Wt = cb - ca, H = rb - ra;
+    // sub-rows per step: the fewest steps over the tile (ties: fewer sub-rows)
+    uint32_t lg = 0, best = ((Wt + 62u) / 63u) * H;
+    for (uint32_t q = 1; q <= 2u; ++q) {
+        const uint32_t wo = (64u >> q) - 1u;
+        const uint32_t steps = ((Wt + wo - 1u) / wo) * ((H + (1u << q) - 1u) >> q);
+        if (steps < best) { best = steps; lg = q; }
+    }
+    const uint32_t S = 1u << lg, Wl = 64u >> lg, Wo = Wl - 1u;
+    const uint32_t sub = ln >> (6u - lg), col = ln & (Wl - 1u);
+    const uint32_t nstrip = (Wt + Wo - 1u) / Wo;
+    const uint32_t unit_rows = kSweepSteps * S;
+    const uint32_t units = nstrip * ((H + unit_rows - 1u) / unit_rows);
     const int32_t xt0 = rd.x0 + (int32_t)ca, xt1 = rd.x0 + (int32_t)cb;   // owned columns [xt0, xt1)
     const uint32_t nx = (uint32_t)c.nx;
+    const uint32_t up_lane = ((ln - Wl) & 63u) << 2;   // byte index of the lane above (permute address)
     for (uint32_t u = (uint32_t)w; u < units; u += (uint32_t)nw) {
         const uint32_t s = u % nstrip, ch = u / nstrip;
-        const int32_t x = xt0 + 63 * (int32_t)s + ln;
+        const int32_t x = xt0 + (int32_t)(Wo * s + col);
         const bool xin = x < c.nx && x <= xt1;   // owned columns and the right neighbour of the last
-        const bool owner = ln < 63 && x < xt1;
-        const uint32_t r0 = ra + ch * kSweepRows, nr = min(rb - r0, kSweepRows);
+        const bool owner = col < Wo && x < xt1;
+        const uint32_t r0 = ra + ch * unit_rows, nr = min(rb - r0, unit_rows);
         const int32_t y0 = rd.y0 + (int32_t)r0;
-        // batch row j is image row y0 - 1 + j; row 0 (above the unit) only
-        // inside the bounding box
-        uint32_t lab[kSweepRows + 1], val[kSweepRows + 1];
-        uint32_t idx = (uint32_t)(y0 - 1) * nx + (uint32_t)x;   // wraps for y0 = 0; row 0 is then unused
+        // step j: image row y0 + j S + sub; the last sub-row also fetches the
+        // row above the unit (its "previous step")
+        uint32_t lab[kSweepSteps], val[kSweepSteps], lab_up = 0u, val_up = 0u;
+        const uint32_t idx0 = (uint32_t)(y0 + (int32_t)sub) * nx + (uint32_t)x;
+        if (xin && sub == S - 1u && y0 > rd.y0) {
+            const uint32_t iu = (uint32_t)(y0 - 1) * nx + (uint32_t)x;
+            lab_up = c.lab(iu);
+            val_up = c.raw(iu);
+        }
 #pragma unroll
-        for (uint32_t j = 0; j <= kSweepRows; ++j, idx += nx) {
+        for (uint32_t j = 0; j < kSweepSteps; ++j) {
             lab[j] = 0u;
             val[j] = 0u;
-            const bool ok = xin && (j == 0 ? y0 > rd.y0 : j <= nr);
-            if (ok) {
+            if (xin && j * S + sub < nr) {
+                const uint32_t idx = idx0 + j * S * nx;
                 lab[j] = c.lab(idx);
                 val[j] = c.raw(idx);
             }
         }
-        uint32_t prev = lab[0] == c.label ? c.level_of(val[0]) : 0u;
+        uint32_t prev = lab_up == c.label ? c.level_of(val_up) : 0u;   // this lane's previous step
 #pragma unroll
-        for (uint32_t j = 1; j <= kSweepRows; ++j) {
-            if (j > nr) break;
+        for (uint32_t j = 0; j < kSweepSteps; ++j) {
+            if (j * S >= nr) break;
             const uint32_t cur = lab[j] == c.label ? c.level_of(val[j]) : 0u;
-            const uint32_t cur_r = lane_next(cur), prev_r = lane_next(prev);
-            if (owner && cur) {
-                if (h >= 0 && cur_r) add((uint32_t)h, cur, cur_r);
-                if (v >= 0 && prev) add((uint32_t)v, cur, prev);
-                if (d45 >= 0 && prev_r) add((uint32_t)d45, cur, prev_r);
+            uint32_t above = prev;
+            if (S > 1u) {
+                const uint32_t offer = sub == S - 1u ? prev : cur;
+                above = (uint32_t)__builtin_amdgcn_ds_bpermute((int)up_lane, (int)offer);
             }
-            if (owner && prev && cur_r && d135 >= 0) add((uint32_t)d135, prev, cur_r);
+            const uint32_t tcur = row_off(cur), tabove = row_off(above);
+            const uint32_t cur_r = lane_next(cur), above_r = lane_next(above);
+            const uint32_t tcur_r = lane_next(tcur), tabove_r = lane_next(tabove);
+            if (owner && cur) {
+                if (h >= 0 && cur_r) add((uint32_t)h, cur, tcur, cur_r, tcur_r);
+                if (v >= 0 && above) add((uint32_t)v, cur, tcur, above, tabove);
+                if (d45 >= 0 && above_r) add((uint32_t)d45, cur, tcur, above_r, tabove_r);
+            }
+            if (owner && above && cur_r && d135 >= 0) add((uint32_t)d135, above, tabove, cur_r, tcur_r);
             prev = cur;
         }
     }
@@ -673,7 +706,9 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
             for (int d0 = 0, pass = 0; d0 < K; d0 += (int)Ly.kp, ++pass) {
                 const int d1 = min(K, d0 + (int)Ly.kp);
                 if (ra < rb && ca < cb) {
-                    auto add = [&](uint32_t dl, uint32_t la, uint32_t lb) { add_pair<MODE>(a, smem, dl, la, lb); };
+                    auto add = [&](uint32_t dl, uint32_t la, uint32_t ta, uint32_t lb, uint32_t tb) {
+                        add_pair<MODE>(a, smem, dl, la, ta, lb, tb);
+                    };
                     if (a.sweep_ok && pass < kMaxSweepPasses)
                         accumulate_sweep2d(rd, c, ra, rb, ca, cb, a.sweep[pass][0], a.sweep[pass][1], a.sweep[pass][2],
                                            a.sweep[pass][3], w, nw, add);
@@ -778,9 +813,8 @@ __global__ __launch_bounds__(64) void k_wave(StepArgs a, uint32_t direct_roi) {
             c.rcpD = c.D ? 1.0f / (float)c.D : 0.0f;
             c.err = &a.counters[C_ERR];
             const uint32_t W = (uint32_t)(rd.x1 - rd.x0 + 1);
-            auto add = [&](uint32_t dl, uint32_t la, uint32_t lb) {
-                const uint32_t lo = (la < lb ? la : lb) - 1u, hi = (la < lb ? lb : la) - 1u;
-                const uint32_t i = tri_idx(lo, hi);
+            auto add = [&](uint32_t dl, uint32_t la, uint32_t ta, uint32_t lb, uint32_t tb) {
+                const uint32_t i = la <= lb ? tb + la : ta + lb;
                 uint32_t *Ud = U + dl * Ly.tri_pad;
                 if (PACKED)
                     __hip_atomic_fetch_add(&Ud[i >> 1], 1u << ((i & 1u) << 4), __ATOMIC_RELAXED,
