@@ -94,6 +94,35 @@ __device__ __forceinline__ T wave_reduce(T v, Op op) {
     return op(op(readlane_(v, 0), readlane_(v, 16)), op(readlane_(v, 32), readlane_(v, 48)));
 }
 
+// Each 16-bit half of w clamped to 1 (packed integer min): bit 0 and bit 16
+// of the result say whether the low and high halves are nonzero.
+__device__ __forceinline__ uint32_t nz_halves(uint32_t w) {
+    uint32_t r;
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(w), "v"(0x00010001u));
+    return r;
+}
+
+// Inclusive prefix sums by DPP: within each 16-lane row (row_shr 1, 2, 4, 8
+// with zero fill), then across rows (row_bcast 15 into rows 1 and 3,
+// row_bcast 31 into rows 2 and 3).
+template <int CTRL, int ROWS, bool BOUND>
+__device__ __forceinline__ uint32_t dpp_add(uint32_t v) {
+    return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, BOUND);
+}
+__device__ __forceinline__ uint32_t row_incl_scan(uint32_t x) {
+    x = dpp_add<0x111, 0xF, true>(x);
+    x = dpp_add<0x112, 0xF, true>(x);
+    x = dpp_add<0x114, 0xF, true>(x);
+    x = dpp_add<0x118, 0xF, true>(x);
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    x = row_incl_scan(x);
+    x = dpp_add<0x142, 0xA, false>(x);
+    x = dpp_add<0x143, 0xC, false>(x);
+    return x;
+}
+
 // Batched row reduction of kSumSlots doubles by recursive halving.  Each of
 // four exchange steps (row_mirror, row_half_mirror, quad_perm [2,3,0,1],
 // quad_perm [1,0,3,2]) pairs lanes that hold the same set of slots; one keeps

@@ -65,6 +65,12 @@ struct WaveGrp {
     }
     __device__ __forceinline__ double bcast(double v, int r) const { return readlane_(v, r); }
     __device__ __forceinline__ uint32_t bcast_u32(uint32_t v, int r) const { return readlane_(v, r); }
+    // exclusive prefix sum over the group; *total receives the group sum
+    __device__ __forceinline__ uint32_t excl_scan(uint32_t n, uint32_t *total) const {
+        const uint32_t x = wave_incl_scan(n);
+        *total = readlane_(x, kWave - 1);
+        return x - n;
+    }
     __device__ __forceinline__ void sync() const {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -85,6 +91,11 @@ struct RowGrp {
     __device__ __forceinline__ double reduce_pair(double a, double b) const { return row_reduce_pair(a, b); }
     __device__ __forceinline__ double bcast(double v, int r) const { return __shfl(v, r, 16); }
     __device__ __forceinline__ uint32_t bcast_u32(uint32_t v, int r) const { return __shfl(v, r, 16); }
+    __device__ __forceinline__ uint32_t excl_scan(uint32_t n, uint32_t *total) const {
+        const uint32_t x = row_incl_scan(n);
+        *total = (uint32_t)__shfl((int)x, 15, 16);
+        return x - n;
+    }
     __device__ __forceinline__ int row() const { return lane() >> 4; }
     __device__ __forceinline__ void sync() const {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -184,33 +195,35 @@ struct SrcTriScan {
             const uint32_t w0 = wbase + 4u * r;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
             if (w0 < words) v = *reinterpret_cast<const uint4 *>(U + w0);
-            uint32_t c[kPerRead];   // counters of the run (cells past tri are zero padding)
+            // nonzero flags of the run's cells (cells past tri are zero
+            // padding); packed: 0/1 in each 16-bit half
+            uint32_t f[4];
+            uint32_t n;
             if (PACKED) {
-                c[0] = v.x & 0xFFFFu; c[1] = v.x >> 16; c[2] = v.y & 0xFFFFu; c[3] = v.y >> 16;
-                c[4] = v.z & 0xFFFFu; c[5] = v.z >> 16; c[6] = v.w & 0xFFFFu; c[7] = v.w >> 16;
+                f[0] = nz_halves(v.x); f[1] = nz_halves(v.y); f[2] = nz_halves(v.z); f[3] = nz_halves(v.w);
+                const uint32_t s = f[0] + f[1] + f[2] + f[3];
+                n = (s & 0xFFFFu) + (s >> 16);
             } else {
-                c[0] = v.x; c[1] = v.y; c[2] = v.z; c[3] = v.w;
+                f[0] = v.x != 0u; f[1] = v.y != 0u; f[2] = v.z != 0u; f[3] = v.w != 0u;
+                n = f[0] + f[1] + f[2] + f[3];
             }
-            uint32_t n = 0;
-#pragma unroll
-            for (uint32_t k = 0; k < kPerRead; ++k) n += c[k] != 0u ? 1u : 0u;
-            // exclusive prefix of n (<= 8) over the group and its total
-            uint32_t pos = 0, cnt = 0;
-#pragma unroll
-            for (uint32_t b = 0; b < 4u; ++b) {
-                const uint64_t m = g.ballot(((n >> b) & 1u) != 0u);
-                pos += (uint32_t)__popcll(m & g.below()) << b;
-                cnt += (uint32_t)__popcll(m) << b;
-            }
+            uint32_t cnt;
+            const uint32_t pos = g.excl_scan(n, &cnt);
             if (held + cnt > cap) {
                 flush(g, held, fn);
                 held = 0;
             }
-            pos += held;
+            uint32_t *p = buf + held + pos;
             const uint32_t i0 = PACKED ? 2u * w0 : w0;   // first cell of the run
 #pragma unroll
-            for (uint32_t k = 0; k < kPerRead; ++k)
-                if (c[k] != 0u) buf[pos++] = i0 + k;
+            for (uint32_t k = 0; k < 4u; ++k) {
+                if (PACKED) {
+                    if (f[k] & 0xFFFFu) *p++ = i0 + 2u * k;
+                    if (f[k] >> 16) *p++ = i0 + 2u * k + 1u;
+                } else {
+                    if (f[k]) *p++ = i0 + k;
+                }
+            }
             held += cnt;
         }
         if (held) flush(g, held, fn);
