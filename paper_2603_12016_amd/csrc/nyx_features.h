@@ -443,7 +443,7 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
     // Level sweeps over the marginals (unnormalised).
     ISum S1 = 0, S2 = 0, Sm1 = 0;
     LaneSum<Acc> rlr, slp, hom1, hom2, idmn, idn, iv, plps;
-    const Acc ngf = (Acc)ng;
+    const Acc ngf = (Acc)ng, rng = (Acc)1 / ngf, rng2 = rng * rng;
     for (uint32_t i = r0; i < ng; i += gs) {
         const uint32_t r = R[i];
         if (r) {
@@ -459,8 +459,8 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
             slp.add(sf * term_log2<Acc>(sf));
             hom1.add(term_div<Acc>(sf, (Acc)1 + k));
             hom2.add(term_div<Acc>(sf, (Acc)1 + k * k));
-            idmn.add(term_div<Acc>(sf, (Acc)1 + (k * k) / (ngf * ngf)));
-            idn.add(term_div<Acc>(sf, (Acc)1 + k / ngf));
+            idmn.add(term_div<Acc>(sf, (Acc)1 + (k * k) * rng2));
+            idn.add(term_div<Acc>(sf, (Acc)1 + k * rng));
             if (i > 0) iv.add(term_div<Acc>(sf, k * k));
         }
     }
