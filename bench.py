@@ -26,10 +26,107 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+COPY_BYTES = 1 << 30    # the copy kernel's size (read and written once per rep)
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+KERNEL_SYMBOLS = {"k_batch": "nyx::k_batch<", "k_scan": "nyx::k_scan(", "k_wave": "nyx::k_wave<"}
+COPY_SYMBOL = "k_copy("
+
+
+def source_digest() -> str:
+    """Digest of the HIP sources: a stored traffic measurement is used only
+    while the kernels it was taken on are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2603_12016_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_path(kernel: str, workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+
+
+def stored_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from two rocprofv3 counter runs
+    (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by what the
+    same counter reads for a copy kernel of known size in the same process;
+    None if absent or taken on other sources."""
+    try:
+        with open(traffic_path(kernel, workload)) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_digest") != source_digest():
+        return None
+    return t["fetch_kib"] * 1024.0 * t["fetch_scale"] + t["write_kib"] * 1024.0 * t["write_scale"]
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, workload: str, copy_bytes: int, command: str) -> None:
+    """Writes profiles/<kernel>_<workload>_traffic.txt (JSON) for every kernel in
+    KERNEL_SYMBOLS from the counter CSVs of a FETCH_SIZE and a WRITE_SIZE run
+    of this script (which runs the copy kernel on copy_bytes once per rep)."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        vals = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                for k, sym in list(KERNEL_SYMBOLS.items()) + [("copy", COPY_SYMBOL)]:
+                    if sym in r["Kernel_Name"]:
+                        vals.setdefault(k, []).append(float(r["Counter_Value"]))
+        return {k: statistics.median(v) for k, v in vals.items()}
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    fs = copy_bytes / (fetch["copy"] * 1024.0)
+    ws = copy_bytes / (write["copy"] * 1024.0)
+    for k in KERNEL_SYMBOLS:
+        if k not in fetch or k not in write:
+            continue
+        rec = {"kernel": k, "workload": workload, "source_digest": source_digest(),
+               "fetch_kib": fetch[k], "write_kib": write[k], "fetch_scale": fs, "write_scale": ws,
+               "copy_kernel": {"bytes_read": copy_bytes, "bytes_written": copy_bytes,
+                               "fetch_kib": fetch["copy"], "write_kib": write["copy"]},
+               "bytes_per_launch": fetch[k] * 1024.0 * fs + write[k] * 1024.0 * ws,
+               "command": command}
+        with open(traffic_path(k, workload), "w") as f:
+            json.dump(rec, f, indent=1)
+        log(f"{k}: {rec['bytes_per_launch'] / 1e9:.3f} GB per launch -> {traffic_path(k, workload)}")
+
+
+def summarize_trace(stats_csv: str, workload: str, command: str, top: int = 14) -> None:
+    """Writes profiles/<kernel>_<workload>.md for the dominant kernels from a
+    rocprofv3 --kernel-trace --stats kernel_stats.csv of this script."""
+    import csv
+    with open(stats_csv) as f:
+        rows = list(csv.DictReader(f))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel trace: {workload}", "", "Command (from the repository root on the GPU host):", "",
+             f"    {command}", "", f"Sources: `paper_2603_12016_amd/csrc` digest {source_digest()}.", "",
+             "| kernel | calls | total us | average us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = r["Name"].replace("|", "/")
+        if len(name) > 90:
+            name = name[:87] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    for k, sym in KERNEL_SYMBOLS.items():
+        if any(sym in r["Name"] for r in rows):
+            path = os.path.join(ROOT, "profiles", f"{k}_{workload}.md")
+            with open(path, "w") as f:
+                f.write("\n".join(lines) + "\n")
+            log(f"wrote {path}")
+            break
 
 
 def cpu_model() -> str:
@@ -90,7 +187,18 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/*_traffic.txt from rocprofv3 counter CSVs of this script and exit")
+    ap.add_argument("--summarize-trace", metavar="STATS_CSV",
+                    help="write profiles/<kernel>_<workload>.md from a rocprofv3 kernel_stats.csv and exit")
+    ap.add_argument("--pmc-command", default="", help="the command the profile CSVs came from (recorded)")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.workload, args.pmc_command)
+        return 0
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, COPY_BYTES, args.pmc_command)
+        return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures a single GPU; multi-GPU runs are not part of this build (use --gpus 1)",
               file=sys.stderr)
@@ -198,7 +306,7 @@ def main() -> int:
     machine = {}
     try:
         from paper_2603_12016_amd import micro
-        machine = {"copy_GBps": micro.copy_bandwidth()["GBps"], "read_GBps": micro.read_bandwidth()["GBps"],
+        machine = {"copy_GBps": micro.copy_bandwidth(COPY_BYTES)["GBps"], "read_GBps": micro.read_bandwidth()["GBps"],
                    "lds_atomics_per_s": micro.lds_atomic_rate()["per_second"]}
         log("machine: " + ", ".join(f"{k}={v:.4g}" for k, v in machine.items()))
     except (ImportError, OSError, RuntimeError) as e:
@@ -233,7 +341,9 @@ def main() -> int:
                         "achieved_per_s": pairs / (sum(prof[p] for p in ("batch", "wave", "split")) * 1e-3)},
         "machine": machine,
         "roofline": {"kernel": kernel_names[dom], "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": stored_traffic(kernel_names[dom], args.workload),
+                     "alg_bytes": alg[dom], "ms": prof[dom]},
         "plan_seconds": plan_s,
     }
     if not args.no_cpu_baseline:
