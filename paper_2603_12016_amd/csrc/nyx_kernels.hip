@@ -86,14 +86,14 @@ __global__ void k_zero_split(StepArgs a) {
 }
 
 // ------------------------------------------------------------------ scan
-// ROI discovery.  A work-group covers a tile of kScanRows image rows (rows
-// of all z-planes, flattened) by kScanCols columns; each lane walks one row
-// segment, cutting it into runs of equal label.  Each run's statistics are
+// ROI discovery.  A work-group covers a tile of kScanTileRows image rows (rows
+// of all z-planes, flattened) by kScanTileCols columns; each lane walks one
+// column down the tile, cutting it into vertical runs of equal label (a run
+// also ends at a z-plane boundary).  Every load of the wave is one contiguous
+// row segment, so the reads are fully coalesced.  Each run's statistics are
 // folded into an LDS table keyed by label, and the table is flushed to the
 // global per-label entries once per tile.  A label that finds no free LDS
 // slot goes straight to the global entry.
-constexpr int kScanRows = 256;
-constexpr int kScanCols = 32;
 constexpr int kScanSlots = 256;
 
 struct ScanLds {
@@ -112,8 +112,9 @@ __device__ __forceinline__ void scan_flush_global(const StepArgs &a, uint32_t K,
     atomicMin(&a.tab.z0[K], z0); atomicMax(&a.tab.z1[K], z1);
 }
 
+// A vertical run at column x, rows y0..y1 of plane z.
 __device__ __forceinline__ void scan_flush_run(const StepArgs &a, ScanLds &S, uint32_t K, uint32_t c, uint32_t mn,
-                                               uint32_t mx, int32_t x0, int32_t x1, int32_t y, int32_t z) {
+                                               uint32_t mx, int32_t x, int32_t y0, int32_t y1, int32_t z) {
     uint32_t h = hash_u32(K) & (kScanSlots - 1);
     for (int probe = 0; probe < 8; ++probe) {
         uint32_t cur = atomicCAS(&S.key[h], kNone, K);
@@ -121,14 +122,14 @@ __device__ __forceinline__ void scan_flush_run(const StepArgs &a, ScanLds &S, ui
             atomicAdd(&S.cnt[h], c);
             atomicMin(&S.mn[h], mn);
             atomicMax(&S.mx[h], mx);
-            atomicMin(&S.x0[h], x0); atomicMax(&S.x1[h], x1);
-            atomicMin(&S.y0[h], y); atomicMax(&S.y1[h], y);
+            atomicMin(&S.x0[h], x); atomicMax(&S.x1[h], x);
+            atomicMin(&S.y0[h], y0); atomicMax(&S.y1[h], y1);
             atomicMin(&S.z0[h], z); atomicMax(&S.z1[h], z);
             return;
         }
         h = (h + 1u) & (kScanSlots - 1);
     }
-    scan_flush_global(a, K, c, mn, mx, x0, x1, y, y, z, z);
+    scan_flush_global(a, K, c, mn, mx, x, x, y0, y1, z, z);
 }
 
 __global__ __launch_bounds__(256) void k_scan(StepArgs a) {
@@ -141,61 +142,50 @@ __global__ __launch_bounds__(256) void k_scan(StepArgs a) {
     const uint32_t tile = blockIdx.x;
     const int im = find_image_chunk(a.imgs, a.n_images, tile);
     const ImgDesc d = a.imgs[im];
-    const uint32_t nxc = ((uint32_t)d.nx + kScanCols - 1u) / kScanCols;
+    const uint32_t nxc = ((uint32_t)d.nx + kScanTileCols - 1u) / kScanTileCols;
     const uint32_t t = tile - d.chunk_base;
     const uint32_t rblk = t / nxc, cblk = t - rblk * nxc;
     const uint32_t rows = (uint32_t)d.nz * (uint32_t)d.ny;
-    const uint32_t row = rblk * kScanRows + threadIdx.x;
-    const int32_t xs = (int32_t)(cblk * kScanCols);
-    const int32_t ncol = min(kScanCols, d.nx - xs);
+    const uint32_t row0 = rblk * kScanTileRows;
+    const int32_t x = (int32_t)(cblk * kScanTileCols + threadIdx.x);
     __syncthreads();
-    if (row < rows && im < a.n_images) {
-        const int32_t z = (int32_t)(row / (uint32_t)d.ny), y = (int32_t)(row - (uint32_t)z * (uint32_t)d.ny);
-        const uint64_t base = (uint64_t)row * (uint32_t)d.nx + (uint32_t)xs;
-        uint32_t lab[kScanCols], val[kScanCols];
-        if (d.vec_ok && ncol == kScanCols) {
-            const uint4 *pl = reinterpret_cast<const uint4 *>(d.L + base);
-            const uint4 *pi = reinterpret_cast<const uint4 *>(d.I + base);
+    if (x < d.nx && row0 < rows && im < a.n_images) {
+        const uint32_t nr = min((uint32_t)kScanTileRows, rows - row0);
+        const uint32_t nx = (uint32_t)d.nx;
+        uint32_t lab[kScanTileRows], val[kScanTileRows];
+        const uint32_t base = row0 * nx + (uint32_t)x;
 #pragma unroll
-            for (int q = 0; q < kScanCols / 4; ++q) {
-                uint4 v = pl[q];
-                lab[4 * q] = v.x; lab[4 * q + 1] = v.y; lab[4 * q + 2] = v.z; lab[4 * q + 3] = v.w;
-            }
-#pragma unroll
-            for (int q = 0; q < kScanCols / 8; ++q) {
-                uint4 v = pi[q];
-                val[8 * q + 0] = v.x & 0xFFFFu; val[8 * q + 1] = v.x >> 16;
-                val[8 * q + 2] = v.y & 0xFFFFu; val[8 * q + 3] = v.y >> 16;
-                val[8 * q + 4] = v.z & 0xFFFFu; val[8 * q + 5] = v.z >> 16;
-                val[8 * q + 6] = v.w & 0xFFFFu; val[8 * q + 7] = v.w >> 16;
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < kScanCols; ++j) {
-                bool ok = j < ncol;
-                lab[j] = ok ? d.L[base + j] : 0u;
-                val[j] = ok ? (uint32_t)d.I[base + j] : 0u;
+        for (uint32_t j = 0; j < kScanTileRows; ++j) {
+            lab[j] = 0u;
+            val[j] = 0u;
+            if (j < nr) {
+                lab[j] = ldg(d.L, base + j * nx);
+                val[j] = ldg(d.I, base + j * nx);
             }
         }
+        // plane and row of the tile's first row (tile rows are uniform)
+        int32_t z = (int32_t)(row0 / (uint32_t)d.ny), y = (int32_t)(row0 - (uint32_t)z * (uint32_t)d.ny);
         uint32_t bad = 0u;
         uint32_t cur = 0u, c = 0u, mn = 0xFFFFu, mx = 0u;
-        int32_t rx0 = 0, rx1 = 0;
+        int32_t ry0 = 0, ry1 = 0, rz = 0;
 #pragma unroll
-        for (int j = 0; j < kScanCols; ++j) {
+        for (uint32_t j = 0; j < kScanTileRows; ++j) {
+            if (j >= nr) break;
             uint32_t l = lab[j];
             if (l > d.max_label) { bad = 1u; l = 0u; }
-            if (l != cur) {
-                if (cur) scan_flush_run(a, S, d.tab_base + cur, c, mn, mx, rx0, rx1, y, z);
-                cur = l; c = 0u; mn = 0xFFFFu; mx = 0u; rx0 = xs + j;
+            if (l != cur || z != rz) {
+                if (cur) scan_flush_run(a, S, d.tab_base + cur, c, mn, mx, x, ry0, ry1, rz);
+                cur = l; c = 0u; mn = 0xFFFFu; mx = 0u; ry0 = y; rz = z;
             }
             if (l) {
                 ++c;
                 mn = min(mn, val[j]);
                 mx = max(mx, val[j]);
-                rx1 = xs + j;
+                ry1 = y;
             }
+            if (++y == d.ny) { y = 0; ++z; }
         }
-        if (cur) scan_flush_run(a, S, d.tab_base + cur, c, mn, mx, rx0, rx1, y, z);
+        if (cur) scan_flush_run(a, S, d.tab_base + cur, c, mn, mx, x, ry0, ry1, rz);
         if (bad) atomicOr(&a.counters[C_ERR], (uint32_t)E_LABEL_RANGE);
     }
     __syncthreads();
@@ -1031,7 +1021,7 @@ hipError_t launch_zero_split(const StepArgs &a, hipStream_t st) {
 
 hipError_t launch_scan(const StepArgs &a, hipStream_t st) {
     if (a.total_chunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scan, dim3(a.total_chunks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_scan, dim3(a.total_chunks), dim3(kScanTileCols), 0, st, a);
     NYX_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -190,11 +190,11 @@ nyx_status discover(nyx_ctx *ctx, const nyx_image *imgs, int32_t n, Work &w, hip
         d.nvox = (uint32_t)(imgs[i].nz * imgs[i].ny * imgs[i].nx);
         d.chunk_base = chunk;
         {
-            // scan tiles: 256 rows (all planes flattened) by 32 columns
+            // discovery tiles: kScanTileRows rows (all planes flattened) by kScanTileCols columns
             uint64_t rows = (uint64_t)d.nz * (uint64_t)d.ny;
-            chunk += (uint32_t)(((rows + 255u) / 256u) * (((uint64_t)d.nx + 31u) / 32u));
+            chunk += (uint32_t)(((rows + kScanTileRows - 1u) / kScanTileRows) *
+                                (((uint64_t)d.nx + kScanTileCols - 1u) / kScanTileCols));
         }
-        d.vec_ok = ((uintptr_t)d.I % 16 == 0) && ((uintptr_t)d.L % 16 == 0) && (d.nx % 8 == 0);
         vbase[i] = tv;
         tv += d.nvox;
     }

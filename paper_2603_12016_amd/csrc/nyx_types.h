@@ -49,7 +49,6 @@ struct ImgDesc {
     uint32_t tab_base;     // label-table index of label 0 of this image
     uint32_t max_label;    // label-table capacity of this image (labels 0..max_label)
     uint32_t chunk_base;   // first scan tile of this image
-    uint32_t vec_ok;       // 1: 16-byte aligned base pointers and nx % 8 == 0
 };
 
 // Per-label statistics, one entry per (image, label), struct of arrays.
@@ -88,6 +87,10 @@ struct DirSums {
 };
 static_assert(sizeof(DirSums) == 160, "DirSums layout");
 constexpr int kSumSlots = 16;
+// ROI discovery tiles: rows (of all z-planes, flattened) x columns; one
+// work-group of kScanTileCols threads per tile.
+constexpr uint32_t kScanTileRows = 32;
+constexpr uint32_t kScanTileCols = 256;
 // Compaction buffer entries (u32 cell indices) per lane of an ordered
 // triangle scan (one 16-byte read: at most 8 packed counters).
 constexpr int kScanCells = 8;
