@@ -339,14 +339,47 @@ __global__ __launch_bounds__(256) void k_bin_image(StepArgs a, uint16_t *bins_ou
 }
 
 // ------------------------------------------------------------------ batch
-// Exact q = f / W for f < 2^31 and 1 <= W < 2^31: the double-precision
-// estimate is within one of the quotient.
-__device__ __forceinline__ uint32_t udiv_exact(uint32_t f, uint32_t W, double rcpW) {
-    int64_t q = (int64_t)((double)f * rcpW);
-    int64_t r = (int64_t)f - q * (int64_t)W;
-    if (r < 0) { --q; r += (int64_t)W; }
-    if (r >= (int64_t)W) { ++q; }
-    return (uint32_t)q;
+// ------------------------------------------------------------------ work queue
+// The queue is the concatenation of the size-class buckets, largest class
+// first.  A ticket (one atomic increment) hands out up to ticket_chunk(cl)
+// consecutive entries of one class: several small items per ticket, one
+// item per ticket from the classes whose items alone keep a work-group busy,
+// so the last tickets of a launch are short.
+__device__ __forceinline__ uint32_t ticket_chunk(int cl) {
+    const uint32_t c = kTicketVox >> cl;
+    return c < 1u ? 1u : (c > (uint32_t)kTicketChunk ? (uint32_t)kTicketChunk : c);
+}
+
+// misc[64 + cl]: first ticket of class cl; misc[96 + cl]: its entries
+// (clamped to the bucket capacity); misc[63]: number of tickets.
+__device__ void ticket_setup(uint32_t *misc, const uint32_t *cls_cnt, uint32_t cap) {
+    uint32_t acc = 0;
+    for (int cl = kClasses - 1; cl >= 0; --cl) {
+        const uint32_t cnt = min(cls_cnt[cl], cap), ch = ticket_chunk(cl);
+        misc[64 + cl] = acc;
+        misc[96 + cl] = cnt;
+        acc += (cnt + ch - 1u) / ch;
+    }
+    misc[63] = acc;
+}
+
+// Claims a ticket and writes its entries as (roi, tile) pairs to misc[0..);
+// returns how many (0 once the queue is drained).
+__device__ uint32_t ticket_claim(uint32_t *misc, uint32_t *ctr, const uint2 *buckets, uint32_t cap) {
+    const uint32_t t = atomicAdd(ctr, 1u);
+    if (t >= misc[63]) return 0u;
+    int cl = kClasses - 1;
+    const auto end_of = [&](int c) { return misc[64 + c] + (misc[96 + c] + ticket_chunk(c) - 1u) / ticket_chunk(c); };
+    while (cl > 0 && t >= end_of(cl)) --cl;
+    const uint32_t ch = ticket_chunk(cl), e0 = (t - misc[64 + cl]) * ch;
+    const uint32_t e1 = min(e0 + ch, misc[96 + cl]);
+    uint32_t n = 0;
+    for (uint32_t e = e0; e < e1; ++e, ++n) {
+        const uint2 it = buckets[(uint32_t)cl * cap + e];
+        misc[2 * n] = it.x;
+        misc[2 * n + 1] = it.y;
+    }
+    return n;
 }
 
 struct ItemCtx {
@@ -447,18 +480,19 @@ template <class Add>
 __device__ void accumulate_rows(const StepArgs &a, const RoiDesc &rd, const ItemCtx &c, uint32_t ra, uint32_t rb,
                                 uint32_t ca, uint32_t cb, int d0, int d1, uint32_t t0, uint32_t ts, Add &&add) {
     const uint32_t W = cb - ca, H = (uint32_t)(rd.y1 - rd.y0 + 1);
-    const double rcpW = 1.0 / (double)W, rcpH = 1.0 / (double)H;
     const uint32_t nv = (rb - ra) * W;
     const uint32_t plane = (uint32_t)c.ny * (uint32_t)c.nx;
+    // voxel f = t0 + k ts of the tile: column xo = f % W, row ra + f / W of
+    // the flattened bbox rows (plane zq, row yo), advanced incrementally
+    const uint32_t dq = ts / W, dxo = ts - dq * W;
+    uint32_t xo = t0 % W, yo = ra + t0 / W, zq = 0;
+    if (yo >= H) { zq = yo / H; yo -= zq * H; }
     for (uint32_t f = t0; f < nv; f += ts) {
-        const uint32_t q = udiv_exact(f, W, rcpW);
-        const int32_t x = rd.x0 + (int32_t)ca + (int32_t)(f - q * W);
-        const uint32_t rr = ra + q;
-        const uint32_t zq = udiv_exact(rr, H, rcpH);
-        const int32_t y = rd.y0 + (int32_t)(rr - zq * H);
+        const int32_t x = rd.x0 + (int32_t)(ca + xo);
+        const int32_t y = rd.y0 + (int32_t)yo;
         const int32_t z = rd.z0 + (int32_t)zq;
         const uint32_t v = (uint32_t)z * plane + (uint32_t)y * (uint32_t)c.nx + (uint32_t)x;
-        const uint32_t lv = c.lab(v), rv = c.raw(v);
+        uint32_t lv = c.lab(v), rv = c.raw(v);
         for (int db = d0; db < d1; db += kGatherDirs) {
             uint32_t nl[kGatherDirs], nr[kGatherDirs];
 #pragma unroll
@@ -476,6 +510,8 @@ __device__ void accumulate_rows(const StepArgs &a, const RoiDesc &rd, const Item
                     }
                 }
             }
+            // every load of the group is issued before the first use
+            asm volatile("" : "+v"(lv), "+v"(rv));
             if (lv != c.label) continue;
             const uint32_t bv = c.level_of(rv);
 #pragma unroll
@@ -484,6 +520,15 @@ __device__ void accumulate_rows(const StepArgs &a, const RoiDesc &rd, const Item
                     const uint32_t bw = c.level_of(nr[k]);
                     add((uint32_t)(db + k - d0), bv, row_off(bv), bw, row_off(bw));
                 }
+        }
+        xo += dxo;
+        uint32_t adv = dq;
+        if (xo >= W) { xo -= W; ++adv; }
+        yo += adv;
+        if (yo >= H) {
+            const uint32_t k2 = yo / H;
+            zq += k2;
+            yo -= k2 * H;
         }
     }
 }
@@ -630,21 +675,10 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
     for (uint32_t i = threadIdx.x; i < min((uint32_t)nw, Ly.kp) * marg_words; i += blockDim.x)
         reinterpret_cast<uint32_t *>(smem + Ly.marg_off)[i] = 0u;
     for (uint32_t i = threadIdx.x; i < Ly.kp; i += blockDim.x) LCNT[i] = 0u;
-    if (threadIdx.x == 0 && direct_roi == kNone) {
-        // class order: largest first; counts clamped to what the buckets hold
-        uint32_t acc = 0;
-        for (int cl = kClasses - 1; cl >= 0; --cl) {
-            uint32_t cnt = min(a.counters[C_CLASS + cl], a.bucket_cap);
-            MISC[64 + cl] = acc;
-            MISC[96 + cl] = cnt;
-            acc += cnt;
-        }
-        MISC[63] = acc;
-    }
+    if (threadIdx.x == 0 && direct_roi == kNone) ticket_setup(MISC, a.counters + C_CLASS, a.bucket_cap);
     __syncthreads();
 
     for (uint32_t iter = 0;; ++iter) {
-        // A chunk of up to kTicketChunk consecutive queue entries per ticket.
         if (threadIdx.x == 0) {
             uint32_t n = 0;
             if (direct_roi != kNone) {
@@ -654,17 +688,7 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
                     n = 1;
                 }
             } else {
-                const uint32_t total = MISC[63];
-                uint32_t t = atomicAdd(&a.counters[C_TICKET], (uint32_t)kTicketChunk);
-                for (uint32_t q = 0; q < (uint32_t)kTicketChunk && t + q < total; ++q) {
-                    uint32_t tt = t + q;
-                    int cl = kClasses - 1;
-                    while (cl > 0 && tt >= MISC[64 + cl] + MISC[96 + cl]) --cl;
-                    uint2 it = a.buckets[(uint32_t)cl * a.bucket_cap + (tt - MISC[64 + cl])];
-                    MISC[2 * n] = it.x;
-                    MISC[2 * n + 1] = it.y;
-                    ++n;
-                }
+                n = ticket_claim(MISC, &a.counters[C_TICKET], a.buckets, a.bucket_cap);
             }
             MISC[32] = n;
         }
@@ -753,16 +777,7 @@ __global__ __launch_bounds__(64) void k_wave(StepArgs a, uint32_t direct_roi) {
     const WaveGrp wg;
     for (uint32_t i = ln; i < (uint32_t)K * Ly.tri_pad; i += kWave) U[i] = 0u;
     for (uint32_t i = ln; i < (uint32_t)K * 4u * ng; i += kWave) MARG[i] = 0u;
-    if (ln == 0 && direct_roi == kNone) {
-        uint32_t acc = 0;
-        for (int cl = kClasses - 1; cl >= 0; --cl) {
-            uint32_t cnt = min(a.counters[C_CLASS_W + cl], a.bucket_cap);
-            MISC[64 + cl] = acc;
-            MISC[96 + cl] = cnt;
-            acc += cnt;
-        }
-        MISC[63] = acc;
-    }
+    if (ln == 0 && direct_roi == kNone) ticket_setup(MISC, a.counters + C_CLASS_W, a.bucket_cap);
     wg.sync();
     for (uint32_t iter = 0;; ++iter) {
         if (ln == 0) {
@@ -770,17 +785,7 @@ __global__ __launch_bounds__(64) void k_wave(StepArgs a, uint32_t direct_roi) {
             if (direct_roi != kNone) {
                 if (iter == 0 && direct_roi < a.roi_cap) { MISC[0] = direct_roi; MISC[1] = 0u; n = 1; }
             } else {
-                const uint32_t total = MISC[63];
-                uint32_t t = atomicAdd(&a.counters[C_TICKET_W], (uint32_t)kTicketChunk);
-                for (uint32_t q = 0; q < (uint32_t)kTicketChunk && t + q < total; ++q) {
-                    uint32_t tt = t + q;
-                    int cl = kClasses - 1;
-                    while (cl > 0 && tt >= MISC[64 + cl] + MISC[96 + cl]) --cl;
-                    uint2 it = a.buckets_w[(uint32_t)cl * a.bucket_cap + (tt - MISC[64 + cl])];
-                    MISC[2 * n] = it.x;
-                    MISC[2 * n + 1] = it.y;
-                    ++n;
-                }
+                n = ticket_claim(MISC, &a.counters[C_TICKET_W], a.buckets_w, a.bucket_cap);
             }
             MISC[32] = n;
         }

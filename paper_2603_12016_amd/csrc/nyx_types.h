@@ -12,7 +12,8 @@ constexpr int kNumFeat = 30;
 constexpr int kMaxOffsets = 64;
 constexpr int kClasses = 32;           // work-item size classes (log2 of voxels)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr int kTicketChunk = 8;        // queue entries taken per work ticket
+constexpr int kTicketChunk = 8;        // most queue entries taken per work ticket
+constexpr uint32_t kTicketVox = 8192u; // voxels a ticket of small items aims at
 constexpr int kMaxSweepPasses = 16;    // passes with a precomputed 2D sweep map
 
 // Counter slots (u32) in the device counter block.
