@@ -193,8 +193,7 @@ typedef enum nyx_phase {
     NYX_PHASE_RESET = 0,     /* clear per-label statistics and counters */
     NYX_PHASE_SCAN = 1,      /* ROI discovery: count, min, max, bbox per label */
     NYX_PHASE_COMPACT = 2,   /* ROI table and size-sorted work queue */
-    NYX_PHASE_ZERO = 3,      /* clear the global matrices of split ROIs; on the gather path
-                                (3D or other offsets) also write the per-voxel level image */
+    NYX_PHASE_ZERO = 3,      /* clear the global matrices of split ROIs */
     NYX_PHASE_BATCH = 4,     /* binning, co-occurrence counts, reduced sums (work-group per item) */
     NYX_PHASE_WAVE = 5,      /* the same for small ROIs, one wavefront per ROI */
     NYX_PHASE_SPLIT = 6,     /* reduced sums of split ROIs from their merged global matrices */

@@ -111,8 +111,6 @@ struct nyx_plan {
     std::string desc;
     int64_t workspace_bytes = 0;
     float tuned_ms = 0.f;
-    bool prebin = false;               // level image written before the batch (gather accumulation)
-    DevBuf bins;
     struct Cfg { int mode; uint32_t kp, block, split_vox, tile_vox, list_cap, hash_cap; int force_split; uint32_t wave_vox; };
     Cfg cfg{};
 };
@@ -602,7 +600,6 @@ nyx_status enqueue_step(nyx_plan *p, hipStream_t st, bool per_roi) {
     HIPC(ctx, launch_scan(a, st));
     HIPC(ctx, launch_compact(a, 0u, 0xFFFFFFFFu, st));
     HIPC(ctx, launch_zero_split(a, st));
-    if (p->prebin) HIPC(ctx, launch_bin_image(a, p->bins.as<uint16_t>(), p->w.total_vox, p->w.vox_base.as<uint64_t>(), st));
     if (!per_roi) {
         HIPC(ctx, launch_batch(a, p->grid, p->block, kNone, st));
         if (a.wave_ok) HIPC(ctx, launch_wave(a, p->wgrid, kNone, st));
@@ -639,11 +636,10 @@ std::string describe(const Config &c, const nyx_plan *p, uint64_t items, uint32_
     snprintf(buf, sizeof buf,
              "mode=%s kp=%u block=%u grid=%u lds=%uB split_vox=%u tile_vox=%u list_cap=%u hash_cap=%u "
              "wave_vox=%u wave_grid=%u wave_lds=%uB wave_rois=%u wave_roi_voxels=%llu rois=%u items=%llu "
-             "split_rois=%u ng=%d K=%d prebin=%d",
+             "split_rois=%u ng=%d K=%d",
              mode_name(c.mode), c.kp, c.block, p->grid, p->w.args.lds.bytes, c.split_vox, c.tile_vox,
              c.list_cap, c.hash_cap, p->w.args.wave_max_vox, p->wgrid, p->w.args.wlds.bytes, wave_rois,
-             (unsigned long long)wave_voxels, p->w.n_rois, (unsigned long long)items, n_split, p->ng, p->K,
-             (int)p->prebin);
+             (unsigned long long)wave_voxels, p->w.n_rois, (unsigned long long)items, n_split, p->ng, p->K);
     return buf;
 }
 
@@ -654,19 +650,6 @@ nyx_status configure(nyx_plan *p, const Config &cfg, const nyx_extract_opts *opt
                               opts->workspace_cap_bytes, &p->workspace_bytes);
     if (s != NYX_OK) return s;
     p->block = cfg.block;
-    // Gather accumulation (3D, or offsets other than the four distance-1
-    // in-plane classes) looks up every voxel's level once per offset that
-    // reaches it: write the level image once per step instead, and let the
-    // batch kernel read levels.
-    p->prebin = !p->w.args.sweep_ok;
-    if (p->prebin) {
-        if (!p->bins.p) HIPC(ctx, p->bins.alloc(std::max<uint64_t>(p->w.total_vox, 1u) * sizeof(uint16_t)));
-        uint64_t off = 0;
-        for (ImgDesc &d : p->w.h_imgs) { d.B = p->bins.as<uint16_t>() + off; off += d.nvox; }
-    } else {
-        for (ImgDesc &d : p->w.h_imgs) d.B = nullptr;
-    }
-    HIPC(ctx, hipMemcpy(p->w.imgs.p, p->w.h_imgs.data(), sizeof(ImgDesc) * p->w.h_imgs.size(), hipMemcpyHostToDevice));
     int occ = 0;
     HIPC(ctx, batch_occupancy(cfg.mode, p->prec == NYX_FP64, cfg.block, p->w.args.lds.bytes, &occ));
     p->grid = (uint32_t)ctx->n_cu * (uint32_t)std::max(occ, 1);
@@ -1069,8 +1052,6 @@ nyx_status nyx_plan_profile(nyx_plan *p, void *table, float *ms_host, nyx_stream
     if (he == hipSuccess) he = launch_compact(a, 0u, 0xFFFFFFFFu, st);
     if (he == hipSuccess) he = hipEventRecord(ev[3], st);
     if (he == hipSuccess) he = launch_zero_split(a, st);
-    if (he == hipSuccess && p->prebin)
-        he = launch_bin_image(a, p->bins.as<uint16_t>(), p->w.total_vox, p->w.vox_base.as<uint64_t>(), st);
     if (he == hipSuccess) he = hipEventRecord(ev[4], st);
     if (he == hipSuccess) he = launch_batch(a, p->grid, p->block, kNone, st);
     if (he == hipSuccess) he = hipEventRecord(ev[5], st);
