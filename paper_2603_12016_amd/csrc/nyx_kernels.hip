@@ -408,6 +408,56 @@ struct ItemCtx {
     }
 };
 
+// One queue entry with everything its processing reads: written to LDS by
+// one thread per entry when the ticket is claimed (the descriptor loads of a
+// whole ticket overlap), then read by every wave as uniform values.
+struct ItemDesc {
+    RoiDesc rd;
+    const uint16_t *I;
+    const uint32_t *L;
+    const uint16_t *B;
+    int32_t nx, ny, nz;
+    uint32_t roi, ra, rb, ca, cb;   // bbox rows [ra, rb) and columns [ca, cb) of the tile
+    float rcpD;                     // 1 / (vmax - vmin), 0 for a constant ROI
+    uint32_t ok;                    // 0: the entry names no valid ROI tile (skipped)
+};
+static_assert(sizeof(ItemDesc) <= kItemBytes, "staged descriptor exceeds its LDS slot");
+
+__device__ void stage_item(const StepArgs &a, uint32_t roi, uint32_t tile, ItemDesc *dst) {
+    ItemDesc it;
+    it.ok = 0u;
+    it.roi = roi;
+    if (roi < a.roi_cap) {
+        const RoiDesc rd = a.rois[roi];
+        it.rd = rd;
+        if (tile < rd.n_tiles && rd.image < (uint32_t)a.n_images) {
+            const ImgDesc im = a.imgs[rd.image];
+            if (!(rd.x0 < 0 || rd.y0 < 0 || rd.z0 < 0 || rd.x1 >= im.nx || rd.y1 >= im.ny || rd.z1 >= im.nz ||
+                  rd.x0 > rd.x1 || rd.y0 > rd.y1 || rd.z0 > rd.z1 || rd.tcols == 0u)) {
+                it.I = im.I; it.L = im.L; it.B = im.B;
+                it.nx = im.nx; it.ny = im.ny; it.nz = im.nz;
+                tile_bounds(rd.rows, (uint32_t)(rd.x1 - rd.x0 + 1), rd.n_tiles, rd.tcols, tile, &it.ra, &it.rb,
+                            &it.ca, &it.cb);
+                const uint32_t D = rd.vmax - rd.vmin;
+                it.rcpD = D ? 1.0f / (float)D : 0.0f;
+                it.ok = 1u;
+            }
+        }
+    }
+    *dst = it;
+}
+
+// A work-group-uniform copy of an LDS object, held in scalar registers.
+template <class T> __device__ __forceinline__ T lds_uniform(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized objects only");
+    T out;
+    const uint32_t *s = reinterpret_cast<const uint32_t *>(p);
+    uint32_t *o = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+    for (uint32_t i = 0; i < sizeof(T) / 4; ++i) o[i] = __builtin_amdgcn_readfirstlane(s[i]);
+    return out;
+}
+
 // Triangle offset of a 1-based level x: the index of cell (lo, hi = x - 1)
 // is row_off(x) + lo + 1, so a pair (a <= b) lands at row_off(b) + a.
 __device__ __forceinline__ uint32_t row_off(uint32_t x) { return (__umul24(x - 1u, x) >> 1) - 1u; }
@@ -655,6 +705,7 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
     uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off);
     uint32_t *BUF = reinterpret_cast<uint32_t *>(smem + Ly.buf_off);
     uint32_t *MISC = reinterpret_cast<uint32_t *>(smem + Ly.misc_off);
+    ItemDesc *ITEMS = reinterpret_cast<ItemDesc *>(smem + Ly.item_off);
     const int nw = (int)(blockDim.x / kWave);
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));   // wave index: uniform
     const int K = a.K;
@@ -693,29 +744,25 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
             MISC[32] = n;
         }
         __syncthreads();
-        // queue entries are work-group uniform: keep them (and every descriptor
-        // field loaded through them) in scalar registers
+        // queue entries are work-group uniform: their staged descriptors are
+        // read into scalar registers
         const uint32_t n_items = __builtin_amdgcn_readfirstlane(MISC[32]);
         if (n_items == 0u) break;
+        if (threadIdx.x < n_items) stage_item(a, MISC[2 * threadIdx.x], MISC[2 * threadIdx.x + 1], ITEMS + threadIdx.x);
+        __syncthreads();
         for (uint32_t q = 0; q < n_items; ++q) {
-            const uint32_t roi = __builtin_amdgcn_readfirstlane(MISC[2 * q]);
-            const uint32_t tile = __builtin_amdgcn_readfirstlane(MISC[2 * q + 1]);
             // an entry that does not name a valid ROI tile is skipped
-            if (roi >= a.roi_cap) continue;
-            const RoiDesc rd = a.rois[roi];
-            if (tile >= rd.n_tiles || rd.image >= (uint32_t)a.n_images) continue;
-            const ImgDesc im = a.imgs[rd.image];
-            if (rd.x0 < 0 || rd.y0 < 0 || rd.z0 < 0 || rd.x1 >= im.nx || rd.y1 >= im.ny || rd.z1 >= im.nz ||
-                rd.x0 > rd.x1 || rd.y0 > rd.y1 || rd.z0 > rd.z1 || rd.tcols == 0u)
-                continue;
+            if (__builtin_amdgcn_readfirstlane(ITEMS[q].ok) == 0u) continue;
+            const ItemDesc it = lds_uniform(ITEMS + q);
+            const RoiDesc &rd = it.rd;
+            const uint32_t roi = it.roi;
             ItemCtx c;
-            c.I = im.I; c.L = im.L; c.B = im.B;
-            c.nx = im.nx; c.ny = im.ny; c.nz = im.nz;
+            c.I = it.I; c.L = it.L; c.B = it.B;
+            c.nx = it.nx; c.ny = it.ny; c.nz = it.nz;
             c.label = rd.label; c.vmin = rd.vmin; c.D = rd.vmax - rd.vmin; c.ng = ng;
-            c.rcpD = c.D ? 1.0f / (float)c.D : 0.0f;
+            c.rcpD = it.rcpD;
             c.err = &a.counters[C_ERR];
-            uint32_t ra, rb, ca, cb;
-            tile_bounds(rd.rows, (uint32_t)(rd.x1 - rd.x0 + 1), rd.n_tiles, rd.tcols, tile, &ra, &rb, &ca, &cb);
+            const uint32_t ra = it.ra, rb = it.rb, ca = it.ca, cb = it.cb;
             const bool split = rd.gslot != kNone;
             for (int d0 = 0, pass = 0; d0 < K; d0 += (int)Ly.kp, ++pass) {
                 const int d1 = min(K, d0 + (int)Ly.kp);

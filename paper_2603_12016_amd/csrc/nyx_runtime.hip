@@ -335,6 +335,7 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K) {
     L.buf_off = take((c.mode == 2 || c.mode == 3) ? L.nwaves * kWave * scan_cells(c.mode) * 4u : 0u);
     L.marg_off = take(std::min(L.nwaves, c.kp) * 4u * ng * 4u);   // one set per wave that reduces a direction
     L.misc_off = take(128u * 4u);
+    L.item_off = take((uint32_t)kTicketChunk * kItemBytes);
     L.bytes = off;
     return L;
 }

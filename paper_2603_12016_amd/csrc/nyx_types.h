@@ -14,6 +14,7 @@ constexpr int kClasses = 32;           // work-item size classes (log2 of voxels
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kTicketChunk = 8;        // most queue entries taken per work ticket
 constexpr uint32_t kTicketVox = 8192u; // voxels a ticket of small items aims at
+constexpr uint32_t kItemBytes = 128u;  // LDS bytes of one staged work-item descriptor
 constexpr int kMaxSweepPasses = 16;    // passes with a precomputed 2D sweep map
 
 // Counter slots (u32) in the device counter block.
@@ -103,6 +104,7 @@ struct LdsLayout {
     uint32_t list_cap;    // entries per direction list
     uint32_t hash_cap;    // slots (power of two, hash mode)
     uint32_t u_off, list_off, lcnt_off, marg_off, feat_off, sums_off, misc_off, hkey_off, hcnt_off, buf_off;
+    uint32_t item_off;    // staged descriptors of the current ticket (work-group kernel)
     uint32_t bytes;       // total dynamic LDS
     uint32_t nwaves;      // waves per work-group
 };
