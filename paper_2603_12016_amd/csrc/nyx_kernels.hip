@@ -519,6 +519,145 @@ __device__ __forceinline__ void add_pair(const StepArgs &a, uint8_t *smem, uint3
     }
 }
 
+constexpr uint32_t kStagedMinRows = 4;   // fewer rows per ring chunk: gather instead
+constexpr uint32_t kStageBatch = 8;      // voxels staged per lane and round
+constexpr int kStagedDirs = 13;          // neighbour levels read per group
+
+// Offset d with the sign that makes it point forward in raster order (z,
+// then y, then x).  Counts are symmetric, so (v, v + d) and (v, v - d) name
+// the same unordered pairs.
+__device__ __forceinline__ void forward_offset(const StepArgs &a, int d, int32_t &dz, int32_t &dy, int32_t &dx) {
+    dz = a.off[d][0]; dy = a.off[d][1]; dx = a.off[d][2];
+    if (dz < 0 || (dz == 0 && (dy < 0 || (dy == 0 && dx < 0)))) { dz = -dz; dy = -dy; dx = -dx; }
+}
+
+// Largest forward distance, in flattened bbox rows (z * H + y), from a voxel
+// to a neighbour of [d0, d1) that can lie in the bbox (|dy| < H, |dx| < W).
+__device__ __forceinline__ uint32_t staged_reach(const StepArgs &a, int d0, int d1, uint32_t H, uint32_t W) {
+    uint32_t m = 0u;
+    for (int d = d0; d < d1; ++d) {
+        int32_t dz, dy, dx;
+        forward_offset(a, d, dz, dy, dx);
+        if ((uint32_t)abs(dy) >= H || (uint32_t)abs(dx) >= W) continue;
+        m = max(m, (uint32_t)(dz * (int32_t)H + dy));
+    }
+    return m;
+}
+
+// Staged accumulation for offsets the row sweep does not cover (volumes,
+// longer distances), over full-width tiles: rows [ra, rb) are taken in
+// chunks of C = ring_rows - reach rows.  Before a chunk, the levels of the
+// rows it reaches that are not yet staged are written once to an LDS ring of
+// ring_rows x W bytes (0 outside the ROI or past the bbox); every pair then
+// reads both levels from the ring, so each voxel is loaded and binned once
+// per pass instead of once per offset that reaches it.  Levels fit a byte
+// (ng <= 255).
+template <class Add>
+__device__ void accumulate_staged(const StepArgs &a, const RoiDesc &rd, const ItemCtx &c, uint32_t ra, uint32_t rb,
+                                  int d0, int d1, uint8_t *ring, uint32_t ring_rows, uint32_t reach, Add &&add) {
+    const uint32_t W = (uint32_t)(rd.x1 - rd.x0 + 1), H = (uint32_t)(rd.y1 - rd.y0 + 1), rows = rd.rows;
+    const uint32_t C = ring_rows - reach;
+    const uint32_t plane = (uint32_t)c.ny * (uint32_t)c.nx;
+    const uint32_t t0 = threadIdx.x, ts = blockDim.x;
+    const uint32_t dq = ts / W, dxo = ts - dq * W;
+    // Walks (row r, its ring slot, its (z, y), column x) by ts voxels.
+    struct Pos {
+        uint32_t r, slot, z, y, x;
+    };
+    const auto start = [&](uint32_t r_first) {
+        Pos p;
+        p.x = t0 % W;
+        p.r = r_first + t0 / W;
+        p.slot = (p.r - ra) % ring_rows;
+        p.z = p.r / H;
+        p.y = p.r - p.z * H;
+        return p;
+    };
+    const auto advance = [&](Pos &p) {
+        p.x += dxo;
+        uint32_t adv = dq;
+        if (p.x >= W) { p.x -= W; ++adv; }
+        p.r += adv;
+        p.slot += adv;
+        if (p.slot >= ring_rows) p.slot %= ring_rows;
+        p.y += adv;
+        if (p.y >= H) {
+            const uint32_t k = p.y / H;
+            p.z += k;
+            p.y -= k * H;
+        }
+    };
+    uint32_t staged = ra;   // rows [ra, staged) are in the ring
+    for (uint32_t r0 = ra; r0 < rb; r0 += C) {
+        const uint32_t r1 = min(r0 + C, rb), s1 = r1 + reach;
+        {
+            // kStageBatch voxels per lane and round: their loads are all in
+            // flight before the first level is formed
+            const uint32_t n = (s1 - staged) * W;
+            Pos p = start(staged);
+            for (uint32_t f = t0; f < n; f += ts * kStageBatch) {
+                uint32_t lab[kStageBatch], val[kStageBatch], at[kStageBatch];
+#pragma unroll
+                for (uint32_t k = 0; k < kStageBatch; ++k) {
+                    lab[k] = 0u;
+                    val[k] = 0u;
+                    at[k] = kNone;
+                    if (f + k * ts < n) {
+                        at[k] = __umul24(p.slot, W) + p.x;
+                        if (p.r < rows) {
+                            const uint32_t v = (uint32_t)(rd.z0 + (int32_t)p.z) * plane +
+                                               (uint32_t)(rd.y0 + (int32_t)p.y) * (uint32_t)c.nx +
+                                               (uint32_t)(rd.x0 + (int32_t)p.x);
+                            lab[k] = c.lab(v);
+                            val[k] = c.raw(v);
+                        }
+                    }
+                    advance(p);
+                }
+#pragma unroll
+                for (uint32_t k = 0; k < kStageBatch; ++k)
+                    if (at[k] != kNone) ring[at[k]] = (uint8_t)(lab[k] == c.label ? c.level_of(val[k]) : 0u);
+            }
+        }
+        staged = s1;
+        __syncthreads();
+        {
+            const uint32_t n = (r1 - r0) * W;
+            Pos p = start(r0);
+            for (uint32_t f = t0; f < n; f += ts) {
+                const uint32_t lv = ring[__umul24(p.slot, W) + p.x];
+                if (lv) {
+                    const uint32_t tv = row_off(lv);
+                    for (int db = d0; db < d1; db += kStagedDirs) {
+                        // every neighbour read of the group is issued before the first add
+                        uint32_t lw[kStagedDirs];
+#pragma unroll
+                        for (int k = 0; k < kStagedDirs; ++k) {
+                            lw[k] = 0u;
+                            const int d = db + k;
+                            if (d < d1) {
+                                int32_t dz, dy, dx;
+                                forward_offset(a, d, dz, dy, dx);
+                                const uint32_t yy = p.y + (uint32_t)dy, xx = p.x + (uint32_t)dx;
+                                if (yy < H && xx < W) {
+                                    uint32_t s2 = p.slot + (uint32_t)(dz * (int32_t)H + dy);
+                                    if (s2 >= ring_rows) s2 -= ring_rows;
+                                    lw[k] = ring[__umul24(s2, W) + xx];
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < kStagedDirs; ++k)
+                            if (lw[k]) add((uint32_t)(db + k - d0), lv, tv, lw[k], row_off(lw[k]));
+                    }
+                }
+                advance(p);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Accumulate the pairs owned by the voxels of bbox rows [ra, rb) (rows of
 // all planes, flattened) and columns [ca, cb) for the directions [d0, d1):
 // each voxel owns the pair (v, v + d) of each offset.  Lanes take voxels
@@ -770,10 +909,17 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
                     auto add = [&](uint32_t dl, uint32_t la, uint32_t ta, uint32_t lb, uint32_t tb) {
                         add_pair<MODE>(a, smem, dl, la, ta, lb, tb);
                     };
+                    const uint32_t W = (uint32_t)(rd.x1 - rd.x0 + 1), H = (uint32_t)(rd.y1 - rd.y0 + 1);
+                    const uint32_t ring_rows = Ly.ring_bytes / W;
+                    const uint32_t reach = Ly.ring_bytes ? staged_reach(a, d0, d1, H, W) : 0u;
                     if (a.sweep_ok && pass < kMaxSweepPasses)
                         accumulate_sweep2d(rd, c, ra, rb, ca, cb, a.sweep[pass][0], a.sweep[pass][1], a.sweep[pass][2],
                                            a.sweep[pass][3], w, nw, add);
-                    else
+                    else if (MODE != 1 && Ly.ring_bytes && ca == 0u && cb == W && ring_rows >= reach + kStagedMinRows) {
+                        // (the hash layout reserves no ring)
+                        if constexpr (MODE != 1)
+                            accumulate_staged(a, rd, c, ra, rb, d0, d1, smem + Ly.ring_off, ring_rows, reach, add);
+                    } else
                         accumulate_rows(a, rd, c, ra, rb, ca, cb, d0, d1, threadIdx.x, blockDim.x, add);
                 }
                 __syncthreads();

@@ -32,6 +32,7 @@ const char *const kFeatureNames[kNumFeat] = {
     "IDN", "IV", "JAVE", "JE", "JMAX", "SUMAVE", "SUMENT", "JVAR", "SUMVAR", "VARIANCE"};
 
 constexpr uint32_t kLdsBudget = 160u * 1024u;   // LDS per CU on gfx950
+constexpr uint32_t kRingMin = 2048u, kRingMax = 32768u;   // staged-accumulation level ring (bytes)
 constexpr uint32_t kMaxNgFused = 8191u;         // hash keys carry 13-bit levels
 constexpr uint64_t kMaxLabelEntries = 1ull << 26;
 
@@ -309,7 +310,9 @@ uint32_t u_words(int mode, uint32_t ng) {
     return (w + 3u) & ~3u;
 }
 
-LdsLayout make_layout(const Config &c, uint32_t ng, int K) {
+// ring: reserve an LDS level ring for the staged accumulation, sized to the
+// LDS the work-group can take without lowering its occupancy.
+LdsLayout make_layout(const Config &c, uint32_t ng, int K, bool ring) {
     LdsLayout L;
     memset(&L, 0, sizeof L);
     L.mode = (uint32_t)c.mode;
@@ -336,6 +339,14 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K) {
     L.marg_off = take(std::min(L.nwaves, c.kp) * 4u * ng * 4u);   // one set per wave that reduces a direction
     L.misc_off = take(128u * 4u);
     L.item_off = take((uint32_t)kTicketChunk * kItemBytes);
+    if (ring && ng <= 255u && c.mode != 1) {
+        const uint32_t per_group = kLdsBudget / std::max(1u, kLdsBudget / off);
+        const uint32_t bytes = off < per_group ? std::min(kRingMax, (per_group - off) & ~15u) : 0u;
+        if (bytes >= kRingMin) {
+            L.ring_off = take(bytes);
+            L.ring_bytes = bytes;
+        }
+    }
     L.bytes = off;
     return L;
 }
@@ -571,8 +582,8 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     a.force_split = cfg.force_split;
     a.enqueue = 1;
     a.fp64 = fp64;
-    a.lds = make_layout(cfg, ng, K);
     set_sweep(a, w.h_imgs, off, K, cfg.kp);
+    a.lds = make_layout(cfg, ng, K, !a.sweep_ok);
     a.wave_ok = wave ? 1 : 0;
     a.wave_max_vox = wave ? std::min<uint32_t>(cfg.wave_vox, 65535u) : 0u;
     a.buckets_w = wave ? w.buckets_w.as<uint2>() : nullptr;

@@ -105,6 +105,7 @@ struct LdsLayout {
     uint32_t hash_cap;    // slots (power of two, hash mode)
     uint32_t u_off, list_off, lcnt_off, marg_off, feat_off, sums_off, misc_off, hkey_off, hcnt_off, buf_off;
     uint32_t item_off;    // staged descriptors of the current ticket (work-group kernel)
+    uint32_t ring_off, ring_bytes;   // level ring of the staged accumulation (0 bytes: none)
     uint32_t bytes;       // total dynamic LDS
     uint32_t nwaves;      // waves per work-group
 };

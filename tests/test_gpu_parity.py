@@ -323,14 +323,23 @@ def test_empty_image(env):
     assert rois.n_rois == 0 and table.shape[0] == 0
 
 
-@pytest.mark.parametrize("offs", [[(0, 0, 2), (0, -2, 2), (0, -2, 0), (0, -2, -2)],
-                                  [(0, 1, 3), (0, 0, -1), (0, 2, 0)]])
-def test_other_offsets(env, oracle_mod, offs):
+_OFF3 = [(0, 0, 1), (0, 1, 0), (1, 0, 0), (0, 1, 1), (0, 1, -1), (1, 0, 1), (1, 0, -1), (1, 1, 0), (1, -1, 0),
+         (1, 1, 1), (1, 1, -1), (1, -1, 1), (1, -1, -1)]
+
+
+# 2D offsets outside the four distance-1 classes, and 3D offsets (given
+# backwards, at distance 2, or few): the staged and gather accumulations.
+@pytest.mark.parametrize("offs,shape", [([(0, 0, 2), (0, -2, 2), (0, -2, 0), (0, -2, -2)], (1, 30, 31)),
+                                        ([(0, 1, 3), (0, 0, -1), (0, 2, 0)], (1, 30, 31)),
+                                        ([(-a, -b, -c) for a, b, c in _OFF3], (7, 19, 23)),
+                                        ([(2 * a, 2 * b, 2 * c) for a, b, c in _OFF3], (9, 17, 15)),
+                                        ([(1, 0, 0), (0, -1, 2), (-2, 1, 1)], (8, 12, 40))])
+def test_other_offsets(env, oracle_mod, offs, shape):
     import torch
     nyx, ctx, dev = env
-    rng = np.random.default_rng(len(offs))
-    I = rng.integers(0, 4000, (1, 30, 31)).astype(np.uint16)
-    L = (rng.integers(1, 5, (1, 30, 31)) * (rng.random((1, 30, 31)) < 0.9)).astype(np.uint32)
+    rng = np.random.default_rng(len(offs) + shape[0])
+    I = rng.integers(0, 4000, shape).astype(np.uint16)
+    L = (rng.integers(1, 5, shape) * (rng.random(shape) < 0.9)).astype(np.uint32)
     say(f"case offsets {offs}")
     rois, table = _run_extract(nyx, ctx, dev, I, L, 16, offs)
     torch.cuda.synchronize()
