@@ -112,24 +112,64 @@ __device__ __forceinline__ void scan_flush_global(const StepArgs &a, uint32_t K,
     atomicMin(&a.tab.z0[K], z0); atomicMax(&a.tab.z1[K], z1);
 }
 
-// A vertical run at column x, rows y0..y1 of plane z.
-__device__ __forceinline__ void scan_flush_run(const StepArgs &a, ScanLds &S, uint32_t K, uint32_t c, uint32_t mn,
-                                               uint32_t mx, int32_t x, int32_t y0, int32_t y1, int32_t z) {
+// Statistics of one or more vertical runs of label key (0: none): voxel
+// count, value range, and the box x0..x1, y0..y1, z0..z1 they span.
+struct RunRec {
+    uint32_t key, c, mn, mx;
+    int32_t x0, x1, y0, y1, z0, z1;
+};
+
+__device__ __forceinline__ void scan_flush_run(const StepArgs &a, ScanLds &S, uint32_t K, const RunRec &r) {
     uint32_t h = hash_u32(K) & (kScanSlots - 1);
     for (int probe = 0; probe < 8; ++probe) {
         uint32_t cur = atomicCAS(&S.key[h], kNone, K);
         if (cur == kNone || cur == K) {
-            atomicAdd(&S.cnt[h], c);
-            atomicMin(&S.mn[h], mn);
-            atomicMax(&S.mx[h], mx);
-            atomicMin(&S.x0[h], x); atomicMax(&S.x1[h], x);
-            atomicMin(&S.y0[h], y0); atomicMax(&S.y1[h], y1);
-            atomicMin(&S.z0[h], z); atomicMax(&S.z1[h], z);
+            atomicAdd(&S.cnt[h], r.c);
+            atomicMin(&S.mn[h], r.mn);
+            atomicMax(&S.mx[h], r.mx);
+            atomicMin(&S.x0[h], r.x0); atomicMax(&S.x1[h], r.x1);
+            atomicMin(&S.y0[h], r.y0); atomicMax(&S.y1[h], r.y1);
+            atomicMin(&S.z0[h], r.z0); atomicMax(&S.z1[h], r.z1);
             return;
         }
         h = (h + 1u) & (kScanSlots - 1);
     }
-    scan_flush_global(a, K, c, mn, mx, x, x, y0, y1, z, z);
+    scan_flush_global(a, K, r.c, r.mn, r.mx, r.x0, r.x1, r.y0, r.y1, r.z0, r.z1);
+}
+
+// Segmented inclusive combination over each 16-lane row: the lanes of a
+// maximal group of adjacent lanes with the same key form a segment, and
+// after the row_shr 1, 2, 4, 8 steps the last lane of a segment holds the
+// combination of the whole segment.  Every lane of the wave takes part.
+template <int S>
+__device__ __forceinline__ void run_step(RunRec &r, uint32_t seg) {
+    const bool take = dpp32<0x110 + S>(seg) == seg;   // out-of-row sources read 0; seg >= 1
+    const uint32_t c = dpp32<0x110 + S>(r.c), mn = dpp32<0x110 + S>(r.mn), mx = dpp32<0x110 + S>(r.mx);
+    const int32_t x0 = (int32_t)dpp32<0x110 + S>((uint32_t)r.x0), x1 = (int32_t)dpp32<0x110 + S>((uint32_t)r.x1);
+    const int32_t y0 = (int32_t)dpp32<0x110 + S>((uint32_t)r.y0), y1 = (int32_t)dpp32<0x110 + S>((uint32_t)r.y1);
+    const int32_t z0 = (int32_t)dpp32<0x110 + S>((uint32_t)r.z0), z1 = (int32_t)dpp32<0x110 + S>((uint32_t)r.z1);
+    if (take) {
+        r.c += c; r.mn = min(r.mn, mn); r.mx = max(r.mx, mx);
+        r.x0 = min(r.x0, x0); r.x1 = max(r.x1, x1);
+        r.y0 = min(r.y0, y0); r.y1 = max(r.y1, y1);
+        r.z0 = min(r.z0, z0); r.z1 = max(r.z1, z1);
+    }
+}
+
+// Returns whether this lane ends its segment (and so holds its total).  The
+// neighbour reads are made by every lane before any test: a DPP read inside
+// a branch would see the lanes the branch disables as 0.
+__device__ __forceinline__ bool row_segment_combine(RunRec &r) {
+    const uint32_t rl = lane() & 15u;
+    const uint32_t prev = dpp32<0x111>(r.key), next = dpp32<0x101>(r.key);   // row_shr:1, row_shl:1
+    const uint32_t head = (uint32_t)(rl == 0u) | (uint32_t)(prev != r.key);
+    const bool tail = (rl == 15u) | (next != r.key);
+    const uint32_t seg = row_incl_scan(head);
+    run_step<1>(r, seg);
+    run_step<2>(r, seg);
+    run_step<4>(r, seg);
+    run_step<8>(r, seg);
+    return tail;
 }
 
 __global__ __launch_bounds__(256) void k_scan(StepArgs a) {
@@ -149,6 +189,8 @@ __global__ __launch_bounds__(256) void k_scan(StepArgs a) {
     const uint32_t row0 = rblk * kScanTileRows;
     const int32_t x = (int32_t)(cblk * kScanTileCols + threadIdx.x);
     __syncthreads();
+    RunRec run{0u, 0u, 0xFFFFu, 0u, x, x, 0, 0, 0, 0};
+    uint32_t bad = 0u;
     if (x < d.nx && row0 < rows && im < a.n_images) {
         const uint32_t nr = min((uint32_t)kScanTileRows, rows - row0);
         const uint32_t nx = (uint32_t)d.nx;
@@ -165,29 +207,29 @@ __global__ __launch_bounds__(256) void k_scan(StepArgs a) {
         }
         // plane and row of the tile's first row (tile rows are uniform)
         int32_t z = (int32_t)(row0 / (uint32_t)d.ny), y = (int32_t)(row0 - (uint32_t)z * (uint32_t)d.ny);
-        uint32_t bad = 0u;
-        uint32_t cur = 0u, c = 0u, mn = 0xFFFFu, mx = 0u;
-        int32_t ry0 = 0, ry1 = 0, rz = 0;
 #pragma unroll
         for (uint32_t j = 0; j < kScanTileRows; ++j) {
             if (j >= nr) break;
             uint32_t l = lab[j];
             if (l > d.max_label) { bad = 1u; l = 0u; }
-            if (l != cur || z != rz) {
-                if (cur) scan_flush_run(a, S, d.tab_base + cur, c, mn, mx, x, ry0, ry1, rz);
-                cur = l; c = 0u; mn = 0xFFFFu; mx = 0u; ry0 = y; rz = z;
+            if (l != run.key || z != run.z0) {
+                if (run.key) scan_flush_run(a, S, d.tab_base + run.key, run);
+                run = RunRec{l, 0u, 0xFFFFu, 0u, x, x, y, y, z, z};
             }
             if (l) {
-                ++c;
-                mn = min(mn, val[j]);
-                mx = max(mx, val[j]);
-                ry1 = y;
+                ++run.c;
+                run.mn = min(run.mn, val[j]);
+                run.mx = max(run.mx, val[j]);
+                run.y1 = y;
             }
             if (++y == d.ny) { y = 0; ++z; }
         }
-        if (cur) scan_flush_run(a, S, d.tab_base + cur, c, mn, mx, x, ry0, ry1, rz);
-        if (bad) atomicOr(&a.counters[C_ERR], (uint32_t)E_LABEL_RANGE);
     }
+    // The runs still open at the tile's last row: adjacent lanes of a row
+    // holding the same label are combined first, so one lane per group
+    // flushes (a wide ROI would otherwise send every lane to one slot).
+    if (row_segment_combine(run) && run.key) scan_flush_run(a, S, d.tab_base + run.key, run);
+    if (bad) atomicOr(&a.counters[C_ERR], (uint32_t)E_LABEL_RANGE);
     __syncthreads();
     for (int i = threadIdx.x; i < kScanSlots; i += blockDim.x) {
         uint32_t K = S.key[i];

@@ -414,6 +414,7 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
     // work-group's share of the voxels
     uint64_t share = total_vox / ((uint64_t)std::max(ctx->n_cu, 1) * 4u) + 1u;
     const uint32_t lb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(share, 4096u), 1u << 20);
+    std::vector<Config> later;
     for (int mode : {3, 2, 0}) {
         uint32_t split = mode == 3 ? std::min<uint32_t>(lb, 65535u) : lb;
         uint64_t mi = max_item_vox(w.h_rois, split, split);
@@ -433,10 +434,20 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
                 c.mode = mode; c.kp = kp; c.block = block; c.split_vox = split; c.tile_vox = split;
                 c.list_cap = list_cap; c.force_split = force_split;
                 out.push_back(c);
+                // many offsets: fewer directions per pass cost another pass
+                // over the voxels but leave LDS for more work-groups per CU
+                // (timed by the autotuner, never the default)
+                if (mode == 3 && K > 4)
+                    for (uint32_t parts : {2u, 3u}) {
+                        Config f = c;
+                        f.kp = ((uint32_t)K + parts - 1u) / parts;
+                        if (f.kp < kp) later.push_back(f);
+                    }
                 break;
             }
         }
     }
+    out.insert(out.end(), later.begin(), later.end());
     if (!out.empty() || fixed >= kLdsBudget) return out;
     // hash mode: items small enough that kp directions of pairs fill at most
     // half the table
