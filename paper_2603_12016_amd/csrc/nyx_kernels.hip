@@ -336,15 +336,36 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
         cls_base[threadIdx.x] = atomicAdd(&a.counters[slot], cls_cnt[threadIdx.x]);
     }
     __syncthreads();
+    // Each ROI's tile entries: a thread writes those of its own ROI when they
+    // are few; the tiles of ROIs cut into many are written by the whole
+    // work-group (one thread would take milliseconds over a huge ROI).
+    constexpr uint32_t kOwnTiles = 32u, kBigMax = 64u;
+    __shared__ uint32_t n_big, big_row[kBigMax], big_nt[kBigMax];
+    __shared__ uint2 *big_dst[kBigMax];
+    if (threadIdx.x == 0) n_big = 0u;
+    __syncthreads();
     if (enq) {
         uint32_t pos = cls_base[(wave_item ? kClasses : 0) + cls] + local;
         uint2 *bk = wave_item ? a.buckets_w : a.buckets;
         if (pos + nt > a.bucket_cap) {
             atomicOr(&a.counters[C_ERR], (uint32_t)E_ITEM_CAP);
         } else {
-            for (uint32_t t = 0; t < nt; ++t) bk[cls * a.bucket_cap + pos + t] = make_uint2(row, t);
+            uint2 *dst = bk + (uint64_t)cls * a.bucket_cap + pos;
+            uint32_t b = kBigMax;
+            if (nt > kOwnTiles) b = atomicAdd(&n_big, 1u);
+            if (b < kBigMax) {
+                big_row[b] = row;
+                big_nt[b] = nt;
+                big_dst[b] = dst;
+            } else {
+                for (uint32_t t = 0; t < nt; ++t) dst[t] = make_uint2(row, t);
+            }
         }
     }
+    __syncthreads();
+    const uint32_t nb = min(n_big, kBigMax);
+    for (uint32_t b = 0; b < nb; ++b)
+        for (uint32_t t = threadIdx.x; t < big_nt[b]; t += blockDim.x) big_dst[b][t] = make_uint2(big_row[b], t);
 }
 
 // In force_split mode the split-slot count is the ROI range size.
