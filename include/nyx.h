@@ -24,7 +24,8 @@
  *    that order.
  *  - Feature table: row r holds (n_offsets + 1) blocks of 30 values; block
  *    k < n_offsets is direction k, the last block is the mean over the
- *    directions that have at least one pair.  Element type float (NYX_FP32)
+ *    directions that have at least one pair (NYX_AGG_MERGED: one block, the
+ *    features of the summed matrix).  Element type float (NYX_FP32)
  *    or double (NYX_FP64).  Undefined values (a direction with no pair) are
  *    quiet NaN.  Column order: nyx_feature_name(0..29).
  *  - Pointers are DEVICE pointers (HIP device memory, e.g. torch CUDA
@@ -108,6 +109,19 @@ typedef struct nyx_glcm {
     int64_t n_rois;     /* set by nyx_glcm_accumulate */
 } nyx_glcm;
 
+/* How the offsets' matrices become features.  The offset set is one of the
+ * texture hyper-parameters (Methods, "Feature Control and Tunability"); how
+ * the per-offset matrices are combined is not fixed there, so both usual
+ * choices are offered:
+ *   NYX_AGG_PER_OFFSET  features of each offset's matrix and their mean
+ *                       (table rows of n_offsets + 1 blocks);
+ *   NYX_AGG_MERGED      features of P = sum over the offsets of P_k, one
+ *                       matrix per ROI (table rows of 1 block).  Needs every
+ *                       offset's triangle in LDS at once and a dense scan
+ *                       accumulation mode; NYX_ERR_UNSUPPORTED otherwise
+ *                       (e.g. 1024 levels). */
+typedef enum nyx_aggregate { NYX_AGG_PER_OFFSET = 0, NYX_AGG_MERGED = 1 } nyx_aggregate;
+
 typedef struct nyx_extract_opts {
     int32_t n_bins;
     const nyx_offset *offsets_host;
@@ -126,6 +140,7 @@ typedef struct nyx_extract_opts {
                                     processed one wavefront each when there are at most 4
                                     offsets and their LDS fits (else ignored) */
     int64_t workspace_cap_bytes; /* 0 = no cap; exceeding it gives NYX_ERR_OOM */
+    int32_t aggregate;           /* NYX_AGG_PER_OFFSET or NYX_AGG_MERGED (table layout above) */
 } nyx_extract_opts;
 
 /* Context on one device (hipSetDevice ordinal).  NYX_ERR_DEVICE if absent. */

@@ -183,6 +183,16 @@ def features_roi(P: np.ndarray) -> np.ndarray:
     return out
 
 
+def features_roi_merged(P: np.ndarray) -> np.ndarray:
+    """(1, 30): the features of the sum of the K direction matrices of one ROI
+    (the offsets' counts pooled into one symmetric matrix before any feature
+    is taken; reading A15)."""
+    M = np.ascontiguousarray(P, np.uint64)
+    if M.ndim != 3 or M.shape[1] != M.shape[2]:
+        raise ValueError("expected (K, Ng, Ng) matrices")
+    return features(M.sum(axis=0, dtype=np.uint64))[None, :]
+
+
 def extract(intensity, labels, n_bins: int, offsets: np.ndarray, stats: dict | None = None,
             rois=None, n_threads: int = 1) -> tuple[dict, np.ndarray]:
     """Feature table of one image: (stats, table (n, K + 1, 30) float64).

@@ -79,7 +79,7 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
 __global__ void k_zero_split(StepArgs a) {
     uint32_t used = a.counters[C_NSPLIT];
     if (used > a.g_cap) used = a.g_cap;
-    uint64_t n = (uint64_t)used * a.K * (uint64_t)a.ng * a.ng;
+    uint64_t n = (uint64_t)used * a.K_out * (uint64_t)a.ng * a.ng;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x)
         a.G[i] = 0ull;
@@ -882,7 +882,7 @@ template <class Acc, class Src>
 __device__ __forceinline__ void dir_or_flush(const StepArgs &a, const WaveGrp &g, const Src &s, bool split,
                                              const RoiDesc &rd, uint32_t roi, int d, uint32_t *MARG, uint32_t ng) {
     if (split) {
-        uint64_t *G = a.G + ((uint64_t)rd.gslot * a.K + d) * (uint64_t)ng * ng;
+        uint64_t *G = a.G + ((uint64_t)rd.gslot * a.K_out + d) * (uint64_t)ng * ng;
         s.for_each(g, [&](uint32_t lo, uint32_t hi, uint32_t c) {
             atomicAdd(reinterpret_cast<unsigned long long *>(&G[(uint64_t)lo * ng + hi]), (unsigned long long)c);
         });
@@ -890,7 +890,7 @@ __device__ __forceinline__ void dir_or_flush(const StepArgs &a, const WaveGrp &g
         s.clear(g);
         g.sync();
     } else {
-        dir_sums<Acc, double>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng, a.dsums + (uint64_t)roi * a.K + d);
+        dir_sums<Acc, double>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng, a.dsums + (uint64_t)roi * a.K_out + d);
     }
 }
 
@@ -986,7 +986,24 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
                         accumulate_rows(a, rd, c, ra, rb, ca, cb, d0, d1, threadIdx.x, blockDim.x, add);
                 }
                 __syncthreads();
-                for (int dl = w; dl < d1 - d0; dl += nw) {
+                if (MODE >= 2 && a.merged) {
+                    // one matrix for all offsets: the pass's triangles (every
+                    // offset is in this one pass) summed into the first, the
+                    // others cleared; the planner keeps every summed cell below
+                    // the counter limit, so packed halves add without carries
+                    uint32_t *U0 = reinterpret_cast<uint32_t *>(smem + Ly.u_off);
+                    for (uint32_t i = threadIdx.x; i < Ly.tri_pad; i += blockDim.x) {
+                        uint32_t s = 0u;
+                        for (int dl = 1; dl < d1 - d0; ++dl) {
+                            s += U0[dl * Ly.tri_pad + i];
+                            U0[dl * Ly.tri_pad + i] = 0u;
+                        }
+                        U0[i] += s;
+                    }
+                    __syncthreads();
+                }
+                const int n_mat = (MODE >= 2 && a.merged) ? 1 : d1 - d0;
+                for (int dl = w; dl < n_mat; dl += nw) {
                     uint32_t *Ud = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
                     const uint32_t n = min(LCNT[dl], Ly.list_cap);
                     const uint32_t *lst = LST + dl * Ly.list_cap;
@@ -994,7 +1011,7 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
                     if (MODE == 2 || MODE == 3) {
                         SrcTriScan<MODE == 3> s{Ud, (ng * (ng + 1u)) >> 1,
                                                 BUF + (uint32_t)w * kWave * SrcTriScan<MODE == 3>::kPerRead};
-                        dir_or_flush<Acc>(a, g, s, split, rd, roi, d0 + dl, MARG, ng);
+                        dir_or_flush<Acc>(a, g, s, split, rd, roi, a.merged ? 0 : d0 + dl, MARG, ng);
                     } else if (MODE == 0) {
                         SrcDenseList s{lst, n, Ud};
                         dir_or_flush<Acc>(a, g, s, split, rd, roi, d0 + dl, MARG, ng);
@@ -1100,7 +1117,7 @@ template <class Acc>
 __global__ __launch_bounds__(512) void k_split_features(StepArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t ng = (uint32_t)a.ng;
-    const int K = a.K;
+    const int K = a.K_out;
     const uint32_t slot = blockIdx.x / K;
     const int d = (int)(blockIdx.x % K);
     if (slot >= min(a.counters[C_NSPLIT], a.g_cap)) return;
@@ -1125,7 +1142,7 @@ __global__ __launch_bounds__(128) void k_features(StepArgs a, const DirSums *ds,
                                                   const uint32_t *n_ptr) {
     extern __shared__ __align__(16) uint8_t smem[];
     double *feat = reinterpret_cast<double *>(smem);
-    const uint32_t K = (uint32_t)a.K;
+    const uint32_t K = (uint32_t)a.K_out;
     const uint32_t rpb = blockDim.x / K;
     const uint32_t n = n_ptr ? min(*n_ptr, n_cap) : n_cap;
     const uint32_t row0 = blockIdx.x * rpb;
@@ -1137,7 +1154,8 @@ __global__ __launch_bounds__(128) void k_features(StepArgs a, const DirSums *ds,
         if (threadIdx.x == 0) atomicOr(&a.counters[C_ERR], (uint32_t)E_TABLE_CAP);
         rows = a.table_rows > row0 ? a.table_rows - row0 : 0u;
     }
-    const uint32_t per = (K + 1u) * kNumFeat;
+    // K direction blocks and their mean, or the one block of the merged matrix
+    const uint32_t per = (a.merged ? 1u : K + 1u) * kNumFeat;
     OutT *out = reinterpret_cast<OutT *>(a.table) + (uint64_t)row0 * per;
     for (uint32_t i = threadIdx.x; i < rows * per; i += blockDim.x) {
         const uint32_t rr = i / per, q = i - rr * per, blk = q / kNumFeat, f = q - blk * kNumFeat;
@@ -1161,7 +1179,7 @@ __global__ __launch_bounds__(128) void k_features(StepArgs a, const DirSums *ds,
 __global__ __launch_bounds__(256) void k_coo_count(StepArgs a, uint32_t n_slots, uint64_t *counts) {
     const uint32_t ng = (uint32_t)a.ng;
     const uint32_t sd = blockIdx.x;
-    if (sd >= n_slots * (uint32_t)a.K) return;
+    if (sd >= n_slots * (uint32_t)a.K_out) return;
     const uint64_t *G = a.G + (uint64_t)sd * ng * ng;
     uint64_t c = 0;
     for (uint32_t e = threadIdx.x; e < ng * ng; e += blockDim.x) {
@@ -1181,8 +1199,8 @@ __global__ __launch_bounds__(256) void k_coo_emit(StepArgs a, uint32_t n_slots, 
                                                   uint64_t *keys, uint64_t *vals) {
     const uint32_t ng = (uint32_t)a.ng;
     const uint32_t sd = blockIdx.x;
-    if (sd >= n_slots * (uint32_t)a.K) return;
-    const uint32_t slot = sd / a.K, d = sd % a.K;
+    if (sd >= n_slots * (uint32_t)a.K_out) return;
+    const uint32_t slot = sd / a.K_out, d = sd % a.K_out;
     const uint64_t roi = a.split_roi[slot];
     const uint64_t *G = a.G + (uint64_t)sd * ng * ng;
     __shared__ uint32_t wc[4], s_base;
@@ -1227,7 +1245,7 @@ __global__ __launch_bounds__(512) void k_coo_features(StepArgs a, const uint64_t
                                                       const uint64_t *seg, uint32_t n_rois, DirSums *sums) {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t ng = (uint32_t)a.ng;
-    const int K = a.K;
+    const int K = a.K_out;
     const uint32_t s = blockIdx.x;
     if (s >= n_rois * (uint32_t)K) return;
     uint32_t *R = reinterpret_cast<uint32_t *>(smem);
@@ -1272,7 +1290,7 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st) 
 
 hipError_t launch_zero_split(const StepArgs &a, hipStream_t st) {
     if (a.g_cap == 0) return hipSuccess;
-    uint64_t n = (uint64_t)a.g_cap * a.K * (uint64_t)a.ng * a.ng;
+    uint64_t n = (uint64_t)a.g_cap * a.K_out * (uint64_t)a.ng * a.ng;
     uint64_t blocks = (n + 255) / 256;
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(k_zero_split, dim3((uint32_t)blocks), dim3(256), 0, st, a);
@@ -1423,7 +1441,7 @@ hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st) {
         if (e != hipSuccess) return e;
     }
     uint32_t lds = 16u * a.ng + 16 * 8;
-    uint32_t grid = a.g_cap * a.K;
+    uint32_t grid = a.g_cap * a.K_out;
     if (a.fp64) hipLaunchKernelGGL(k_split_features<double>, dim3(grid), dim3(512), lds, st, a);
     else hipLaunchKernelGGL(k_split_features<float>, dim3(grid), dim3(512), lds, st, a);
     NYX_CHECK_LAUNCH();
@@ -1433,9 +1451,9 @@ hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st) {
 hipError_t launch_features(const StepArgs &a, const DirSums *ds, uint32_t n_cap, const uint32_t *n_ptr,
                            hipStream_t st) {
     if (n_cap == 0) return hipSuccess;
-    const uint32_t block = 128u, rpb = block / (uint32_t)a.K;
+    const uint32_t block = 128u, rpb = block / (uint32_t)a.K_out;
     const uint32_t grid = (n_cap + rpb - 1u) / rpb;
-    const uint32_t lds = rpb * (uint32_t)a.K * kNumFeat * 8u;
+    const uint32_t lds = rpb * (uint32_t)a.K_out * kNumFeat * 8u;
     if (a.fp64) hipLaunchKernelGGL(k_features<double>, dim3(grid), dim3(block), lds, st, a, ds, n_cap, n_ptr);
     else hipLaunchKernelGGL(k_features<float>, dim3(grid), dim3(block), lds, st, a, ds, n_cap, n_ptr);
     NYX_CHECK_LAUNCH();
@@ -1444,7 +1462,7 @@ hipError_t launch_features(const StepArgs &a, const DirSums *ds, uint32_t n_cap,
 
 hipError_t launch_coo_count(const StepArgs &a, uint32_t n_slots, uint64_t *counts, hipStream_t st) {
     if (n_slots == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coo_count, dim3(n_slots * a.K), dim3(256), 0, st, a, n_slots, counts);
+    hipLaunchKernelGGL(k_coo_count, dim3(n_slots * a.K_out), dim3(256), 0, st, a, n_slots, counts);
     NYX_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1452,16 +1470,16 @@ hipError_t launch_coo_count(const StepArgs &a, uint32_t n_slots, uint64_t *count
 hipError_t launch_coo_emit(const StepArgs &a, uint32_t n_slots, const uint64_t *offsets, uint64_t *keys,
                            uint64_t *vals, hipStream_t st) {
     if (n_slots == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coo_emit, dim3(n_slots * a.K), dim3(256), 0, st, a, n_slots, offsets, keys, vals);
+    hipLaunchKernelGGL(k_coo_emit, dim3(n_slots * a.K_out), dim3(256), 0, st, a, n_slots, offsets, keys, vals);
     NYX_CHECK_LAUNCH();
     return hipSuccess;
 }
 
 hipError_t launch_coo_features(const StepArgs &a, const uint64_t *keys, const uint64_t *vals, uint64_t nnz,
                                uint32_t n_rois, uint64_t *seg, DirSums *sums, hipStream_t st) {
-    uint32_t n_seg = n_rois * (uint32_t)a.K;
+    uint32_t n_seg = n_rois * (uint32_t)a.K_out;
     hipLaunchKernelGGL(k_coo_segments_k, dim3((n_seg + 1 + 255) / 256), dim3(256), 0, st, keys, nnz, n_rois,
-                       a.K, seg);
+                       a.K_out, seg);
     NYX_CHECK_LAUNCH();
     if (n_seg == 0) return hipSuccess;
     {

@@ -289,6 +289,7 @@ struct Config {
     uint32_t list_cap = 0, hash_cap = 0;
     int force_split = 0;
     uint32_t wave_vox = 0;   // unsplit ROIs up to this many voxels go to the wavefront kernel (0: none)
+    int merged = 0;          // one matrix per ROI: the sum of the K offsets' matrices
 };
 
 const char *mode_name(int m) {
@@ -397,8 +398,11 @@ uint64_t max_item_vox(const std::vector<RoiDesc> &rois, uint32_t split_vox, uint
 // Feasible LDS configurations for this workload, one per accumulation mode,
 // each with as many directions per pass as fit.  Dense triangles first; the
 // hash table only when no dense triangle fits.
+// merged: the K matrices are summed in LDS after one pass over every offset,
+// so only the dense scan modes with all K offsets in one pass qualify, and
+// packed 16-bit counters need K x (voxels of an item) < 65536.
 std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_t ng, int K, int force_split,
-                                      uint32_t block) {
+                                      uint32_t block, bool merged = false) {
     std::vector<Config> out;
     const uint32_t nw = block / kWave;
     const uint32_t tri = ng * (ng + 1u) / 2u;
@@ -416,24 +420,27 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
     const uint32_t lb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(share, 4096u), 1u << 20);
     std::vector<Config> later;
     for (int mode : {3, 2, 0}) {
-        uint32_t split = mode == 3 ? std::min<uint32_t>(lb, 65535u) : lb;
+        if (merged && mode == 0) continue;
+        const uint32_t cell_max = merged ? 65535u / (uint32_t)K : 65535u;   // 16-bit counters
+        uint32_t split = mode == 3 ? std::min<uint32_t>(lb, cell_max) : lb;
         uint64_t mi = max_item_vox(w.h_rois, split, split);
-        while (mode == 3 && mi > 65535u && split > 64u) {
+        while (mode == 3 && mi > cell_max && split > 64u) {
             split /= 2u;
             mi = max_item_vox(w.h_rois, split, split);
         }
-        if (mode == 3 && mi > 65535u) continue;
+        if (mode == 3 && mi > cell_max) continue;
         const bool scan = mode == 2 || mode == 3;
         const uint32_t list_cap = scan ? 0u : (uint32_t)std::min<uint64_t>(tri, std::max<uint64_t>(mi, 1u));
         const uint64_t scan_buf = scan ? (uint64_t)nw * kWave * scan_cells(mode) * 4u : 0u;
-        for (uint32_t kp = (uint32_t)K; kp >= 1u; --kp) {
+        for (uint32_t kp = (uint32_t)K; kp >= (merged ? (uint32_t)K : 1u); --kp) {
             uint64_t bytes = (uint64_t)kp * u_words(mode, ng) * 4u + (uint64_t)kp * list_cap * 4u + kp * 4u +
                              fixed_for(kp) + scan_buf;
             if (bytes <= kLdsBudget) {
                 Config c;
                 c.mode = mode; c.kp = kp; c.block = block; c.split_vox = split; c.tile_vox = split;
-                c.list_cap = list_cap; c.force_split = force_split;
+                c.list_cap = list_cap; c.force_split = force_split; c.merged = merged ? 1 : 0;
                 out.push_back(c);
+                if (merged) break;
                 // many offsets: fewer directions per pass cost another pass
                 // over the voxels but leave LDS for more work-groups per CU
                 // (timed by the autotuner, never the default)
@@ -448,7 +455,7 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
         }
     }
     out.insert(out.end(), later.begin(), later.end());
-    if (!out.empty() || fixed >= kLdsBudget) return out;
+    if (!out.empty() || fixed >= kLdsBudget || merged) return out;
     // hash mode: items small enough that kp directions of pairs fill at most
     // half the table
     for (uint32_t kp = (uint32_t)K; kp >= 1u; --kp) {
@@ -559,9 +566,10 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     if (g_cap_override) n_split = g_cap_override;
     if (items >= (1ull << 31)) return fail(ctx, NYX_ERR_UNSUPPORTED, "too many work items");
     uint32_t bucket_cap = (uint32_t)std::max<uint64_t>(items, 1u);
-    uint64_t g_bytes = (uint64_t)n_split * K * (uint64_t)ng * ng * 8u;
-    const bool wave = cfg.wave_vox > 0u && wave_feasible(ng, K);
-    const uint64_t sums_bytes = (uint64_t)std::max<uint32_t>(w.n_rois, 1u) * K * sizeof(DirSums);
+    const int K_out = cfg.merged ? 1 : K;
+    uint64_t g_bytes = (uint64_t)n_split * K_out * (uint64_t)ng * ng * 8u;
+    const bool wave = !cfg.merged && cfg.wave_vox > 0u && wave_feasible(ng, K);
+    const uint64_t sums_bytes = (uint64_t)std::max<uint32_t>(w.n_rois, 1u) * K_out * sizeof(DirSums);
     uint64_t need = (uint64_t)kClasses * bucket_cap * 8u * (wave ? 2u : 1u) + g_bytes + sums_bytes + n_split * 4u;
     for (auto &b : w.tab) need += b.bytes;
     need += w.rois.bytes + w.counters.bytes;
@@ -587,6 +595,8 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
         a.off[k][2] = off[k].dx;
     }
     a.K = K;
+    a.K_out = K_out;
+    a.merged = cfg.merged;
     a.ng = (int32_t)ng;
     a.split_vox = cfg.split_vox;
     a.tile_vox = cfg.tile_vox;
@@ -908,6 +918,7 @@ nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, nyx_precision p
     StepArgs a;
     memset(&a, 0, sizeof a);
     a.K = K;
+    a.K_out = K;
     a.ng = glcm->n_bins;
     a.fp64 = prec == NYX_FP64;
     a.table = table;
@@ -934,6 +945,8 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
     if ((s = validate_bins(ctx, opts->n_bins)) != NYX_OK) return s;
     if (opts->symmetric != 1) return fail(ctx, NYX_ERR_UNSUPPORTED, "only symmetric matrices are supported");
     if (opts->precision != NYX_FP32 && opts->precision != NYX_FP64) return fail(ctx, NYX_ERR_INVALID, "bad precision");
+    if (opts->aggregate != NYX_AGG_PER_OFFSET && opts->aggregate != NYX_AGG_MERGED)
+        return fail(ctx, NYX_ERR_INVALID, "aggregate must be NYX_AGG_PER_OFFSET or NYX_AGG_MERGED");
     HIPC(ctx, hipSetDevice(ctx->device));
     hipStream_t st = ctx->capture_stream;
     std::unique_ptr<nyx_plan> p(new nyx_plan());
@@ -944,12 +957,14 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
     p->prec = opts->precision;
     if ((s = discover(ctx, imgs, n_images, p->w, st)) != NYX_OK) return s;
     if ((s = fetch_rois(ctx, p->w, st)) != NYX_OK) return s;
-    std::vector<Config> cands = candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256);
+    const bool merged = opts->aggregate == NYX_AGG_MERGED;
+    std::vector<Config> cands = candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256, merged);
     if (cands.empty())
-        return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%d with %d offsets", p->ng, p->K);
+        return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%d with %d offsets%s", p->ng, p->K,
+                    merged ? " merged in one pass" : "");
     // wavefront-per-ROI share: automatic (off unless timing finds a share
-    // that pays), off, or a given ROI size limit
-    const bool wave_ok = wave_feasible((uint32_t)p->ng, p->K);
+    // that pays), off, or a given ROI size limit; not for merged matrices
+    const bool wave_ok = !merged && wave_feasible((uint32_t)p->ng, p->K);
     const uint32_t wave_vox = !wave_ok || opts->wave_max_vox <= 0 ? 0u : (uint32_t)std::min(opts->wave_max_vox, 65535);
     for (Config &c : cands) c.wave_vox = wave_vox;
     if (opts->autotune && opts->wave_max_vox < 0 && wave_ok) {
@@ -972,7 +987,7 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
     if (opts->autotune && cands.size() > 1) {
         // time one step of every candidate and keep the fastest
         DevBuf tmp;
-        size_t row_bytes = (size_t)(p->K + 1) * kNumFeat * (p->prec == NYX_FP64 ? 8u : 4u);
+        size_t row_bytes = (size_t)(merged ? 1 : p->K + 1) * kNumFeat * (p->prec == NYX_FP64 ? 8u : 4u);
         HIPC(ctx, tmp.alloc(std::max<size_t>(p->w.n_rois, 1u) * row_bytes));
         hipEvent_t e0, e1;
         HIPC(ctx, hipEventCreate(&e0));

@@ -125,7 +125,9 @@ struct StepArgs {
     DirSums *dsums;             // roi_cap * K reduced sums, row-major by ROI
     uint32_t *split_roi;        // g_cap: ROI row of each split slot
     int32_t off[kMaxOffsets][3];
-    int32_t K;
+    int32_t K;                  // offsets
+    int32_t K_out;              // matrices per ROI: K, or 1 when the offsets' matrices are merged
+    int32_t merged;             // 1: features of the sum of the K matrices (dense scan modes only)
     int32_t ng;
     uint32_t split_vox;         // ROIs above this many voxels are split
     uint32_t tile_vox;          // target voxels per tile of a split ROI

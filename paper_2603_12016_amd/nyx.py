@@ -51,7 +51,7 @@ class nyx_glcm(ctypes.Structure):
 class nyx_extract_opts(ctypes.Structure):
     _fields_ = [("n_bins", c_int32), ("offsets_host", POINTER(nyx_offset)), ("n_offsets", c_int32),
                 ("symmetric", c_int32), ("precision", c_int), ("autotune", c_int32), ("accum_mode", c_int32),
-                ("wave_max_vox", c_int32), ("workspace_cap_bytes", c_int64)]
+                ("wave_max_vox", c_int32), ("workspace_cap_bytes", c_int64), ("aggregate", c_int32)]
 
 
 _lib = None
@@ -156,14 +156,22 @@ def _offsets(offsets):
 
 
 MODES = {"auto": -1, "dense-list": 0, "hash": 1, "dense-scan": 2, "dense16-scan": 3}
+NYX_AGG_PER_OFFSET, NYX_AGG_MERGED = 0, 1
 
 
-def _opts(n_bins, offsets, precision, autotune=0, workspace_cap=0, mode="auto", wave=-1):
+def _opts(n_bins, offsets, precision, autotune=0, workspace_cap=0, mode="auto", wave=-1,
+          aggregate=NYX_AGG_PER_OFFSET):
     arr, K = _offsets(offsets)
     o = nyx_extract_opts(int(n_bins), ctypes.cast(arr, POINTER(nyx_offset)), K, 1, int(precision),
                          int(autotune), int(MODES[mode] if isinstance(mode, str) else mode), int(wave),
-                         int(workspace_cap))
+                         int(workspace_cap), int(aggregate))
     return o, arr
+
+
+def table_blocks(n_offsets: int, aggregate: int = NYX_AGG_PER_OFFSET) -> int:
+    """Blocks of 30 features per table row: one per offset plus their mean, or
+    the one block of the merged matrix."""
+    return 1 if aggregate == NYX_AGG_MERGED else n_offsets + 1
 
 
 def _dev():
@@ -310,10 +318,11 @@ def nyx_glcm_features(ctx: Ctx, glcm: Glcm, precision: int = NYX_FP32, stream=No
 
 
 def nyx_extract_batch(ctx: Ctx, images, n_bins: int, offsets, precision: int = NYX_FP32, stream=None,
-                      capacity=None, mode="auto", wave: int = -1):
-    """One-shot extraction: returns (RoiTable, table (n, K + 1, 30))."""
+                      capacity=None, mode="auto", wave: int = -1, aggregate: int = NYX_AGG_PER_OFFSET):
+    """One-shot extraction: returns (RoiTable, table (n, blocks, 30)), blocks = K + 1, or 1 when the
+    offsets' matrices are merged."""
     imgs = _images(images)
-    opts, keep = _opts(n_bins, offsets, precision, mode=mode, wave=wave)
+    opts, keep = _opts(n_bins, offsets, precision, mode=mode, wave=wave, aggregate=aggregate)
     dev = _dev()
     if capacity is None:
         probe = RoiTable(0, dev)
@@ -325,7 +334,7 @@ def nyx_extract_batch(ctx: Ctx, images, n_bins: int, offsets, precision: int = N
         capacity = probe.n_rois
     rois = RoiTable(capacity, dev)
     dtype = torch.float64 if precision == NYX_FP64 else torch.float32
-    table = torch.zeros((max(capacity, 1), opts.n_offsets + 1, 30), dtype=dtype, device=dev)
+    table = torch.zeros((max(capacity, 1), table_blocks(opts.n_offsets, aggregate), 30), dtype=dtype, device=dev)
     st = rois.struct()
     _check(lib().nyx_extract_batch(ctx.handle, imgs, len(images), byref(opts), byref(st), table.data_ptr(),
                                    int(capacity), _stream(stream)), ctx)
@@ -333,11 +342,12 @@ def nyx_extract_batch(ctx: Ctx, images, n_bins: int, offsets, precision: int = N
 
 
 def nyx_plan_create(ctx: Ctx, images, n_bins: int, offsets, precision: int = NYX_FP32, autotune: bool = False,
-                    workspace_cap: int = 0, mode="auto", wave: int = -1) -> Plan:
+                    workspace_cap: int = 0, mode="auto", wave: int = -1,
+                    aggregate: int = NYX_AGG_PER_OFFSET) -> Plan:
     """mode: accumulation mode name (MODES) or -1/auto; wave: -1 automatic, 0 off, n > 0 the largest
     ROI (voxels) processed one wavefront per ROI."""
     imgs = _images(images)
-    opts, keep = _opts(n_bins, offsets, precision, int(autotune), workspace_cap, mode, wave)
+    opts, keep = _opts(n_bins, offsets, precision, int(autotune), workspace_cap, mode, wave, aggregate)
     h = c_void_p()
     n = c_int64(0)
     _check(lib().nyx_plan_create(ctx.handle, imgs, len(images), byref(opts), byref(h), byref(n)), ctx)
@@ -377,6 +387,6 @@ def nyx_plan_destroy(plan: Plan):
         plan.handle = None
 
 
-def new_table(plan: Plan, n_offsets: int, precision: int = NYX_FP32):
+def new_table(plan: Plan, n_offsets: int, precision: int = NYX_FP32, aggregate: int = NYX_AGG_PER_OFFSET):
     dtype = torch.float64 if precision == NYX_FP64 else torch.float32
-    return torch.zeros((max(plan.n_rois, 1), n_offsets + 1, 30), dtype=dtype, device=_dev())
+    return torch.zeros((max(plan.n_rois, 1), table_blocks(n_offsets, aggregate), 30), dtype=dtype, device=_dev())

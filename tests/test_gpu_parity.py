@@ -411,3 +411,71 @@ def test_full_size_sampled(env, workloads, oracle_mod, name):
     _check_features(got, want, Ps, TOL_FP32, f"{name} sampled")
     tab = table.cpu().numpy()[:len(ro)]
     assert np.all(np.isfinite(tab[n >= 4][:, -1, 0]))
+
+
+# ------------------------------------------------------------------ merged matrices
+# NYX_AGG_MERGED: the features of the sum of the offsets' matrices, one block
+# per row, through the one-shot call, the plan and the per-ROI launches.
+@pytest.mark.parametrize("name,prec", [("c1_tiny", 1), ("c3_small", 0), ("c3_small", 1), ("c4_small", 0)])
+def test_merged_matrices(env, workloads, oracle_mod, name, prec):
+    import torch
+    nyx, ctx, dev = env
+    w = workloads(name)
+    say(f"case {name} merged prec={prec}")
+    offs = _offsets(nyx, w)
+    imgs = device_images(w, dev)
+    rois, t0 = nyx.nyx_extract_batch(ctx, imgs, w.n_bins, offs, prec, aggregate=nyx.NYX_AGG_MERGED)
+    plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, prec, aggregate=nyx.NYX_AGG_MERGED)
+    say("  plan:", nyx.nyx_plan_describe(plan))
+    t1 = nyx.new_table(plan, len(offs), prec, aggregate=nyx.NYX_AGG_MERGED)
+    t2 = nyx.new_table(plan, len(offs), prec, aggregate=nyx.NYX_AGG_MERGED)
+    nyx.nyx_plan_execute(plan, t1)
+    nyx.nyx_plan_execute_per_roi(plan, t2)
+    torch.cuda.synchronize()
+    nyx.nyx_plan_check(plan)
+    off = np.array(offs, np.int32)
+    want, M = [], []
+    for k, r, st in oracle_rois(oracle_mod, w):
+        P = oracle_mod.glcm_roi(w.intensity[k], w.labels[k], st["label"][r], st["vmin"][r], st["vmax"][r],
+                                st["bbox"][r], w.n_bins, off)
+        want.append(oracle_mod.features_roi_merged(P))
+        M.append(scales(P.sum(axis=0, dtype=np.uint64)[None])[:1])
+    want = np.array(want)
+    tol = TOL_FP64 if prec == 1 else TOL_FP32
+    for tag, got in (("one-shot", t0), ("plan", t1), ("per-roi", t2)):
+        got = got.cpu().numpy()[:len(want)]
+        assert got.shape == want.shape, (tag, got.shape, want.shape)
+        e, fname, idx = worst(np.stack([feature_errors(got[i], want[i], M[i]) for i in range(len(want))]))
+        say(f"  {name} merged {tag}: {len(want)} ROIs, max error {e:.3e} ({fname} at {idx})")
+        assert e <= tol, (tag, fname, idx)
+
+
+def test_merged_needs_triangles_in_lds(env):
+    # 256 levels x 4 offsets: the four 32-bit triangles do not fit LDS at once
+    nyx, ctx, dev = env
+    rng = np.random.default_rng(4)
+    I = rng.integers(0, 4000, (1, 40, 40)).astype(np.uint16)
+    L = np.ones((1, 40, 40), np.uint32)
+    with pytest.raises(nyx.NyxError) as e:
+        _run_extract_merged(nyx, ctx, dev, I, L, 256)
+    assert e.value.status == nyx.NYX_ERR_UNSUPPORTED
+
+
+def test_merged_checkerboard_closed_form(env):
+    import torch
+    nyx, ctx, dev = env
+    y, x = np.mgrid[0:8, 0:8]
+    I = (((x + y) % 2) * 4095).astype(np.uint16)[None]
+    L = np.ones((1, 8, 8), np.uint32)
+    rois, table = _run_extract_merged(nyx, ctx, dev, I, L, 8)
+    f = dict(zip(NAMES, table.cpu().numpy()[0, 0]))
+    assert table.shape == (1, 1, 30)
+    assert f["CONTRAST"] == pytest.approx(392 / 15, rel=1e-14)
+    assert f["DIS"] == pytest.approx(56 / 15, rel=1e-14)
+
+
+def _run_extract_merged(nyx, ctx, dev, I, L, ng):
+    from types import SimpleNamespace
+    w = SimpleNamespace(intensity=I[None], labels=L[None], n_images=1)
+    return nyx.nyx_extract_batch(ctx, device_images(w, dev), ng, nyx.nyx_offsets_default(2, 1), nyx.NYX_FP64,
+                                 aggregate=nyx.NYX_AGG_MERGED)

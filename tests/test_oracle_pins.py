@@ -385,3 +385,65 @@ def test_iid_uniform_statistics(oracle_mod, synth_mod):
     P = oracle_mod.glcm_roi(w.intensity[0], w.labels[0], 1, st["vmin"][0], st["vmax"][0],
                             st["bbox"][0], 8, oracle_mod.default_offsets(2))
     assert P.sum(axis=(1, 2)).tolist() == [8064, 7938, 8064, 7938]
+
+
+# ---------------------------------------------------------------- merged matrices
+# Reading A15: the offsets' counts pooled into one symmetric matrix, then the
+# 30 features of that matrix.
+@pytest.mark.parametrize("dims,seed", [(2, 1), (2, 2), (3, 3)])
+def test_merged_pairlist_route(oracle_mod, dims, seed):
+    # independent route: the brute-force pair lists of all offsets pooled
+    rng = np.random.default_rng(500 + seed)
+    shape = (1, 9, 10) if dims == 2 else (4, 4, 5)
+    I, L = _rand_scene(rng, shape, 3 if dims == 2 else 2, fill=0.9, hi=60 if dims == 2 else 40)
+    ng = 9
+    off = oracle_mod.default_offsets(dims)
+    st = oracle_mod.roi_stats(I, L)
+    B = oracle_mod.bin_image(I, L, ng, st)
+    n = 0
+    for r, lab in enumerate(st["label"]):
+        P = oracle_mod.glcm_roi(I, L, lab, st["vmin"][r], st["vmax"][r], st["bbox"][r], ng, off)
+        got = oracle_mod.features_roi_merged(P)
+        assert got.shape == (1, 30)
+        f = features_from_pairs(np.concatenate([ordered_pairs(B, L, lab, d) for d in off]), ng)
+        if f is None:
+            assert np.all(np.isnan(got))
+            continue
+        for q, name in enumerate(NAMES):
+            want = f[name]
+            assert abs(got[0, q] - want) <= 1e-11 * max(abs(want), 1.0), (lab, name, got[0, q], want)
+        n += 1
+    assert n >= 2
+
+
+def test_merged_checkerboard_contrast(oracle_mod):
+    # 8 x 8 two-level checkerboard at 8 levels (1 and 8): the 0 and 90 degree
+    # offsets give 56 + 56 unordered pairs of levels (1, 8), the diagonals
+    # 49 + 49 same-level pairs.  Pooled symmetric counts: T = 2 (112 + 98) =
+    # 420, of which 224 at |i - j| = 7, so CONTRAST = 224 * 49 / 420 = 392/15
+    # and DIS = 224 * 7 / 420 = 56/15.
+    n = 8
+    y, x = np.mgrid[0:n, 0:n]
+    I = (((x + y) % 2) * 4095).astype(np.uint16)[None]
+    L = np.ones((1, n, n), np.uint32)
+    st = oracle_mod.roi_stats(I, L)
+    P = oracle_mod.glcm_roi(I, L, 1, st["vmin"][0], st["vmax"][0], st["bbox"][0], 8, oracle_mod.default_offsets(2))
+    f = oracle_mod.features_roi_merged(P)[0]
+    assert f[NAMES.index("CONTRAST")] == pytest.approx(392 / 15, rel=1e-14)
+    assert f[NAMES.index("DIS")] == pytest.approx(56 / 15, rel=1e-14)
+
+
+def test_merged_scale_invariance(oracle_mod):
+    # an offset listed twice doubles every count: the normalised matrix, and
+    # so every feature, is that of the offset alone
+    rng = np.random.default_rng(91)
+    I, L = _rand_scene(rng, (1, 12, 11), 2, fill=0.9)
+    st = oracle_mod.roi_stats(I, L)
+    for r, lab in enumerate(st["label"]):
+        one = oracle_mod.glcm_roi(I, L, lab, st["vmin"][r], st["vmax"][r], st["bbox"][r], 16,
+                                  np.array([[0, 1, 1]], np.int32))
+        two = oracle_mod.glcm_roi(I, L, lab, st["vmin"][r], st["vmax"][r], st["bbox"][r], 16,
+                                  np.array([[0, 1, 1], [0, -1, -1]], np.int32))
+        assert np.array_equal(two.sum(axis=0), 2 * one[0])
+        np.testing.assert_allclose(oracle_mod.features_roi_merged(two)[0], oracle_mod.features_roi(one)[0],
+                                   rtol=1e-12, atol=1e-13)
