@@ -187,6 +187,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--aggregate", choices=("per-offset", "merged"), default="per-offset",
+                    help="features per offset and their mean (default), or of the summed matrix")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/*_traffic.txt from rocprofv3 counter CSVs of this script and exit")
     ap.add_argument("--summarize-trace", metavar="STATS_CSV",
@@ -233,13 +235,14 @@ def main() -> int:
     prec = nyx.NYX_FP64 if w.precision == "fp64" else nyx.NYX_FP32
     ctx = nyx.nyx_create(0)
     t0 = time.perf_counter()
-    plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, prec, autotune=not args.no_autotune)
+    agg = nyx.NYX_AGG_MERGED if args.aggregate == "merged" else nyx.NYX_AGG_PER_OFFSET
+    plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, prec, autotune=not args.no_autotune, aggregate=agg)
     plan_s = time.perf_counter() - t0
     log(f"plan in {plan_s:.2f} s: {nyx.nyx_plan_describe(plan)}")
     n_rois = plan.n_rois
     roi_vox = int(np.count_nonzero(w.labels))
     img_vox = int(w.labels.size)
-    table = nyx.new_table(plan, K, prec)
+    table = nyx.new_table(plan, K, prec, aggregate=agg)
 
     for _ in range(args.warmup):
         nyx.nyx_plan_execute(plan, table)
@@ -274,7 +277,7 @@ def main() -> int:
     # one launch per ROI
     dt_roi, same = None, None
     if args.per_roi_steps > 0:
-        t2 = nyx.new_table(plan, K, prec)
+        t2 = nyx.new_table(plan, K, prec, aggregate=agg)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.per_roi_steps):
@@ -291,7 +294,7 @@ def main() -> int:
     desc = nyx.nyx_plan_describe(plan)
     fields = dict(kv.split("=", 1) for kv in desc.split() if "=" in kv)
     wave_rois, wave_vox = int(fields.get("wave_rois", 0)), int(fields.get("wave_roi_voxels", 0))
-    row_bytes = (K + 1) * 30 * (8 if prec == nyx.NYX_FP64 else 4)
+    row_bytes = nyx.table_blocks(K, agg) * 30 * (8 if prec == nyx.NYX_FP64 else 4)
     out_bytes = n_rois * row_bytes
     alg = {"scan": img_vox * 6.0,
            "batch": (roi_vox - wave_vox) * 6.0 + (n_rois - wave_rois) * row_bytes,
@@ -327,7 +330,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "description": w.description, "images": w.n_images,
                    "image_voxels": img_vox, "roi_voxels": roi_vox, "rois": n_rois, "n_bins": w.n_bins,
-                   "offsets": K, "plan": nyx.nyx_plan_describe(plan)},
+                   "offsets": K, "aggregate": args.aggregate, "plan": nyx.nyx_plan_describe(plan)},
         "per_roi_launch": None if dt_roi is None else {"value": roi_vox / dt_roi, "ms_per_step": dt_roi * 1e3,
                                                        "steps": args.per_roi_steps, "tables_agree": same},
         "speedup_vs_per_roi": None if dt_roi is None else dt_roi * 1e3 / ms,
@@ -342,11 +345,14 @@ def main() -> int:
         "machine": machine,
         "roofline": {"kernel": kernel_names[dom], "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": stored_traffic(kernel_names[dom], args.workload),
+                     "traffic": stored_traffic(kernel_names[dom], args.workload) if agg == nyx.NYX_AGG_PER_OFFSET
+                     else None,
                      "alg_bytes": alg[dom], "ms": prof[dom]},
         "plan_seconds": plan_s,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and agg == nyx.NYX_AGG_MERGED:
+        log("cpu baseline skipped: the oracle's timed extraction is the per-offset one")
+    elif not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(w, offs, args.cpu_seconds)
         log(f"cpu baseline: {rec['cpu_baseline']['value'] / 1e6:.2f} M ROI-voxels/s")

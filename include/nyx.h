@@ -116,10 +116,10 @@ typedef struct nyx_glcm {
  *   NYX_AGG_PER_OFFSET  features of each offset's matrix and their mean
  *                       (table rows of n_offsets + 1 blocks);
  *   NYX_AGG_MERGED      features of P = sum over the offsets of P_k, one
- *                       matrix per ROI (table rows of 1 block).  Needs every
- *                       offset's triangle in LDS at once and a dense scan
- *                       accumulation mode; NYX_ERR_UNSUPPORTED otherwise
- *                       (e.g. 1024 levels). */
+ *                       matrix per ROI (table rows of 1 block): every offset
+ *                       counts into one LDS triangle, so it needs that
+ *                       triangle in LDS and a dense scan accumulation mode;
+ *                       NYX_ERR_UNSUPPORTED otherwise (e.g. 1024 levels). */
 typedef enum nyx_aggregate { NYX_AGG_PER_OFFSET = 0, NYX_AGG_MERGED = 1 } nyx_aggregate;
 
 typedef struct nyx_extract_opts {

@@ -918,14 +918,14 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
     // LDS starts clean and every item leaves it clean.
     if (MODE != 1) {
         uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off);
-        for (uint32_t i = threadIdx.x; i < Ly.kp * Ly.tri_pad; i += blockDim.x) U[i] = 0u;
+        for (uint32_t i = threadIdx.x; i < Ly.n_tri * Ly.tri_pad; i += blockDim.x) U[i] = 0u;
     } else {
         uint32_t *HK = reinterpret_cast<uint32_t *>(smem + Ly.hkey_off);
         uint32_t *HC = reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off);
         for (uint32_t i = threadIdx.x; i < Ly.hash_cap; i += blockDim.x) { HK[i] = kNone; HC[i] = 0u; }
     }
     // marginal sets exist for the waves that reduce a direction (w < kp)
-    for (uint32_t i = threadIdx.x; i < min((uint32_t)nw, Ly.kp) * marg_words; i += blockDim.x)
+    for (uint32_t i = threadIdx.x; i < Ly.marg_sets * marg_words; i += blockDim.x)
         reinterpret_cast<uint32_t *>(smem + Ly.marg_off)[i] = 0u;
     for (uint32_t i = threadIdx.x; i < Ly.kp; i += blockDim.x) LCNT[i] = 0u;
     if (threadIdx.x == 0 && direct_roi == kNone) ticket_setup(MISC, a.counters + C_CLASS, a.bucket_cap);
@@ -969,8 +969,10 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
             for (int d0 = 0, pass = 0; d0 < K; d0 += (int)Ly.kp, ++pass) {
                 const int d1 = min(K, d0 + (int)Ly.kp);
                 if (ra < rb && ca < cb) {
+                    // merged matrices: every offset counts into the one triangle
+                    const bool merged = MODE >= 2 && a.merged;
                     auto add = [&](uint32_t dl, uint32_t la, uint32_t ta, uint32_t lb, uint32_t tb) {
-                        add_pair<MODE>(a, smem, dl, la, ta, lb, tb);
+                        add_pair<MODE>(a, smem, merged ? 0u : dl, la, ta, lb, tb);
                     };
                     const uint32_t W = (uint32_t)(rd.x1 - rd.x0 + 1), H = (uint32_t)(rd.y1 - rd.y0 + 1);
                     const uint32_t ring_rows = Ly.ring_bytes / W;
@@ -986,22 +988,6 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
                         accumulate_rows(a, rd, c, ra, rb, ca, cb, d0, d1, threadIdx.x, blockDim.x, add);
                 }
                 __syncthreads();
-                if (MODE >= 2 && a.merged) {
-                    // one matrix for all offsets: the pass's triangles (every
-                    // offset is in this one pass) summed into the first, the
-                    // others cleared; the planner keeps every summed cell below
-                    // the counter limit, so packed halves add without carries
-                    uint32_t *U0 = reinterpret_cast<uint32_t *>(smem + Ly.u_off);
-                    for (uint32_t i = threadIdx.x; i < Ly.tri_pad; i += blockDim.x) {
-                        uint32_t s = 0u;
-                        for (int dl = 1; dl < d1 - d0; ++dl) {
-                            s += U0[dl * Ly.tri_pad + i];
-                            U0[dl * Ly.tri_pad + i] = 0u;
-                        }
-                        U0[i] += s;
-                    }
-                    __syncthreads();
-                }
                 const int n_mat = (MODE >= 2 && a.merged) ? 1 : d1 - d0;
                 for (int dl = w; dl < n_mat; dl += nw) {
                     uint32_t *Ud = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;

@@ -329,7 +329,8 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K, bool ring) {
         return o;
     };
     if (c.mode != 1) {
-        L.u_off = take(c.kp * L.tri_pad * 4u);
+        L.n_tri = c.merged ? 1u : c.kp;   // merged: one triangle for all offsets
+        L.u_off = take(L.n_tri * L.tri_pad * 4u);
     } else {
         L.hkey_off = take(c.hash_cap * 4u);
         L.hcnt_off = take(c.hash_cap * 4u);
@@ -337,7 +338,8 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K, bool ring) {
     L.list_off = take(c.kp * c.list_cap * 4u);
     L.lcnt_off = take(c.kp * 4u);
     L.buf_off = take((c.mode == 2 || c.mode == 3) ? L.nwaves * kWave * scan_cells(c.mode) * 4u : 0u);
-    L.marg_off = take(std::min(L.nwaves, c.kp) * 4u * ng * 4u);   // one set per wave that reduces a direction
+    L.marg_sets = std::min(L.nwaves, c.merged ? 1u : c.kp);   // one set per wave that reduces a matrix
+    L.marg_off = take(L.marg_sets * 4u * ng * 4u);
     L.misc_off = take(128u * 4u);
     L.item_off = take((uint32_t)kTicketChunk * kItemBytes);
     if (ring && ng <= 255u && c.mode != 1) {
@@ -368,8 +370,10 @@ LdsLayout make_wave_layout(uint32_t ng, int K) {
         off += (bytes + 15u) & ~15u;
         return o;
     };
+    L.n_tri = (uint32_t)K;
     L.u_off = take((uint32_t)K * L.tri_pad * 4u);
     L.buf_off = take(kWave * (uint32_t)kScanCells * 4u);
+    L.marg_sets = (uint32_t)K;
     L.marg_off = take((uint32_t)K * 4u * ng * 4u);
     L.misc_off = take(128u * 4u);
     L.bytes = off;
@@ -398,9 +402,10 @@ uint64_t max_item_vox(const std::vector<RoiDesc> &rois, uint32_t split_vox, uint
 // Feasible LDS configurations for this workload, one per accumulation mode,
 // each with as many directions per pass as fit.  Dense triangles first; the
 // hash table only when no dense triangle fits.
-// merged: the K matrices are summed in LDS after one pass over every offset,
-// so only the dense scan modes with all K offsets in one pass qualify, and
-// packed 16-bit counters need K x (voxels of an item) < 65536.
+// merged: every offset counts into one LDS triangle in one pass, so only the
+// dense scan modes qualify, and packed 16-bit counters need K x (voxels of an
+// item) < 65536 (offered only when that bound leaves the load-balance tile
+// size alone; 32-bit counters otherwise).
 std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_t ng, int K, int force_split,
                                       uint32_t block, bool merged = false) {
     std::vector<Config> out;
@@ -429,12 +434,14 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
             mi = max_item_vox(w.h_rois, split, split);
         }
         if (mode == 3 && mi > cell_max) continue;
+        if (merged && mode == 3 && split < std::min<uint32_t>(lb, 65535u)) continue;
         const bool scan = mode == 2 || mode == 3;
         const uint32_t list_cap = scan ? 0u : (uint32_t)std::min<uint64_t>(tri, std::max<uint64_t>(mi, 1u));
         const uint64_t scan_buf = scan ? (uint64_t)nw * kWave * scan_cells(mode) * 4u : 0u;
         for (uint32_t kp = (uint32_t)K; kp >= (merged ? (uint32_t)K : 1u); --kp) {
-            uint64_t bytes = (uint64_t)kp * u_words(mode, ng) * 4u + (uint64_t)kp * list_cap * 4u + kp * 4u +
-                             fixed_for(kp) + scan_buf;
+            const uint32_t n_tri = merged ? 1u : kp;
+            uint64_t bytes = (uint64_t)n_tri * u_words(mode, ng) * 4u + (uint64_t)kp * list_cap * 4u + kp * 4u +
+                             fixed_for(n_tri) + scan_buf;
             if (bytes <= kLdsBudget) {
                 Config c;
                 c.mode = mode; c.kp = kp; c.block = block; c.split_vox = split; c.tile_vox = split;

@@ -108,6 +108,8 @@ struct LdsLayout {
     uint32_t ring_off, ring_bytes;   // level ring of the staged accumulation (0 bytes: none)
     uint32_t bytes;       // total dynamic LDS
     uint32_t nwaves;      // waves per work-group
+    uint32_t marg_sets;   // marginal sets at marg_off (one per wave that reduces a matrix)
+    uint32_t n_tri;       // dense triangles at u_off (kp, or 1 when the offsets' matrices are merged)
 };
 
 struct StepArgs {

@@ -416,7 +416,8 @@ def test_full_size_sampled(env, workloads, oracle_mod, name):
 # ------------------------------------------------------------------ merged matrices
 # NYX_AGG_MERGED: the features of the sum of the offsets' matrices, one block
 # per row, through the one-shot call, the plan and the per-ROI launches.
-@pytest.mark.parametrize("name,prec", [("c1_tiny", 1), ("c3_small", 0), ("c3_small", 1), ("c4_small", 0)])
+@pytest.mark.parametrize("name,prec", [("c1_tiny", 1), ("c2_small", 0), ("c3_small", 0), ("c3_small", 1),
+                                       ("c4_small", 0)])
 def test_merged_matrices(env, workloads, oracle_mod, name, prec):
     import torch
     nyx, ctx, dev = env
@@ -450,14 +451,14 @@ def test_merged_matrices(env, workloads, oracle_mod, name, prec):
         assert e <= tol, (tag, fname, idx)
 
 
-def test_merged_needs_triangles_in_lds(env):
-    # 256 levels x 4 offsets: the four 32-bit triangles do not fit LDS at once
+def test_merged_needs_a_triangle_in_lds(env):
+    # 1024 levels: one 32-bit triangle is 2 MB, beyond LDS
     nyx, ctx, dev = env
     rng = np.random.default_rng(4)
     I = rng.integers(0, 4000, (1, 40, 40)).astype(np.uint16)
     L = np.ones((1, 40, 40), np.uint32)
     with pytest.raises(nyx.NyxError) as e:
-        _run_extract_merged(nyx, ctx, dev, I, L, 256)
+        _run_extract_merged(nyx, ctx, dev, I, L, 1024)
     assert e.value.status == nyx.NYX_ERR_UNSUPPORTED
 
 
