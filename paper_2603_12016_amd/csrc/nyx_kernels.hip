@@ -414,22 +414,30 @@ __device__ __forceinline__ uint32_t ticket_chunk(int cl) {
 }
 
 // misc[64 + cl]: first ticket of class cl; misc[96 + cl]: its entries
-// (clamped to the bucket capacity); misc[63]: number of tickets.
-__device__ void ticket_setup(uint32_t *misc, const uint32_t *cls_cnt, uint32_t cap) {
+// (clamped to the bucket capacity); misc[63]: number of tickets.  The class
+// counts are loaded by lanes 0..kClasses-1 at once (ticket_load, every thread
+// calls it), then one thread forms the offsets (ticket_prefix) after a
+// barrier.
+__device__ __forceinline__ void ticket_load(uint32_t *misc, const uint32_t *cls_cnt, uint32_t cap, uint32_t tid) {
+    if (tid < (uint32_t)kClasses) misc[96 + tid] = min(cls_cnt[tid], cap);
+}
+
+__device__ void ticket_prefix(uint32_t *misc) {
     uint32_t acc = 0;
     for (int cl = kClasses - 1; cl >= 0; --cl) {
-        const uint32_t cnt = min(cls_cnt[cl], cap), ch = ticket_chunk(cl);
         misc[64 + cl] = acc;
-        misc[96 + cl] = cnt;
-        acc += (cnt + ch - 1u) / ch;
+        acc += (misc[96 + cl] + ticket_chunk(cl) - 1u) / ticket_chunk(cl);
     }
     misc[63] = acc;
 }
 
-// Claims a ticket and writes its entries as (roi, tile) pairs to misc[0..);
-// returns how many (0 once the queue is drained).
-__device__ uint32_t ticket_claim(uint32_t *misc, uint32_t *ctr, const uint2 *buckets, uint32_t cap) {
-    const uint32_t t = atomicAdd(ctr, 1u);
+// Claims ticket `atomicAdd(ctr) * lanes + lane` and writes its entries as
+// (roi, tile) pairs to misc[0..); returns how many (0 once the queue is
+// drained).  The counters of lanes 0..lanes-1 together hand out every ticket
+// once.
+__device__ uint32_t ticket_claim(uint32_t *misc, uint32_t *ctr, uint32_t lane_, uint32_t lanes, const uint2 *buckets,
+                                 uint32_t cap) {
+    const uint32_t t = atomicAdd(ctr, 1u) * lanes + lane_;
     if (t >= misc[63]) return 0u;
     int cl = kClasses - 1;
     const auto end_of = [&](int c) { return misc[64 + c] + (misc[96 + c] + ticket_chunk(c) - 1u) / ticket_chunk(c); };
@@ -928,7 +936,9 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
     for (uint32_t i = threadIdx.x; i < Ly.marg_sets * marg_words; i += blockDim.x)
         reinterpret_cast<uint32_t *>(smem + Ly.marg_off)[i] = 0u;
     for (uint32_t i = threadIdx.x; i < Ly.kp; i += blockDim.x) LCNT[i] = 0u;
-    if (threadIdx.x == 0 && direct_roi == kNone) ticket_setup(MISC, a.counters + C_CLASS, a.bucket_cap);
+    if (direct_roi == kNone) ticket_load(MISC, a.counters + C_CLASS, a.bucket_cap, threadIdx.x);
+    __syncthreads();
+    if (threadIdx.x == 0 && direct_roi == kNone) ticket_prefix(MISC);
     __syncthreads();
 
     for (uint32_t iter = 0;; ++iter) {
@@ -941,7 +951,10 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
                     n = 1;
                 }
             } else {
-                n = ticket_claim(MISC, &a.counters[C_TICKET], a.buckets, a.bucket_cap);
+                // (every lane has a work-group: a grid below kTicketLanes uses fewer)
+                const uint32_t lanes = min(kTicketLanes, gridDim.x), tl = blockIdx.x % lanes;
+                n = ticket_claim(MISC, &a.counters[C_TICKETS + tl * kTicketStride], tl, lanes, a.buckets,
+                                 a.bucket_cap);
             }
             MISC[32] = n;
         }
@@ -1036,7 +1049,9 @@ __global__ __launch_bounds__(64) void k_wave(StepArgs a, uint32_t direct_roi) {
     const WaveGrp wg;
     for (uint32_t i = ln; i < (uint32_t)K * Ly.tri_pad; i += kWave) U[i] = 0u;
     for (uint32_t i = ln; i < (uint32_t)K * 4u * ng; i += kWave) MARG[i] = 0u;
-    if (ln == 0 && direct_roi == kNone) ticket_setup(MISC, a.counters + C_CLASS_W, a.bucket_cap);
+    if (direct_roi == kNone) ticket_load(MISC, a.counters + C_CLASS_W, a.bucket_cap, ln);
+    wg.sync();
+    if (ln == 0 && direct_roi == kNone) ticket_prefix(MISC);
     wg.sync();
     for (uint32_t iter = 0;; ++iter) {
         if (ln == 0) {
@@ -1044,7 +1059,7 @@ __global__ __launch_bounds__(64) void k_wave(StepArgs a, uint32_t direct_roi) {
             if (direct_roi != kNone) {
                 if (iter == 0 && direct_roi < a.roi_cap) { MISC[0] = direct_roi; MISC[1] = 0u; n = 1; }
             } else {
-                n = ticket_claim(MISC, &a.counters[C_TICKET_W], a.buckets_w, a.bucket_cap);
+                n = ticket_claim(MISC, &a.counters[C_TICKET_W], 0u, 1u, a.buckets_w, a.bucket_cap);
             }
             MISC[32] = n;
         }

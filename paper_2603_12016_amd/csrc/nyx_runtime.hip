@@ -33,6 +33,7 @@ const char *const kFeatureNames[kNumFeat] = {
 
 constexpr uint32_t kLdsBudget = 160u * 1024u;   // LDS per CU on gfx950
 constexpr uint32_t kRingMin = 2048u, kRingMax = 32768u;   // staged-accumulation level ring (bytes)
+constexpr uint32_t kMaxGroupsPerCu = 5u;                  // k_batch, single precision: 5 waves per SIMD
 constexpr uint32_t kMaxNgFused = 8191u;         // hash keys carry 13-bit levels
 constexpr uint64_t kMaxLabelEntries = 1ull << 26;
 
@@ -343,7 +344,9 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K, bool ring) {
     L.misc_off = take(128u * 4u);
     L.item_off = take((uint32_t)kTicketChunk * kItemBytes);
     if (ring && ng <= 255u && c.mode != 1) {
-        const uint32_t per_group = kLdsBudget / std::max(1u, kLdsBudget / off);
+        // work-groups per CU: LDS-bound, and at most kMaxGroupsPerCu (the
+        // single-precision kernel's register bound)
+        const uint32_t per_group = kLdsBudget / std::max(1u, std::min(kMaxGroupsPerCu, kLdsBudget / off));
         const uint32_t bytes = off < per_group ? std::min(kRingMax, (per_group - off) & ~15u) : 0u;
         if (bytes >= kRingMin) {
             L.ring_off = take(bytes);

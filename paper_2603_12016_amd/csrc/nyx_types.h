@@ -21,14 +21,19 @@ constexpr int kMaxSweepPasses = 16;    // passes with a precomputed 2D sweep map
 enum Counter : int {
     C_NROIS = 0,    // ROIs found by the last compaction
     C_NSPLIT = 1,   // ROIs split into several tiles (global-matrix slots used)
-    C_TICKET = 2,   // work-stealing ticket of the persistent kernel
     C_ERR = 3,      // error bits (see ErrBit)
     C_NITEMS = 4,   // work items enqueued
     C_TICKET_W = 5, // work-stealing ticket of the wave-per-ROI kernel
     C_CLASS = 8,    // kClasses counters: work-group items per size class
     C_CLASS_W = 64, // kClasses counters: wave-per-ROI items per size class
-    C_BLOCKS = 128, // per-block ROI counts of the compaction (variable length)
+    C_TICKETS = 128,  // kTicketLanes ticket counters of the persistent kernel, kTicketStride apart
+    C_BLOCKS = 128 + 32 * 32, // per-block ROI counts of the compaction (variable length)
 };
+// Work-group w draws tickets w mod kTicketLanes, +kTicketLanes, ... from
+// its own counter: the claims spread over kTicketLanes memory lines instead
+// of serialising on one.
+constexpr uint32_t kTicketLanes = 32, kTicketStride = 32;
+static_assert(C_TICKETS + kTicketLanes * kTicketStride <= C_BLOCKS, "ticket counters overlap");
 
 enum ErrBit : uint32_t {
     E_LABEL_RANGE = 1u,   // a label exceeds the planned label-table capacity
