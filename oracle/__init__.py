@@ -9,7 +9,7 @@ Definitions follow the paper's problem statement (one row of measurements per
 unique nonzero label of the mask, Supplementary Table S7) and its GLCM feature
 list (Supplementary Table S3, rows 140-174 marked NY; 3D: Table S5, row 361),
 with the standard IBSI formulas the paper defers to.  Readings of points the
-paper leaves open are the [A#] items of the design doc.
+paper leaves open carry [A#] labels where they are applied.
 """
 from __future__ import annotations
 

@@ -19,7 +19,7 @@
  *    formulas and defers to the IBSI standard it cites (Results, "Accuracy and
  *    Reproducibility"); the formulas below are the standard IBSI/Haralick
  *    definitions.  Readings of points the paper leaves open are marked [A#]
- *    and listed in the design doc's ambiguity register.
+ *    where they are applied (the same labels name them in the design notes).
  *
  * Conventions:
  *  - Image layout [nz][ny][nx], x fastest.  Label 0 is background; voxels
