@@ -202,7 +202,7 @@ def main() -> int:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, COPY_BYTES, args.pmc_command)
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures a single GPU; multi-GPU runs are not part of this build (use --gpus 1)",
+        print("bench.py measures a single GPU: the path runs on one GPU and several GPUs are not supported (use --gpus 1)",
               file=sys.stderr)
         return 2
 

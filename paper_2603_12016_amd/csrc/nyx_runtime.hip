@@ -170,7 +170,7 @@ nyx_status validate_offsets(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_image
 nyx_status validate_bins(nyx_ctx *ctx, int32_t ng) {
     if (ng < 2 || ng > 65535) return fail(ctx, NYX_ERR_INVALID, "n_bins must be in [2, 65535]");
     if ((uint32_t)ng > kMaxNgFused)
-        return fail(ctx, NYX_ERR_UNSUPPORTED, "n_bins above %u is not supported by this build", kMaxNgFused);
+        return fail(ctx, NYX_ERR_UNSUPPORTED, "n_bins above %u is not supported", kMaxNgFused);
     return NYX_OK;
 }
 
