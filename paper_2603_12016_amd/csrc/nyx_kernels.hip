@@ -695,33 +695,49 @@ __device__ void accumulate_staged(const StepArgs &a, const RoiDesc &rd, const It
         {
             const uint32_t n = (r1 - r0) * W;
             Pos p = start(r0);
-            for (uint32_t f = t0; f < n; f += ts) {
-                const uint32_t lv = ring[__umul24(p.slot, W) + p.x];
-                if (lv) {
-                    const uint32_t tv = row_off(lv);
+            // two voxels per lane in flight: their neighbour reads are all
+            // issued before the first pair add
+            for (uint32_t f = t0; f < n; f += 2u * ts) {
+                Pos q = p;
+                advance(q);
+                const bool second = f + ts < n;
+                const uint32_t lv0 = ring[__umul24(p.slot, W) + p.x];
+                const uint32_t lv1 = second ? (uint32_t)ring[__umul24(q.slot, W) + q.x] : 0u;
+                if (lv0 | lv1) {
+                    const uint32_t tv0 = row_off(lv0), tv1 = row_off(lv1);
                     for (int db = d0; db < d1; db += kStagedDirs) {
-                        // every neighbour read of the group is issued before the first add
-                        uint32_t lw[kStagedDirs];
+                        uint32_t lw0[kStagedDirs], lw1[kStagedDirs];
 #pragma unroll
                         for (int k = 0; k < kStagedDirs; ++k) {
-                            lw[k] = 0u;
+                            lw0[k] = 0u;
+                            lw1[k] = 0u;
                             const int d = db + k;
                             if (d < d1) {
                                 int32_t dz, dy, dx;
                                 forward_offset(a, d, dz, dy, dx);
-                                const uint32_t yy = p.y + (uint32_t)dy, xx = p.x + (uint32_t)dx;
-                                if (yy < H && xx < W) {
-                                    uint32_t s2 = p.slot + (uint32_t)(dz * (int32_t)H + dy);
+                                const uint32_t dr = (uint32_t)(dz * (int32_t)H + dy);
+                                const uint32_t yy0 = p.y + (uint32_t)dy, xx0 = p.x + (uint32_t)dx;
+                                if (lv0 && yy0 < H && xx0 < W) {
+                                    uint32_t s2 = p.slot + dr;
                                     if (s2 >= ring_rows) s2 -= ring_rows;
-                                    lw[k] = ring[__umul24(s2, W) + xx];
+                                    lw0[k] = ring[__umul24(s2, W) + xx0];
+                                }
+                                const uint32_t yy1 = q.y + (uint32_t)dy, xx1 = q.x + (uint32_t)dx;
+                                if (lv1 && yy1 < H && xx1 < W) {
+                                    uint32_t s2 = q.slot + dr;
+                                    if (s2 >= ring_rows) s2 -= ring_rows;
+                                    lw1[k] = ring[__umul24(s2, W) + xx1];
                                 }
                             }
                         }
 #pragma unroll
-                        for (int k = 0; k < kStagedDirs; ++k)
-                            if (lw[k]) add((uint32_t)(db + k - d0), lv, tv, lw[k], row_off(lw[k]));
+                        for (int k = 0; k < kStagedDirs; ++k) {
+                            if (lw0[k]) add((uint32_t)(db + k - d0), lv0, tv0, lw0[k], row_off(lw0[k]));
+                            if (lw1[k]) add((uint32_t)(db + k - d0), lv1, tv1, lw1[k], row_off(lw1[k]));
+                        }
                     }
                 }
+                p = q;
                 advance(p);
             }
         }
