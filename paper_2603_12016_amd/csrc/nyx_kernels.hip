@@ -845,7 +845,11 @@ __device__ void accumulate_sweep2d(const RoiDesc &rd, const ItemCtx &c, uint32_t
     const uint32_t S = 1u << lg, Wl = 64u >> lg, Wo = Wl - 1u;
     const uint32_t sub = ln >> (6u - lg), col = ln & (Wl - 1u);
     const uint32_t nstrip = (Wt + Wo - 1u) / Wo;
-    const uint32_t unit_rows = kSweepSteps * S;
+    // steps per unit: kSweepSteps, or fewer (at least 2) when a small tile
+    // would otherwise leave some of the nw wavefronts without a unit
+    uint32_t su = (((H + S - 1u) >> lg) * nstrip + (uint32_t)nw - 1u) / (uint32_t)nw;
+    su = su < 2u ? 2u : (su > kSweepSteps ? kSweepSteps : su);
+    const uint32_t unit_rows = su * S;
     const uint32_t units = nstrip * ((H + unit_rows - 1u) / unit_rows);
     const int32_t xt0 = rd.x0 + (int32_t)ca, xt1 = rd.x0 + (int32_t)cb;   // owned columns [xt0, xt1)
     const uint32_t nx = (uint32_t)c.nx;
