@@ -1,5 +1,7 @@
-"""C-ABI checks that need no GPU: the library loads and exports every symbol
-include/nyx.h declares; static tables agree with the oracle; device-free calls."""
+"""Checks that need no GPU: the library loads and exports every symbol
+include/nyx.h declares; static tables agree with the oracle; device-free
+calls; host copies of the kernels' index rules (tiling, work tickets, the
+staged ring) against brute force; the benchmark's one-GPU contract."""
 from __future__ import annotations
 
 import os
@@ -106,3 +108,115 @@ def test_split_rule_covers_rows_and_columns():
             ra, rb_, ca, cb_ = bounds(rows, width, rb * cb, cb, t)
             cover[ra:rb_, ca:cb_] += 1
         assert np.all(cover == 1), (rows, width, n, tile)
+
+
+def test_ticket_scheme_hands_out_every_entry_once():
+    # host copy of the work-queue rule: classes largest first, up to 8 entries
+    # (about 8192 voxels) per ticket of a class, tickets t = k * lanes + lane
+    # drawn from `lanes` counters by the work-groups of each lane
+    def chunk(cl):
+        return max(1, min(8, 8192 >> cl))
+
+    rng = np.random.default_rng(5)
+    for trial in range(40):
+        counts = [int(c) for c in rng.integers(0, 30, 32) * (rng.random(32) < 0.4)]
+        first, acc = {}, 0
+        for cl in range(31, -1, -1):
+            first[cl] = acc
+            acc += (counts[cl] + chunk(cl) - 1) // chunk(cl)
+        total = acc
+        grid = int(rng.choice([1, 5, 32, 100, 1280]))
+        lanes = min(32, grid)
+        seen = []
+        for lane in range(lanes):
+            k = 0
+            while True:
+                t = k * lanes + lane
+                k += 1
+                if t >= total:
+                    break
+                cl = 31
+                while cl > 0 and t >= first[cl] + (counts[cl] + chunk(cl) - 1) // chunk(cl):
+                    cl -= 1
+                e0 = (t - first[cl]) * chunk(cl)
+                seen += [(cl, e) for e in range(e0, min(e0 + chunk(cl), counts[cl]))]
+        assert sorted(seen) == sorted((cl, e) for cl in range(32) for e in range(counts[cl])), trial
+
+
+def test_staged_ring_indexing_counts_every_pair_once():
+    # host copy of the staged accumulation's ring walk (rows staged once per
+    # chunk into ring_rows x W bytes, neighbours read at slot + dz*H + dy,
+    # offsets flipped forward) against brute force, over tile partitions
+    def fwd(o):
+        dz, dy, dx = o
+        return (-dz, -dy, -dx) if dz < 0 or (dz == 0 and (dy < 0 or (dy == 0 and dx < 0))) else o
+
+    def staged(lev, offs, ra, rb, ring_bytes, ts):
+        D, H, W = lev.shape
+        rows, ring_rows = D * H, ring_bytes // W
+        reach = max([fz * H + fy for fz, fy, fx in map(fwd, offs) if abs(fy) < H and abs(fx) < W] + [0])
+        if ring_rows < reach + 4:
+            return None
+        C, ring, cnt, staged_to, r0 = ring_rows - reach, np.full(ring_rows * W, -1), {}, ra, ra
+        while r0 < rb:
+            r1 = min(r0 + C, rb)
+            for f in range(0, (r1 + reach - staged_to) * W):
+                r, x = staged_to + f // W, f % W
+                ring[((r - ra) % ring_rows) * W + x] = lev.reshape(rows, W)[r, x] if r < rows else 0
+            staged_to = r1 + reach
+            for f in range((r1 - r0) * W):
+                r, x = r0 + f // W, f % W
+                slot, y = (r - ra) % ring_rows, r % H
+                lv = ring[slot * W + x]
+                assert lv >= 0
+                for d, o in enumerate(offs):
+                    dz, dy, dx = fwd(o)
+                    if lv and 0 <= y + dy < H and 0 <= x + dx < W:
+                        s2 = slot + dz * H + dy
+                        s2 -= ring_rows if s2 >= ring_rows else 0
+                        lw = ring[s2 * W + x + dx]
+                        assert lw >= 0
+                        if lw:
+                            k = (d, min(lv, lw), max(lv, lw))
+                            cnt[k] = cnt.get(k, 0) + 1
+            r0 += C
+        return cnt
+
+    rng = np.random.default_rng(12)
+    off3 = [(0, 0, 1), (0, 1, 0), (1, 0, 0), (0, 1, 1), (0, 1, -1), (1, 0, 1), (1, 0, -1), (1, 1, 0), (1, -1, 0),
+            (1, 1, 1), (1, 1, -1), (1, -1, 1), (1, -1, -1)]
+    sets = [off3, [(-a, -b, -c) for a, b, c in off3[:7]], [(0, 0, 2), (0, -2, 2), (0, -2, 0), (0, -2, -2)]]
+    checked = 0
+    for trial in range(24):
+        D, H, W = int(rng.integers(1, 5)), int(rng.integers(1, 8)), int(rng.integers(1, 10))
+        offs = sets[trial % 3]
+        lev = rng.integers(1, 5, (D, H, W)) * (rng.random((D, H, W)) < 0.7)
+        want = {}
+        for z, y, x in zip(*np.nonzero(lev)):
+            for d, (dz, dy, dx) in enumerate(offs):
+                zz, yy, xx = z + dz, y + dy, x + dx
+                if 0 <= zz < D and 0 <= yy < H and 0 <= xx < W and lev[zz, yy, xx]:
+                    a, b = lev[z, y, x], lev[zz, yy, xx]
+                    want[(d, min(a, b), max(a, b))] = want.get((d, min(a, b), max(a, b)), 0) + 1
+        cuts = sorted({0, D * H, *map(int, rng.integers(0, D * H + 1, 2))})
+        for ring_bytes in (W * (H + 5), W * (2 * H + 3), 300):
+            got, ok = {}, True
+            for ra, rb in zip(cuts[:-1], cuts[1:]):
+                part = staged(lev, offs, ra, rb, ring_bytes, 7) if ra < rb else {}
+                if part is None:
+                    ok = False
+                    break
+                for k, v in part.items():
+                    got[k] = got.get(k, 0) + v
+            if ok:
+                assert got == want, (D, H, W, cuts, ring_bytes)
+                checked += 1
+    assert checked >= 20
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr, (r.returncode, r.stderr)
