@@ -480,3 +480,30 @@ def _run_extract_merged(nyx, ctx, dev, I, L, ng):
     w = SimpleNamespace(intensity=I[None], labels=L[None], n_images=1)
     return nyx.nyx_extract_batch(ctx, device_images(w, dev), ng, nyx.nyx_offsets_default(2, 1), nyx.NYX_FP64,
                                  aggregate=nyx.NYX_AGG_MERGED)
+
+
+@pytest.mark.parametrize("offs,shape", [([(2 * a, 2 * b, 2 * c) for a, b, c in _OFF3], (9, 17, 15)),
+                                        ([(0, 0, 2), (0, -2, 2), (0, -2, 0), (0, -2, -2), (0, 0, 1)], (1, 30, 31))])
+def test_merged_other_offsets(env, oracle_mod, offs, shape):
+    # merged matrices through the staged accumulation (3D distance 2; a 2D
+    # set mixing distances 1 and 2)
+    import torch
+    from types import SimpleNamespace
+    nyx, ctx, dev = env
+    rng = np.random.default_rng(len(offs) + 7 * shape[0])
+    I = rng.integers(0, 4000, shape).astype(np.uint16)
+    L = (rng.integers(1, 5, shape) * (rng.random(shape) < 0.9)).astype(np.uint32)
+    say(f"case merged offsets {offs}")
+    w = SimpleNamespace(intensity=I[None], labels=L[None], n_images=1)
+    rois, table = nyx.nyx_extract_batch(ctx, device_images(w, dev), 16, offs, nyx.NYX_FP64,
+                                        aggregate=nyx.NYX_AGG_MERGED)
+    torch.cuda.synchronize()
+    off = np.array(offs, np.int32)
+    st = oracle_mod.roi_stats(I, L)
+    got = table.cpu().numpy()
+    assert got.shape == (st["label"].size, 1, 30)
+    for r in range(st["label"].size):
+        P = oracle_mod.glcm_roi(I, L, st["label"][r], st["vmin"][r], st["vmax"][r], st["bbox"][r], 16, off)
+        want = oracle_mod.features_roi_merged(P)
+        e = feature_errors(got[r], want, scales(P.sum(axis=0, dtype=np.uint64)[None])[:1])
+        assert np.max(e) <= TOL_FP64, (r, NAMES[int(np.argmax(e[0]))], float(np.max(e)))
