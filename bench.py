@@ -176,6 +176,63 @@ def same_label_pairs(lab, off) -> int:
     return int(((a == b) & (a != 0)).sum().item())
 
 
+# Nested offset sets for the cost grid: each adds offsets to the previous one
+# (2D: 0, then 90, then 45 and 135 degrees at distance 1, then the four at 2).
+GRID_OFFSETS = ([(0, 0, 1)], [(0, 0, 1), (0, -1, 0)], [(0, 0, 1), (0, -1, 0), (0, -1, 1), (0, -1, -1)],
+                [(0, 0, 1), (0, -1, 0), (0, -1, 1), (0, -1, -1), (0, 0, 2), (0, -2, 0), (0, -2, 2), (0, -2, -2)])
+GRID_BINS = (8, 16, 32, 64, 128, 256)
+
+
+def cost_grid(args) -> int:
+    """Soft-feature cost grid (Methods, "Feature Control and Tunability",
+    Eqs. 2-5): the whole step's time t(p) over an ordered grid of the two GLCM
+    hyperparameters, the bin count and a nested set of offsets, on one
+    synthetic workload; a soft feature's time never decreases along either
+    axis.  Default plans (no autotuning), so that only p changes."""
+    import torch
+    import synth
+    from paper_2603_12016_amd import nyx
+    w = synth.make(args.workload)
+    dev = torch.device("cuda:0")
+    imgs = [(torch.from_numpy(w.intensity[k].view(np.int16)).to(dev),
+             torch.from_numpy(w.labels[k].view(np.int32)).to(dev)) for k in range(w.n_images)]
+    if w.dims != 2:
+        print("the cost grid uses 2D workloads", file=sys.stderr)
+        return 2
+    ctx = nyx.nyx_create(0)
+    grid = []
+    for ng in GRID_BINS:
+        row = []
+        for offs in GRID_OFFSETS:
+            plan = nyx.nyx_plan_create(ctx, imgs, ng, offs, nyx.NYX_FP32)
+            table = nyx.new_table(plan, len(offs), nyx.NYX_FP32)
+            for _ in range(args.warmup):
+                nyx.nyx_plan_execute(plan, table)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                nyx.nyx_plan_execute(plan, table)
+            torch.cuda.synchronize()
+            nyx.nyx_plan_check(plan)
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            row.append(ms)
+            log(f"n_bins={ng} offsets={len(offs)}: {ms:.3f} ms ({nyx.nyx_plan_describe(plan).split()[0]})")
+            del plan, table
+        grid.append(row)
+    tol = 0.03   # timing noise allowed before a decrease counts
+    down_bins = [(GRID_BINS[i], len(GRID_OFFSETS[j])) for j in range(len(GRID_OFFSETS))
+                 for i in range(1, len(GRID_BINS)) if grid[i][j] < grid[i - 1][j] * (1 - tol)]
+    down_offs = [(GRID_BINS[i], len(GRID_OFFSETS[j])) for i in range(len(GRID_BINS))
+                 for j in range(1, len(GRID_OFFSETS)) if grid[i][j] < grid[i][j - 1] * (1 - tol)]
+    print(json.dumps({"metric": "GLCM step time over (n_bins, nested offset sets)", "unit": "ms per step",
+                      "workload": args.workload, "roi_voxels": int(np.count_nonzero(w.labels)),
+                      "n_bins": list(GRID_BINS), "offsets": [len(o) for o in GRID_OFFSETS],
+                      "offset_sets": GRID_OFFSETS, "ms": grid,
+                      "decreases_along_bins": down_bins, "decreases_along_offsets": down_offs,
+                      "noise_tolerance": tol}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +251,9 @@ def main() -> int:
     ap.add_argument("--summarize-trace", metavar="STATS_CSV",
                     help="write profiles/<kernel>_<workload>.md from a rocprofv3 kernel_stats.csv and exit")
     ap.add_argument("--pmc-command", default="", help="the command the profile CSVs came from (recorded)")
+    ap.add_argument("--cost-grid", action="store_true",
+                    help="time the step over a grid of bin counts x nested offset sets and check that the "
+                         "time is monotone along both axes (prints one JSON line)")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.workload, args.pmc_command)
@@ -207,6 +267,8 @@ def main() -> int:
         return 2
 
     import torch
+    if args.cost_grid:
+        return cost_grid(args)
 
     import synth
     from paper_2603_12016_amd import nyx
