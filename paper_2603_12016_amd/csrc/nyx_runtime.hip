@@ -405,6 +405,11 @@ uint64_t max_item_vox(const std::vector<RoiDesc> &rois, uint32_t split_vox, uint
 // Feasible LDS configurations for this workload, one per accumulation mode,
 // each with as many directions per pass as fit.  Dense triangles first; the
 // hash table only when no dense triangle fits.
+// Work-groups of the persistent kernel per CU for a given LDS footprint.
+uint32_t groups_per_cu(uint64_t lds_bytes) {
+    return (uint32_t)std::min<uint64_t>(kMaxGroupsPerCu, kLdsBudget / std::max<uint64_t>(lds_bytes, 1u));
+}
+
 // merged: every offset counts into one LDS triangle in one pass, so only the
 // dense scan modes qualify, and packed 16-bit counters need K x (voxels of an
 // item) < 65536 (offered only when that bound leaves the load-balance tile
@@ -454,11 +459,11 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
                 // many offsets: fewer directions per pass cost another pass
                 // over the voxels but leave LDS for more work-groups per CU
                 // (timed by the autotuner, never the default)
-                if (mode == 3 && K > 4)
-                    for (uint32_t parts : {2u, 3u}) {
+                if (mode == 3 && (K > 4 || groups_per_cu(bytes) < 3u))
+                    for (uint32_t parts : {2u, 3u, 4u}) {
                         Config f = c;
                         f.kp = ((uint32_t)K + parts - 1u) / parts;
-                        if (f.kp < kp) later.push_back(f);
+                        if (f.kp < kp && (later.empty() || later.back().kp != f.kp)) later.push_back(f);
                     }
                 break;
             }
@@ -496,16 +501,23 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
 // Default choice without timing: an ordered scan of the triangle costs
 // O(Ng^2) per direction and item, a returning-atomic list costs O(pairs);
 // scan while the triangle is small next to the average item.
-Config default_config(const std::vector<Config> &cands, const Work &w, uint32_t ng) {
+Config default_config(const std::vector<Config> &cands, const Work &w, uint32_t ng, int K) {
     uint64_t total_vox = 0;
     for (const RoiDesc &r : w.h_rois) total_vox += r.n;
     const uint64_t avg = w.h_rois.empty() ? 1u : std::max<uint64_t>(1u, total_vox / w.h_rois.size());
     const uint64_t tri = (uint64_t)ng * (ng + 1u) / 2u;
     const bool prefer_scan = tri <= 8u * avg;
+    // among the candidates of the preferred kind: fewest passes over the
+    // voxels per work-group slot (passes / work-groups per CU); ties keep the
+    // earlier candidate (more directions per pass)
     const Config *best = nullptr;
+    double best_score = 0.0;
     for (const Config &c : cands) {
-        bool scan = c.mode == 2 || c.mode == 3;
-        if (prefer_scan == scan || c.mode == 1) { best = &c; break; }
+        const bool scan = c.mode == 2 || c.mode == 3;
+        if (!(prefer_scan == scan || c.mode == 1)) continue;
+        const uint32_t passes = ((uint32_t)K + c.kp - 1u) / c.kp;
+        const double score = (double)passes / (double)std::max(1u, groups_per_cu(make_layout(c, ng, K, false).bytes));
+        if (!best || score < best_score) { best = &c; best_score = score; }
     }
     return best ? *best : cands.front();
 }
@@ -514,7 +526,7 @@ nyx_status choose_config(nyx_ctx *ctx, const Work &w, uint32_t ng, int K, int fo
                          Config &cfg) {
     std::vector<Config> c = candidate_configs(ctx, w, ng, K, force_split, block);
     if (c.empty()) return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%u with %d offsets", ng, K);
-    cfg = default_config(c, w, ng);
+    cfg = default_config(c, w, ng, K);
     return NYX_OK;
 }
 
@@ -987,7 +999,7 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
                 cands.push_back(c);
             }
     }
-    Config cfg = default_config(cands, p->w, (uint32_t)p->ng);
+    Config cfg = default_config(cands, p->w, (uint32_t)p->ng, p->K);
     if (opts->accum_mode >= 0) {
         bool found = false;
         for (const Config &c : cands)
