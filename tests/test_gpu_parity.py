@@ -388,10 +388,10 @@ def test_full_size_sampled(env, workloads, oracle_mod, name):
     import torch
     nyx, ctx, dev = env
     w = workloads(name)
-    say(f"case {name} full size: plan + execute")
+    say(f"case {name} full size: autotuned plan (as the benchmark) + execute")
     imgs = device_images(w, dev)
     offs = _offsets(nyx, w)
-    plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32)
+    plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32, autotune=True)
     say("  plan:", nyx.nyx_plan_describe(plan))
     table = nyx.new_table(plan, len(offs))
     rois = nyx.RoiTable(plan.n_rois, dev)
