@@ -33,7 +33,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-KERNEL_SYMBOLS = {"k_batch": "nyx::k_batch<", "k_scan": "nyx::k_scan(", "k_wave": "nyx::k_wave<"}
+KERNEL_SYMBOLS = {"k_batch": "nyx::k_batch<", "k_scan": "nyx::k_scan(", "k_band": "nyx::k_band<"}
 COPY_SYMBOL = "k_copy("
 
 
@@ -166,6 +166,54 @@ def cpu_baseline(w, offs, seconds: float) -> dict:
             "cpu_model": cpu_model()}
 
 
+def oracle_parity(w, offs, table: np.ndarray, n_images: int, prec: int) -> dict:
+    """Largest error of the benched feature table against the FP64 oracle over
+    every ROI of the first n_images images, under the precision contract's
+    measure: |gpu - oracle| / max(|oracle|, M_f), M_f = 1 for CORR, the
+    information measures and the entropies (bits), the cluster-shade magnitude
+    sum |i + j - mu_x - mu_y|^3 p for cluster shade, 0 otherwise; NaN must
+    match NaN."""
+    import oracle
+    names = oracle.feature_names()
+    unit = [n in ("CORR", "INFOMEAS1", "INFOMEAS2", "JE", "ENTROPY", "DIFENTRO", "SUMENT") for n in names]
+    shade = names.index("CLUSHADE")
+    off = np.array(offs, np.int32)
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    row, worst, where, rois = 0, 0.0, None, 0
+    n_images = min(n_images, w.n_images)
+    for k in range(n_images):
+        _, want, mag = oracle.extract(w.intensity[k], w.labels[k], w.n_bins, off, n_threads=threads,
+                                      want_shade_magnitude=True)
+        got = table[row:row + len(want)].astype(np.float64)
+        row += len(want)
+        rois += len(want)
+        M = np.zeros_like(want)
+        M[:, :, np.array(unit)] = 1.0
+        mv = np.where(np.isnan(mag), 0.0, mag)
+        M[:, :-1, shade] = mv
+        cnt = np.maximum((~np.isnan(mag)).sum(axis=1), 1)
+        M[:, -1, shade] = mv.sum(axis=1) / cnt
+        with np.errstate(divide="ignore", invalid="ignore"):
+            err = np.abs(got - want) / np.maximum(np.abs(want), M)
+        err = np.where(np.isnan(got) & np.isnan(want), 0.0, err)
+        err = np.where(np.isnan(got) != np.isnan(want), np.inf, err)
+        err = np.where(got == want, 0.0, err)
+        if err.size and float(err.max()) > worst:
+            i = np.unravel_index(int(np.argmax(err)), err.shape)
+            worst, where = float(err[i]), f"image {k} row {int(i[0])} block {int(i[1])} {names[i[2]]}"
+    tol = 1e-12 if prec == 1 else 1e-5
+    return {"images": n_images, "rois": rois, "max_error": worst, "at": where, "tolerance": tol,
+            "pass": bool(worst <= tol)}
+
+
+def split_band_voxels(plan, w) -> int:
+    """Voxels of the ROIs the plan sends through the band kernel (0 unless the
+    description reports any)."""
+    from paper_2603_12016_amd import nyx
+    fields = dict(kv.split("=", 1) for kv in nyx.nyx_plan_describe(plan).split() if "=" in kv)
+    return int(fields.get("band_voxels", 0))
+
+
 def same_label_pairs(lab, off) -> int:
     """Voxel pairs (v, v + off) inside one ROI (equal nonzero labels); lab is
     a (nz, ny, nx) device tensor."""
@@ -239,7 +287,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3_batch")
-    ap.add_argument("--per-roi-steps", type=int, default=1)
+    ap.add_argument("--per-roi-steps", type=int, default=3)
+    ap.add_argument("--per-roi-warmup", type=int, default=3)
+    ap.add_argument("--parity-images", type=int, default=2,
+                    help="images of the benched table compared with the FP64 oracle (untimed)")
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -336,10 +387,18 @@ def main() -> int:
             prof[p] += r[p] / args.profile_steps
     log("phases (ms): " + ", ".join(f"{p}={v:.4f}" for p, v in prof.items()))
 
+    # the benched table against the oracle on whole images (untimed)
+    parity = None
+    if args.parity_images > 0 and agg == nyx.NYX_AGG_PER_OFFSET:
+        parity = oracle_parity(w, offs, table.cpu().numpy(), args.parity_images, prec)
+        log(f"parity vs oracle: {parity}")
+
     # one launch per ROI
     dt_roi, same = None, None
     if args.per_roi_steps > 0:
         t2 = nyx.new_table(plan, K, prec, aggregate=agg)
+        for _ in range(args.per_roi_warmup):
+            nyx.nyx_plan_execute_per_roi(plan, t2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.per_roi_steps):
@@ -348,21 +407,21 @@ def main() -> int:
         dt_roi = (time.perf_counter() - t0) / args.per_roi_steps
         nyx.nyx_plan_check(plan)
         same = bool(torch.allclose(table, t2, rtol=1e-5, atol=1e-6, equal_nan=True))
-        log(f"per-ROI launches: {dt_roi * 1e3:.1f} ms/step, tables agree: {same}")
+        log(f"per-ROI launches: {dt_roi * 1e3:.1f} ms/step ({args.per_roi_warmup} warm-up, "
+            f"{args.per_roi_steps} timed), tables agree: {same}")
 
     # algorithmic bytes: the scan reads 4 B label + 2 B intensity per image
     # voxel; each accumulate/feature kernel reads 4 B label + 2 B intensity per
     # voxel of the ROIs it owns and writes their feature rows.
-    desc = nyx.nyx_plan_describe(plan)
-    fields = dict(kv.split("=", 1) for kv in desc.split() if "=" in kv)
-    wave_rois, wave_vox = int(fields.get("wave_rois", 0)), int(fields.get("wave_roi_voxels", 0))
     row_bytes = nyx.table_blocks(K, agg) * 30 * (8 if prec == nyx.NYX_FP64 else 4)
     out_bytes = n_rois * row_bytes
+    # the band kernel reads the voxels of the split ROIs whose triangle exceeds LDS
+    band_vox = split_band_voxels(plan, w)
     alg = {"scan": img_vox * 6.0,
-           "batch": (roi_vox - wave_vox) * 6.0 + (n_rois - wave_rois) * row_bytes,
-           "wave": wave_vox * 6.0 + wave_rois * row_bytes}
-    kernel_names = {"scan": "k_scan", "batch": "k_batch", "wave": "k_wave"}
-    dom = max(("scan", "batch", "wave"), key=lambda p: prof[p])
+           "batch": (roi_vox - band_vox) * 6.0 + n_rois * row_bytes,
+           "band": band_vox * 6.0}
+    kernel_names = {"scan": "k_scan", "batch": "k_batch", "band": "k_band"}
+    dom = max(("scan", "batch", "band"), key=lambda p: prof[p])
     achieved = alg[dom] / (prof[dom] * 1e-3) / 1e9
     step_alg = img_vox * 4.0 + roi_vox * 2.0 + out_bytes
 
@@ -403,7 +462,7 @@ def main() -> int:
         "inputs_h2d": {"bytes": in_bytes, "seconds": h2d_s, "GBps": in_bytes / h2d_s / 1e9,
                        "value_incl_h2d": roi_vox / (h2d_s + dt / args.steps)},
         "lds_atomics": {"pairs_per_step": pairs,
-                        "achieved_per_s": pairs / (sum(prof[p] for p in ("batch", "wave", "split")) * 1e-3)},
+                        "achieved_per_s": pairs / (sum(prof[p] for p in ("batch", "band", "split")) * 1e-3)},
         "machine": machine,
         "roofline": {"kernel": kernel_names[dom], "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -411,6 +470,7 @@ def main() -> int:
                      else None,
                      "alg_bytes": alg[dom], "ms": prof[dom]},
         "plan_seconds": plan_s,
+        "parity_vs_oracle": parity,
     }
     if not args.no_cpu_baseline and agg == nyx.NYX_AGG_MERGED:
         log("cpu baseline skipped: the oracle's timed extraction is the per-offset one")

@@ -134,11 +134,13 @@ typedef struct nyx_extract_opts {
                                     1 LDS hash table, 2 LDS triangle + ordered scan,
                                     3 LDS triangle of 16-bit counters + ordered scan
                                     (NYX_ERR_UNSUPPORTED when it does not fit) */
-    int32_t wave_max_vox;        /* -1 = automatic (none, unless autotune times a share that
-                                    pays); 0 = every ROI on the work-group kernel;
-                                    n > 0 = unsplit ROIs of at most n voxels (n <= 65535) are
-                                    processed one wavefront each when there are at most 4
-                                    offsets and their LDS fits (else ignored) */
+    int32_t copies;              /* privatised copies of each LDS triangle (dense scan modes):
+                                    0 = automatic (1, or the fastest of 1, 2 and 4 when autotune
+                                    is set); 1, 2 or 4 = forced.  Lane l of a wavefront counts
+                                    into copy l mod copies, so neighbouring lanes that hit the
+                                    same cell add to different words; the copies are summed when
+                                    the triangle is read.  NYX_ERR_UNSUPPORTED when the copies do
+                                    not fit LDS */
     int64_t workspace_cap_bytes; /* 0 = no cap; exceeding it gives NYX_ERR_OOM */
     int32_t aggregate;           /* NYX_AGG_PER_OFFSET or NYX_AGG_MERGED (table layout above) */
 } nyx_extract_opts;
@@ -175,10 +177,16 @@ nyx_status nyx_glcm_accumulate(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t
                                const nyx_offset *offsets_host, int32_t n_offsets, int32_t symmetric,
                                int32_t n_bins, nyx_glcm *out, nyx_stream stream);
 
-/* Feature table from a COO list as written by nyx_glcm_accumulate.
- * table has room for table_capacity_rows rows (glcm->n_rois needed). */
-nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, nyx_precision prec, void *table,
-                             int64_t table_capacity_rows, nyx_stream stream);
+/* Feature table (normalisation, marginals and the 30 features per direction
+ * and their mean) from a COO list as written by nyx_glcm_accumulate: row r
+ * of the table belongs to ROI r of the list.  `rois` (nullable) is the ROI
+ * table the list was accumulated for; when given, its *n_rois_host must equal
+ * glcm->n_rois (NYX_ERR_INVALID otherwise), so a table is never paired with
+ * another image batch's counts.  table has room for table_capacity_rows rows
+ * (glcm->n_rois needed).  Synchronises to report entries outside their
+ * matrix (NYX_ERR_INVALID). */
+nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, const nyx_roi_table *rois, nyx_precision prec,
+                             void *table, int64_t table_capacity_rows, nyx_stream stream);
 
 /* Whole path in one call: plan, execute once, destroy the plan. */
 nyx_status nyx_extract_batch(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n_images,
@@ -210,7 +218,7 @@ typedef enum nyx_phase {
     NYX_PHASE_COMPACT = 2,   /* ROI table and size-sorted work queue */
     NYX_PHASE_ZERO = 3,      /* clear the global matrices of split ROIs */
     NYX_PHASE_BATCH = 4,     /* binning, co-occurrence counts, reduced sums (work-group per item) */
-    NYX_PHASE_WAVE = 5,      /* the same for small ROIs, one wavefront per ROI */
+    NYX_PHASE_BAND = 5,      /* split ROIs whose triangle exceeds LDS: banded counts, fold */
     NYX_PHASE_SPLIT = 6,     /* reduced sums of split ROIs from their merged global matrices */
     NYX_PHASE_FEATURES = 7,  /* the 30 features per direction and their mean, every ROI */
     NYX_PHASE_COUNT = 8

@@ -29,7 +29,7 @@ NFEAT = 30
 
 def build(force: bool = True) -> str:
     """Compile oracle.c with gcc into liboracle.so next to it."""
-    if force or not os.path.exists(_LIB_PATH):
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
                "-o", tmp, _SRC, "-lm"]
@@ -67,7 +67,9 @@ def _load():
     lib.oracle_features_roi.argtypes = [P, i32, i32, P]
     lib.oracle_extract.restype = ctypes.c_int
     lib.oracle_extract.argtypes = [P, P, i64, i64, i64, i32, P, i32, i64,
-                                   P, P, P, P, P, i32]
+                                   P, P, P, P, P, P, i32]
+    lib.oracle_shade_magnitude.restype = ctypes.c_double
+    lib.oracle_shade_magnitude.argtypes = [P, i32]
     lib.oracle_default_offsets.restype = i32
     lib.oracle_default_offsets.argtypes = [i32, i32, P]
     _lib = lib
@@ -193,9 +195,21 @@ def features_roi_merged(P: np.ndarray) -> np.ndarray:
     return features(M.sum(axis=0, dtype=np.uint64))[None, :]
 
 
+def shade_magnitude(P: np.ndarray) -> float:
+    """sum |i + j - mux - muy|^3 p of one (Ng, Ng) count matrix: the
+    magnitude the signed cluster-shade sum is formed from (the parity tests'
+    error scale for that feature); NaN for an empty matrix."""
+    M = np.ascontiguousarray(P, np.uint64)
+    if M.ndim != 2 or M.shape[0] != M.shape[1]:
+        raise ValueError("expected a square matrix")
+    return float(_load().oracle_shade_magnitude(_ptr(M), M.shape[0]))
+
+
 def extract(intensity, labels, n_bins: int, offsets: np.ndarray, stats: dict | None = None,
-            rois=None, n_threads: int = 1) -> tuple[dict, np.ndarray]:
-    """Feature table of one image: (stats, table (n, K + 1, 30) float64).
+            rois=None, n_threads: int = 1, want_shade_magnitude: bool = False):
+    """Feature table of one image: (stats, table (n, K + 1, 30) float64),
+    plus the (n, K) cluster-shade magnitudes (shade_magnitude of each
+    direction's matrix) when want_shade_magnitude is set.
 
     ``rois`` optionally selects ROI indices (into the ascending-label order);
     the table then has one row per selected ROI."""
@@ -212,8 +226,10 @@ def extract(intensity, labels, n_bins: int, offsets: np.ndarray, stats: dict | N
     off = np.ascontiguousarray(offsets, np.int32).reshape(-1, 3)
     K = off.shape[0]
     table = np.zeros((idx.size, K + 1, NFEAT), np.float64)
+    mag = np.zeros((idx.size, K), np.float64) if want_shade_magnitude else None
     rc = lib.oracle_extract(_ptr(I), _ptr(L), nz, ny, nx, n_bins, _ptr(off), K, idx.size,
-                            _ptr(lab), _ptr(lo), _ptr(hi), _ptr(bb), _ptr(table), n_threads)
+                            _ptr(lab), _ptr(lo), _ptr(hi), _ptr(bb), _ptr(table),
+                            _ptr(mag) if mag is not None else None, n_threads)
     if rc != 0:
         raise RuntimeError("oracle_extract failed")
-    return st, table
+    return (st, table, mag) if want_shade_magnitude else (st, table)

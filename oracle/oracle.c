@@ -425,10 +425,41 @@ void oracle_features_roi(const uint64_t *P, int32_t n_bins, int32_t n_offsets, d
     for (int q = 0; q < NFEAT; ++q) mean[q] = used ? mean[q] / (double)used : NAN;
 }
 
+/* ------------------------------------------------------- error scale */
+/* Magnitude the cluster-shade sum is formed from: sum |i + j - mux - muy|^3 p
+ * over the normalised matrix (the same centring as CLUSHADE).  Not a
+ * feature: the error measure of the parity tests divides a cluster-shade
+ * difference by it, because a signed sum of cubes can cancel to near zero
+ * while its rounding error scales with the magnitudes summed.  NaN for an
+ * empty matrix. */
+double oracle_shade_magnitude(const uint64_t *P, int32_t n_bins) {
+    const int64_t ng = n_bins;
+    uint64_t T = 0;
+    for (int64_t c = 0; c < ng * ng; ++c) T += P[c];
+    if (T == 0) return NAN;
+    const double Td = (double)T;
+    nsum mx = {0, 0}, my = {0, 0};
+    for (int64_t i = 0; i < ng; ++i)
+        for (int64_t j = 0; j < ng; ++j) {
+            double p = (double)P[i * ng + j] / Td;
+            nadd(&mx, (double)(i + 1) * p);
+            nadd(&my, (double)(j + 1) * p);
+        }
+    const double mux = nval(&mx), muy = nval(&my);
+    nsum a = {0, 0};
+    for (int64_t i = 0; i < ng; ++i)
+        for (int64_t j = 0; j < ng; ++j) {
+            double d = fabs((double)(i + 1) + (double)(j + 1) - mux - muy);
+            nadd(&a, d * d * d * (double)P[i * ng + j] / Td);
+        }
+    return nval(&a);
+}
+
 /* ------------------------------------------------------------- pipeline */
 /* Feature table for a list of ROIs of one image (ROI statistics as produced
  * by oracle_roi_stats): table[r][blk][f] with blk = 0..n_offsets-1 the
- * directions and blk = n_offsets the direction mean.  n_threads > 1 runs
+ * directions and blk = n_offsets the direction mean; shade_mag (nullable)
+ * receives oracle_shade_magnitude of every (ROI, direction).  n_threads > 1 runs
  * independent ROIs on OpenMP threads (timing only; results do not depend on
  * it).  Returns 0, or -1 on allocation failure. */
 int oracle_extract(const uint16_t *intensity, const uint32_t *labels,
@@ -436,7 +467,7 @@ int oracle_extract(const uint16_t *intensity, const uint32_t *labels,
                    const int32_t *offsets, int32_t n_offsets, int64_t n_rois,
                    const uint32_t *roi_label, const uint16_t *roi_min,
                    const uint16_t *roi_max, const int32_t *roi_bbox,
-                   double *table, int32_t n_threads) {
+                   double *table, double *shade_mag, int32_t n_threads) {
     const size_t cells = (size_t)n_bins * (size_t)n_bins * (size_t)n_offsets;
     int failed = 0;
 #pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1) reduction(| : failed)
@@ -449,6 +480,10 @@ int oracle_extract(const uint16_t *intensity, const uint32_t *labels,
             oracle_glcm_roi(intensity, labels, nz, ny, nx, roi_label[r], roi_min[r], roi_max[r],
                             roi_bbox + 6 * r, n_bins, offsets, n_offsets, P);
             oracle_features_roi(P, n_bins, n_offsets, table + (size_t)r * (size_t)(n_offsets + 1) * NFEAT);
+            if (shade_mag)
+                for (int32_t k = 0; k < n_offsets; ++k)
+                    shade_mag[(size_t)r * (size_t)n_offsets + (size_t)k] =
+                        oracle_shade_magnitude(P + (size_t)k * (size_t)n_bins * (size_t)n_bins, n_bins);
         }
         free(P);
     }

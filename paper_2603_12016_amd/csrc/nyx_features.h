@@ -165,14 +165,22 @@ __device__ __forceinline__ void tri_decode(uint32_t i, uint32_t &lo, uint32_t &h
 // next chunk might not fit, and at the end: lanes stay busy however sparse
 // the triangle is, and the order of every floating sum is fixed.  U must be
 // 16-byte aligned and padded with zero words to a multiple of 4 words.
+// The triangle may be held in `ncp` privatised copies `stride` words apart;
+// every read sums them (packed 16-bit halves add without carry: a cell's
+// total over the copies stays below 2^16, as for a single copy).
 template <bool PACKED>
 struct SrcTriScan {
     uint32_t *U;
     uint32_t tri;
     uint32_t *buf;
+    uint32_t ncp = 1u;
+    uint32_t stride = 0u;
     static constexpr uint32_t kPerRead = PACKED ? 8u : 4u;   // cells per 16-byte read
     __device__ __forceinline__ uint32_t count(uint32_t i) const {
-        return PACKED ? (uint32_t)reinterpret_cast<const uint16_t *>(U)[i] : U[i];
+        uint32_t c = 0;
+        for (uint32_t k = 0; k < ncp; ++k)
+            c += PACKED ? (uint32_t)reinterpret_cast<const uint16_t *>(U + k * stride)[i] : U[k * stride + i];
+        return c;
     }
     template <class Grp, class Fn>
     __device__ __forceinline__ void flush(const Grp &g, uint32_t n, Fn &&fn) const {
@@ -194,7 +202,13 @@ struct SrcTriScan {
         for (uint32_t wbase = 0; wbase < words; wbase += 4u * gs) {
             const uint32_t w0 = wbase + 4u * r;
             uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (w0 < words) v = *reinterpret_cast<const uint4 *>(U + w0);
+            if (w0 < words) {
+                v = *reinterpret_cast<const uint4 *>(U + w0);
+                for (uint32_t k = 1; k < ncp; ++k) {
+                    const uint4 u = *reinterpret_cast<const uint4 *>(U + k * stride + w0);
+                    v.x += u.x; v.y += u.y; v.z += u.z; v.w += u.w;
+                }
+            }
             // nonzero flags of the run's cells (cells past tri are zero
             // padding); packed: 0/1 in each 16-bit half
             uint32_t f[4];
@@ -231,8 +245,9 @@ struct SrcTriScan {
     template <class Grp>
     __device__ __forceinline__ void clear(const Grp &g) const {
         const uint32_t words = PACKED ? (tri + 1u) >> 1 : tri;
-        for (uint32_t w = 4u * (uint32_t)g.rank(); w < words; w += 4u * (uint32_t)g.size())
-            *reinterpret_cast<uint4 *>(U + w) = make_uint4(0u, 0u, 0u, 0u);
+        for (uint32_t k = 0; k < ncp; ++k)
+            for (uint32_t w = 4u * (uint32_t)g.rank(); w < words; w += 4u * (uint32_t)g.size())
+                *reinterpret_cast<uint4 *>(U + k * stride + w) = make_uint4(0u, 0u, 0u, 0u);
     }
 };
 

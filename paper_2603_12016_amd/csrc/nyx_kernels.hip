@@ -6,7 +6,6 @@
 //   k_compact_*        ROI table in (image, label) order + size-sorted work queue
 //   k_bin_image        per-voxel grey levels (explicit binning output)
 //   k_batch            persistent work-stealing accumulation + reduced sums per direction
-//   k_wave             the same for small ROIs, one wavefront per ROI
 //   k_split_features   reduced sums of ROIs whose matrices were merged in global memory
 //   k_features         the 30 features per direction and their mean, one lane per direction
 //   k_coo_*            sorted COO export / import of the co-occurrence counts
@@ -258,8 +257,8 @@ __global__ __launch_bounds__(1024) void k_compact_count(StepArgs a) {
 // class, so the persistent kernel can drain the largest work first.
 __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi_lo, uint32_t roi_hi) {
     __shared__ uint32_t wc[16], wpre[16], s_part[16], s_prefix;
-    __shared__ uint32_t cls_cnt[2 * kClasses], cls_base[2 * kClasses];   // work-group queue, then wave queue
-    if (threadIdx.x < 2 * kClasses) cls_cnt[threadIdx.x] = 0u;
+    __shared__ uint32_t cls_cnt[kClasses], cls_base[kClasses];
+    if (threadIdx.x < kClasses) cls_cnt[threadIdx.x] = 0u;
     uint32_t part = 0;
     for (uint32_t b = threadIdx.x; b < blockIdx.x; b += 1024u) part += a.counters[C_BLOCKS + b];
     part = wave_sum(part);
@@ -283,7 +282,7 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
     bool live = p;
     if (live && row >= a.roi_cap) { atomicOr(&a.counters[C_ERR], (uint32_t)E_ROI_CAP); live = false; }
     RoiDesc rd;
-    bool enq = false, wave_item = false;
+    bool enq = false;
     uint32_t cls = 0u, nt = 1u, local = 0u;
     if (live) {
     const int im = find_image_entry(a.imgs, a.n_images, e);
@@ -316,9 +315,8 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
     a.rois[row] = rd;
     if (take && (rd.gslot != kNone || nt == 1u)) {
         enq = true;
-        wave_item = a.wave_ok && rd.gslot == kNone && nt == 1u && rd.n <= a.wave_max_vox;
         cls = size_class((rd.n + nt - 1u) / nt);
-        local = atomicAdd(&cls_cnt[(wave_item ? kClasses : 0) + cls], nt);
+        local = atomicAdd(&cls_cnt[cls], nt);
     }
     if (a.o_label) a.o_label[row] = label;
     if (a.o_image) a.o_image[row] = (uint32_t)im;
@@ -331,10 +329,8 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
     }
     }  // live
     __syncthreads();
-    if (threadIdx.x < 2 * kClasses && cls_cnt[threadIdx.x]) {
-        const uint32_t slot = threadIdx.x < kClasses ? C_CLASS + threadIdx.x : C_CLASS_W + threadIdx.x - kClasses;
-        cls_base[threadIdx.x] = atomicAdd(&a.counters[slot], cls_cnt[threadIdx.x]);
-    }
+    if (threadIdx.x < kClasses && cls_cnt[threadIdx.x])
+        cls_base[threadIdx.x] = atomicAdd(&a.counters[C_CLASS + threadIdx.x], cls_cnt[threadIdx.x]);
     __syncthreads();
     // Each ROI's tile entries: a thread writes those of its own ROI when they
     // are few; the tiles of ROIs cut into many are written by the whole
@@ -345,12 +341,11 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
     if (threadIdx.x == 0) n_big = 0u;
     __syncthreads();
     if (enq) {
-        uint32_t pos = cls_base[(wave_item ? kClasses : 0) + cls] + local;
-        uint2 *bk = wave_item ? a.buckets_w : a.buckets;
+        uint32_t pos = cls_base[cls] + local;
         if (pos + nt > a.bucket_cap) {
             atomicOr(&a.counters[C_ERR], (uint32_t)E_ITEM_CAP);
         } else {
-            uint2 *dst = bk + (uint64_t)cls * a.bucket_cap + pos;
+            uint2 *dst = a.buckets + (uint64_t)cls * a.bucket_cap + pos;
             uint32_t b = kBigMax;
             if (nt > kOwnTiles) b = atomicAdd(&n_big, 1u);
             if (b < kBigMax) {
@@ -403,33 +398,16 @@ __global__ __launch_bounds__(256) void k_bin_image(StepArgs a, uint16_t *bins_ou
 
 // ------------------------------------------------------------------ batch
 // ------------------------------------------------------------------ work queue
-// The queue is the concatenation of the size-class buckets, largest class
-// first.  A ticket (one atomic increment) hands out up to ticket_chunk(cl)
-// consecutive entries of one class: several small items per ticket, one
-// item per ticket from the classes whose items alone keep a work-group busy,
-// so the last tickets of a launch are short.
-__device__ __forceinline__ uint32_t ticket_chunk(int cl) {
-    const uint32_t c = kTicketVox >> cl;
-    return c < 1u ? 1u : (c > (uint32_t)kTicketChunk ? (uint32_t)kTicketChunk : c);
-}
-
-// misc[64 + cl]: first ticket of class cl; misc[96 + cl]: its entries
-// (clamped to the bucket capacity); misc[63]: number of tickets.  The class
-// counts are loaded by lanes 0..kClasses-1 at once (ticket_load, every thread
-// calls it), then one thread forms the offsets (ticket_prefix) after a
-// barrier.
+// Tickets follow ticket_offsets / ticket_range (nyx_types.h).  misc[64 + cl]:
+// first ticket of class cl; misc[96 + cl]: its entries (clamped to the bucket
+// capacity); misc[63]: number of tickets.  The class counts are loaded by
+// lanes 0..kClasses-1 at once (ticket_load, every thread calls it), then one
+// thread forms the offsets (ticket_prefix) after a barrier.
 __device__ __forceinline__ void ticket_load(uint32_t *misc, const uint32_t *cls_cnt, uint32_t cap, uint32_t tid) {
     if (tid < (uint32_t)kClasses) misc[96 + tid] = min(cls_cnt[tid], cap);
 }
 
-__device__ void ticket_prefix(uint32_t *misc) {
-    uint32_t acc = 0;
-    for (int cl = kClasses - 1; cl >= 0; --cl) {
-        misc[64 + cl] = acc;
-        acc += (misc[96 + cl] + ticket_chunk(cl) - 1u) / ticket_chunk(cl);
-    }
-    misc[63] = acc;
-}
+__device__ void ticket_prefix(uint32_t *misc) { misc[63] = ticket_offsets(misc + 96, misc + 64); }
 
 // Claims ticket `atomicAdd(ctr) * lanes + lane` and writes its entries as
 // (roi, tile) pairs to misc[0..); returns how many (0 once the queue is
@@ -439,11 +417,9 @@ __device__ uint32_t ticket_claim(uint32_t *misc, uint32_t *ctr, uint32_t lane_, 
                                  uint32_t cap) {
     const uint32_t t = atomicAdd(ctr, 1u) * lanes + lane_;
     if (t >= misc[63]) return 0u;
-    int cl = kClasses - 1;
-    const auto end_of = [&](int c) { return misc[64 + c] + (misc[96 + c] + ticket_chunk(c) - 1u) / ticket_chunk(c); };
-    while (cl > 0 && t >= end_of(cl)) --cl;
-    const uint32_t ch = ticket_chunk(cl), e0 = (t - misc[64 + cl]) * ch;
-    const uint32_t e1 = min(e0 + ch, misc[96 + cl]);
+    int cl;
+    uint32_t e0, e1;
+    ticket_range(t, misc + 96, misc + 64, &cl, &e0, &e1);
     uint32_t n = 0;
     for (uint32_t e = e0; e < e1; ++e, ++n) {
         const uint2 it = buckets[(uint32_t)cl * cap + e];
@@ -543,7 +519,9 @@ __device__ __forceinline__ void add_pair(const StepArgs &a, uint8_t *smem, uint3
     uint32_t *LCNT = reinterpret_cast<uint32_t *>(smem + Ly.lcnt_off);
     uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off) + dl * Ly.list_cap;
     if (MODE == 2 || MODE == 3) {
-        uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
+        // privatised copies: lane l adds to copy l mod copies (copies is a power of two)
+        const uint32_t cp = Ly.copies > 1u ? (uint32_t)lane() & (Ly.copies - 1u) : 0u;
+        uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + (dl * Ly.copies + cp) * Ly.tri_pad;
         const uint32_t i = la <= lb ? tb + la : ta + lb;
         if (MODE == 2)
             __hip_atomic_fetch_add(&U[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -946,7 +924,7 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
     // LDS starts clean and every item leaves it clean.
     if (MODE != 1) {
         uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off);
-        for (uint32_t i = threadIdx.x; i < Ly.n_tri * Ly.tri_pad; i += blockDim.x) U[i] = 0u;
+        for (uint32_t i = threadIdx.x; i < Ly.n_tri * Ly.copies * Ly.tri_pad; i += blockDim.x) U[i] = 0u;
     } else {
         uint32_t *HK = reinterpret_cast<uint32_t *>(smem + Ly.hkey_off);
         uint32_t *HC = reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off);
@@ -1023,13 +1001,14 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
                 __syncthreads();
                 const int n_mat = (MODE >= 2 && a.merged) ? 1 : d1 - d0;
                 for (int dl = w; dl < n_mat; dl += nw) {
-                    uint32_t *Ud = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
+                    uint32_t *Ud = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.copies * Ly.tri_pad;
                     const uint32_t n = min(LCNT[dl], Ly.list_cap);
                     const uint32_t *lst = LST + dl * Ly.list_cap;
                     WaveGrp g;
                     if (MODE == 2 || MODE == 3) {
                         SrcTriScan<MODE == 3> s{Ud, (ng * (ng + 1u)) >> 1,
-                                                BUF + (uint32_t)w * kWave * SrcTriScan<MODE == 3>::kPerRead};
+                                                BUF + (uint32_t)w * kWave * SrcTriScan<MODE == 3>::kPerRead,
+                                                Ly.copies, Ly.tri_pad};
                         dir_or_flush<Acc>(a, g, s, split, rd, roi, a.merged ? 0 : d0 + dl, MARG, ng);
                     } else if (MODE == 0) {
                         SrcDenseList s{lst, n, Ud};
@@ -1045,89 +1024,6 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
             }
         }
         __syncthreads();
-    }
-}
-
-// ------------------------------------------------------------------ wave per ROI
-// Small unsplit ROIs of images with at most four offsets: one wavefront owns a
-// whole ROI.  It accumulates the ROI's voxels alone (row sweep or gather) into
-// its own LDS triangles, then each 16-lane DPP row reduces one direction, so
-// the four directions share every reduction instruction and no work-group
-// barrier is ever needed.  One wavefront per work-group.
-template <bool PACKED, class OutT>
-__global__ __launch_bounds__(64) void k_wave(StepArgs a, uint32_t direct_roi) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    typedef typename std::conditional<sizeof(OutT) == 8, double, float>::type Acc;
-    const LdsLayout &Ly = a.wlds;
-    uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off);
-    uint32_t *BUF = reinterpret_cast<uint32_t *>(smem + Ly.buf_off);
-    uint32_t *MARG = reinterpret_cast<uint32_t *>(smem + Ly.marg_off);
-    uint32_t *MISC = reinterpret_cast<uint32_t *>(smem + Ly.misc_off);
-    const int K = a.K;
-    const uint32_t ng = (uint32_t)a.ng, tri = (ng * (ng + 1u)) >> 1;
-    const uint32_t ln = (uint32_t)lane();
-    const WaveGrp wg;
-    for (uint32_t i = ln; i < (uint32_t)K * Ly.tri_pad; i += kWave) U[i] = 0u;
-    for (uint32_t i = ln; i < (uint32_t)K * 4u * ng; i += kWave) MARG[i] = 0u;
-    if (direct_roi == kNone) ticket_load(MISC, a.counters + C_CLASS_W, a.bucket_cap, ln);
-    wg.sync();
-    if (ln == 0 && direct_roi == kNone) ticket_prefix(MISC);
-    wg.sync();
-    for (uint32_t iter = 0;; ++iter) {
-        if (ln == 0) {
-            uint32_t n = 0;
-            if (direct_roi != kNone) {
-                if (iter == 0 && direct_roi < a.roi_cap) { MISC[0] = direct_roi; MISC[1] = 0u; n = 1; }
-            } else {
-                n = ticket_claim(MISC, &a.counters[C_TICKET_W], 0u, 1u, a.buckets_w, a.bucket_cap);
-            }
-            MISC[32] = n;
-        }
-        wg.sync();
-        const uint32_t n_items = __builtin_amdgcn_readfirstlane(MISC[32]);
-        if (n_items == 0u) break;
-        for (uint32_t q = 0; q < n_items; ++q) {
-            const uint32_t roi = __builtin_amdgcn_readfirstlane(MISC[2 * q]);
-            if (roi >= a.roi_cap) continue;
-            const RoiDesc rd = a.rois[roi];
-            if (rd.n_tiles != 1u || rd.gslot != kNone || rd.image >= (uint32_t)a.n_images) continue;
-            const ImgDesc im = a.imgs[rd.image];
-            if (rd.x0 < 0 || rd.y0 < 0 || rd.z0 < 0 || rd.x1 >= im.nx || rd.y1 >= im.ny || rd.z1 >= im.nz ||
-                rd.x0 > rd.x1 || rd.y0 > rd.y1 || rd.z0 > rd.z1)
-                continue;
-            ItemCtx c;
-            c.I = im.I; c.L = im.L; c.B = im.B;
-            c.nx = im.nx; c.ny = im.ny; c.nz = im.nz;
-            c.label = rd.label; c.vmin = rd.vmin; c.D = rd.vmax - rd.vmin; c.ng = ng;
-            c.rcpD = c.D ? 1.0f / (float)c.D : 0.0f;
-            c.err = &a.counters[C_ERR];
-            const uint32_t W = (uint32_t)(rd.x1 - rd.x0 + 1);
-            auto add = [&](uint32_t dl, uint32_t la, uint32_t ta, uint32_t lb, uint32_t tb) {
-                const uint32_t i = la <= lb ? tb + la : ta + lb;
-                uint32_t *Ud = U + dl * Ly.tri_pad;
-                if (PACKED)
-                    __hip_atomic_fetch_add(&Ud[i >> 1], 1u << ((i & 1u) << 4), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                else
-                    __hip_atomic_fetch_add(&Ud[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            };
-            if (a.wsweep_ok)
-                accumulate_sweep2d(rd, c, 0u, rd.rows, 0u, W, a.wsweep[0], a.wsweep[1], a.wsweep[2], a.wsweep[3], 0,
-                                   1, add);
-            else
-                accumulate_rows(a, rd, c, 0u, rd.rows, 0u, W, 0, K, ln, (uint32_t)kWave, add);
-            wg.sync();
-            // one 16-lane row per direction
-            const RowGrp g;
-            const int r = g.row();
-            if (r < K) {
-                SrcTriScan<PACKED> s{U + (uint32_t)r * Ly.tri_pad, tri,
-                                     BUF + (uint32_t)r * 16u * kScanCells};
-                uint32_t *M = MARG + (uint32_t)r * 4u * ng;
-                dir_sums<Acc, double>(g, s, M, M + ng, M + 3u * ng - 1u, ng, a.dsums + (uint64_t)roi * K + r);
-            }
-            wg.sync();
-        }
     }
 }
 
@@ -1376,41 +1272,6 @@ hipError_t launch_batch(const StepArgs &a, uint32_t grid, uint32_t block, uint32
         default: return a.fp64 ? launch_batch_t<3, double>(a, grid, block, direct_roi, st)
                                : launch_batch_t<3, float>(a, grid, block, direct_roi, st);
     }
-}
-
-static const void *wave_kernel(int packed, int fp64) {
-    if (packed) return fp64 ? reinterpret_cast<const void *>(&k_wave<true, double>) : reinterpret_cast<const void *>(&k_wave<true, float>);
-    return fp64 ? reinterpret_cast<const void *>(&k_wave<false, double>) : reinterpret_cast<const void *>(&k_wave<false, float>);
-}
-
-hipError_t launch_wave(const StepArgs &a, uint32_t grid, uint32_t direct_roi, hipStream_t st) {
-    if (!a.wave_ok) return hipSuccess;
-    static bool attr_done = false;
-    if (!attr_done) {
-        for (int p = 0; p < 2; ++p)
-            for (int f = 0; f < 2; ++f) {
-                hipError_t e = hipFuncSetAttribute(wave_kernel(p, f), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-                if (e != hipSuccess) return e;
-            }
-        attr_done = true;
-    }
-    const bool packed = a.wlds.mode == 3;
-    if (packed) {
-        if (a.fp64) hipLaunchKernelGGL((k_wave<true, double>), dim3(grid), dim3(64), a.wlds.bytes, st, a, direct_roi);
-        else hipLaunchKernelGGL((k_wave<true, float>), dim3(grid), dim3(64), a.wlds.bytes, st, a, direct_roi);
-    } else {
-        if (a.fp64) hipLaunchKernelGGL((k_wave<false, double>), dim3(grid), dim3(64), a.wlds.bytes, st, a, direct_roi);
-        else hipLaunchKernelGGL((k_wave<false, float>), dim3(grid), dim3(64), a.wlds.bytes, st, a, direct_roi);
-    }
-    NYX_CHECK_LAUNCH();
-    return hipSuccess;
-}
-
-hipError_t wave_occupancy(int packed, int fp64, uint32_t lds_bytes, int *blocks_per_cu) {
-    const void *f = wave_kernel(packed, fp64);
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, 64, (size_t)lds_bytes);
 }
 
 static const void *batch_kernel(int mode, int fp64) {

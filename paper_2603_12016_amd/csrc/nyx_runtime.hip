@@ -89,7 +89,7 @@ struct nyx_ctx {
 // All device state of one discovery/step over a batch of images.
 struct Work {
     std::vector<ImgDesc> h_imgs;
-    DevBuf imgs, tab[10], counters, rois, buckets, buckets_w, G, dsums, split_roi, vox_base;
+    DevBuf imgs, tab[10], counters, rois, buckets, G, dsums, split_roi, vox_base;
     uint32_t tab_total = 0, n_blocks = 0, n_counters = 0, total_chunks = 0;
     uint32_t n_rois = 0;
     uint64_t total_vox = 0;
@@ -103,9 +103,8 @@ struct nyx_plan {
     std::vector<nyx_image> imgs;
     int K = 0, ng = 0;
     nyx_precision prec = NYX_FP32;
-    uint32_t grid = 0, block = 256, wgrid = 0;
+    uint32_t grid = 0, block = 256;
     std::vector<uint32_t> roi_tiles;   // per-ROI tile count for the per-ROI path
-    std::vector<uint8_t> roi_wave;     // per-ROI: processed by the wavefront kernel
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     void *graph_table = nullptr;
@@ -113,7 +112,7 @@ struct nyx_plan {
     std::string desc;
     int64_t workspace_bytes = 0;
     float tuned_ms = 0.f;
-    struct Cfg { int mode; uint32_t kp, block, split_vox, tile_vox, list_cap, hash_cap; int force_split; uint32_t wave_vox; };
+    struct Cfg { int mode; uint32_t kp, block, split_vox, tile_vox, list_cap, hash_cap; int force_split; };
     Cfg cfg{};
 };
 
@@ -289,8 +288,9 @@ struct Config {
     uint32_t split_vox = 0, tile_vox = 0;
     uint32_t list_cap = 0, hash_cap = 0;
     int force_split = 0;
-    uint32_t wave_vox = 0;   // unsplit ROIs up to this many voxels go to the wavefront kernel (0: none)
     int merged = 0;          // one matrix per ROI: the sum of the K offsets' matrices
+    uint32_t copies = 1;     // privatised copies of each dense triangle (scan modes)
+    float tile_scale = 1.f;  // split ROIs above tile_scale x the load-balance share
 };
 
 const char *mode_name(int m) {
@@ -321,6 +321,7 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K, bool ring) {
     L.kp = c.kp;
     L.nwaves = c.block / kWave;
     L.tri_pad = u_words(c.mode, ng);
+    L.copies = (c.mode == 2 || c.mode == 3) ? c.copies : 1u;
     L.list_cap = c.list_cap;
     L.hash_cap = c.hash_cap;
     uint32_t off = 0;
@@ -331,7 +332,7 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K, bool ring) {
     };
     if (c.mode != 1) {
         L.n_tri = c.merged ? 1u : c.kp;   // merged: one triangle for all offsets
-        L.u_off = take(L.n_tri * L.tri_pad * 4u);
+        L.u_off = take(L.n_tri * L.copies * L.tri_pad * 4u);
     } else {
         L.hkey_off = take(c.hash_cap * 4u);
         L.hcnt_off = take(c.hash_cap * 4u);
@@ -356,37 +357,6 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K, bool ring) {
     L.bytes = off;
     return L;
 }
-
-// LDS of one wavefront of the wave-per-ROI kernel: K packed triangles, the
-// compaction buffer of four 16-lane rows, K marginal sets, sums, features,
-// misc.  The triangles hold 16-bit counters, so items stay below 65536 voxels.
-LdsLayout make_wave_layout(uint32_t ng, int K) {
-    LdsLayout L;
-    memset(&L, 0, sizeof L);
-    L.mode = 3;
-    L.kp = (uint32_t)K;
-    L.nwaves = 1;
-    L.tri_pad = u_words(3, ng);
-    uint32_t off = 0;
-    auto take = [&](uint32_t bytes) {
-        uint32_t o = off;
-        off += (bytes + 15u) & ~15u;
-        return o;
-    };
-    L.n_tri = (uint32_t)K;
-    L.u_off = take((uint32_t)K * L.tri_pad * 4u);
-    L.buf_off = take(kWave * (uint32_t)kScanCells * 4u);
-    L.marg_sets = (uint32_t)K;
-    L.marg_off = take((uint32_t)K * 4u * ng * 4u);
-    L.misc_off = take(128u * 4u);
-    L.bytes = off;
-    return L;
-}
-
-// Wavefront path: at most four offsets and a per-wave LDS footprint that
-// leaves room for several waves per CU.
-constexpr uint32_t kWaveLdsMax = 40u * 1024u;
-bool wave_feasible(uint32_t ng, int K) { return K <= 4 && make_wave_layout(ng, K).bytes <= kWaveLdsMax; }
 
 // Largest voxel count any work item can hold under a split rule.
 uint64_t max_item_vox(const std::vector<RoiDesc> &rois, uint32_t split_vox, uint32_t tile_vox) {
@@ -413,9 +383,12 @@ uint32_t groups_per_cu(uint64_t lds_bytes) {
 // merged: every offset counts into one LDS triangle in one pass, so only the
 // dense scan modes qualify, and packed 16-bit counters need K x (voxels of an
 // item) < 65536 (offered only when that bound leaves the load-balance tile
-// size alone; 32-bit counters otherwise).
+// size alone; 32-bit counters otherwise).  copies: privatised copies of each
+// dense scan triangle (list and hash modes keep one); tile_scale scales the
+// load-balance share above which ROIs are split.
 std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_t ng, int K, int force_split,
-                                      uint32_t block, bool merged = false) {
+                                      uint32_t block, bool merged = false, uint32_t copies = 1u,
+                                      float tile_scale = 1.f) {
     std::vector<Config> out;
     const uint32_t nw = block / kWave;
     const uint32_t tri = ng * (ng + 1u) / 2u;
@@ -429,11 +402,12 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
     for (const RoiDesc &r : w.h_rois) total_vox += r.n;
     // load balance: split ROIs that would take more than ~1/4 of one
     // work-group's share of the voxels
-    uint64_t share = total_vox / ((uint64_t)std::max(ctx->n_cu, 1) * 4u) + 1u;
+    uint64_t share = (uint64_t)((double)(total_vox / ((uint64_t)std::max(ctx->n_cu, 1) * 4u) + 1u) * tile_scale);
     const uint32_t lb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(share, 4096u), 1u << 20);
     std::vector<Config> later;
     for (int mode : {3, 2, 0}) {
         if (merged && mode == 0) continue;
+        if (copies > 1u && mode == 0) continue;   // the returning-atomic list keeps one triangle
         const uint32_t cell_max = merged ? 65535u / (uint32_t)K : 65535u;   // 16-bit counters
         uint32_t split = mode == 3 ? std::min<uint32_t>(lb, cell_max) : lb;
         uint64_t mi = max_item_vox(w.h_rois, split, split);
@@ -446,14 +420,16 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
         const bool scan = mode == 2 || mode == 3;
         const uint32_t list_cap = scan ? 0u : (uint32_t)std::min<uint64_t>(tri, std::max<uint64_t>(mi, 1u));
         const uint64_t scan_buf = scan ? (uint64_t)nw * kWave * scan_cells(mode) * 4u : 0u;
+        const uint32_t cp = scan ? copies : 1u;
         for (uint32_t kp = (uint32_t)K; kp >= (merged ? (uint32_t)K : 1u); --kp) {
             const uint32_t n_tri = merged ? 1u : kp;
-            uint64_t bytes = (uint64_t)n_tri * u_words(mode, ng) * 4u + (uint64_t)kp * list_cap * 4u + kp * 4u +
+            uint64_t bytes = (uint64_t)n_tri * cp * u_words(mode, ng) * 4u + (uint64_t)kp * list_cap * 4u + kp * 4u +
                              fixed_for(n_tri) + scan_buf;
             if (bytes <= kLdsBudget) {
                 Config c;
                 c.mode = mode; c.kp = kp; c.block = block; c.split_vox = split; c.tile_vox = split;
                 c.list_cap = list_cap; c.force_split = force_split; c.merged = merged ? 1 : 0;
+                c.copies = cp; c.tile_scale = tile_scale;
                 out.push_back(c);
                 if (merged) break;
                 // many offsets: fewer directions per pass cost another pass
@@ -470,7 +446,7 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
         }
     }
     out.insert(out.end(), later.begin(), later.end());
-    if (!out.empty() || fixed >= kLdsBudget || merged) return out;
+    if (!out.empty() || fixed >= kLdsBudget || merged || copies > 1u) return out;
     // hash mode: items small enough that kp directions of pairs fill at most
     // half the table
     for (uint32_t kp = (uint32_t)K; kp >= 1u; --kp) {
@@ -489,7 +465,7 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
             if (bytes <= kLdsBudget) {
                 Config c;
                 c.mode = 1; c.kp = kp; c.block = block; c.hash_cap = hc; c.split_vox = split; c.tile_vox = split;
-                c.list_cap = list_cap; c.force_split = force_split;
+                c.list_cap = list_cap; c.force_split = force_split; c.tile_scale = tile_scale;
                 out.push_back(c);
                 return out;
             }
@@ -575,7 +551,6 @@ bool sweep_table(const std::vector<ImgDesc> &imgs, const nyx_offset *off, int K,
 
 void set_sweep(StepArgs &a, const std::vector<ImgDesc> &imgs, const nyx_offset *off, int K, uint32_t kp) {
     a.sweep_ok = sweep_table(imgs, off, K, kp, a.sweep, kMaxSweepPasses) ? 1 : 0;
-    a.wsweep_ok = K <= 4 && sweep_table(imgs, off, K, (uint32_t)K, &a.wsweep, 1) ? 1 : 0;
 }
 
 // Allocates queue, split matrices and fills the step arguments.
@@ -590,9 +565,8 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     uint32_t bucket_cap = (uint32_t)std::max<uint64_t>(items, 1u);
     const int K_out = cfg.merged ? 1 : K;
     uint64_t g_bytes = (uint64_t)n_split * K_out * (uint64_t)ng * ng * 8u;
-    const bool wave = !cfg.merged && cfg.wave_vox > 0u && wave_feasible(ng, K);
     const uint64_t sums_bytes = (uint64_t)std::max<uint32_t>(w.n_rois, 1u) * K_out * sizeof(DirSums);
-    uint64_t need = (uint64_t)kClasses * bucket_cap * 8u * (wave ? 2u : 1u) + g_bytes + sums_bytes + n_split * 4u;
+    uint64_t need = (uint64_t)kClasses * bucket_cap * 8u + g_bytes + sums_bytes + n_split * 4u;
     for (auto &b : w.tab) need += b.bytes;
     need += w.rois.bytes + w.counters.bytes;
     if (ws_bytes) *ws_bytes = (int64_t)need;
@@ -600,8 +574,6 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
         return fail(ctx, NYX_ERR_OOM, "workspace needs %llu bytes, cap is %lld", (unsigned long long)need,
                     (long long)cap_bytes);
     HIPC(ctx, w.buckets.alloc((size_t)kClasses * bucket_cap * sizeof(uint2)));
-    if (wave) HIPC(ctx, w.buckets_w.alloc((size_t)kClasses * bucket_cap * sizeof(uint2)));
-    else w.buckets_w.release();
     HIPC(ctx, w.G.alloc(std::max<uint64_t>(g_bytes, 16u)));
     HIPC(ctx, w.dsums.alloc(sums_bytes));
     HIPC(ctx, w.split_roi.alloc((size_t)std::max<uint32_t>(n_split, 1u) * 4u));
@@ -627,10 +599,6 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     a.fp64 = fp64;
     set_sweep(a, w.h_imgs, off, K, cfg.kp);
     a.lds = make_layout(cfg, ng, K, !a.sweep_ok);
-    a.wave_ok = wave ? 1 : 0;
-    a.wave_max_vox = wave ? std::min<uint32_t>(cfg.wave_vox, 65535u) : 0u;
-    a.buckets_w = wave ? w.buckets_w.as<uint2>() : nullptr;
-    a.wlds = wave ? make_wave_layout(ng, K) : LdsLayout{};
     return NYX_OK;
 }
 
@@ -657,12 +625,8 @@ nyx_status enqueue_step(nyx_plan *p, hipStream_t st, bool per_roi) {
     HIPC(ctx, launch_zero_split(a, st));
     if (!per_roi) {
         HIPC(ctx, launch_batch(a, p->grid, p->block, kNone, st));
-        if (a.wave_ok) HIPC(ctx, launch_wave(a, p->wgrid, kNone, st));
     } else {
-        for (uint32_t r = 0; r < p->w.n_rois; ++r) {
-            if (p->roi_wave[r]) HIPC(ctx, launch_wave(a, 1u, r, st));
-            else HIPC(ctx, launch_batch(a, p->roi_tiles[r], p->block, r, st));
-        }
+        for (uint32_t r = 0; r < p->w.n_rois; ++r) HIPC(ctx, launch_batch(a, p->roi_tiles[r], p->block, r, st));
     }
     HIPC(ctx, launch_split_finalize(a, st));
     HIPC(ctx, launch_features(a, a.dsums, a.roi_cap, a.counters + C_NROIS, st));
@@ -685,16 +649,14 @@ nyx_status check_counters(nyx_ctx *ctx, Work &w, hipStream_t st) {
     return NYX_OK;
 }
 
-std::string describe(const Config &c, const nyx_plan *p, uint64_t items, uint32_t n_split, uint32_t wave_rois,
-                     uint64_t wave_voxels) {
+std::string describe(const Config &c, const nyx_plan *p, uint64_t items, uint32_t n_split) {
     char buf[512];
     snprintf(buf, sizeof buf,
-             "mode=%s kp=%u block=%u grid=%u lds=%uB split_vox=%u tile_vox=%u list_cap=%u hash_cap=%u "
-             "wave_vox=%u wave_grid=%u wave_lds=%uB wave_rois=%u wave_roi_voxels=%llu rois=%u items=%llu "
-             "split_rois=%u ng=%d K=%d",
-             mode_name(c.mode), c.kp, c.block, p->grid, p->w.args.lds.bytes, c.split_vox, c.tile_vox,
-             c.list_cap, c.hash_cap, p->w.args.wave_max_vox, p->wgrid, p->w.args.wlds.bytes, wave_rois,
-             (unsigned long long)wave_voxels, p->w.n_rois, (unsigned long long)items, n_split, p->ng, p->K);
+             "mode=%s kp=%u copies=%u block=%u grid=%u lds=%uB split_vox=%u tile_vox=%u tile_scale=%g list_cap=%u "
+             "hash_cap=%u rois=%u items=%llu split_rois=%u ng=%d K=%d tuned_ms=%.4f",
+             mode_name(c.mode), c.kp, p->w.args.lds.copies, c.block, p->grid, p->w.args.lds.bytes, c.split_vox,
+             c.tile_vox, (double)c.tile_scale, c.list_cap, c.hash_cap, p->w.n_rois, (unsigned long long)items,
+             n_split, p->ng, p->K, (double)p->tuned_ms);
     return buf;
 }
 
@@ -711,26 +673,9 @@ nyx_status configure(nyx_plan *p, const Config &cfg, const nyx_extract_opts *opt
     uint64_t items;
     uint32_t n_split;
     count_items(p->w.h_rois, cfg, &items, &n_split, &p->roi_tiles);
-    // the wavefront kernel's share, decided as the compaction decides it
-    const StepArgs &a = p->w.args;
-    p->roi_wave.assign(p->w.n_rois, 0);
-    uint32_t wave_rois = 0;
-    uint64_t wave_voxels = 0;
-    p->wgrid = 0;
-    if (a.wave_ok) {
-        for (uint32_t r = 0; r < p->w.n_rois; ++r)
-            if (p->roi_tiles[r] == 1u && !cfg.force_split && p->w.h_rois[r].n <= a.wave_max_vox) {
-                p->roi_wave[r] = 1;
-                ++wave_rois;
-                wave_voxels += p->w.h_rois[r].n;
-            }
-        int wocc = 0;
-        HIPC(ctx, wave_occupancy(1, p->prec == NYX_FP64, a.wlds.bytes, &wocc));
-        p->wgrid = (uint32_t)ctx->n_cu * (uint32_t)std::max(wocc, 1);
-    }
     p->cfg = nyx_plan::Cfg{cfg.mode, cfg.kp, cfg.block, cfg.split_vox, cfg.tile_vox, cfg.list_cap, cfg.hash_cap,
-                           cfg.force_split, a.wave_max_vox};
-    p->desc = describe(cfg, p, items, n_split, wave_rois, wave_voxels);
+                           cfg.force_split};
+    p->desc = describe(cfg, p, items, n_split);
     return NYX_OK;
 }
 
@@ -913,10 +858,13 @@ nyx_status nyx_glcm_accumulate(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_im
     return NYX_OK;
 }
 
-nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, nyx_precision prec, void *table,
-                             int64_t table_capacity_rows, nyx_stream stream) {
+nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, const nyx_roi_table *rois, nyx_precision prec,
+                             void *table, int64_t table_capacity_rows, nyx_stream stream) {
     if (!ctx) return NYX_ERR_INVALID;
     if (!glcm || !table) return fail(ctx, NYX_ERR_INVALID, "NULL argument");
+    if (rois && rois->n_rois_host && *rois->n_rois_host != glcm->n_rois)
+        return fail(ctx, NYX_ERR_INVALID, "ROI table has %lld rows, the COO list %lld ROIs",
+                    (long long)*rois->n_rois_host, (long long)glcm->n_rois);
     if (glcm->n_offsets < 1 || glcm->n_offsets > kMaxOffsets) return fail(ctx, NYX_ERR_INVALID, "bad n_offsets");
     nyx_status s = validate_bins(ctx, glcm->n_bins);
     if (s != NYX_OK) return s;
@@ -980,25 +928,14 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
     if ((s = discover(ctx, imgs, n_images, p->w, st)) != NYX_OK) return s;
     if ((s = fetch_rois(ctx, p->w, st)) != NYX_OK) return s;
     const bool merged = opts->aggregate == NYX_AGG_MERGED;
-    std::vector<Config> cands = candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256, merged);
+    if (opts->copies != 0 && opts->copies != 1 && opts->copies != 2 && opts->copies != 4)
+        return fail(ctx, NYX_ERR_INVALID, "copies must be 0, 1, 2 or 4");
+    // the default plan: one copy (or the forced count) at the load-balance tile size
+    const uint32_t copies0 = opts->copies > 0 ? (uint32_t)opts->copies : 1u;
+    std::vector<Config> cands = candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256, merged, copies0);
     if (cands.empty())
-        return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%d with %d offsets%s", p->ng, p->K,
-                    merged ? " merged in one pass" : "");
-    // wavefront-per-ROI share: automatic (off unless timing finds a share
-    // that pays), off, or a given ROI size limit; not for merged matrices
-    const bool wave_ok = !merged && wave_feasible((uint32_t)p->ng, p->K);
-    const uint32_t wave_vox = !wave_ok || opts->wave_max_vox <= 0 ? 0u : (uint32_t)std::min(opts->wave_max_vox, 65535);
-    for (Config &c : cands) c.wave_vox = wave_vox;
-    if (opts->autotune && opts->wave_max_vox < 0 && wave_ok) {
-        // also time wavefront shares of each candidate
-        const size_t n0 = cands.size();
-        for (size_t i = 0; i < n0; ++i)
-            for (uint32_t v : {1024u, 4096u}) {
-                Config c = cands[i];
-                c.wave_vox = v;
-                cands.push_back(c);
-            }
-    }
+        return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%d with %d offsets%s%s", p->ng, p->K,
+                    merged ? " merged in one pass" : "", copies0 > 1u ? " with privatised copies" : "");
     Config cfg = default_config(cands, p->w, (uint32_t)p->ng, p->K);
     if (opts->accum_mode >= 0) {
         bool found = false;
@@ -1006,32 +943,49 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
             if (c.mode == opts->accum_mode) { cfg = c; found = true; break; }
         if (!found) return fail(ctx, NYX_ERR_UNSUPPORTED, "accumulation mode %d does not fit this workload", opts->accum_mode);
     }
+    if (opts->autotune) {
+        // further axes: privatised copies (when not forced) and the tile size of split ROIs
+        for (uint32_t cp : {1u, 2u, 4u}) {
+            if (opts->copies > 0 && cp != copies0) continue;
+            for (float ts : {0.5f, 1.f, 2.f}) {
+                if (cp == copies0 && ts == 1.f) continue;
+                for (const Config &c : candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256, merged, cp, ts))
+                    if (cp == 1u || c.copies == cp) cands.push_back(c);
+            }
+        }
+    }
     if (opts->autotune && cands.size() > 1) {
-        // time one step of every candidate and keep the fastest
+        // every candidate: one warm-up step, then the median of kTuneSteps timed steps
+        constexpr int kTuneSteps = 5;
         DevBuf tmp;
         size_t row_bytes = (size_t)(merged ? 1 : p->K + 1) * kNumFeat * (p->prec == NYX_FP64 ? 8u : 4u);
         HIPC(ctx, tmp.alloc(std::max<size_t>(p->w.n_rois, 1u) * row_bytes));
-        hipEvent_t e0, e1;
-        HIPC(ctx, hipEventCreate(&e0));
-        HIPC(ctx, hipEventCreate(&e1));
+        hipEvent_t ev[kTuneSteps + 1];
+        for (auto &e : ev) HIPC(ctx, hipEventCreate(&e));
         float best = 1e30f;
         for (const Config &c : cands) {
             if (opts->accum_mode >= 0 && c.mode != opts->accum_mode) continue;
             if ((s = configure(p.get(), c, opts)) != NYX_OK) continue;
             set_outputs(ctx, p->w.args, nullptr, tmp.p, p->w.n_rois);
             if ((s = enqueue_step(p.get(), st, false)) != NYX_OK) break;
-            HIPC(ctx, hipEventRecord(e0, st));
-            if ((s = enqueue_step(p.get(), st, false)) != NYX_OK) break;
-            HIPC(ctx, hipEventRecord(e1, st));
-            HIPC(ctx, hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPC(ctx, hipEventElapsedTime(&ms, e0, e1));
+            hipError_t he = hipEventRecord(ev[0], st);
+            for (int k = 0; k < kTuneSteps && he == hipSuccess && s == NYX_OK; ++k) {
+                s = enqueue_step(p.get(), st, false);
+                he = hipEventRecord(ev[k + 1], st);
+            }
+            if (s != NYX_OK) break;
+            HIPC(ctx, he);
+            HIPC(ctx, hipEventSynchronize(ev[kTuneSteps]));
+            float t[kTuneSteps];
+            for (int k = 0; k < kTuneSteps; ++k) HIPC(ctx, hipEventElapsedTime(&t[k], ev[k], ev[k + 1]));
+            std::sort(t, t + kTuneSteps);
+            const float ms = t[kTuneSteps / 2];
             if (log_level() > 0)
-                fprintf(stderr, "[nyx] autotune %s kp=%u wave_vox=%u: %.3f ms\n", mode_name(c.mode), c.kp, c.wave_vox, ms);
+                fprintf(stderr, "[nyx] autotune %s kp=%u copies=%u tile_scale=%g: %.3f ms\n", mode_name(c.mode), c.kp,
+                        c.copies, (double)c.tile_scale, ms);
             if (ms < best) { best = ms; cfg = c; }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        for (auto &e : ev) (void)hipEventDestroy(e);
         if (s != NYX_OK) return s;
         p->tuned_ms = best;
     }
@@ -1115,13 +1069,11 @@ nyx_status nyx_plan_profile(nyx_plan *p, void *table, float *ms_host, nyx_stream
     if (he == hipSuccess) he = hipEventRecord(ev[4], st);
     if (he == hipSuccess) he = launch_batch(a, p->grid, p->block, kNone, st);
     if (he == hipSuccess) he = hipEventRecord(ev[5], st);
-    if (he == hipSuccess && a.wave_ok) he = launch_wave(a, p->wgrid, kNone, st);
-    if (he == hipSuccess) he = hipEventRecord(ev[6], st);
     if (he == hipSuccess) he = launch_split_finalize(a, st);
-    if (he == hipSuccess) he = hipEventRecord(ev[7], st);
+    if (he == hipSuccess) he = hipEventRecord(ev[6], st);
     if (he == hipSuccess) he = launch_features(a, a.dsums, a.roi_cap, a.counters + C_NROIS, st);
-    if (he == hipSuccess) he = hipEventRecord(ev[8], st);
-    if (he == hipSuccess) he = hipEventSynchronize(ev[8]);
+    if (he == hipSuccess) he = hipEventRecord(ev[7], st);
+    if (he == hipSuccess) he = hipEventSynchronize(ev[7]);
     if (he == hipSuccess)
         for (int i = 0; i < NYX_PHASE_COUNT; ++i) {
             he = hipEventElapsedTime(&ms_host[i], ev[i], ev[i + 1]);

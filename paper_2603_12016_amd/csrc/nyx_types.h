@@ -23,9 +23,7 @@ enum Counter : int {
     C_NSPLIT = 1,   // ROIs split into several tiles (global-matrix slots used)
     C_ERR = 3,      // error bits (see ErrBit)
     C_NITEMS = 4,   // work items enqueued
-    C_TICKET_W = 5, // work-stealing ticket of the wave-per-ROI kernel
     C_CLASS = 8,    // kClasses counters: work-group items per size class
-    C_CLASS_W = 64, // kClasses counters: wave-per-ROI items per size class
     C_TICKETS = 128,  // kTicketLanes ticket counters of the persistent kernel, kTicketStride apart
     C_BLOCKS = 128 + 32 * 32, // per-block ROI counts of the compaction (variable length)
 };
@@ -114,7 +112,9 @@ struct LdsLayout {
     uint32_t bytes;       // total dynamic LDS
     uint32_t nwaves;      // waves per work-group
     uint32_t marg_sets;   // marginal sets at marg_off (one per wave that reduces a matrix)
-    uint32_t n_tri;       // dense triangles at u_off (kp, or 1 when the offsets' matrices are merged)
+    uint32_t n_tri;       // dense matrices at u_off (kp, or 1 when the offsets' matrices are merged)
+    uint32_t copies;      // privatised copies of each dense triangle (1, 2 or 4): lane l adds to copy
+                          // l mod copies; copy c of matrix m starts (m * copies + c) * tri_pad words in
 };
 
 struct StepArgs {
@@ -153,14 +153,6 @@ struct StepArgs {
     // of the H, V, D45, D135 neighbour classes (-1 = absent)
     int32_t sweep_ok;
     int8_t sweep[kMaxSweepPasses][4];
-    // wave-per-ROI path: unsplit ROIs up to wave_max_vox voxels (wave_ok = 1)
-    // go to their own queue, one wavefront per ROI, LDS layout wlds per wave
-    int32_t wave_ok;
-    uint32_t wave_max_vox;
-    uint2 *buckets_w;
-    LdsLayout wlds;
-    int32_t wsweep_ok;   // row sweep with all K directions in one pass
-    int8_t wsweep[4];
 };
 
 // Deterministic split rule shared by host planning and device enqueueing:
@@ -198,6 +190,56 @@ inline void tile_bounds(uint32_t rows, uint32_t width, uint32_t n_tiles, uint32_
     *cb = *ca + cpt < width ? *ca + cpt : width;
     if (*ra > rows) *ra = rows;
     if (*ca > width) *ca = width;
+}
+
+// Work tickets.  The queue is the concatenation of the size-class buckets,
+// largest class first; a ticket hands out up to ticket_chunk(cl) consecutive
+// entries of one class (several small items per ticket, one item per ticket
+// from the classes whose items alone keep a work-group busy).
+#ifdef __HIPCC__
+__host__ __device__
+#endif
+inline uint32_t ticket_chunk(int cl) {
+    const uint32_t c = kTicketVox >> cl;
+    return c < 1u ? 1u : (c > (uint32_t)kTicketChunk ? (uint32_t)kTicketChunk : c);
+}
+
+#ifdef __HIPCC__
+__host__ __device__
+#endif
+inline uint32_t class_tickets(uint32_t entries, int cl) {
+    const uint32_t ch = ticket_chunk(cl);
+    return (entries + ch - 1u) / ch;
+}
+
+// first[cl] = tickets of all larger classes (entries[cl]: queue entries of
+// class cl); returns the number of tickets.
+#ifdef __HIPCC__
+__host__ __device__
+#endif
+inline uint32_t ticket_offsets(const uint32_t *entries, uint32_t *first) {
+    uint32_t acc = 0;
+    for (int cl = kClasses - 1; cl >= 0; --cl) {
+        first[cl] = acc;
+        acc += class_tickets(entries[cl], cl);
+    }
+    return acc;
+}
+
+// Class and entry range [*e0, *e1) of ticket t < total (as ticket_offsets
+// laid them out).
+#ifdef __HIPCC__
+__host__ __device__
+#endif
+inline void ticket_range(uint32_t t, const uint32_t *entries, const uint32_t *first, int *cl_out, uint32_t *e0,
+                         uint32_t *e1) {
+    int cl = kClasses - 1;
+    while (cl > 0 && t >= first[cl] + class_tickets(entries[cl], cl)) --cl;
+    const uint32_t ch = ticket_chunk(cl);
+    *cl_out = cl;
+    *e0 = (t - first[cl]) * ch;
+    const uint32_t end = *e0 + ch;
+    *e1 = end < entries[cl] ? end : entries[cl];
 }
 
 #ifdef __HIPCC__

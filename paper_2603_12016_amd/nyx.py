@@ -51,7 +51,7 @@ class nyx_glcm(ctypes.Structure):
 class nyx_extract_opts(ctypes.Structure):
     _fields_ = [("n_bins", c_int32), ("offsets_host", POINTER(nyx_offset)), ("n_offsets", c_int32),
                 ("symmetric", c_int32), ("precision", c_int), ("autotune", c_int32), ("accum_mode", c_int32),
-                ("wave_max_vox", c_int32), ("workspace_cap_bytes", c_int64), ("aggregate", c_int32)]
+                ("copies", c_int32), ("workspace_cap_bytes", c_int64), ("aggregate", c_int32)]
 
 
 _lib = None
@@ -62,7 +62,7 @@ EXPORTS = ("nyx_create", "nyx_destroy", "nyx_last_error", "nyx_status_string", "
            "nyx_extract_batch", "nyx_plan_create", "nyx_plan_execute", "nyx_plan_execute_per_roi",
            "nyx_plan_check", "nyx_plan_describe", "nyx_plan_destroy", "nyx_plan_profile")
 
-PHASES = ("reset", "scan", "compact", "zero", "batch", "wave", "split", "features")
+PHASES = ("reset", "scan", "compact", "zero", "batch", "band", "split", "features")
 
 
 def lib():
@@ -88,7 +88,7 @@ def lib():
     L.nyx_bin_rois.argtypes = [P, POINTER(nyx_image), c_int32, c_int32, POINTER(nyx_roi_table), P, P]
     L.nyx_glcm_accumulate.argtypes = [P, POINTER(nyx_image), c_int32, POINTER(nyx_roi_table), P,
                                       POINTER(nyx_offset), c_int32, c_int32, c_int32, POINTER(nyx_glcm), P]
-    L.nyx_glcm_features.argtypes = [P, POINTER(nyx_glcm), c_int, P, c_int64, P]
+    L.nyx_glcm_features.argtypes = [P, POINTER(nyx_glcm), POINTER(nyx_roi_table), c_int, P, c_int64, P]
     L.nyx_extract_batch.argtypes = [P, POINTER(nyx_image), c_int32, POINTER(nyx_extract_opts),
                                     POINTER(nyx_roi_table), P, c_int64, P]
     L.nyx_plan_create.argtypes = [P, POINTER(nyx_image), c_int32, POINTER(nyx_extract_opts), POINTER(P),
@@ -159,11 +159,11 @@ MODES = {"auto": -1, "dense-list": 0, "hash": 1, "dense-scan": 2, "dense16-scan"
 NYX_AGG_PER_OFFSET, NYX_AGG_MERGED = 0, 1
 
 
-def _opts(n_bins, offsets, precision, autotune=0, workspace_cap=0, mode="auto", wave=-1,
+def _opts(n_bins, offsets, precision, autotune=0, workspace_cap=0, mode="auto", copies=0,
           aggregate=NYX_AGG_PER_OFFSET):
     arr, K = _offsets(offsets)
     o = nyx_extract_opts(int(n_bins), ctypes.cast(arr, POINTER(nyx_offset)), K, 1, int(precision),
-                         int(autotune), int(MODES[mode] if isinstance(mode, str) else mode), int(wave),
+                         int(autotune), int(MODES[mode] if isinstance(mode, str) else mode), int(copies),
                          int(workspace_cap), int(aggregate))
     return o, arr
 
@@ -307,22 +307,25 @@ def nyx_glcm_accumulate(ctx: Ctx, images, rois: RoiTable, n_bins: int, offsets, 
     return Glcm(keys[:n], counts[:n], n, int(n_bins), K, int(out.n_rois))
 
 
-def nyx_glcm_features(ctx: Ctx, glcm: Glcm, precision: int = NYX_FP32, stream=None, capacity=None):
+def nyx_glcm_features(ctx: Ctx, glcm: Glcm, precision: int = NYX_FP32, stream=None, capacity=None,
+                      rois: RoiTable | None = None):
     dtype = torch.float64 if precision == NYX_FP64 else torch.float32
     rows = glcm.n_rois if capacity is None else int(capacity)
     table = torch.zeros((max(rows, 1), glcm.n_offsets + 1, 30), dtype=dtype, device=_dev())
     nnz = c_int64(glcm.nnz)
     g = glcm.struct(nnz)
-    _check(lib().nyx_glcm_features(ctx.handle, byref(g), int(precision), table.data_ptr(), rows, _stream(stream)), ctx)
+    rs = rois.struct() if rois is not None else None
+    _check(lib().nyx_glcm_features(ctx.handle, byref(g), byref(rs) if rs is not None else None, int(precision),
+                                   table.data_ptr(), rows, _stream(stream)), ctx)
     return table[:glcm.n_rois]
 
 
 def nyx_extract_batch(ctx: Ctx, images, n_bins: int, offsets, precision: int = NYX_FP32, stream=None,
-                      capacity=None, mode="auto", wave: int = -1, aggregate: int = NYX_AGG_PER_OFFSET):
+                      capacity=None, mode="auto", copies: int = 0, aggregate: int = NYX_AGG_PER_OFFSET):
     """One-shot extraction: returns (RoiTable, table (n, blocks, 30)), blocks = K + 1, or 1 when the
     offsets' matrices are merged."""
     imgs = _images(images)
-    opts, keep = _opts(n_bins, offsets, precision, mode=mode, wave=wave, aggregate=aggregate)
+    opts, keep = _opts(n_bins, offsets, precision, mode=mode, copies=copies, aggregate=aggregate)
     dev = _dev()
     if capacity is None:
         probe = RoiTable(0, dev)
@@ -342,12 +345,12 @@ def nyx_extract_batch(ctx: Ctx, images, n_bins: int, offsets, precision: int = N
 
 
 def nyx_plan_create(ctx: Ctx, images, n_bins: int, offsets, precision: int = NYX_FP32, autotune: bool = False,
-                    workspace_cap: int = 0, mode="auto", wave: int = -1,
+                    workspace_cap: int = 0, mode="auto", copies: int = 0,
                     aggregate: int = NYX_AGG_PER_OFFSET) -> Plan:
-    """mode: accumulation mode name (MODES) or -1/auto; wave: -1 automatic, 0 off, n > 0 the largest
-    ROI (voxels) processed one wavefront per ROI."""
+    """mode: accumulation mode name (MODES) or -1/auto; copies: privatised LDS triangle copies per
+    direction (0 automatic, else 1, 2 or 4)."""
     imgs = _images(images)
-    opts, keep = _opts(n_bins, offsets, precision, int(autotune), workspace_cap, mode, wave, aggregate)
+    opts, keep = _opts(n_bins, offsets, precision, int(autotune), workspace_cap, mode, copies, aggregate)
     h = c_void_p()
     n = c_int64(0)
     _check(lib().nyx_plan_create(ctx.handle, imgs, len(images), byref(opts), byref(h), byref(n)), ctx)

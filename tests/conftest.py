@@ -24,3 +24,14 @@ def synth_mod():
     import synth
     synth.build(force=False)
     return synth
+
+
+def pytest_sessionfinish(session, exitstatus):
+    # per-feature maxima of every GPU parity comparison of the session
+    try:
+        import gpu_util
+    except ImportError:
+        return
+    path = gpu_util.write_record(ROOT)
+    if path:
+        print(f"\nper-feature parity errors: {path}")

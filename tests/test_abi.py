@@ -81,70 +81,94 @@ def test_create_without_device_reports_device_error(nyx):
     assert e.value.status == nyx.NYX_ERR_DEVICE
 
 
-def test_split_rule_covers_rows_and_columns():
-    # host copy of the tiling rule the device uses: tiles partition the bbox
+@pytest.fixture(scope="module")
+def rules():
+    """The index rules of nyx_types.h compiled for the host by hipcc (the same
+    inline functions the kernels instantiate), loaded with ctypes."""
+    import ctypes
+    import subprocess
+    src = os.path.join(ROOT, "tests", "index_rules.hip")
+    lib = os.path.join(ROOT, "tests", "libindex_rules.so")
+    hipcc = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc"
+    tmp = lib + ".tmp%d" % os.getpid()
+    subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O2", "-std=c++17", "-fPIC", "-shared",
+                           "-I" + os.path.join(ROOT, "paper_2603_12016_amd", "csrc"), "-o", tmp, src])
+    os.replace(tmp, lib)
+    L = ctypes.CDLL(lib)
+    u32, P = ctypes.c_uint32, ctypes.c_void_p
+    L.rules_tiles_for.argtypes = [u32, u32, u32, u32, u32, P, P]
+    L.rules_tile_bounds.argtypes = [u32, u32, u32, u32, u32, P]
+    L.rules_size_class.argtypes = [u32]
+    L.rules_size_class.restype = u32
+    L.rules_ticket_chunk.argtypes = [ctypes.c_int]
+    L.rules_ticket_chunk.restype = u32
+    L.rules_ticket_offsets.argtypes = [P, P]
+    L.rules_ticket_offsets.restype = u32
+    L.rules_ticket_range.argtypes = [u32, P, P, P, P, P]
+    return L
+
+
+def test_split_rule_covers_rows_and_columns(rules):
+    # the compiled tiling rule: the tiles of a split ROI partition its bbox
     from itertools import product
-
-    def tiles_for(n, rows, width, split, tile):
-        if n <= split or tile == 0:
-            return 1, 1
-        nt = (n + tile - 1) // tile
-        rb = min(nt, rows)
-        cb = min((nt + rb - 1) // rb, width)
-        return rb, max(cb, 1)
-
-    def bounds(rows, width, nt, tc, t):
-        nrb = nt // tc
-        rpt = (rows + nrb - 1) // nrb
-        cpt = (width + tc - 1) // tc
-        r, c = divmod(t, tc)
-        ra, ca = min(r * rpt, rows), min(c * cpt, width)
-        return ra, min(ra + rpt, rows), ca, min(ca + cpt, width)
-
+    rb, cb = np.zeros(1, np.uint32), np.zeros(1, np.uint32)
+    b4 = np.zeros(4, np.uint32)
     for rows, width, n, tile in product([1, 3, 17, 100], [1, 5, 64, 300], [10, 1000, 30000], [7, 64, 1024]):
-        rb, cb = tiles_for(n, rows, width, tile, tile)
+        rules.rules_tiles_for(n, rows, width, tile, tile, rb.ctypes.data, cb.ctypes.data)
+        nt, tc = int(rb[0] * cb[0]), int(cb[0])
+        assert 1 <= rb[0] <= rows and 1 <= cb[0] <= width
+        if n > tile:
+            assert nt >= min((n + tile - 1) // tile, rows) or cb[0] == width
         cover = np.zeros((rows, width), int)
-        for t in range(rb * cb):
-            ra, rb_, ca, cb_ = bounds(rows, width, rb * cb, cb, t)
+        for t in range(nt):
+            rules.rules_tile_bounds(rows, width, nt, tc, t, b4.ctypes.data)
+            ra, rb_, ca, cb_ = (int(v) for v in b4)
+            assert 0 <= ra <= rb_ <= rows and 0 <= ca <= cb_ <= width
             cover[ra:rb_, ca:cb_] += 1
         assert np.all(cover == 1), (rows, width, n, tile)
 
 
-def test_ticket_scheme_hands_out_every_entry_once():
-    # host copy of the work-queue rule: classes largest first, up to 8 entries
-    # (about 8192 voxels) per ticket of a class, tickets t = k * lanes + lane
-    # drawn from `lanes` counters by the work-groups of each lane
-    def chunk(cl):
-        return max(1, min(8, 8192 >> cl))
+def test_size_class_is_floor_log2(rules):
+    for v in [0, 1, 2, 3, 4, 7, 8, 1023, 1024, 65535, 65536, 2**31 - 1, 2**31, 2**32 - 1]:
+        want = 0 if v <= 1 else v.bit_length() - 1
+        assert rules.rules_size_class(v) == want, v
 
+
+def test_ticket_scheme_hands_out_every_entry_once(rules):
+    # the compiled work-queue rule: classes largest first, at most 8 entries
+    # (about 8192 voxels) per ticket; tickets t = k * lanes + lane drawn from
+    # `lanes` counters by the work-groups of each lane
+    ncls = rules.rules_classes()
+    for cl in range(ncls):
+        assert rules.rules_ticket_chunk(cl) == max(1, min(8, 8192 >> cl)), cl
     rng = np.random.default_rng(5)
+    first = np.zeros(ncls, np.uint32)
+    c_cl, e0, e1 = np.zeros(1, np.int32), np.zeros(1, np.uint32), np.zeros(1, np.uint32)
     for trial in range(40):
-        counts = [int(c) for c in rng.integers(0, 30, 32) * (rng.random(32) < 0.4)]
-        first, acc = {}, 0
-        for cl in range(31, -1, -1):
-            first[cl] = acc
-            acc += (counts[cl] + chunk(cl) - 1) // chunk(cl)
-        total = acc
+        counts = (rng.integers(0, 30, ncls) * (rng.random(ncls) < 0.4)).astype(np.uint32)
+        total = int(rules.rules_ticket_offsets(counts.ctypes.data, first.ctypes.data))
+        assert total == sum(-(-int(counts[c]) // max(1, min(8, 8192 >> c))) for c in range(ncls))
         grid = int(rng.choice([1, 5, 32, 100, 1280]))
         lanes = min(32, grid)
         seen = []
-        for lane in range(lanes):
-            k = 0
-            while True:
-                t = k * lanes + lane
-                k += 1
-                if t >= total:
-                    break
-                cl = 31
-                while cl > 0 and t >= first[cl] + (counts[cl] + chunk(cl) - 1) // chunk(cl):
-                    cl -= 1
-                e0 = (t - first[cl]) * chunk(cl)
-                seen += [(cl, e) for e in range(e0, min(e0 + chunk(cl), counts[cl]))]
-        assert sorted(seen) == sorted((cl, e) for cl in range(32) for e in range(counts[cl])), trial
+        last_cl = ncls
+        for t in range(total):
+            rules.rules_ticket_range(t, counts.ctypes.data, first.ctypes.data, c_cl.ctypes.data, e0.ctypes.data,
+                                     e1.ctypes.data)
+            assert int(c_cl[0]) <= last_cl     # largest classes first
+            last_cl = int(c_cl[0])
+            assert e0[0] < e1[0] <= counts[c_cl[0]]
+            seen += [(int(c_cl[0]), e) for e in range(int(e0[0]), int(e1[0]))]
+        # every ticket index below total is claimed by exactly one lane counter
+        claimed = sorted(k * lanes + ln for ln in range(lanes) for k in range(total) if k * lanes + ln < total)
+        assert claimed == list(range(total))
+        assert sorted(seen) == sorted((cl, e) for cl in range(ncls) for e in range(int(counts[cl]))), trial
 
 
 def test_staged_ring_indexing_counts_every_pair_once():
-    # host copy of the staged accumulation's ring walk (rows staged once per
+    # a model of the staged accumulation's ring walk (it lives inside the
+    # kernel, not in a host-callable rule; the GPU parity tests of volumes and
+    # longer offsets cover the kernel itself) (rows staged once per
     # chunk into ring_rows x W bytes, neighbours read at slot + dz*H + dy,
     # offsets flipped forward) against brute force, over tile partitions
     def fwd(o):

@@ -6,12 +6,14 @@ error measure in gpu_util).
 """
 from __future__ import annotations
 
+import os
 import sys
 
 import numpy as np
 import pytest
 
-from gpu_util import NAMES, device_images, feature_errors, oracle_rois, scales, worst
+from gpu_util import (NAMES, device_images, feature_errors, oracle_rois, record, scales,
+                      scales_from_magnitudes, worst)
 
 pytestmark = pytest.mark.gpu
 
@@ -65,14 +67,23 @@ def _oracle_table(oracle, w, offs, rows=None):
     return np.array(out), Ps
 
 
+def _check_scaled(got, want, M, tol, tag):
+    """got, want: (n, blocks, 30); M: (n, blocks, 30) error floors."""
+    assert got.shape == want.shape, (got.shape, want.shape)
+    if len(want) == 0:
+        return
+    errs = feature_errors(got, want, M)
+    record(tag, errs, got, want, len(want), tol)
+    e, name, idx = worst(errs)
+    say(f"  {tag}: {len(want)} ROIs, max error {e:.3e} ({name} at {idx})")
+    assert e <= tol, (tag, name, idx, got[idx[0], idx[1]], want[idx[0], idx[1]])
+
+
 def _check_features(got, want, Ps, tol, tag):
     assert got.shape == want.shape, (got.shape, want.shape)
-    errs = np.stack([feature_errors(got[i], want[i], scales(Ps[i])) for i in range(len(Ps))]) if len(Ps) else None
-    if errs is None:
+    if len(Ps) == 0:
         return
-    e, name, idx = worst(errs)
-    say(f"  {tag}: {len(Ps)} ROIs, max error {e:.3e} ({name} at {idx})")
-    assert e <= tol, (tag, name, idx, got[idx[0], idx[1]], want[idx[0], idx[1]])
+    _check_scaled(got, want, np.stack([scales(P) for P in Ps]), tol, tag)
 
 
 # ------------------------------------------------------------------ C1
@@ -148,8 +159,6 @@ def _triangle(P):
 def test_glcm_counts_exact(env, workloads, oracle_mod, name, use_bins):
     nyx, ctx, dev = env
     w = workloads(name)
-    if name == "c5_small" and use_bins:
-        pytest.skip("covered by the on-the-fly case")
     say(f"case {name} glcm_accumulate bins={use_bins}")
     imgs = device_images(w, dev)
     offs = _offsets(nyx, w)
@@ -217,62 +226,67 @@ def test_features_from_oracle_coo(env, workloads, oracle_mod, name, prec):
 
 
 # ------------------------------------------------------------------ batched path
-# (workload, accumulation mode, wavefront share: 0 none, n > 0 unsplit ROIs up to n voxels)
+# (workload, accumulation mode, privatised triangle copies: 0 automatic)
 MODE_CASES = ([(n, m, 0) for n in SMALL for m in ("auto", "dense-list", "dense-scan", "dense16-scan")
                if not (n == "c5_small" and m != "auto")] +
-              [(n, "auto", v) for n in SMALL for v in (1024, 65535)] + [("c3_small", "autotune", -1)])
+              [(n, m, c) for n in ("c2_small", "c3_small", "c4_small") for m in ("dense-scan", "dense16-scan")
+               for c in (2, 4)] + [("c3_small", "autotune", 0)])
 
 
-@pytest.mark.parametrize("name,mode,wave", MODE_CASES)
-def test_plan_batched_and_per_roi(env, workloads, oracle_mod, name, mode, wave):
+@pytest.mark.parametrize("name,mode,copies", MODE_CASES)
+def test_plan_batched_and_per_roi(env, workloads, oracle_mod, name, mode, copies):
     import torch
     nyx, ctx, dev = env
     w = workloads(name)
-    say(f"case {name} plan_execute + per_roi, mode {mode}, wave {wave}")
+    say(f"case {name} plan_execute + per_roi, mode {mode}, copies {copies}")
     imgs = device_images(w, dev)
     offs = _offsets(nyx, w)
     if mode == "autotune":
         plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32, autotune=True)
     else:
         try:
-            plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32, mode=mode, wave=wave)
+            plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32, mode=mode, copies=copies)
         except nyx.NyxError as e:
             if e.status == nyx.NYX_ERR_UNSUPPORTED:
-                pytest.skip(f"{mode} does not fit LDS for {name}")
+                pytest.skip(f"{mode} with {copies} copies does not fit LDS for {name}")
             raise
     desc = nyx.nyx_plan_describe(plan)
     say("  plan:", desc)
-    if wave == 0:
-        assert "wave_rois=0 " in desc
-    elif wave == 65535 and "wave_lds=0B" not in desc:
-        assert "wave_rois=0 " not in desc
+    if copies > 0:
+        assert f"copies={copies} " in desc
     t1 = nyx.new_table(plan, len(offs))
     t2 = nyx.new_table(plan, len(offs))
-    for _ in range(3):  # repeated graph replays with eager work in between
+    want, Ps = _oracle_table(oracle_mod, w, offs)
+    replays = []
+    for rep in range(3):
+        # every replay writes the whole table: it starts from NaN, so a row a
+        # replay leaves unwritten cannot pass as a copy of an earlier replay
+        t1.fill_(float("nan"))
         nyx.nyx_plan_execute(plan, t1)
-        torch.cuda.synchronize()
+        torch.cuda.synchronize()   # eager work between the replays
         nyx.nyx_plan_check(plan)
-        first = t1.clone()
+        replays.append(t1.cpu().numpy()[:plan.n_rois].copy())
+        _check_features(replays[-1], want, Ps, TOL_FP32, f"{name} batched")
     nyx.nyx_plan_execute_per_roi(plan, t2)
     torch.cuda.synchronize()
     nyx.nyx_plan_check(plan)
-    want, Ps = _oracle_table(oracle_mod, w, offs)
-    got = t1.cpu().numpy()[:plan.n_rois]
-    _check_features(got, want, Ps, TOL_FP32, f"{name} batched")
-    _check_features(t2.cpu().numpy()[:plan.n_rois], want, Ps, TOL_FP32, f"{name} per-roi")
-    assert np.allclose(first.cpu().numpy(), got, rtol=1e-6, atol=1e-6, equal_nan=True)
+    per_roi = t2.cpu().numpy()[:plan.n_rois]
+    _check_features(per_roi, want, Ps, TOL_FP32, f"{name} per-roi")
+    for rep in range(1, 3):
+        assert np.allclose(replays[0], replays[rep], rtol=1e-6, atol=1e-6, equal_nan=True), rep
     if "scan" in desc:
-        # ordered nonzero lists: replays and the per-ROI path agree bit for bit
-        assert np.array_equal(first.cpu().numpy(), got, equal_nan=True)
-        assert np.array_equal(t2.cpu().numpy()[:plan.n_rois], got, equal_nan=True)
+        # ordered nonzero lists: every replay and the per-ROI path agree with
+        # the first replay bit for bit
+        for rep in range(1, 3):
+            assert np.array_equal(replays[0], replays[rep], equal_nan=True), f"replay {rep}"
+        assert np.array_equal(replays[0], per_roi, equal_nan=True)
 
 
 # ------------------------------------------------------------------ edge cases
-def _run_extract(nyx, ctx, dev, I, L, ng, offs, prec=1, wave=-1):
-    import torch
+def _run_extract(nyx, ctx, dev, I, L, ng, offs, prec=1, copies=0):
     from types import SimpleNamespace
     w = SimpleNamespace(intensity=I[None], labels=L[None], n_images=1)
-    return nyx.nyx_extract_batch(ctx, device_images(w, dev), ng, offs, prec, wave=wave)
+    return nyx.nyx_extract_batch(ctx, device_images(w, dev), ng, offs, prec, copies=copies)
 
 
 def _oracle_direct(oracle, I, L, ng, offs):
@@ -295,10 +309,10 @@ EDGE = {
 }
 
 
-@pytest.mark.parametrize("wave", [65535, 0])
+@pytest.mark.parametrize("copies", [1, 2])
 @pytest.mark.parametrize("case", sorted(EDGE))
 @pytest.mark.parametrize("ng", [2, 8, 30, 100])
-def test_edge_cases(env, oracle_mod, case, ng, wave):
+def test_edge_cases(env, oracle_mod, case, ng, copies):
     import torch
     nyx, ctx, dev = env
     rng = np.random.default_rng(sum(map(ord, case)) % 1000 + ng)
@@ -307,8 +321,8 @@ def test_edge_cases(env, oracle_mod, case, ng, wave):
     L = np.ascontiguousarray(L, np.uint32)
     dims = 3 if I.shape[0] > 1 else 2
     offs = nyx.nyx_offsets_default(dims, 1)
-    say(f"case edge {case} ng={ng} wave={wave}")
-    rois, table = _run_extract(nyx, ctx, dev, I, L, ng, offs, wave=wave)
+    say(f"case edge {case} ng={ng} copies={copies}")
+    rois, table = _run_extract(nyx, ctx, dev, I, L, ng, offs, copies=copies)
     torch.cuda.synchronize()
     want, Ps = _oracle_direct(oracle_mod, I, L, ng, offs)
     assert rois.n_rois == len(Ps)
@@ -413,6 +427,82 @@ def test_full_size_sampled(env, workloads, oracle_mod, name):
     assert np.all(np.isfinite(tab[n >= 4][:, -1, 0]))
 
 
+# ------------------------------------------------------------------ full sizes (every row / giant ROI)
+def _host_threads() -> int:
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+
+@pytest.mark.timeout(600)
+def test_c3_full_table_every_roi(env, workloads, oracle_mod):
+    """The benchmark's configuration (64-image batch, autotuned plan, graph
+    replay) against the oracle on every ROI and every feature column."""
+    import torch
+    nyx, ctx, dev = env
+    w = workloads("c3_batch")
+    say("case c3_batch full table: autotuned plan + execute, every ROI against the oracle")
+    imgs = device_images(w, dev)
+    offs = _offsets(nyx, w)
+    plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32, autotune=True)
+    say("  plan:", nyx.nyx_plan_describe(plan))
+    table = nyx.new_table(plan, len(offs))
+    table.fill_(float("nan"))
+    nyx.nyx_plan_execute(plan, table)
+    torch.cuda.synchronize()
+    nyx.nyx_plan_check(plan)
+    got = table.cpu().numpy()[:plan.n_rois]
+    off = np.array(offs, np.int32)
+    threads = _host_threads()
+    wants, mags = [], []
+    for k in range(w.n_images):
+        _, t, mag = oracle_mod.extract(w.intensity[k], w.labels[k], w.n_bins, off, n_threads=threads,
+                                       want_shade_magnitude=True)
+        wants.append(t)
+        mags.append(mag)
+    want = np.concatenate(wants)
+    M = np.stack([scales_from_magnitudes(m) for m in np.concatenate(mags)])
+    assert got.shape == want.shape, (got.shape, want.shape)
+    _check_scaled(got, want, M, TOL_FP32, "c3_batch every ROI")
+
+
+@pytest.mark.timeout(600)
+def test_c5_full_counts_exact(env, workloads, oracle_mod):
+    """64-bit counts of the 1024-level stress tile at full size: the giant
+    ROI (90 % of the tile) and a sample of the small ROIs, bit for bit."""
+    nyx, ctx, dev = env
+    w = workloads("c5_stress")
+    say("case c5_stress full size: glcm_accumulate, giant ROI + sampled small ROIs")
+    imgs = device_images(w, dev)
+    offs = _offsets(nyx, w)
+    rois, _ = nyx.nyx_bin_rois(ctx, imgs, w.n_bins)
+    g = nyx.nyx_glcm_accumulate(ctx, imgs, rois, w.n_bins, offs)
+    ro = oracle_rois(oracle_mod, w)
+    assert g.n_rois == len(ro)
+    keys = g.keys.cpu().numpy().view(np.uint64)
+    cnt = g.counts.cpu().numpy().view(np.uint64)
+    assert np.all(keys[1:] > keys[:-1]), "COO keys not strictly sorted"
+    roi = (keys >> np.uint64(38)).astype(np.int64)
+    n = np.array([st["count"][r] for _, r, st in ro])
+    giant = int(np.argmax(n))
+    rng = np.random.default_rng(11)
+    sample = sorted({giant, 0, len(ro) - 1, *rng.choice(len(ro), size=40, replace=False).tolist()})
+    start = np.searchsorted(roi, np.arange(len(ro) + 1))
+    for gi in sample:
+        k, r, st = ro[gi]
+        P = oracle_mod.glcm_roi(w.intensity[k], w.labels[k], st["label"][r], st["vmin"][r], st["vmax"][r],
+                                st["bbox"][r], w.n_bins, np.array(offs, np.int32))
+        U = _triangle(P)
+        kk, cc = keys[start[gi]:start[gi + 1]], cnt[start[gi]:start[gi + 1]]
+        d = ((kk >> np.uint64(32)) & np.uint64(63)).astype(np.int64)
+        i = ((kk >> np.uint64(16)) & np.uint64(0xFFFF)).astype(np.int64)
+        j = (kk & np.uint64(0xFFFF)).astype(np.int64)
+        assert len(kk) == np.count_nonzero(U), (gi, len(kk), np.count_nonzero(U))
+        assert np.array_equal(U[d, i, j], cc), gi
+        if gi == giant:
+            say(f"  giant ROI {gi}: {int(n[gi])} voxels, {len(kk)} nonzero cells, "
+                f"largest count {int(cc.max())}, bit-exact")
+    say(f"  {len(sample)} ROIs bit-exact")
+
+
 # ------------------------------------------------------------------ merged matrices
 # NYX_AGG_MERGED: the features of the sum of the offsets' matrices, one block
 # per row, through the one-shot call, the plan and the per-ROI launches.
@@ -507,3 +597,20 @@ def test_merged_other_offsets(env, oracle_mod, offs, shape):
         want = oracle_mod.features_roi_merged(P)
         e = feature_errors(got[r], want, scales(P.sum(axis=0, dtype=np.uint64)[None])[:1])
         assert np.max(e) <= TOL_FP64, (r, NAMES[int(np.argmax(e[0]))], float(np.max(e)))
+
+
+def test_glcm_features_checks_roi_table(env, workloads):
+    # the ROI table passed with a COO list must describe as many ROIs
+    nyx, ctx, dev = env
+    w = workloads("c2_small")
+    imgs = device_images(w, dev)
+    offs = _offsets(nyx, w)
+    rois, _ = nyx.nyx_bin_rois(ctx, imgs, w.n_bins)
+    g = nyx.nyx_glcm_accumulate(ctx, imgs, rois, w.n_bins, offs)
+    t = nyx.nyx_glcm_features(ctx, g, nyx.NYX_FP32, rois=rois)
+    assert t.shape[0] == rois.n_rois
+    other = nyx.RoiTable(rois.n_rois + 1, dev)
+    other.n.value = rois.n_rois + 1
+    with pytest.raises(nyx.NyxError) as e:
+        nyx.nyx_glcm_features(ctx, g, nyx.NYX_FP32, rois=other)
+    assert e.value.status == nyx.NYX_ERR_INVALID

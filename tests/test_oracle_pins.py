@@ -447,3 +447,59 @@ def test_merged_scale_invariance(oracle_mod):
         assert np.array_equal(two.sum(axis=0), 2 * one[0])
         np.testing.assert_allclose(oracle_mod.features_roi_merged(two)[0], oracle_mod.features_roi(one)[0],
                                    rtol=1e-12, atol=1e-13)
+
+
+# ------------------------------------------------------------------ sanitizers
+def test_oracle_under_address_and_ub_sanitizers(tmp_path):
+    """The oracle's C entry points on small seeded inputs, built with
+    AddressSanitizer and UndefinedBehaviorSanitizer (host code only)."""
+    import os
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    here = os.path.dirname(os.path.abspath(__file__))
+    root = os.path.dirname(here)
+    exe = str(tmp_path / "oracle_sanitized")
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                           "-fno-sanitize-recover=undefined", "-o", exe, os.path.join(here, "oracle_sanitize_main.c"),
+                           os.path.join(root, "oracle", "oracle.c"), "-lm"])
+    # the ASan runtime is linked into the driver; a library the environment
+    # preloads ahead of it is accepted rather than refused
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120, env=env)
+    assert r.returncode == 0, (r.returncode, r.stdout[-2000:], r.stderr[-4000:])
+    assert "oracle sanitized run ok" in r.stdout
+
+
+# ------------------------------------------------------------------ error-measure scale
+def test_shade_magnitude_definition(oracle_mod):
+    """sum |i + j - mux - muy|^3 p, the cluster-shade error scale, against an
+    independent numpy evaluation on random (also non-symmetric) matrices, the
+    checkerboard closed form, and the bound |CLUSHADE| <= magnitude."""
+    rng = np.random.default_rng(17)
+    for ng in (2, 5, 16):
+        for sym in (True, False):
+            P = rng.integers(0, 50, (ng, ng)).astype(np.uint64)
+            if sym:
+                P = P + P.T
+            p = P.astype(np.float64) / P.sum()
+            lv = np.arange(1, ng + 1)
+            mux, muy = (p.sum(axis=1) * lv).sum(), (p.sum(axis=0) * lv).sum()
+            want = (np.abs(lv[:, None] + lv[None, :] - mux - muy) ** 3 * p).sum()
+            got = oracle_mod.shade_magnitude(P)
+            assert got == pytest.approx(want, rel=1e-12)
+            if sym:
+                assert abs(oracle_mod.features(P)[3]) <= got * (1 + 1e-12)
+    # checkerboard at 0 degrees: both cells sit on i + j = 1 + Ng = mux + muy
+    P = np.zeros((8, 8), np.uint64)
+    P[0, 7] = P[7, 0] = 56
+    assert oracle_mod.shade_magnitude(P) == 0.0
+    # two diagonal cells (1,1) weight q, (Ng,Ng) weight 1-q: mu = q + Ng (1 - q)
+    P = np.zeros((8, 8), np.uint64)
+    P[0, 0], P[7, 7] = 30, 10
+    q, mu = 0.75, 0.75 + 8 * 0.25
+    assert oracle_mod.shade_magnitude(P) == pytest.approx(q * abs(2 - 2 * mu) ** 3 + (1 - q) * abs(16 - 2 * mu) ** 3,
+                                                          rel=1e-14)
+    assert np.isnan(oracle_mod.shade_magnitude(np.zeros((4, 4), np.uint64)))
