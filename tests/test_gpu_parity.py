@@ -614,3 +614,27 @@ def test_glcm_features_checks_roi_table(env, workloads):
     with pytest.raises(nyx.NyxError) as e:
         nyx.nyx_glcm_features(ctx, g, nyx.NYX_FP32, rois=other)
     assert e.value.status == nyx.NYX_ERR_INVALID
+
+
+def test_plan_profile_phases(env, workloads):
+    """nyx_plan_profile times every phase of one eager step and leaves the same
+    table as a graph replay (scan mode: bit-identical)."""
+    import torch
+    nyx, ctx, dev = env
+    w = workloads("c3_small")
+    imgs = device_images(w, dev)
+    offs = _offsets(nyx, w)
+    plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, nyx.NYX_FP32, mode="dense16-scan")
+    t1 = nyx.new_table(plan, len(offs))
+    t2 = torch.full_like(t1, float("nan"))
+    nyx.nyx_plan_execute(plan, t1)
+    say("profile: c3_small, 16-bit scan mode")
+    ms = nyx.nyx_plan_profile(plan, t2)
+    torch.cuda.synchronize()
+    nyx.nyx_plan_check(plan)
+    assert tuple(ms) == nyx.PHASES
+    assert all(v >= 0.0 for v in ms.values()), ms
+    assert ms["batch"] > 0.0 and ms["scan"] > 0.0, ms
+    a, b = t1.cpu().numpy(), t2.cpu().numpy()
+    assert ((a == b) | (np.isnan(a) & np.isnan(b))).all()
+
