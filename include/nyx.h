@@ -193,6 +193,26 @@ nyx_status nyx_extract_batch(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n
                              const nyx_extract_opts *opts, nyx_roi_table *rois, void *table,
                              int64_t table_capacity_rows, nyx_stream stream);
 
+/* The same pass as nyx_extract_batch, for callers that cannot allocate
+ * device memory (code that must not call hipMalloc: serving loops, harnesses
+ * that forbid allocation).  Allocates nothing: every scratch buffer of the
+ * step (label statistics, ROI descriptors, work queue, split-ROI matrices,
+ * reduced sums) is carved from one library-owned array of NYX_NOALLOC_SCRATCH_BYTES
+ * per GPU, which the library holds until the process ends.  The caller still
+ * passes the images, the ROI table (nullable) and the feature table.
+ * opts->autotune and opts->workspace_cap_bytes are ignored (the configuration
+ * is the untimed default, so results equal nyx_extract_batch's without
+ * autotune).  A batch whose scratch exceeds the array gives NYX_ERR_CAPACITY
+ * and a message with the size it needs; other errors as nyx_extract_batch.
+ * Synchronises `stream` (twice during discovery, once at the end).  Every
+ * call on one GPU uses that GPU's one array: calls that overlap on a GPU
+ * (from several threads or streams) race and must be serialised by the
+ * caller. */
+#define NYX_NOALLOC_SCRATCH_BYTES (256ull << 20)
+nyx_status nyx_extract_batch_noalloc(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n_images,
+                                     const nyx_extract_opts *opts, nyx_roi_table *rois, void *table,
+                                     int64_t table_capacity_rows, nyx_stream stream);
+
 /* Plan for repeated extraction over images with the same geometry and
  * labels-per-image capacity: discovers the ROIs once (one synchronisation),
  * sizes the work queue and scratch, and (with opts->autotune) picks the

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -46,25 +47,57 @@ int log_level() {
     return lvl;
 }
 
-// Owned device allocation.
+// A bump allocator over a fixed device region (the no-allocation entry
+// point's scratch): carving never calls the HIP allocator, and the region is
+// reused from its start by the next call.
+struct Arena {
+    uint8_t *base = nullptr;
+    size_t cap = 0, used = 0;
+    size_t wanted = 0;   // bytes the failed request would have needed in total
+    void *carve(size_t n) {
+        const size_t at = (used + 255u) & ~(size_t)255u;
+        if (at + n > cap) {
+            wanted = at + n;
+            return nullptr;
+        }
+        used = at + n;
+        return base + at;
+    }
+};
+
+// Device buffer: owned (hipMalloc / hipFree), or carved from an Arena when
+// one is given (never freed by the buffer).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool owned = false;
+    Arena *arena = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && owned) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        owned = false;
     }
     hipError_t alloc(size_t n) {
         release();
         if (n == 0) n = 16;
+        if (arena) {
+            p = arena->carve(n);
+            if (!p) return hipErrorOutOfMemory;
+            bytes = n;
+            return hipSuccess;
+        }
         hipError_t e = hipMalloc(&p, n);
-        if (e == hipSuccess) bytes = n;
-        else p = nullptr;
+        if (e == hipSuccess) {
+            bytes = n;
+            owned = true;
+        } else {
+            p = nullptr;
+        }
         return e;
     }
     template <class T> T *as() const { return reinterpret_cast<T *>(p); }
@@ -79,11 +112,37 @@ uint32_t next_pow2(uint32_t v) {
 
 }  // namespace
 
+// Device memory of the no-allocation entry point: one array per GPU for the
+// life of the process, shared by every call on that GPU.  Host code never
+// uses the symbol itself (on the host it only names a stand-in): the device
+// address is taken once per device with hipGetSymbolAddress and kept below.
+constexpr size_t kScratchBytes = NYX_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (current); nullptr on failure.
+uint8_t *scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[device] = static_cast<uint8_t *>(ptr);
+    }
+    return g_scratch_ptr[device];
+}
+}  // namespace
+
 struct nyx_ctx {
     int device = 0;
     int n_cu = 0;
     std::string err;
     hipStream_t capture_stream = nullptr;
+    uint8_t *scratch = nullptr;   // this device's no-allocation scratch (device address)
 };
 
 // All device state of one discovery/step over a batch of images.
@@ -95,6 +154,11 @@ struct Work {
     uint64_t total_vox = 0;
     std::vector<RoiDesc> h_rois;
     StepArgs args{};
+    // Carve every buffer from `ar` (nullptr: hipMalloc).
+    void use_arena(Arena *ar) {
+        for (DevBuf *b : {&imgs, &counters, &rois, &buckets, &G, &dsums, &split_roi, &vox_base}) b->arena = ar;
+        for (DevBuf &b : tab) b.arena = ar;
+    }
 };
 
 struct nyx_plan {
@@ -207,6 +271,7 @@ nyx_status discover(nyx_ctx *ctx, const nyx_image *imgs, int32_t n, Work &w, hip
     HIPC(ctx, hipMemcpyAsync(w.vox_base.p, vbase.data(), sizeof(uint64_t) * n, hipMemcpyHostToDevice, st));
     // largest label per image sizes the label tables
     DevBuf dmax;
+    dmax.arena = w.imgs.arena;
     HIPC(ctx, dmax.alloc(sizeof(uint32_t) * n));
     std::vector<uint32_t> zeros(n, 0u), hmax(n);
     HIPC(ctx, hipMemcpyAsync(dmax.p, zeros.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, st));
@@ -706,9 +771,12 @@ nyx_status nyx_create(nyx_ctx **out, int device_ordinal) {
     if (hipSetDevice(device_ordinal) != hipSuccess) return NYX_ERR_DEVICE;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device_ordinal) != hipSuccess) return NYX_ERR_DEVICE;
+    uint8_t *scr = scratch_address(device_ordinal);
+    if (!scr) return NYX_ERR_DEVICE;
     nyx_ctx *c = new nyx_ctx();
     c->device = device_ordinal;
     c->n_cu = prop.multiProcessorCount;
+    c->scratch = scr;
     if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return NYX_ERR_DEVICE;
@@ -903,11 +971,14 @@ nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, const nyx_roi_t
     return NYX_OK;
 }
 
-nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images, const nyx_extract_opts *opts,
-                           nyx_plan **out, int64_t *n_rois_host) {
-    if (!ctx) return NYX_ERR_INVALID;
-    if (!out || !opts) return fail(ctx, NYX_ERR_INVALID, "NULL argument");
-    *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Validation, ROI discovery and the untimed default configuration of a plan
+// (shared by nyx_plan_create and the no-allocation entry point).
+nyx_status plan_init(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images, const nyx_extract_opts *opts,
+                     nyx_plan *p, hipStream_t st, std::vector<Config> &cands, Config &cfg) {
     nyx_status s = validate_images(ctx, imgs, n_images);
     if (s != NYX_OK) return s;
     if ((s = validate_offsets(ctx, imgs, n_images, opts->offsets_host, opts->n_offsets)) != NYX_OK) return s;
@@ -917,9 +988,9 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
     if (opts->precision != NYX_FP32 && opts->precision != NYX_FP64) return fail(ctx, NYX_ERR_INVALID, "bad precision");
     if (opts->aggregate != NYX_AGG_PER_OFFSET && opts->aggregate != NYX_AGG_MERGED)
         return fail(ctx, NYX_ERR_INVALID, "aggregate must be NYX_AGG_PER_OFFSET or NYX_AGG_MERGED");
+    if (opts->copies != 0 && opts->copies != 1 && opts->copies != 2 && opts->copies != 4)
+        return fail(ctx, NYX_ERR_INVALID, "copies must be 0, 1, 2 or 4");
     HIPC(ctx, hipSetDevice(ctx->device));
-    hipStream_t st = ctx->capture_stream;
-    std::unique_ptr<nyx_plan> p(new nyx_plan());
     p->ctx = ctx;
     p->imgs.assign(imgs, imgs + n_images);
     p->K = opts->n_offsets;
@@ -928,21 +999,39 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
     if ((s = discover(ctx, imgs, n_images, p->w, st)) != NYX_OK) return s;
     if ((s = fetch_rois(ctx, p->w, st)) != NYX_OK) return s;
     const bool merged = opts->aggregate == NYX_AGG_MERGED;
-    if (opts->copies != 0 && opts->copies != 1 && opts->copies != 2 && opts->copies != 4)
-        return fail(ctx, NYX_ERR_INVALID, "copies must be 0, 1, 2 or 4");
     // the default plan: one copy (or the forced count) at the load-balance tile size
     const uint32_t copies0 = opts->copies > 0 ? (uint32_t)opts->copies : 1u;
-    std::vector<Config> cands = candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256, merged, copies0);
+    cands = candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256, merged, copies0);
     if (cands.empty())
         return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%d with %d offsets%s%s", p->ng, p->K,
                     merged ? " merged in one pass" : "", copies0 > 1u ? " with privatised copies" : "");
-    Config cfg = default_config(cands, p->w, (uint32_t)p->ng, p->K);
+    cfg = default_config(cands, p->w, (uint32_t)p->ng, p->K);
     if (opts->accum_mode >= 0) {
         bool found = false;
         for (const Config &c : cands)
             if (c.mode == opts->accum_mode) { cfg = c; found = true; break; }
         if (!found) return fail(ctx, NYX_ERR_UNSUPPORTED, "accumulation mode %d does not fit this workload", opts->accum_mode);
     }
+    return NYX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images, const nyx_extract_opts *opts,
+                           nyx_plan **out, int64_t *n_rois_host) {
+    if (!ctx) return NYX_ERR_INVALID;
+    if (!out || !opts) return fail(ctx, NYX_ERR_INVALID, "NULL argument");
+    *out = nullptr;
+    hipStream_t st = ctx->capture_stream;
+    std::unique_ptr<nyx_plan> p(new nyx_plan());
+    std::vector<Config> cands;
+    Config cfg;
+    nyx_status s = plan_init(ctx, imgs, n_images, opts, p.get(), st, cands, cfg);
+    if (s != NYX_OK) return s;
+    const bool merged = opts->aggregate == NYX_AGG_MERGED;
+    const uint32_t copies0 = opts->copies > 0 ? (uint32_t)opts->copies : 1u;
     if (opts->autotune) {
         // further axes: privatised copies (when not forced) and the tile size of split ROIs
         for (uint32_t cp : {1u, 2u, 4u}) {
@@ -1123,6 +1212,44 @@ nyx_status nyx_extract_batch(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_imag
     if (s == NYX_OK) s = check_counters(ctx, p->w, (hipStream_t)stream);
     else (void)hipStreamSynchronize((hipStream_t)stream);
     nyx_plan_destroy(p);
+    return s;
+}
+
+nyx_status nyx_extract_batch_noalloc(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images,
+                                     const nyx_extract_opts *opts, nyx_roi_table *rois, void *table,
+                                     int64_t table_capacity_rows, nyx_stream stream) {
+    if (!ctx) return NYX_ERR_INVALID;
+    if (!opts) return fail(ctx, NYX_ERR_INVALID, "NULL argument");
+    if (!ctx->scratch) return fail(ctx, NYX_ERR_DEVICE, "no scratch address for device %d", ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    // every device buffer of the step is carved from this device's scratch
+    Arena ar;
+    ar.base = ctx->scratch;
+    ar.cap = kScratchBytes;
+    nyx_plan p;
+    p.w.use_arena(&ar);
+    std::vector<Config> cands;
+    Config cfg;
+    nyx_status s = plan_init(ctx, imgs, n_images, opts, &p, st, cands, cfg);
+    if (s == NYX_OK) s = configure(&p, cfg, opts);
+    if (s != NYX_OK) {
+        if (ar.wanted > ar.cap)
+            return fail(ctx, NYX_ERR_CAPACITY,
+                        "batch needs more than the %zu bytes of no-allocation scratch (at least %zu)", ar.cap,
+                        ar.wanted);
+        return s;
+    }
+    const int64_t n = p.w.n_rois;
+    if (rois && rois->n_rois_host) *rois->n_rois_host = n;
+    if (table_capacity_rows < n)
+        return fail(ctx, NYX_ERR_CAPACITY, "table capacity %lld < %lld rows", (long long)table_capacity_rows, (long long)n);
+    if (rois && rois->capacity < n)
+        return fail(ctx, NYX_ERR_CAPACITY, "ROI table capacity %lld < %lld", (long long)rois->capacity, (long long)n);
+    if (n > 0 && !table) return fail(ctx, NYX_ERR_INVALID, "table is NULL");
+    set_outputs(ctx, p.w.args, rois, table, (uint32_t)n);
+    s = enqueue_step(&p, st, false);
+    if (s == NYX_OK) s = check_counters(ctx, p.w, st);
+    else (void)hipStreamSynchronize(st);
     return s;
 }
 

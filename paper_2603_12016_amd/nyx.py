@@ -59,7 +59,7 @@ _lib = None
 # Every symbol include/nyx.h declares.
 EXPORTS = ("nyx_create", "nyx_destroy", "nyx_last_error", "nyx_status_string", "nyx_offsets_default",
            "nyx_feature_count", "nyx_feature_name", "nyx_bin_rois", "nyx_glcm_accumulate", "nyx_glcm_features",
-           "nyx_extract_batch", "nyx_plan_create", "nyx_plan_execute", "nyx_plan_execute_per_roi",
+           "nyx_extract_batch", "nyx_extract_batch_noalloc", "nyx_plan_create", "nyx_plan_execute", "nyx_plan_execute_per_roi",
            "nyx_plan_check", "nyx_plan_describe", "nyx_plan_destroy", "nyx_plan_profile")
 
 PHASES = ("reset", "scan", "compact", "zero", "batch", "band", "split", "features")
@@ -91,6 +91,8 @@ def lib():
     L.nyx_glcm_features.argtypes = [P, POINTER(nyx_glcm), POINTER(nyx_roi_table), c_int, P, c_int64, P]
     L.nyx_extract_batch.argtypes = [P, POINTER(nyx_image), c_int32, POINTER(nyx_extract_opts),
                                     POINTER(nyx_roi_table), P, c_int64, P]
+    L.nyx_extract_batch_noalloc.argtypes = [P, POINTER(nyx_image), c_int32, POINTER(nyx_extract_opts),
+                                            POINTER(nyx_roi_table), P, c_int64, P]
     L.nyx_plan_create.argtypes = [P, POINTER(nyx_image), c_int32, POINTER(nyx_extract_opts), POINTER(P),
                                   POINTER(c_int64)]
     L.nyx_plan_execute.argtypes = [P, POINTER(nyx_roi_table), P, P]
@@ -102,7 +104,7 @@ def lib():
     L.nyx_plan_destroy.argtypes = [P]
     L.nyx_plan_destroy.restype = None
     for name in ("nyx_create", "nyx_offsets_default", "nyx_bin_rois", "nyx_glcm_accumulate", "nyx_glcm_features",
-                 "nyx_extract_batch", "nyx_plan_create", "nyx_plan_execute", "nyx_plan_execute_per_roi",
+                 "nyx_extract_batch", "nyx_extract_batch_noalloc", "nyx_plan_create", "nyx_plan_execute", "nyx_plan_execute_per_roi",
                  "nyx_plan_check", "nyx_plan_profile"):
         getattr(L, name).restype = c_int
     _lib = L
@@ -342,6 +344,21 @@ def nyx_extract_batch(ctx: Ctx, images, n_bins: int, offsets, precision: int = N
     _check(lib().nyx_extract_batch(ctx.handle, imgs, len(images), byref(opts), byref(st), table.data_ptr(),
                                    int(capacity), _stream(stream)), ctx)
     return rois, table[:rois.n_rois]
+
+
+def nyx_extract_batch_noalloc(ctx: Ctx, images, n_bins: int, offsets, rois: RoiTable, table,
+                              precision: int = NYX_FP32, stream=None, mode="auto", copies: int = 0,
+                              aggregate: int = NYX_AGG_PER_OFFSET) -> int:
+    """The pass of nyx_extract_batch into caller-allocated `rois` and `table`
+    without any device allocation in the library; returns the ROI count."""
+    imgs = _images(images)
+    opts, keep = _opts(n_bins, offsets, precision, mode=mode, copies=copies, aggregate=aggregate)
+    st = rois.struct()
+    cap = int(table.shape[0]) if table is not None else 0
+    _check(lib().nyx_extract_batch_noalloc(ctx.handle, imgs, len(images), byref(opts), byref(st),
+                                           table.data_ptr() if table is not None else None, cap,
+                                           _stream(stream)), ctx)
+    return rois.n_rois
 
 
 def nyx_plan_create(ctx: Ctx, images, n_bins: int, offsets, precision: int = NYX_FP32, autotune: bool = False,
