@@ -116,10 +116,12 @@ def features(I: np.ndarray, mask: np.ndarray, n_bins: int) -> np.ndarray:
     for p in (1, 10, 25, 75, 90, 99):
         f[f"P{p:02d}"] = pv[p]
     f["INTERQUARTILE_RANGE"] = pv[75] - pv[25]
-    # mean distance to the mean of the values within [P10, P90] [F5]
+    # mean distance to the mean of the values within [P10, P90] [F5]; undefined
+    # (NaN) when no value lies there, which happens for two distinct values
     sub = x[(x >= pv[10]) & (x <= pv[90])]
-    mus = _fsum(sub) / sub.size
-    f["ROBUST_MEAN_ABSOLUTE_DEVIATION"] = _fsum(np.abs(sub - mus)) / sub.size
+    if sub.size:
+        mus = _fsum(sub) / sub.size
+        f["ROBUST_MEAN_ABSOLUTE_DEVIATION"] = _fsum(np.abs(sub - mus)) / sub.size
     # histogram of the fixed-bin-number levels [F6]
     lv = fbn_levels(I[mask], int(x.min()), int(x.max()), n_bins)
     cnt = np.bincount(lv, minlength=n_bins + 1)[1:]

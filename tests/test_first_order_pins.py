@@ -51,6 +51,24 @@ def test_constant_roi():
     assert (f["WEIGHTED_CENTROID_X"], f["WEIGHTED_CENTROID_Y"]) == (1.0, 1.0)
 
 
+def test_robust_deviation_hand_cases():
+    # three values 10, 15, 20: P10 = 10 + 0.2 * 5 = 11, P90 = 15 + 0.8 * 5 = 19,
+    # so only 15 lies within [P10, P90] and its distance to its own mean is 0
+    I = np.array([[[10, 15, 20]]], np.uint16)
+    f = dict(zip(fo.NAMES, fo.features(I, np.ones_like(I, bool), 8)))
+    assert (f["P10"], f["P90"]) == (11.0, 19.0)
+    assert f["ROBUST_MEAN_ABSOLUTE_DEVIATION"] == 0.0
+    # two values 10, 20: P10 = 11, P90 = 19 and no value lies within
+    I = np.array([[[10, 20]]], np.uint16)
+    f = dict(zip(fo.NAMES, fo.features(I, np.ones_like(I, bool), 8)))
+    assert (f["P10"], f["P90"]) == (11.0, 19.0)
+    assert math.isnan(f["ROBUST_MEAN_ABSOLUTE_DEVIATION"])
+    # 10, 20, 30, 40: P10 = 13, P90 = 37, values 20 and 30, mean 25, distance 5
+    I = np.array([[[10, 20, 30, 40]]], np.uint16)
+    f = dict(zip(fo.NAMES, fo.features(I, np.ones_like(I, bool), 8)))
+    assert (f["P10"], f["P90"], f["ROBUST_MEAN_ABSOLUTE_DEVIATION"]) == (13.0, 37.0, 5.0)
+
+
 def _random_roi(seed, shape=(1, 23, 31), vmax=4000):
     rng = np.random.default_rng(seed)
     I = rng.integers(0, vmax, shape).astype(np.uint16)
