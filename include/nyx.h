@@ -188,6 +188,39 @@ nyx_status nyx_glcm_accumulate(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t
 nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, const nyx_roi_table *rois, nyx_precision prec,
                              void *table, int64_t table_capacity_rows, nyx_stream stream);
 
+/* First-order intensity features of every ROI (the intensity group of
+ * Supplementary Table S1, rows with the NY mark; Table S5 for volumes): the
+ * statistics of each ROI's voxel values, in the column order of
+ * nyx_intensity_feature_name(0..36): MEAN, MIN, MAX, RANGE,
+ * INTEGRATED_INTENSITY, ENERGY (sum of squares), RMS, VARIANCE and STDDEV
+ * (unbiased; 0 for one voxel), STANDARD_ERROR, SKEWNESS, KURTOSIS,
+ * HYPERSKEWNESS, HYPERFLATNESS (biased central moments m3..m6 over
+ * m2^(k/2); 0 for a constant ROI), MEAN_ABSOLUTE_DEVIATION, MEDIAN,
+ * MEDIAN_ABSOLUTE_DEVIATION (mean distance to the median), P01, P10, P25,
+ * P75, P90, P99 (linear interpolation between the closest ranks,
+ * h = (n - 1) p / 100), INTERQUARTILE_RANGE, ROBUST_MEAN_ABSOLUTE_DEVIATION
+ * (values within [P10, P90] about their mean; NaN when none lies there),
+ * MODE (lowest fixed-bin-number level among the most frequent), ENTROPY
+ * (log2) and UNIFORMITY of the level histogram (levels as for the texture
+ * features, n_bins of them), UNIFORMITY_PIU (100 (1 - range / (max + min)),
+ * 100 when max + min = 0), WEIGHTED_CENTROID_X/Y/Z (image column, row,
+ * plane weighted by intensity; NaN when the intensities sum to 0), and the
+ * integrated intensity, min, max, mean and unbiased standard deviation of
+ * the edge voxels (ROI voxels with a face neighbour, 4 in a plane or 6 in a
+ * volume, outside the image or the ROI).  The cost is O(m) per ROI of m
+ * voxels for the moments and O(m, h) with h = n_bins for the histogram
+ * features (Materials and methods, "Feature Control and Tunability").
+ * table: n_rois rows of 37 values, float (NYX_FP32) or double (NYX_FP64);
+ * every value is computed in double from exact integer sums, the order
+ * statistics exactly.  rois (nullable) receives the ROI table.  n_bins in
+ * [2, 8191] (NYX_ERR_UNSUPPORTED above).  Synchronises the stream (ROI count
+ * and capacity checks). */
+int32_t nyx_intensity_feature_count(void);         /* 37 */
+const char *nyx_intensity_feature_name(int32_t f); /* NULL outside [0, 37) */
+nyx_status nyx_intensity_features(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n_images, int32_t n_bins,
+                                  nyx_precision prec, nyx_roi_table *rois, void *table,
+                                  int64_t table_capacity_rows, nyx_stream stream);
+
 /* Whole path in one call: plan, execute once, destroy the plan. */
 nyx_status nyx_extract_batch(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n_images,
                              const nyx_extract_opts *opts, nyx_roi_table *rois, void *table,

@@ -25,5 +25,7 @@ hipError_t launch_coo_emit(const StepArgs &a, uint32_t n_slots, const uint64_t *
                            uint64_t *vals, hipStream_t st);
 hipError_t launch_coo_features(const StepArgs &a, const uint64_t *keys, const uint64_t *vals, uint64_t nnz,
                                uint32_t n_rois, uint64_t *seg, DirSums *sums, hipStream_t st);
+hipError_t launch_intensity(const StepArgs &a, uint32_t grid, int fp64, void *table, uint32_t table_rows,
+                            hipStream_t st);
 
 }  // namespace nyx

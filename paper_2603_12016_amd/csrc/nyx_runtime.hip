@@ -32,6 +32,14 @@ const char *const kFeatureNames[kNumFeat] = {
     "DIS", "ENERGY", "ENTROPY", "HOM1", "HOM2", "IDM", "INFOMEAS1", "INFOMEAS2", "IDMN", "ID",
     "IDN", "IV", "JAVE", "JE", "JMAX", "SUMAVE", "SUMENT", "JVAR", "SUMVAR", "VARIANCE"};
 
+const char *const kIntensityNames[kNumIntensityFeat] = {
+    "MEAN", "MIN", "MAX", "RANGE", "INTEGRATED_INTENSITY", "ENERGY", "RMS", "VARIANCE", "STDDEV",
+    "STANDARD_ERROR", "SKEWNESS", "KURTOSIS", "HYPERSKEWNESS", "HYPERFLATNESS", "MEAN_ABSOLUTE_DEVIATION",
+    "MEDIAN", "MEDIAN_ABSOLUTE_DEVIATION", "P01", "P10", "P25", "P75", "P90", "P99", "INTERQUARTILE_RANGE",
+    "ROBUST_MEAN_ABSOLUTE_DEVIATION", "MODE", "ENTROPY", "UNIFORMITY", "UNIFORMITY_PIU", "WEIGHTED_CENTROID_X",
+    "WEIGHTED_CENTROID_Y", "WEIGHTED_CENTROID_Z", "EDGE_INTEGRATED_INTENSITY", "EDGE_MIN", "EDGE_MAX",
+    "EDGE_MEAN", "EDGE_STDDEV"};
+
 constexpr uint32_t kLdsBudget = 160u * 1024u;   // LDS per CU on gfx950
 constexpr uint32_t kRingMin = 2048u, kRingMax = 32768u;   // staged-accumulation level ring (bytes)
 constexpr uint32_t kMaxGroupsPerCu = 5u;                  // k_batch, single precision: 5 waves per SIMD
@@ -924,6 +932,44 @@ nyx_status nyx_glcm_accumulate(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_im
         }
     }
     return NYX_OK;
+}
+
+int32_t nyx_intensity_feature_count(void) { return kNumIntensityFeat; }
+
+const char *nyx_intensity_feature_name(int32_t f) {
+    return (f >= 0 && f < kNumIntensityFeat) ? kIntensityNames[f] : nullptr;
+}
+
+nyx_status nyx_intensity_features(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images, int32_t n_bins,
+                                  nyx_precision prec, nyx_roi_table *rois, void *table, int64_t table_capacity_rows,
+                                  nyx_stream stream) {
+    if (!ctx) return NYX_ERR_INVALID;
+    nyx_status s = validate_images(ctx, imgs, n_images);
+    if (s != NYX_OK) return s;
+    if (n_bins < 2 || n_bins > 65535) return fail(ctx, NYX_ERR_INVALID, "n_bins must be in [2, 65535]");
+    if ((s = validate_bins(ctx, n_bins)) != NYX_OK) return s;
+    if (prec != NYX_FP32 && prec != NYX_FP64) return fail(ctx, NYX_ERR_INVALID, "bad precision");
+    hipStream_t st = (hipStream_t)stream;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    Work w;
+    if ((s = discover(ctx, imgs, n_images, w, st)) != NYX_OK) return s;
+    const int64_t n = w.n_rois;
+    if (rois && rois->n_rois_host) *rois->n_rois_host = n;
+    if (rois && rois->capacity < n)
+        return fail(ctx, NYX_ERR_CAPACITY, "ROI table capacity %lld < %lld ROIs", (long long)rois->capacity, (long long)n);
+    if (table_capacity_rows < n)
+        return fail(ctx, NYX_ERR_CAPACITY, "table capacity %lld < %lld rows", (long long)table_capacity_rows, (long long)n);
+    if (n > 0 && !table) return fail(ctx, NYX_ERR_INVALID, "table is NULL");
+    StepArgs a = w.args;
+    a.ng = n_bins;
+    a.enqueue = 0;
+    set_outputs(ctx, a, rois, nullptr, 0);
+    HIPC(ctx, launch_reset(a, w.n_counters, st));
+    HIPC(ctx, launch_scan(a, st));
+    HIPC(ctx, launch_compact(a, 0u, 0u, st));
+    HIPC(ctx, launch_intensity(a, (uint32_t)n, prec == NYX_FP64, table,
+                               (uint32_t)std::min<int64_t>(table_capacity_rows, 0xFFFFFFFFll), st));
+    return check_counters(ctx, w, st);
 }
 
 nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, const nyx_roi_table *rois, nyx_precision prec,

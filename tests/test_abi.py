@@ -45,6 +45,13 @@ def test_feature_names_match_oracle(nyx, oracle_mod):
     assert nyx.nyx_feature_name(30) is None and nyx.nyx_feature_name(-1) is None
 
 
+def test_intensity_feature_names_match_oracle(nyx):
+    from oracle import first_order as fo
+    assert nyx.nyx_intensity_feature_count() == fo.NFO
+    assert tuple(nyx.nyx_intensity_feature_name(f) for f in range(fo.NFO)) == fo.NAMES
+    assert nyx.nyx_intensity_feature_name(fo.NFO) is None and nyx.nyx_intensity_feature_name(-1) is None
+
+
 @pytest.mark.parametrize("dims,dist", [(2, 1), (2, 3), (3, 1), (3, 2)])
 def test_default_offsets_match_oracle(nyx, oracle_mod, dims, dist):
     assert np.array_equal(np.array(nyx.nyx_offsets_default(dims, dist), np.int32),
