@@ -60,14 +60,14 @@ def _load():
     lib.oracle_bin_image.argtypes = [P, P, i64, i64, P, P, P, i32, P]
     lib.oracle_glcm_roi.restype = ctypes.c_int
     lib.oracle_glcm_roi.argtypes = [P, P, i64, i64, i64, u32, ctypes.c_uint16,
-                                    ctypes.c_uint16, P, i32, P, i32, P]
+                                    ctypes.c_uint16, P, i32, P, i32, i32, P]
     lib.oracle_features.restype = None
     lib.oracle_features.argtypes = [P, i32, P]
     lib.oracle_features_roi.restype = None
     lib.oracle_features_roi.argtypes = [P, i32, i32, P]
     lib.oracle_extract.restype = ctypes.c_int
     lib.oracle_extract.argtypes = [P, P, i64, i64, i64, i32, P, i32, i64,
-                                   P, P, P, P, P, P, i32]
+                                   P, P, P, P, P, P, i32, i32]
     lib.oracle_shade_magnitude.restype = ctypes.c_double
     lib.oracle_shade_magnitude.argtypes = [P, i32]
     lib.oracle_default_offsets.restype = i32
@@ -150,8 +150,9 @@ def bin_image(intensity: np.ndarray, labels: np.ndarray, n_bins: int, stats: dic
 
 
 def glcm_roi(intensity, labels, label: int, vmin: int, vmax: int, bbox, n_bins: int,
-             offsets: np.ndarray) -> np.ndarray:
-    """(K, Ng, Ng) uint64 symmetric co-occurrence matrices of one ROI."""
+             offsets: np.ndarray, symmetric: bool = True) -> np.ndarray:
+    """(K, Ng, Ng) uint64 co-occurrence matrices of one ROI: symmetric
+    P = C + C^T [A6], or the ordered counts C when symmetric is False [A16]."""
     lib = _load()
     I = _img3(intensity, np.uint16)
     L = _img3(labels, np.uint32)
@@ -160,12 +161,12 @@ def glcm_roi(intensity, labels, label: int, vmin: int, vmax: int, bbox, n_bins: 
     bb = np.ascontiguousarray(bbox, np.int32).reshape(6)
     P = np.zeros((off.shape[0], n_bins, n_bins), np.uint64)
     lib.oracle_glcm_roi(_ptr(I), _ptr(L), nz, ny, nx, int(label), int(vmin), int(vmax), _ptr(bb),
-                        n_bins, _ptr(off), off.shape[0], _ptr(P))
+                        n_bins, _ptr(off), off.shape[0], 1 if symmetric else 0, _ptr(P))
     return P
 
 
 def features(P: np.ndarray) -> np.ndarray:
-    """The 30 features of one symmetric (Ng, Ng) count matrix."""
+    """The 30 features of one (Ng, Ng) count matrix (symmetric or not)."""
     lib = _load()
     M = np.ascontiguousarray(P, np.uint64)
     if M.ndim != 2 or M.shape[0] != M.shape[1]:
@@ -206,7 +207,7 @@ def shade_magnitude(P: np.ndarray) -> float:
 
 
 def extract(intensity, labels, n_bins: int, offsets: np.ndarray, stats: dict | None = None,
-            rois=None, n_threads: int = 1, want_shade_magnitude: bool = False):
+            rois=None, n_threads: int = 1, want_shade_magnitude: bool = False, symmetric: bool = True):
     """Feature table of one image: (stats, table (n, K + 1, 30) float64),
     plus the (n, K) cluster-shade magnitudes (shade_magnitude of each
     direction's matrix) when want_shade_magnitude is set.
@@ -229,7 +230,7 @@ def extract(intensity, labels, n_bins: int, offsets: np.ndarray, stats: dict | N
     mag = np.zeros((idx.size, K), np.float64) if want_shade_magnitude else None
     rc = lib.oracle_extract(_ptr(I), _ptr(L), nz, ny, nx, n_bins, _ptr(off), K, idx.size,
                             _ptr(lab), _ptr(lo), _ptr(hi), _ptr(bb), _ptr(table),
-                            _ptr(mag) if mag is not None else None, n_threads)
+                            _ptr(mag) if mag is not None else None, 1 if symmetric else 0, n_threads)
     if rc != 0:
         raise RuntimeError("oracle_extract failed")
     return (st, table, mag) if want_shade_magnitude else (st, table)

@@ -27,7 +27,8 @@
  *  - Fixed-bin-number discretisation over the ROI's own [min, max] with
  *    1-based levels 1..Ng, computed in exact integer arithmetic [A2, A3].
  *  - A pair (v, v+d) counts only if both voxels are inside the image and
- *    carry the ROI's label [A5]; the matrix is symmetrised P = C + C^T [A6].
+ *    carry the ROI's label [A5]; the matrix is symmetrised P = C + C^T [A6]
+ *    by default, or kept as the ordered counts P = C on request [A16].
  *  - Logarithms are base 2; 0 log 0 = 0 [A7].
  *  - Sums use Neumaier compensation; all arithmetic is binary64.
  */
@@ -170,15 +171,17 @@ int oracle_bin_image(const uint16_t *intensity, const uint32_t *labels, int64_t 
 }
 
 /* ------------------------------------------------------------ matrices */
-/* Symmetric co-occurrence matrices of one ROI, one per offset: P[k][i][j]
- * (Ng x Ng, 0-based level indices).  For each ROI voxel v and offset d_k,
- * the pair (v, v + d_k) counts when v + d_k is inside the image and carries
- * the same label [A5]; C is the ordered count and P = C + C^T [A6]. */
+/* Co-occurrence matrices of one ROI, one per offset: P[k][i][j] (Ng x Ng,
+ * 0-based level indices).  For each ROI voxel v and offset d_k, the pair
+ * (v, v + d_k) counts when v + d_k is inside the image and carries the same
+ * label [A5]; C(i, j) is the number of such pairs with level i at v and j at
+ * v + d_k.  symmetric != 0: P = C + C^T [A6]; symmetric == 0: P = C, the
+ * ordered counts [A16]. */
 int oracle_glcm_roi(const uint16_t *intensity, const uint32_t *labels,
                     int64_t nz, int64_t ny, int64_t nx, uint32_t label,
                     uint16_t vmin, uint16_t vmax, const int32_t *bbox,
                     int32_t n_bins, const int32_t *offsets, int32_t n_offsets,
-                    uint64_t *P) {
+                    int32_t symmetric, uint64_t *P) {
     int64_t ng = n_bins;
     memset(P, 0, (size_t)n_offsets * (size_t)(ng * ng) * sizeof(uint64_t));
     for (int32_t k = 0; k < n_offsets; ++k) {
@@ -195,15 +198,15 @@ int oracle_glcm_roi(const uint16_t *intensity, const uint32_t *labels,
                     if (labels[w] != label) continue;
                     int64_t i = (int64_t)oracle_bin(intensity[v], vmin, vmax, n_bins) - 1;
                     int64_t j = (int64_t)oracle_bin(intensity[w], vmin, vmax, n_bins) - 1;
-                    Pk[i * ng + j] += 1; /* C(i, j) */
-                    Pk[j * ng + i] += 1; /* C^T contributes C(i, j) at (j, i) */
+                    Pk[i * ng + j] += 1;                 /* C(i, j) */
+                    if (symmetric) Pk[j * ng + i] += 1;  /* C^T contributes C(i, j) at (j, i) */
                 }
     }
     return 0;
 }
 
 /* ------------------------------------------------------------ features */
-/* The 30 GLCM features of one symmetric matrix P (Ng x Ng counts), written to
+/* The 30 GLCM features of one matrix P (Ng x Ng counts, symmetric or not), written to
  * out[0..29] in ORACLE_NAMES order.  Every feature is its own plain loop over
  * the normalised matrix p = P / T, following the standard definitions. */
 void oracle_features(const uint64_t *P, int32_t n_bins, double *out) {
@@ -261,14 +264,18 @@ void oracle_features(const uint64_t *P, int32_t n_bins, double *out) {
     a = (nsum){0, 0}; for (int64_t j = 0; j < ng; ++j) { double d = (double)(j + 1) - muy; nadd(&a, d * d * py[j]); }
     const double sy = sqrt(nval(&a));
 
-    /* single-level test on integers: exactly one level has a nonzero row [A11] */
-    int64_t nonzero_levels = 0;
+    /* single-level test on integers [A11, A16]: exactly one level has a
+     * nonzero row, or exactly one level has a nonzero column (the same test
+     * for a symmetric matrix).  Then p_ij = p_x(i) p_y(j), so the correlation
+     * is 0/0 and the mutual information is exactly 0. */
+    int64_t nonzero_rows = 0, nonzero_cols = 0;
     for (int64_t i = 0; i < ng; ++i) {
-        uint64_t row = 0;
-        for (int64_t j = 0; j < ng; ++j) row += P[i * ng + j];
-        if (row) ++nonzero_levels;
+        uint64_t row = 0, col = 0;
+        for (int64_t j = 0; j < ng; ++j) { row += P[i * ng + j]; col += P[j * ng + i]; }
+        if (row) ++nonzero_rows;
+        if (col) ++nonzero_cols;
     }
-    const int single_level = (nonzero_levels == 1);
+    const int single_level = (nonzero_rows == 1 || nonzero_cols == 1);
 
     double f[NFEAT];
     /* 1 ASM: sum p^2 */
@@ -357,7 +364,7 @@ void oracle_features(const uint64_t *P, int32_t n_bins, double *out) {
         f[16] = single_level ? 0.0 : (hxy - HXY1) / hmax;           /* 0/0 -> 0 [A11] */
         double arg = HXY2 - hxy;
         if (arg < 0) arg = 0;                                      /* [A7] */
-        f[17] = sqrt(1.0 - exp(-2.0 * arg));
+        f[17] = single_level ? 0.0 : sqrt(1.0 - exp(-2.0 * arg));  /* MI = 0 exactly [A16] */
     }
     /* 19 IDMN: sum p / (1 + (i - j)^2 / Ng^2) */
     a = (nsum){0, 0};
@@ -459,7 +466,8 @@ double oracle_shade_magnitude(const uint64_t *P, int32_t n_bins) {
 /* Feature table for a list of ROIs of one image (ROI statistics as produced
  * by oracle_roi_stats): table[r][blk][f] with blk = 0..n_offsets-1 the
  * directions and blk = n_offsets the direction mean; shade_mag (nullable)
- * receives oracle_shade_magnitude of every (ROI, direction).  n_threads > 1 runs
+ * receives oracle_shade_magnitude of every (ROI, direction); symmetric as for
+ * oracle_glcm_roi.  n_threads > 1 runs
  * independent ROIs on OpenMP threads (timing only; results do not depend on
  * it).  Returns 0, or -1 on allocation failure. */
 int oracle_extract(const uint16_t *intensity, const uint32_t *labels,
@@ -467,7 +475,7 @@ int oracle_extract(const uint16_t *intensity, const uint32_t *labels,
                    const int32_t *offsets, int32_t n_offsets, int64_t n_rois,
                    const uint32_t *roi_label, const uint16_t *roi_min,
                    const uint16_t *roi_max, const int32_t *roi_bbox,
-                   double *table, double *shade_mag, int32_t n_threads) {
+                   double *table, double *shade_mag, int32_t symmetric, int32_t n_threads) {
     const size_t cells = (size_t)n_bins * (size_t)n_bins * (size_t)n_offsets;
     int failed = 0;
 #pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1) reduction(| : failed)
@@ -478,7 +486,7 @@ int oracle_extract(const uint16_t *intensity, const uint32_t *labels,
         for (int64_t r = 0; r < n_rois; ++r) {
             if (!P) continue;
             oracle_glcm_roi(intensity, labels, nz, ny, nx, roi_label[r], roi_min[r], roi_max[r],
-                            roi_bbox + 6 * r, n_bins, offsets, n_offsets, P);
+                            roi_bbox + 6 * r, n_bins, offsets, n_offsets, symmetric, P);
             oracle_features_roi(P, n_bins, n_offsets, table + (size_t)r * (size_t)(n_offsets + 1) * NFEAT);
             if (shade_mag)
                 for (int32_t k = 0; k < n_offsets; ++k)

@@ -15,12 +15,12 @@ int64_t oracle_roi_stats(const uint16_t *, const uint32_t *, int64_t, int64_t, i
 int oracle_bin_image(const uint16_t *, const uint32_t *, int64_t, int64_t, const uint32_t *, const uint16_t *,
                      const uint16_t *, int32_t, uint16_t *);
 int oracle_glcm_roi(const uint16_t *, const uint32_t *, int64_t, int64_t, int64_t, uint32_t, uint16_t, uint16_t,
-                    const int32_t *, int32_t, const int32_t *, int32_t, uint64_t *);
+                    const int32_t *, int32_t, const int32_t *, int32_t, int32_t, uint64_t *);
 void oracle_features_roi(const uint64_t *, int32_t, int32_t, double *);
 double oracle_shade_magnitude(const uint64_t *, int32_t);
 int oracle_extract(const uint16_t *, const uint32_t *, int64_t, int64_t, int64_t, int32_t, const int32_t *, int32_t,
                    int64_t, const uint32_t *, const uint16_t *, const uint16_t *, const int32_t *, double *,
-                   double *, int32_t);
+                   double *, int32_t, int32_t);
 int32_t oracle_default_offsets(int32_t dims, int32_t d, int32_t *out);
 
 static uint64_t state = 0x9E3779B97F4A7C15ull;
@@ -51,10 +51,11 @@ static int run(int64_t nz, int64_t ny, int64_t nx, int32_t ng, int32_t dims, int
     if (oracle_bin_image(I, L, n, r, lab, lo, hi, ng, bins) != 0) return 2;
     double *table = malloc((size_t)(r + 1) * (size_t)(K + 1) * 30 * sizeof *table);
     double *mag = malloc((size_t)(r + 1) * (size_t)K * sizeof *mag);
-    if (oracle_extract(I, L, nz, ny, nx, ng, off, K, r, lab, lo, hi, bb, table, mag, 1) != 0) return 3;
+    for (int32_t sym = 0; sym <= 1; ++sym)
+        if (oracle_extract(I, L, nz, ny, nx, ng, off, K, r, lab, lo, hi, bb, table, mag, sym, 1) != 0) return 3;
     uint64_t *P = malloc((size_t)K * (size_t)ng * (size_t)ng * sizeof *P);
     for (int64_t q = 0; q < r; ++q) {
-        oracle_glcm_roi(I, L, nz, ny, nx, lab[q], lo[q], hi[q], bb + 6 * q, ng, off, K, P);
+        oracle_glcm_roi(I, L, nz, ny, nx, lab[q], lo[q], hi[q], bb + 6 * q, ng, off, K, (int32_t)(q & 1), P);
         double f[(13 + 1) * 30];
         oracle_features_roi(P, ng, K, f);
         for (int32_t k = 0; k < K; ++k) {

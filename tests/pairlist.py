@@ -33,12 +33,14 @@ def ordered_pairs(bins: np.ndarray, labels: np.ndarray, label: int, offset) -> n
     return np.stack([bv, bw], axis=1).reshape(-1, 2)
 
 
-def count_matrix(pairs: np.ndarray, n_bins: int) -> np.ndarray:
-    """Symmetric counts from brute-force ordered pairs (both orders)."""
+def count_matrix(pairs: np.ndarray, n_bins: int, symmetric: bool = True) -> np.ndarray:
+    """Counts from brute-force ordered pairs: both orders (symmetric), or
+    each pair once in its own order."""
     P = np.zeros((n_bins, n_bins), np.uint64)
     for x, y in pairs:
         P[x - 1, y - 1] += 1
-        P[y - 1, x - 1] += 1
+        if symmetric:
+            P[y - 1, x - 1] += 1
     return P
 
 
@@ -47,12 +49,18 @@ def _entropy_bits(values) -> float:
     return float(stats.entropy(c, base=2))
 
 
-def features_from_pairs(pairs: np.ndarray, n_bins: int) -> dict:
-    """The 30 features from the pair list (both orders), via library statistics."""
+def features_from_pairs(pairs: np.ndarray, n_bins: int, symmetric: bool = True) -> dict:
+    """The 30 features from the pair list (both orders when symmetric, else
+    each pair in its own order: x the level at v, y the level at v + d), via
+    library statistics."""
     if len(pairs) == 0:
         return None
-    x = np.concatenate([pairs[:, 0], pairs[:, 1]]).astype(float)
-    y = np.concatenate([pairs[:, 1], pairs[:, 0]]).astype(float)
+    if symmetric:
+        x = np.concatenate([pairs[:, 0], pairs[:, 1]]).astype(float)
+        y = np.concatenate([pairs[:, 1], pairs[:, 0]]).astype(float)
+    else:
+        x = pairs[:, 0].astype(float)
+        y = pairs[:, 1].astype(float)
     s = x + y
     d = x - y
     ad = np.abs(d)
@@ -65,7 +73,9 @@ def features_from_pairs(pairs: np.ndarray, n_bins: int) -> dict:
     f["CLUSHADE"] = float(stats.moment(s, 3))
     f["CLUTEND"] = float(np.var(s))
     f["CONTRAST"] = float(np.mean(d ** 2))
-    single = len(np.unique(x)) == 1
+    # one level in either coordinate: the correlation is 0/0 and the mutual
+    # information exactly 0
+    single = len(np.unique(x)) == 1 or len(np.unique(y)) == 1
     f["CORR"] = 1.0 if single else float(np.corrcoef(x, y)[0, 1])
     f["DIFAVE"] = float(np.mean(ad))
     f["DIFENTRO"] = _entropy_bits(ad.tolist())
@@ -79,7 +89,7 @@ def features_from_pairs(pairs: np.ndarray, n_bins: int) -> dict:
     hy = _entropy_bits(y.tolist())
     mi = mutual_info_score(x.astype(int), y.astype(int)) / math.log(2.0)  # bits
     f["INFOMEAS1"] = 0.0 if single else -mi / max(hx, hy)
-    f["INFOMEAS2"] = math.sqrt(1.0 - math.exp(-2.0 * max(mi, 0.0)))
+    f["INFOMEAS2"] = 0.0 if single else math.sqrt(1.0 - math.exp(-2.0 * max(mi, 0.0)))
     f["IDMN"] = float(np.mean(1.0 / (1.0 + d ** 2 / n_bins ** 2)))
     f["IDN"] = float(np.mean(1.0 / (1.0 + ad / n_bins)))
     nz = d != 0

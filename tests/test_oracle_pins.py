@@ -503,3 +503,81 @@ def test_shade_magnitude_definition(oracle_mod):
     assert oracle_mod.shade_magnitude(P) == pytest.approx(q * abs(2 - 2 * mu) ** 3 + (1 - q) * abs(16 - 2 * mu) ** 3,
                                                           rel=1e-14)
     assert np.isnan(oracle_mod.shade_magnitude(np.zeros((4, 4), np.uint64)))
+
+
+# ------------------------------------------------------------------ non-symmetric matrices [A16]
+@pytest.mark.parametrize("dims,distance,seed", [(2, 1, 41), (2, 2, 42), (3, 1, 43)])
+def test_ordered_counts_brute_force(oracle_mod, dims, distance, seed):
+    """Ordered counts C against the brute-force pair list (each pair once, in
+    its own order), their sum with the transpose against the symmetric
+    matrix, and the reversed offset giving the transpose."""
+    rng = np.random.default_rng(seed)
+    shape = (1, 8, 9) if dims == 2 else (4, 5, 6)
+    I, L = _rand_scene(rng, shape, 3, fill=0.8)
+    ng = 6
+    st = oracle_mod.roi_stats(I, L)
+    B = oracle_mod.bin_image(I, L, ng, st)
+    off = oracle_mod.default_offsets(dims, distance)
+    for r, lab in enumerate(st["label"]):
+        args = (I, L, lab, st["vmin"][r], st["vmax"][r], st["bbox"][r], ng)
+        C = oracle_mod.glcm_roi(*args, off, symmetric=False)
+        Cneg = oracle_mod.glcm_roi(*args, -off, symmetric=False)
+        P = oracle_mod.glcm_roi(*args, off)
+        for k, d in enumerate(off):
+            assert np.array_equal(C[k], count_matrix(ordered_pairs(B, L, lab, d), ng, symmetric=False)), (lab, d)
+            assert np.array_equal(C[k] + C[k].T, P[k])
+            assert np.array_equal(Cneg[k], C[k].T)
+
+
+def _pairlist_compare_ordered(oracle_mod, I, L, ng, off, rel=1e-11):
+    st, t = oracle_mod.extract(I, L, ng, off, symmetric=False)
+    B = oracle_mod.bin_image(I, L, ng, st)
+    n_checked = 0
+    for r, lab in enumerate(st["label"]):
+        for k, d in enumerate(off):
+            f = features_from_pairs(ordered_pairs(B, L, lab, d), ng, symmetric=False)
+            if f is None:
+                assert np.all(np.isnan(t[r, k]))
+                continue
+            for q, name in enumerate(NAMES):
+                want = f[name]
+                assert abs(t[r, k, q] - want) <= rel * max(abs(want), 1.0), (lab, tuple(d), name, t[r, k, q], want)
+            n_checked += 1
+    return n_checked
+
+
+@pytest.mark.parametrize("ng,seed", [(8, 11), (10, 12), (30, 13), (5, 14)])
+def test_ordered_features_pairlist_route_2d(oracle_mod, ng, seed):
+    rng = np.random.default_rng(200 + seed)
+    I, L = _rand_scene(rng, (1, 9, 10), 3, fill=0.9, hi=60)
+    assert _pairlist_compare_ordered(oracle_mod, I, L, ng, oracle_mod.default_offsets(2)) >= 8
+
+
+def test_ordered_features_pairlist_route_ramp_and_3d(oracle_mod):
+    # a ramp: the level at v + d differs systematically from the level at v,
+    # so the two marginals and means differ
+    y, x = np.mgrid[0:10, 0:11]
+    I = (40 * x + 25 * y).astype(np.uint16)[None]
+    L = np.ones((1, 10, 11), np.uint32)
+    assert _pairlist_compare_ordered(oracle_mod, I, L, 16, oracle_mod.default_offsets(2)) == 4
+    rng = np.random.default_rng(34)
+    I, L = _rand_scene(rng, (4, 4, 5), 2, fill=0.95, hi=40)
+    assert _pairlist_compare_ordered(oracle_mod, I, L, 7, oracle_mod.default_offsets(3)) >= 20
+
+
+def test_ordered_single_level_marginal(oracle_mod):
+    """A matrix with one occupied row but several columns: the product of its
+    marginals, so CORR = 1, INFOMEAS1 = INFOMEAS2 = 0 [A16], and the other
+    features from the column marginal alone."""
+    C = np.zeros((5, 5), np.uint64)
+    C[2, [0, 1, 4]] = [1, 2, 3]   # level 3 at v; levels 1, 2, 5 at v + d with p = 1/6, 2/6, 3/6
+    f = dict(zip(NAMES, oracle_mod.features(C)))
+    assert (f["CORR"], f["INFOMEAS1"], f["INFOMEAS2"]) == (1.0, 0.0, 0.0)
+    p = np.array([1, 2, 3]) / 6.0
+    j = np.array([1, 2, 5])
+    assert f["JAVE"] == pytest.approx(3.0, rel=1e-15)
+    assert f["JVAR"] == pytest.approx(0.0, abs=1e-15)
+    assert f["SUMAVE"] == pytest.approx(3.0 + float(np.sum(j * p)), rel=1e-14)
+    assert f["CONTRAST"] == pytest.approx(float(np.sum((3 - j) ** 2 * p)), rel=1e-14)
+    assert f["JE"] == pytest.approx(float(-np.sum(p * np.log2(p))), rel=1e-14)
+    assert f["ACOR"] == pytest.approx(3.0 * float(np.sum(j * p)), rel=1e-14)
