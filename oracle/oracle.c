@@ -276,6 +276,21 @@ void oracle_features(const uint64_t *P, int32_t n_bins, double *out) {
         if (col) ++nonzero_cols;
     }
     const int single_level = (nonzero_rows == 1 || nonzero_cols == 1);
+    /* occupied levels of the sum and difference marginals, on integers [A17] */
+    int64_t nonzero_sums = 0, nonzero_difs = 0;
+    for (int64_t k = 0; k <= 2 * ng - 2; ++k) {
+        uint64_t c = 0;
+        for (int64_t i = 0; i < ng; ++i) if (k - i >= 0 && k - i < ng) c += P[i * ng + (k - i)];
+        if (c) ++nonzero_sums;
+    }
+    for (int64_t k = 0; k < ng; ++k) {
+        uint64_t c = 0;
+        for (int64_t i = 0; i < ng; ++i) {
+            if (i + k < ng) c += P[i * ng + i + k];
+            if (k > 0 && i - k >= 0) c += P[i * ng + i - k];
+        }
+        if (c) ++nonzero_difs;
+    }
 
     double f[NFEAT];
     /* 1 ASM: sum p^2 */
@@ -410,6 +425,11 @@ void oracle_features(const uint64_t *P, int32_t n_bins, double *out) {
     a = (nsum){0, 0}; for (int64_t k = 2; k <= 2 * ng; ++k) { double d = (double)k - sumave; nadd(&a, d * d * psum[k]); }
     f[28] = nval(&a);
 #undef PIJ
+    /* A centred moment of a distribution on one value is exactly 0; the sums
+     * above leave the rounding of the computed mean instead [A17]. */
+    if (nonzero_rows == 1) f[27] = f[29] = 0.0;                  /* JVAR, VARIANCE */
+    if (nonzero_sums == 1) f[2] = f[3] = f[4] = f[28] = 0.0;     /* CLUPROM, CLUSHADE, CLUTEND, SUMVAR */
+    if (nonzero_difs == 1) f[9] = 0.0;                           /* DIFVAR */
     for (int q = 0; q < NFEAT; ++q) out[q] = f[q];
     free(px); free(py); free(psum); free(pdif);
 }

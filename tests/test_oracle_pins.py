@@ -576,8 +576,29 @@ def test_ordered_single_level_marginal(oracle_mod):
     p = np.array([1, 2, 3]) / 6.0
     j = np.array([1, 2, 5])
     assert f["JAVE"] == pytest.approx(3.0, rel=1e-15)
-    assert f["JVAR"] == pytest.approx(0.0, abs=1e-15)
+    assert f["JVAR"] == 0.0 and f["VARIANCE"] == 0.0   # one occupied row level [A17]
     assert f["SUMAVE"] == pytest.approx(3.0 + float(np.sum(j * p)), rel=1e-14)
     assert f["CONTRAST"] == pytest.approx(float(np.sum((3 - j) ** 2 * p)), rel=1e-14)
     assert f["JE"] == pytest.approx(float(-np.sum(p * np.log2(p))), rel=1e-14)
     assert f["ACOR"] == pytest.approx(3.0 * float(np.sum(j * p)), rel=1e-14)
+
+
+def test_centred_moments_of_one_value_are_exactly_zero(oracle_mod):
+    """[A17] Sum and difference marginals concentrated on one value: the
+    cluster moments, the sum variance and the difference variance are 0
+    exactly, where summing with a rounded mean would leave ~1e-31; a matrix
+    whose sum marginal has two values keeps the plain sums."""
+    P = np.zeros((9, 9), np.uint64)
+    P[0, 6] = P[6, 0] = 5; P[2, 4] = P[4, 2] = 3; P[3, 3] = 7    # i + j = 8 everywhere (0-based 6)
+    f = dict(zip(NAMES, oracle_mod.features(P)))
+    for k in ("CLUPROM", "CLUSHADE", "CLUTEND", "SUMVAR"):
+        assert f[k] == 0.0, k
+    assert f["SUMAVE"] == pytest.approx(8.0, rel=1e-15)
+    Q = np.zeros((9, 9), np.uint64)
+    Q[0, 2] = 4; Q[3, 5] = 1; Q[6, 8] = 6; Q[8, 6] = 2            # |i - j| = 2 everywhere
+    g = dict(zip(NAMES, oracle_mod.features(Q)))
+    assert g["DIFVAR"] == 0.0 and g["DIFAVE"] == pytest.approx(2.0, rel=1e-15)
+    assert g["CONTRAST"] == pytest.approx(4.0, rel=1e-15)
+    R = P.copy(); R[0, 0] = 1                                      # a second sum value
+    h = dict(zip(NAMES, oracle_mod.features(R)))
+    assert h["CLUTEND"] > 0 and h["SUMVAR"] == pytest.approx(h["CLUTEND"], rel=1e-12)
