@@ -19,7 +19,14 @@
  *    level = 1 + floor(n_bins (I - min) / (max - min)), clamped to n_bins;
  *    a constant ROI is level 1.  Computed exactly in integers.
  *  - A voxel pair (v, v + d) is counted only when both voxels are inside the
- *    image and carry the ROI's label.  Matrices are symmetric, P = C + C^T.
+ *    image and carry the ROI's label.  C(i, j) counts the pairs with level i
+ *    at v and j at v + d.  Matrices are symmetric, P = C + C^T, unless a call
+ *    asks for the ordered counts P = C (symmetric = 0): the texture
+ *    hyper-parameters the paper names leave the symmetry open (Methods,
+ *    "Feature Control and Tunability"), and the 30 features are defined for
+ *    either (row and column marginals then differ; a matrix whose row or
+ *    column marginal has one occupied level gives CORR = 1 and
+ *    INFOMEAS1 = INFOMEAS2 = 0).
  *  - ROIs are ordered by (image index, label), ascending.  Output rows follow
  *    that order.
  *  - Feature table: row r holds (n_offsets + 1) blocks of 30 values; block
@@ -94,10 +101,11 @@ typedef struct nyx_roi_table {
     int64_t *n_rois_host; /* out: number of ROIs found */
 } nyx_roi_table;
 
-/* Sparse co-occurrence counts: the upper triangle U(i, j), i <= j, of each
- * symmetric matrix, U(i, j) = P(i, j) for i < j and U(i, i) = P(i, i) / 2,
- * as a COO list sorted by key.  key = roi << 38 | dir << 32 | (i - 1) << 16
- * | (j - 1) with 1-based levels i <= j; count is exact (64-bit). */
+/* Sparse co-occurrence counts as a COO list sorted by key, key = roi << 38 |
+ * dir << 32 | (i - 1) << 16 | (j - 1) with 1-based levels; count is exact
+ * (64-bit).  Symmetric matrices: the upper triangle U(i, j), i <= j,
+ * U(i, j) = P(i, j) for i < j and U(i, i) = P(i, i) / 2.  Ordered counts
+ * (symmetric = 0): every nonzero cell C(i, j). */
 typedef struct nyx_glcm {
     uint64_t *key;
     uint64_t *count;
@@ -105,7 +113,7 @@ typedef struct nyx_glcm {
     int64_t *nnz_host;  /* out: number of nonzero cells */
     int32_t n_bins;     /* set by nyx_glcm_accumulate */
     int32_t n_offsets;  /* set by nyx_glcm_accumulate */
-    int32_t symmetric;  /* always 1 */
+    int32_t symmetric;  /* set by nyx_glcm_accumulate: 1 triangle of P = C + C^T, 0 ordered counts C */
     int64_t n_rois;     /* set by nyx_glcm_accumulate */
 } nyx_glcm;
 
@@ -126,7 +134,8 @@ typedef struct nyx_extract_opts {
     int32_t n_bins;
     const nyx_offset *offsets_host;
     int32_t n_offsets;
-    int32_t symmetric;           /* must be 1 */
+    int32_t symmetric;           /* 1: P = C + C^T; 0: ordered counts P = C (dense square per
+                                    direction in LDS, or the hash table; gather accumulation) */
     nyx_precision precision;     /* feature output type */
     int32_t autotune;            /* 1: time candidate kernel configurations at plan time */
     int32_t accum_mode;          /* -1 = automatic; else force one accumulation mode:

@@ -171,11 +171,25 @@ __device__ __forceinline__ void tri_decode(uint32_t i, uint32_t &lo, uint32_t &h
 template <bool PACKED>
 struct SrcTriScan {
     uint32_t *U;
-    uint32_t tri;
+    uint32_t tri;            // cells: ng (ng + 1) / 2, or ng^2 for a square
     uint32_t *buf;
     uint32_t ncp = 1u;
     uint32_t stride = 0u;
+    uint32_t sq_ng = 0u;     // > 0: a full row-major square of sq_ng x sq_ng ordered cells
     static constexpr uint32_t kPerRead = PACKED ? 8u : 4u;   // cells per 16-byte read
+    // Cell i as (lo, hi): triangle row and column, or square row and column
+    // (a single-precision quotient corrected by one step; i < 2^16 here).
+    __device__ __forceinline__ void decode(uint32_t i, uint32_t &lo, uint32_t &hi) const {
+        if (sq_ng) {
+            uint32_t q = (uint32_t)((float)i * __builtin_amdgcn_rcpf((float)sq_ng));
+            if (__umul24(q, sq_ng) > i) --q;
+            else if (__umul24(q + 1u, sq_ng) <= i) ++q;
+            lo = q;
+            hi = i - __umul24(q, sq_ng);
+        } else {
+            tri_decode(i, lo, hi);
+        }
+    }
     __device__ __forceinline__ uint32_t count(uint32_t i) const {
         uint32_t c = 0;
         for (uint32_t k = 0; k < ncp; ++k)
@@ -188,7 +202,7 @@ struct SrcTriScan {
         for (uint32_t e = (uint32_t)g.rank(); e < n; e += (uint32_t)g.size()) {
             const uint32_t i = buf[e];
             uint32_t lo, hi;
-            tri_decode(i, lo, hi);
+            decode(i, lo, hi);
             fn(lo, hi, count(i));
         }
         g.sync();
@@ -303,11 +317,12 @@ struct SrcHashList {
 struct SrcSquare {
     const uint64_t *G;
     uint32_t ng;
+    bool all = false;        // every cell (ordered counts), not only the upper triangle
     template <class Grp, class Fn>
     __device__ __forceinline__ void for_each(const Grp &g, Fn &&fn) const {
         for (uint32_t e = g.rank(); e < ng * ng; e += g.size()) {
             const uint32_t lo = e / ng, hi = e - lo * ng;
-            if (lo > hi) continue;
+            if (lo > hi && !all) continue;
             const uint64_t c = G[e];
             if (c) fn(lo, hi, (uint32_t)c);
         }
@@ -324,13 +339,15 @@ struct SrcCoo {
     uint64_t prefix;         // expected roi << 38 | dir << 32
     uint32_t ng;
     uint32_t *err;
+    bool ordered = false;    // cells below the diagonal are valid (ordered counts)
     template <class Grp, class Fn>
     __device__ __forceinline__ void for_each(const Grp &g, Fn &&fn) const {
         for (uint32_t e = g.rank(); e < n; e += g.size()) {
             const uint64_t k = key[e];
             const uint32_t lo = (uint32_t)(k >> 16) & 0xFFFFu, hi = (uint32_t)k & 0xFFFFu;
             const uint64_t c = cnt[e];
-            if ((k & ~0xFFFFFFFFull) != prefix || lo > hi || hi >= ng || c >= (1ull << 31)) {
+            if ((k & ~0xFFFFFFFFull) != prefix || (lo > hi && !ordered) || hi >= ng || lo >= ng ||
+                c >= (1ull << 31)) {
                 if (c) atomicOr(err, (uint32_t)E_COO_RANGE);
                 continue;
             }
@@ -342,34 +359,43 @@ struct SrcCoo {
 
 // ------------------------------------------------------------- sums
 // The 30 features of one direction from its reduced sums (one lane).
-__device__ __noinline__ void finalize_dir(const DirSums &s, double *out) {
+// y: the column-marginal sums of a non-symmetric matrix (nullptr: the matrix
+// is symmetric and its column marginal is its row marginal).
+__device__ __noinline__ void finalize_dir(const DirSums &s, const DirSumsY *y, double *out) {
     const uint64_t T = s.T;
     if (T == 0) {
         for (int f = 0; f < kNumFeat; ++f) out[f] = __builtin_nan("");
         return;
     }
     const uint64_t S1 = s.S1, S2 = s.S2, S11 = s.S11, Sm1 = s.Sm1;
+    const uint64_t S1y = y ? y->S1y : S1, S2y = y ? y->S2y : S2;
     const double Td = (double)T, invT = 1.0 / Td, lgT = log2(Td);
     const double T2 = Td * Td;
     const u128 Tq = (u128)T;
-    const u128 s1sq = (u128)S1 * (u128)S1;
-    const u128 nvar = Tq * (u128)S2 - s1sq;
-    const i128 ncov = (i128)(Tq * (u128)S11) - (i128)s1sq;
-    const u128 sm2 = 2 * (u128)S2 - 2 * (u128)S11;     // sum (i - j)^2 P
+    // T^2 var_x, T^2 var_y and T^2 cov as exact integers
+    const u128 nvar = Tq * (u128)S2 - (u128)S1 * (u128)S1;
+    const u128 nvary = Tq * (u128)S2y - (u128)S1y * (u128)S1y;
+    const i128 ncov = (i128)(Tq * (u128)S11) - (i128)((u128)S1 * (u128)S1y);
+    const u128 sm2 = (u128)S2 + (u128)S2y - 2 * (u128)S11;     // sum (i - j)^2 P
     const u128 ndv = Tq * sm2 - (u128)Sm1 * (u128)Sm1;
-    const bool single = nvar == 0;
+    // one occupied level in the row or the column marginal: the matrix is the
+    // product of its marginals (correlation 0/0, mutual information 0)
+    const bool single = nvar == 0 || nvary == 0;
     const double var = u128_to_double(nvar) / T2;
     // entropies H = log2 T - (sum n log2 n) / T
     const double JE = lgT - s.plp * invT;
     const double HX = lgT - s.rlr * invT;
-    const double MI = isnan(s.MI) ? 2.0 * HX - JE : s.MI;
+    const double HY = y ? lgT - y->clc * invT : HX;
+    const double MI = isnan(s.MI) ? HX + HY - JE : s.MI;
     out[F_ASM] = out[F_ENERGY] = (double)s.sumP2 / T2;
     out[F_ACOR] = (double)S11 / Td;
     out[F_CLUPROM] = s.CPROM;
     out[F_CLUSHADE] = s.CSHADE;
-    out[F_CLUTEND] = out[F_SUMVAR] = i128_to_double(2 * (i128)nvar + 2 * ncov) / T2;
+    out[F_CLUTEND] = out[F_SUMVAR] = i128_to_double((i128)nvar + (i128)nvary + 2 * ncov) / T2;
     out[F_CONTRAST] = u128_to_double(sm2) / Td;
-    out[F_CORR] = single ? 1.0 : i128_to_double(ncov) / u128_to_double(nvar);
+    out[F_CORR] = single ? 1.0
+                         : i128_to_double(ncov) /
+                               (y ? sqrt(u128_to_double(nvar)) * sqrt(u128_to_double(nvary)) : u128_to_double(nvar));
     out[F_DIFAVE] = out[F_DIS] = (double)Sm1 / Td;
     out[F_DIFENTRO] = lgT - s.slp * invT;
     out[F_DIFVAR] = u128_to_double(ndv) / T2;
@@ -377,14 +403,14 @@ __device__ __noinline__ void finalize_dir(const DirSums &s, double *out) {
     out[F_HOM1] = out[F_ID] = s.hom1 * invT;
     out[F_HOM2] = out[F_IDM] = s.hom2 * invT;
     const double mi = MI > 0.0 ? MI : 0.0;
-    out[F_INFOMEAS1] = single ? 0.0 : -MI / HX;
-    out[F_INFOMEAS2] = sqrt(1.0 - exp(-2.0 * mi));
+    out[F_INFOMEAS1] = single ? 0.0 : -MI / (HX > HY ? HX : HY);
+    out[F_INFOMEAS2] = single ? 0.0 : sqrt(1.0 - exp(-2.0 * mi));
     out[F_IDMN] = s.idmn * invT;
     out[F_IDN] = s.idn * invT;
     out[F_IV] = s.iv * invT;
     out[F_JAVE] = (double)S1 / Td;
     out[F_JMAX] = (double)s.maxP / Td;
-    out[F_SUMAVE] = 2.0 * (double)S1 / Td;
+    out[F_SUMAVE] = ((double)S1 + (double)S1y) / Td;
     out[F_SUMENT] = lgT - s.plps * invT;
     out[F_JVAR] = out[F_VARIANCE] = var;
 }
@@ -524,7 +550,9 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
     }
     const double Td = (double)T, invT = 1.0 / Td;
     // Cluster shade / prominence: moments of the sum marginal about 2 mu.
-    const double two_mu = 2.0 * (double)S1t * invT;
+    // (an exact integer over T, one rounding: a sum marginal on one value
+    // gives d = 0 exactly)
+    const double two_mu = (double)(2u * S1t) / Td;
     double cs = 0.0, cp = 0.0;
     for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) {
         const uint32_t s = Sp[k];
@@ -587,6 +615,125 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
     // Clean up for the next direction / item.
     g.sync();
     for (uint32_t i = r0; i < ng; i += gs) { R[i] = 0u; Sm[i] = 0u; }
+    for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) Sp[k] = 0u;
+    src.clear(g);
+    g.sync();
+    return T;
+}
+
+// Reduced sums of one direction of a non-symmetric matrix (ordered counts):
+// the source hands cells (a, b, c) with P(a, b) = c, a the level at v and b
+// the level at v + d.  R and Cm are the row and column marginals (ng u32
+// each), Sp and Sm the sum and difference marginals (2 ng - 1 and ng u32),
+// all zeroed LDS arrays that are zeroed again on return; *out and *outy
+// receive the sums (the column-marginal ones in *outy).  Every total is
+// reduced value by value in exact integers or double.  Returns T.
+template <class Acc, class Grp, class Src>
+__device__ uint64_t dir_sums_ns(const Grp &g, const Src &src, uint32_t *R, uint32_t *Cm, uint32_t *Sp, uint32_t *Sm,
+                                uint32_t ng, DirSums *out, DirSumsY *outy) {
+    const int r0 = g.rank(), gs = g.size();
+    uint64_t Tl = 0, sumP2 = 0, S11 = 0;
+    uint32_t maxP = 0;
+    LaneSum<Acc> plp;
+    src.for_each(g, [&](uint32_t a, uint32_t b, uint32_t c) {
+        atomicAdd(&R[a], c);
+        atomicAdd(&Cm[b], c);
+        atomicAdd(&Sp[a + b], c);
+        atomicAdd(&Sm[a > b ? a - b : b - a], c);
+        Tl += c;
+        sumP2 += (uint64_t)c * c;
+        maxP = c > maxP ? c : maxP;
+        S11 += (uint64_t)c * __umul24(a + 1u, b + 1u);   // levels < 2^16: exact
+        plp.add((Acc)c * term_log2<Acc>((Acc)c));
+    });
+    g.sync();
+    uint64_t S1 = 0, S2 = 0, S1y = 0, S2y = 0, Sm1 = 0;
+    LaneSum<Acc> rlr, clc, slp, hom1, hom2, idmn, idn, iv, plps;
+    const Acc ngf = (Acc)ng, rng = (Acc)1 / ngf, rng2 = rng * rng;
+    for (uint32_t i = r0; i < ng; i += gs) {
+        const uint64_t lv = i + 1u;
+        const uint32_t r = R[i];
+        if (r) {
+            S1 += lv * r;
+            S2 += lv * lv * r;
+            rlr.add((Acc)r * term_log2<Acc>((Acc)r));
+        }
+        const uint32_t q = Cm[i];
+        if (q) {
+            S1y += lv * q;
+            S2y += lv * lv * q;
+            clc.add((Acc)q * term_log2<Acc>((Acc)q));
+        }
+        const uint32_t sm = Sm[i];
+        if (sm) {
+            Sm1 += (uint64_t)i * sm;
+            const Acc sf = (Acc)sm, k = (Acc)i;
+            slp.add(sf * term_log2<Acc>(sf));
+            hom1.add(term_div<Acc>(sf, (Acc)1 + k));
+            hom2.add(term_div<Acc>(sf, (Acc)1 + k * k));
+            idmn.add(term_div<Acc>(sf, (Acc)1 + (k * k) * rng2));
+            idn.add(term_div<Acc>(sf, (Acc)1 + k * rng));
+            if (i > 0) iv.add(term_div<Acc>(sf, k * k));
+        }
+    }
+    for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) {
+        const uint32_t sp = Sp[k];
+        if (sp) plps.add((Acc)sp * term_log2<Acc>((Acc)sp));
+    }
+    const uint64_t T = g.sum(Tl);
+    const uint64_t S1t = g.sum(S1), S2t = g.sum(S2), S1yt = g.sum(S1y), S2yt = g.sum(S2y), Sm1t = g.sum(Sm1);
+    const uint64_t S11t = g.sum(S11), sumP2t = g.sum(sumP2);
+    const double plp_t = g.sum(comp_value(plp)), rlr_t = g.sum(comp_value(rlr)), clc_t = g.sum(comp_value(clc));
+    const double slp_t = g.sum(comp_value(slp)), plps_t = g.sum(comp_value(plps));
+    const double hom1_t = g.sum(comp_value(hom1)), hom2_t = g.sum(comp_value(hom2));
+    const double idmn_t = g.sum(comp_value(idmn)), idn_t = g.sum(comp_value(idn)), iv_t = g.sum(comp_value(iv));
+    const uint32_t maxPt = g.max(maxP);
+    double CSHADE = 0.0, CPROM = 0.0, MI = __builtin_nan("");
+    if (T) {
+        const double Td = (double)T, invT = 1.0 / Td;
+        // cluster shade / prominence: moments of the sum marginal about mu_x + mu_y
+        const double mu_s = (double)(S1t + S1yt) / Td;   // one rounding (see dir_sums)
+        double cs = 0.0, cp = 0.0;
+        for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) {
+            const uint32_t sp = Sp[k];
+            if (sp) {
+                const double p = (double)sp * invT;
+                const double d = (double)(k + 2u) - mu_s;
+                const double d3 = d * d * d;
+                cs += d3 * p;
+                cp += d3 * d * p;
+            }
+        }
+        CSHADE = g.sum(cs);
+        CPROM = g.sum(cp);
+        // mutual information HX + HY - HXY, re-summed cell by cell when the
+        // closed form would lose the digits the information measures need
+        const double mi_cf = (double)__log2f((float)Td) - (rlr_t + clc_t - plp_t) * invT;
+        if (mi_cf < mi_resum_threshold<Acc>()) {
+            Comp<Acc> m;
+            const Acc invTa = (Acc)invT;
+            src.for_each(g, [&](uint32_t a, uint32_t b, uint32_t c) {
+                const uint64_t A = (uint64_t)c * T;                    // P T < 2^64
+                const uint64_t B = (uint64_t)R[a] * (uint64_t)Cm[b];   // px py T^2
+                const Acc delta = A >= B ? (Acc)(A - B) / (Acc)B : -((Acc)(B - A) / (Acc)B);
+                m.add((Acc)c * invTa * log1p_<Acc>(delta) * (Acc)1.4426950408889634);
+            });
+            MI = g.sum(comp_value(m));
+        }
+    }
+    if (r0 == 0) {
+        out->T = T; out->S1 = S1t; out->S2 = S2t; out->Sm1 = Sm1t; out->S11 = S11t; out->sumP2 = sumP2t;
+        out->plp = plp_t; out->rlr = rlr_t; out->slp = slp_t; out->plps = plps_t;
+        out->hom1 = hom1_t; out->hom2 = hom2_t; out->idmn = idmn_t; out->idn = idn_t; out->iv = iv_t;
+        out->spare = 0.0;
+        out->maxP = maxPt;
+        out->CSHADE = CSHADE;
+        out->CPROM = CPROM;
+        out->MI = MI;
+        outy->S1y = S1yt; outy->S2y = S2yt; outy->clc = clc_t; outy->spare = 0.0;
+    }
+    g.sync();
+    for (uint32_t i = r0; i < ng; i += gs) { R[i] = 0u; Cm[i] = 0u; Sm[i] = 0u; }
     for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) Sp[k] = 0u;
     src.clear(g);
     g.sync();

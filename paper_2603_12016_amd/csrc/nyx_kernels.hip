@@ -508,21 +508,32 @@ template <class T> __device__ __forceinline__ T lds_uniform(const T *p) {
 // Triangle offset of a 1-based level x: the index of cell (lo, hi = x - 1)
 // is row_off(x) + lo + 1, so a pair (a <= b) lands at row_off(b) + a.
 __device__ __forceinline__ uint32_t row_off(uint32_t x) { return (__umul24(x - 1u, x) >> 1) - 1u; }
+struct RowOff {
+    __device__ __forceinline__ uint32_t operator()(uint32_t x) const { return row_off(x); }
+};
+// Square (ordered counts) offset of a 1-based level x: the ordered pair
+// (a, b) lands at sq_off(a) + b = (a - 1) ng + b - 1.
+struct SqOff {
+    uint32_t ng;
+    __device__ __forceinline__ uint32_t operator()(uint32_t x) const { return __umul24(x - 1u, ng) - 1u; }
+};
 
-// Add one unordered level pair (1-based la, lb, with their row offsets ta,
-// tb) to local direction dl.
-template <int MODE>
+// Add one level pair (1-based la, lb, with their row offsets ta, tb) to
+// local direction dl: unordered into the triangle (SQ false), or ordered
+// (la at v, lb at v + d) into the square of ordered counts (SQ true; ta from
+// SqOff, hash keys keep the order).
+template <int MODE, bool SQ = false>
 __device__ __forceinline__ void add_pair(const StepArgs &a, uint8_t *smem, uint32_t dl, uint32_t la, uint32_t ta,
                                          uint32_t lb, uint32_t tb) {
     const LdsLayout &Ly = a.lds;
-    uint32_t lo = (la < lb ? la : lb) - 1u, hi = (la < lb ? lb : la) - 1u;
+    uint32_t lo = (SQ || la < lb ? la : lb) - 1u, hi = (SQ || la < lb ? lb : la) - 1u;
     uint32_t *LCNT = reinterpret_cast<uint32_t *>(smem + Ly.lcnt_off);
     uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off) + dl * Ly.list_cap;
     if (MODE == 2 || MODE == 3) {
         // privatised copies: lane l adds to copy l mod copies (copies is a power of two)
         const uint32_t cp = Ly.copies > 1u ? (uint32_t)lane() & (Ly.copies - 1u) : 0u;
         uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + (dl * Ly.copies + cp) * Ly.tri_pad;
-        const uint32_t i = la <= lb ? tb + la : ta + lb;
+        const uint32_t i = SQ ? ta + lb : (la <= lb ? tb + la : ta + lb);
         if (MODE == 2)
             __hip_atomic_fetch_add(&U[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         else
@@ -730,9 +741,10 @@ __device__ void accumulate_staged(const StepArgs &a, const RoiDesc &rd, const It
 // to kGatherDirs neighbours are loaded in one batch before any is used.
 constexpr int kGatherDirs = 8;
 
-template <class Add>
+template <class Add, class Off = RowOff>
 __device__ void accumulate_rows(const StepArgs &a, const RoiDesc &rd, const ItemCtx &c, uint32_t ra, uint32_t rb,
-                                uint32_t ca, uint32_t cb, int d0, int d1, uint32_t t0, uint32_t ts, Add &&add) {
+                                uint32_t ca, uint32_t cb, int d0, int d1, uint32_t t0, uint32_t ts, Add &&add,
+                                Off off = Off{}) {
     const uint32_t W = cb - ca, H = (uint32_t)(rd.y1 - rd.y0 + 1);
     const uint32_t nv = (rb - ra) * W;
     const uint32_t plane = (uint32_t)c.ny * (uint32_t)c.nx;
@@ -772,7 +784,7 @@ __device__ void accumulate_rows(const StepArgs &a, const RoiDesc &rd, const Item
             for (int k = 0; k < kGatherDirs; ++k)
                 if (db + k < d1 && nl[k] == c.label) {
                     const uint32_t bw = c.level_of(nr[k]);
-                    add((uint32_t)(db + k - d0), bv, row_off(bv), bw, row_off(bw));
+                    add((uint32_t)(db + k - d0), bv, off(bv), bw, off(bw));
                 }
         }
         xo += dxo;
@@ -895,6 +907,10 @@ __device__ __forceinline__ void dir_or_flush(const StepArgs &a, const WaveGrp &g
         g.sync();
         s.clear(g);
         g.sync();
+    } else if (a.nonsym) {
+        // marginals: row, column, sum, difference
+        const uint64_t at = (uint64_t)roi * a.K_out + d;
+        dir_sums_ns<Acc>(g, s, MARG, MARG + ng, MARG + 2u * ng, MARG + 4u * ng - 1u, ng, a.dsums + at, a.dsums_y + at);
     } else {
         dir_sums<Acc, double>(g, s, MARG, MARG + ng, MARG + 3u * ng - 1u, ng, a.dsums + (uint64_t)roi * a.K_out + d);
     }
@@ -918,7 +934,8 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));   // wave index: uniform
     const int K = a.K;
     const uint32_t ng = (uint32_t)a.ng;
-    const uint32_t marg_words = 4u * ng;
+    const bool ns = a.nonsym != 0;   // ordered counts: squares, gather accumulation, four marginals
+    const uint32_t marg_words = (ns ? 5u : 4u) * ng;
     uint32_t *MARG = reinterpret_cast<uint32_t *>(smem + Ly.marg_off) + w * marg_words;
 
     // LDS starts clean and every item leaves it clean.
@@ -979,7 +996,16 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
             const bool split = rd.gslot != kNone;
             for (int d0 = 0, pass = 0; d0 < K; d0 += (int)Ly.kp, ++pass) {
                 const int d1 = min(K, d0 + (int)Ly.kp);
-                if (ra < rb && ca < cb) {
+                if (ns && ra < rb && ca < cb) {
+                    // ordered pairs (level at v, level at v + d) by gather, into squares
+                    if constexpr (MODE != 0) {
+                        const bool merged = MODE >= 2 && a.merged;
+                        auto add = [&](uint32_t dl, uint32_t la, uint32_t ta, uint32_t lb, uint32_t tb) {
+                            add_pair<MODE, true>(a, smem, merged ? 0u : dl, la, ta, lb, tb);
+                        };
+                        accumulate_rows(a, rd, c, ra, rb, ca, cb, d0, d1, threadIdx.x, blockDim.x, add, SqOff{ng});
+                    }
+                } else if (ra < rb && ca < cb) {
                     // merged matrices: every offset counts into the one triangle
                     const bool merged = MODE >= 2 && a.merged;
                     auto add = [&](uint32_t dl, uint32_t la, uint32_t ta, uint32_t lb, uint32_t tb) {
@@ -1006,9 +1032,9 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
                     const uint32_t *lst = LST + dl * Ly.list_cap;
                     WaveGrp g;
                     if (MODE == 2 || MODE == 3) {
-                        SrcTriScan<MODE == 3> s{Ud, (ng * (ng + 1u)) >> 1,
+                        SrcTriScan<MODE == 3> s{Ud, ns ? ng * ng : (ng * (ng + 1u)) >> 1,
                                                 BUF + (uint32_t)w * kWave * SrcTriScan<MODE == 3>::kPerRead,
-                                                Ly.copies, Ly.tri_pad};
+                                                Ly.copies, Ly.tri_pad, ns ? ng : 0u};
                         dir_or_flush<Acc>(a, g, s, split, rd, roi, a.merged ? 0 : d0 + dl, MARG, ng);
                     } else if (MODE == 0) {
                         SrcDenseList s{lst, n, Ud};
@@ -1040,13 +1066,18 @@ __global__ __launch_bounds__(512) void k_split_features(StepArgs a) {
     if (slot >= min(a.counters[C_NSPLIT], a.g_cap)) return;
     const uint32_t roi = a.split_roi[slot];
     if (roi >= a.roi_cap) return;
+    const uint32_t mw = (a.nonsym ? 5u : 4u) * ng;   // marginal words
     uint32_t *R = reinterpret_cast<uint32_t *>(smem);
-    uint64_t *scratch = reinterpret_cast<uint64_t *>(smem + 16u * ng);
-    for (uint32_t i = threadIdx.x; i < 4u * ng; i += blockDim.x) R[i] = 0u;
+    uint64_t *scratch = reinterpret_cast<uint64_t *>(smem + 4u * mw);
+    for (uint32_t i = threadIdx.x; i < mw; i += blockDim.x) R[i] = 0u;
     __syncthreads();
     BlockGrp g{scratch};
-    SrcSquare s{a.G + ((uint64_t)slot * K + d) * (uint64_t)ng * ng, ng};
-    dir_sums<Acc, uint64_t>(g, s, R, R + ng, R + 3u * ng - 1u, ng, a.dsums + (uint64_t)roi * K + d);
+    SrcSquare s{a.G + ((uint64_t)slot * K + d) * (uint64_t)ng * ng, ng, a.nonsym != 0};
+    const uint64_t at = (uint64_t)roi * K + d;
+    if (a.nonsym)
+        dir_sums_ns<Acc>(g, s, R, R + ng, R + 2u * ng, R + 4u * ng - 1u, ng, a.dsums + at, a.dsums_y + at);
+    else
+        dir_sums<Acc, uint64_t>(g, s, R, R + ng, R + 3u * ng - 1u, ng, a.dsums + at);
 }
 
 // ------------------------------------------------------------------ features
@@ -1055,8 +1086,8 @@ __global__ __launch_bounds__(512) void k_split_features(StepArgs a) {
 // the non-empty directions, written as one contiguous run of the table.
 // Rows [0, n) with n = min(*n_ptr, n_cap) (n_cap without n_ptr).
 template <class OutT>
-__global__ __launch_bounds__(128) void k_features(StepArgs a, const DirSums *ds, uint32_t n_cap,
-                                                  const uint32_t *n_ptr) {
+__global__ __launch_bounds__(128) void k_features(StepArgs a, const DirSums *ds, const DirSumsY *dsy,
+                                                  uint32_t n_cap, const uint32_t *n_ptr) {
     extern __shared__ __align__(16) uint8_t smem[];
     double *feat = reinterpret_cast<double *>(smem);
     const uint32_t K = (uint32_t)a.K_out;
@@ -1065,7 +1096,10 @@ __global__ __launch_bounds__(128) void k_features(StepArgs a, const DirSums *ds,
     const uint32_t row0 = blockIdx.x * rpb;
     if (row0 >= n) return;
     uint32_t rows = min(rpb, n - row0);
-    if (threadIdx.x < rows * K) finalize_dir(ds[(uint64_t)row0 * K + threadIdx.x], feat + threadIdx.x * kNumFeat);
+    if (threadIdx.x < rows * K) {
+        const uint64_t at = (uint64_t)row0 * K + threadIdx.x;
+        finalize_dir(ds[at], a.nonsym ? dsy + at : nullptr, feat + threadIdx.x * kNumFeat);
+    }
     __syncthreads();
     if (row0 + rows > a.table_rows) {
         if (threadIdx.x == 0) atomicOr(&a.counters[C_ERR], (uint32_t)E_TABLE_CAP);
@@ -1101,7 +1135,7 @@ __global__ __launch_bounds__(256) void k_coo_count(StepArgs a, uint32_t n_slots,
     uint64_t c = 0;
     for (uint32_t e = threadIdx.x; e < ng * ng; e += blockDim.x) {
         uint32_t i = e / ng, j = e - i * ng;
-        if (i <= j && G[e]) ++c;
+        if ((i <= j || a.nonsym) && G[e]) ++c;
     }
     __shared__ uint64_t part[4];
     c = wave_sum(c);
@@ -1125,7 +1159,7 @@ __global__ __launch_bounds__(256) void k_coo_emit(StepArgs a, uint32_t n_slots, 
     for (uint32_t e0 = 0; e0 < ng * ng; e0 += blockDim.x) {
         uint32_t e = e0 + threadIdx.x;
         uint32_t i = e / ng, j = e - i * ng;
-        uint64_t v = (e < ng * ng && i <= j) ? G[e] : 0ull;
+        uint64_t v = (e < ng * ng && (i <= j || a.nonsym)) ? G[e] : 0ull;
         uint64_t m = __ballot(v != 0ull);
         if (lane() == 0) wc[threadIdx.x / 64] = (uint32_t)__popcll(m);
         __syncthreads();
@@ -1159,20 +1193,25 @@ __global__ void k_coo_segments_k(const uint64_t *keys, uint64_t nnz, uint32_t n_
 // One work-group per (roi, direction) of a COO list.
 template <class Acc>
 __global__ __launch_bounds__(512) void k_coo_features(StepArgs a, const uint64_t *keys, const uint64_t *vals,
-                                                      const uint64_t *seg, uint32_t n_rois, DirSums *sums) {
+                                                      const uint64_t *seg, uint32_t n_rois, DirSums *sums,
+                                                      DirSumsY *sums_y) {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t ng = (uint32_t)a.ng;
     const int K = a.K_out;
     const uint32_t s = blockIdx.x;
     if (s >= n_rois * (uint32_t)K) return;
+    const uint32_t mw = (a.nonsym ? 5u : 4u) * ng;   // marginal words
     uint32_t *R = reinterpret_cast<uint32_t *>(smem);
-    uint64_t *scr = reinterpret_cast<uint64_t *>(smem + 16u * ng);
-    for (uint32_t i = threadIdx.x; i < 4u * ng; i += blockDim.x) R[i] = 0u;
+    uint64_t *scr = reinterpret_cast<uint64_t *>(smem + 4u * mw);
+    for (uint32_t i = threadIdx.x; i < mw; i += blockDim.x) R[i] = 0u;
     __syncthreads();
     BlockGrp g{scr};
     SrcCoo src{keys + seg[s], vals + seg[s], (uint32_t)(seg[s + 1] - seg[s]),
-               ((uint64_t)(s / K) << 38) | ((uint64_t)(s % K) << 32), ng, &a.counters[C_ERR]};
-    dir_sums<Acc, uint64_t>(g, src, R, R + ng, R + 3u * ng - 1u, ng, sums + s);
+               ((uint64_t)(s / K) << 38) | ((uint64_t)(s % K) << 32), ng, &a.counters[C_ERR], a.nonsym != 0};
+    if (a.nonsym)
+        dir_sums_ns<Acc>(g, src, R, R + ng, R + 2u * ng, R + 4u * ng - 1u, ng, sums + s, sums_y + s);
+    else
+        dir_sums<Acc, uint64_t>(g, src, R, R + ng, R + 3u * ng - 1u, ng, sums + s);
 }
 
 // ================================================================== launchers
@@ -1322,7 +1361,7 @@ hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st) {
         hipError_t e = set_feature_kernel_attrs();
         if (e != hipSuccess) return e;
     }
-    uint32_t lds = 16u * a.ng + 16 * 8;
+    uint32_t lds = (a.nonsym ? 20u : 16u) * a.ng + 16 * 8;
     uint32_t grid = a.g_cap * a.K_out;
     if (a.fp64) hipLaunchKernelGGL(k_split_features<double>, dim3(grid), dim3(512), lds, st, a);
     else hipLaunchKernelGGL(k_split_features<float>, dim3(grid), dim3(512), lds, st, a);
@@ -1330,14 +1369,14 @@ hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st) {
     return hipSuccess;
 }
 
-hipError_t launch_features(const StepArgs &a, const DirSums *ds, uint32_t n_cap, const uint32_t *n_ptr,
-                           hipStream_t st) {
+hipError_t launch_features(const StepArgs &a, const DirSums *ds, const DirSumsY *dsy, uint32_t n_cap,
+                           const uint32_t *n_ptr, hipStream_t st) {
     if (n_cap == 0) return hipSuccess;
     const uint32_t block = 128u, rpb = block / (uint32_t)a.K_out;
     const uint32_t grid = (n_cap + rpb - 1u) / rpb;
     const uint32_t lds = rpb * (uint32_t)a.K_out * kNumFeat * 8u;
-    if (a.fp64) hipLaunchKernelGGL(k_features<double>, dim3(grid), dim3(block), lds, st, a, ds, n_cap, n_ptr);
-    else hipLaunchKernelGGL(k_features<float>, dim3(grid), dim3(block), lds, st, a, ds, n_cap, n_ptr);
+    if (a.fp64) hipLaunchKernelGGL(k_features<double>, dim3(grid), dim3(block), lds, st, a, ds, dsy, n_cap, n_ptr);
+    else hipLaunchKernelGGL(k_features<float>, dim3(grid), dim3(block), lds, st, a, ds, dsy, n_cap, n_ptr);
     NYX_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1358,7 +1397,7 @@ hipError_t launch_coo_emit(const StepArgs &a, uint32_t n_slots, const uint64_t *
 }
 
 hipError_t launch_coo_features(const StepArgs &a, const uint64_t *keys, const uint64_t *vals, uint64_t nnz,
-                               uint32_t n_rois, uint64_t *seg, DirSums *sums, hipStream_t st) {
+                               uint32_t n_rois, uint64_t *seg, DirSums *sums, DirSumsY *sums_y, hipStream_t st) {
     uint32_t n_seg = n_rois * (uint32_t)a.K_out;
     hipLaunchKernelGGL(k_coo_segments_k, dim3((n_seg + 1 + 255) / 256), dim3(256), 0, st, keys, nnz, n_rois,
                        a.K_out, seg);
@@ -1368,13 +1407,15 @@ hipError_t launch_coo_features(const StepArgs &a, const uint64_t *keys, const ui
         hipError_t e = set_feature_kernel_attrs();
         if (e != hipSuccess) return e;
     }
-    uint32_t lds = 16u * a.ng + 16 * 8;
+    uint32_t lds = (a.nonsym ? 20u : 16u) * a.ng + 16 * 8;
     if (a.fp64)
-        hipLaunchKernelGGL(k_coo_features<double>, dim3(n_seg), dim3(512), lds, st, a, keys, vals, seg, n_rois, sums);
+        hipLaunchKernelGGL(k_coo_features<double>, dim3(n_seg), dim3(512), lds, st, a, keys, vals, seg, n_rois, sums,
+                           sums_y);
     else
-        hipLaunchKernelGGL(k_coo_features<float>, dim3(n_seg), dim3(512), lds, st, a, keys, vals, seg, n_rois, sums);
+        hipLaunchKernelGGL(k_coo_features<float>, dim3(n_seg), dim3(512), lds, st, a, keys, vals, seg, n_rois, sums,
+                           sums_y);
     NYX_CHECK_LAUNCH();
-    return launch_features(a, sums, n_rois, nullptr, st);
+    return launch_features(a, sums, sums_y, n_rois, nullptr, st);
 }
 
 }  // namespace nyx

@@ -18,13 +18,13 @@ hipError_t launch_batch(const StepArgs &a, uint32_t grid, uint32_t block, uint32
 hipError_t get_batch_attributes(int mode, int fp64, hipFuncAttributes *attr);
 hipError_t batch_occupancy(int mode, int fp64, uint32_t block, uint32_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st);
-hipError_t launch_features(const StepArgs &a, const DirSums *ds, uint32_t n_cap, const uint32_t *n_ptr,
-                           hipStream_t st);
+hipError_t launch_features(const StepArgs &a, const DirSums *ds, const DirSumsY *dsy, uint32_t n_cap,
+                           const uint32_t *n_ptr, hipStream_t st);
 hipError_t launch_coo_count(const StepArgs &a, uint32_t n_slots, uint64_t *counts, hipStream_t st);
 hipError_t launch_coo_emit(const StepArgs &a, uint32_t n_slots, const uint64_t *offsets, uint64_t *keys,
                            uint64_t *vals, hipStream_t st);
 hipError_t launch_coo_features(const StepArgs &a, const uint64_t *keys, const uint64_t *vals, uint64_t nnz,
-                               uint32_t n_rois, uint64_t *seg, DirSums *sums, hipStream_t st);
+                               uint32_t n_rois, uint64_t *seg, DirSums *sums, DirSumsY *sums_y, hipStream_t st);
 hipError_t launch_intensity(const StepArgs &a, uint32_t grid, int fp64, void *table, uint32_t table_rows,
                             hipStream_t st);
 

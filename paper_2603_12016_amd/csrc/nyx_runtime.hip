@@ -156,7 +156,7 @@ struct nyx_ctx {
 // All device state of one discovery/step over a batch of images.
 struct Work {
     std::vector<ImgDesc> h_imgs;
-    DevBuf imgs, tab[10], counters, rois, buckets, G, dsums, split_roi, vox_base;
+    DevBuf imgs, tab[10], counters, rois, buckets, G, dsums, dsums_y, split_roi, vox_base;
     uint32_t tab_total = 0, n_blocks = 0, n_counters = 0, total_chunks = 0;
     uint32_t n_rois = 0;
     uint64_t total_vox = 0;
@@ -164,7 +164,7 @@ struct Work {
     StepArgs args{};
     // Carve every buffer from `ar` (nullptr: hipMalloc).
     void use_arena(Arena *ar) {
-        for (DevBuf *b : {&imgs, &counters, &rois, &buckets, &G, &dsums, &split_roi, &vox_base}) b->arena = ar;
+        for (DevBuf *b : {&imgs, &counters, &rois, &buckets, &G, &dsums, &dsums_y, &split_roi, &vox_base}) b->arena = ar;
         for (DevBuf &b : tab) b.arena = ar;
     }
 };
@@ -364,6 +364,7 @@ struct Config {
     int merged = 0;          // one matrix per ROI: the sum of the K offsets' matrices
     uint32_t copies = 1;     // privatised copies of each dense triangle (scan modes)
     float tile_scale = 1.f;  // split ROIs above tile_scale x the load-balance share
+    int nonsym = 0;          // ordered counts: full squares (dense modes 2 and 3, or the hash)
 };
 
 const char *mode_name(int m) {
@@ -379,11 +380,19 @@ const char *mode_name(int m) {
 // 16-byte read holds 8 packed 16-bit or 4 32-bit counters.
 uint32_t scan_cells(int mode) { return mode == 3 ? (uint32_t)kScanCells : (uint32_t)kScanCells / 2u; }
 
-uint32_t u_words(int mode, uint32_t ng) {
-    uint32_t tri = ng * (ng + 1u) / 2u;
+// Cells of one dense matrix: the upper triangle, or the full square of
+// ordered counts.
+uint32_t mat_cells(uint32_t ng, bool nonsym) { return nonsym ? ng * ng : ng * (ng + 1u) / 2u; }
+
+uint32_t u_words(int mode, uint32_t ng, bool nonsym = false) {
+    uint32_t tri = mat_cells(ng, nonsym);
     uint32_t w = mode == 3 ? (tri + 1u) / 2u : tri;
     return (w + 3u) & ~3u;
 }
+
+// Marginal words per reducing wave: row, sum and difference marginals, plus
+// the column marginal of an ordered matrix.
+uint32_t marg_words(uint32_t ng, bool nonsym) { return (nonsym ? 5u : 4u) * ng; }
 
 // ring: reserve an LDS level ring for the staged accumulation, sized to the
 // LDS the work-group can take without lowering its occupancy.
@@ -393,7 +402,7 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K, bool ring) {
     L.mode = (uint32_t)c.mode;
     L.kp = c.kp;
     L.nwaves = c.block / kWave;
-    L.tri_pad = u_words(c.mode, ng);
+    L.tri_pad = u_words(c.mode, ng, c.nonsym != 0);
     L.copies = (c.mode == 2 || c.mode == 3) ? c.copies : 1u;
     L.list_cap = c.list_cap;
     L.hash_cap = c.hash_cap;
@@ -414,10 +423,10 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K, bool ring) {
     L.lcnt_off = take(c.kp * 4u);
     L.buf_off = take((c.mode == 2 || c.mode == 3) ? L.nwaves * kWave * scan_cells(c.mode) * 4u : 0u);
     L.marg_sets = std::min(L.nwaves, c.merged ? 1u : c.kp);   // one set per wave that reduces a matrix
-    L.marg_off = take(L.marg_sets * 4u * ng * 4u);
+    L.marg_off = take(L.marg_sets * marg_words(ng, c.nonsym != 0) * 4u);
     L.misc_off = take(128u * 4u);
     L.item_off = take((uint32_t)kTicketChunk * kItemBytes);
-    if (ring && ng <= 255u && c.mode != 1) {
+    if (ring && ng <= 255u && c.mode != 1 && !c.nonsym) {
         // work-groups per CU: LDS-bound, and at most kMaxGroupsPerCu (the
         // single-precision kernel's register bound)
         const uint32_t per_group = kLdsBudget / std::max(1u, std::min(kMaxGroupsPerCu, kLdsBudget / off));
@@ -461,14 +470,14 @@ uint32_t groups_per_cu(uint64_t lds_bytes) {
 // load-balance share above which ROIs are split.
 std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_t ng, int K, int force_split,
                                       uint32_t block, bool merged = false, uint32_t copies = 1u,
-                                      float tile_scale = 1.f) {
+                                      float tile_scale = 1.f, bool nonsym = false) {
     std::vector<Config> out;
     const uint32_t nw = block / kWave;
-    const uint32_t tri = ng * (ng + 1u) / 2u;
+    const uint32_t tri = mat_cells(ng, nonsym);
     // LDS besides triangles / hash / lists: marginals for up to nw directions
     // at a time, misc, alignment slack
     auto fixed_for = [&](uint32_t kp) {
-        return (std::min(nw, kp) * 4u * ng * 4u + 15u) / 16u * 16u + 128u * 4u + 64u * 4u + 64;
+        return (std::min(nw, kp) * marg_words(ng, nonsym) * 4u + 15u) / 16u * 16u + 128u * 4u + 64u * 4u + 64;
     };
     const uint32_t fixed = fixed_for(1u);
     uint64_t total_vox = 0;
@@ -479,7 +488,7 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
     const uint32_t lb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(share, 4096u), 1u << 20);
     std::vector<Config> later;
     for (int mode : {3, 2, 0}) {
-        if (merged && mode == 0) continue;
+        if ((merged || nonsym) && mode == 0) continue;   // the returning-atomic list keeps triangles only
         if (copies > 1u && mode == 0) continue;   // the returning-atomic list keeps one triangle
         const uint32_t cell_max = merged ? 65535u / (uint32_t)K : 65535u;   // 16-bit counters
         uint32_t split = mode == 3 ? std::min<uint32_t>(lb, cell_max) : lb;
@@ -496,13 +505,13 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
         const uint32_t cp = scan ? copies : 1u;
         for (uint32_t kp = (uint32_t)K; kp >= (merged ? (uint32_t)K : 1u); --kp) {
             const uint32_t n_tri = merged ? 1u : kp;
-            uint64_t bytes = (uint64_t)n_tri * cp * u_words(mode, ng) * 4u + (uint64_t)kp * list_cap * 4u + kp * 4u +
+            uint64_t bytes = (uint64_t)n_tri * cp * u_words(mode, ng, nonsym) * 4u + (uint64_t)kp * list_cap * 4u + kp * 4u +
                              fixed_for(n_tri) + scan_buf;
             if (bytes <= kLdsBudget) {
                 Config c;
                 c.mode = mode; c.kp = kp; c.block = block; c.split_vox = split; c.tile_vox = split;
                 c.list_cap = list_cap; c.force_split = force_split; c.merged = merged ? 1 : 0;
-                c.copies = cp; c.tile_scale = tile_scale;
+                c.copies = cp; c.tile_scale = tile_scale; c.nonsym = nonsym ? 1 : 0;
                 out.push_back(c);
                 if (merged) break;
                 // many offsets: fewer directions per pass cost another pass
@@ -539,6 +548,7 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
                 Config c;
                 c.mode = 1; c.kp = kp; c.block = block; c.hash_cap = hc; c.split_vox = split; c.tile_vox = split;
                 c.list_cap = list_cap; c.force_split = force_split; c.tile_scale = tile_scale;
+                c.nonsym = nonsym ? 1 : 0;
                 out.push_back(c);
                 return out;
             }
@@ -572,8 +582,8 @@ Config default_config(const std::vector<Config> &cands, const Work &w, uint32_t 
 }
 
 nyx_status choose_config(nyx_ctx *ctx, const Work &w, uint32_t ng, int K, int force_split, uint32_t block,
-                         Config &cfg) {
-    std::vector<Config> c = candidate_configs(ctx, w, ng, K, force_split, block);
+                         Config &cfg, bool nonsym = false) {
+    std::vector<Config> c = candidate_configs(ctx, w, ng, K, force_split, block, false, 1u, 1.f, nonsym);
     if (c.empty()) return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%u with %d offsets", ng, K);
     cfg = default_config(c, w, ng, K);
     return NYX_OK;
@@ -639,7 +649,9 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     const int K_out = cfg.merged ? 1 : K;
     uint64_t g_bytes = (uint64_t)n_split * K_out * (uint64_t)ng * ng * 8u;
     const uint64_t sums_bytes = (uint64_t)std::max<uint32_t>(w.n_rois, 1u) * K_out * sizeof(DirSums);
-    uint64_t need = (uint64_t)kClasses * bucket_cap * 8u + g_bytes + sums_bytes + n_split * 4u;
+    const uint64_t sums_y_bytes =
+        cfg.nonsym ? (uint64_t)std::max<uint32_t>(w.n_rois, 1u) * K_out * sizeof(DirSumsY) : 16u;
+    uint64_t need = (uint64_t)kClasses * bucket_cap * 8u + g_bytes + sums_bytes + sums_y_bytes + n_split * 4u;
     for (auto &b : w.tab) need += b.bytes;
     need += w.rois.bytes + w.counters.bytes;
     if (ws_bytes) *ws_bytes = (int64_t)need;
@@ -649,12 +661,15 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     HIPC(ctx, w.buckets.alloc((size_t)kClasses * bucket_cap * sizeof(uint2)));
     HIPC(ctx, w.G.alloc(std::max<uint64_t>(g_bytes, 16u)));
     HIPC(ctx, w.dsums.alloc(sums_bytes));
+    HIPC(ctx, w.dsums_y.alloc(sums_y_bytes));
     HIPC(ctx, w.split_roi.alloc((size_t)std::max<uint32_t>(n_split, 1u) * 4u));
     a.buckets = w.buckets.as<uint2>();
     a.bucket_cap = bucket_cap;
     a.G = w.G.as<uint64_t>();
     a.g_cap = n_split;
     a.dsums = w.dsums.as<DirSums>();
+    a.dsums_y = w.dsums_y.as<DirSumsY>();
+    a.nonsym = cfg.nonsym;
     a.split_roi = w.split_roi.as<uint32_t>();
     for (int k = 0; k < K; ++k) {
         a.off[k][0] = off[k].dz;
@@ -670,7 +685,9 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     a.force_split = cfg.force_split;
     a.enqueue = 1;
     a.fp64 = fp64;
-    set_sweep(a, w.h_imgs, off, K, cfg.kp);
+    // ordered counts take the gather accumulation (no sweep, no staged ring)
+    if (cfg.nonsym) a.sweep_ok = 0;
+    else set_sweep(a, w.h_imgs, off, K, cfg.kp);
     a.lds = make_layout(cfg, ng, K, !a.sweep_ok);
     return NYX_OK;
 }
@@ -702,7 +719,7 @@ nyx_status enqueue_step(nyx_plan *p, hipStream_t st, bool per_roi) {
         for (uint32_t r = 0; r < p->w.n_rois; ++r) HIPC(ctx, launch_batch(a, p->roi_tiles[r], p->block, r, st));
     }
     HIPC(ctx, launch_split_finalize(a, st));
-    HIPC(ctx, launch_features(a, a.dsums, a.roi_cap, a.counters + C_NROIS, st));
+    HIPC(ctx, launch_features(a, a.dsums, a.dsums_y, a.roi_cap, a.counters + C_NROIS, st));
     return NYX_OK;
 }
 
@@ -725,9 +742,9 @@ nyx_status check_counters(nyx_ctx *ctx, Work &w, hipStream_t st) {
 std::string describe(const Config &c, const nyx_plan *p, uint64_t items, uint32_t n_split) {
     char buf[512];
     snprintf(buf, sizeof buf,
-             "mode=%s kp=%u copies=%u block=%u grid=%u lds=%uB split_vox=%u tile_vox=%u tile_scale=%g list_cap=%u "
-             "hash_cap=%u rois=%u items=%llu split_rois=%u ng=%d K=%d tuned_ms=%.4f",
-             mode_name(c.mode), c.kp, p->w.args.lds.copies, c.block, p->grid, p->w.args.lds.bytes, c.split_vox,
+             "mode=%s kp=%u copies=%u symmetric=%d block=%u grid=%u lds=%uB split_vox=%u tile_vox=%u tile_scale=%g "
+             "list_cap=%u hash_cap=%u rois=%u items=%llu split_rois=%u ng=%d K=%d tuned_ms=%.4f",
+             mode_name(c.mode), c.kp, p->w.args.lds.copies, c.nonsym ? 0 : 1, c.block, p->grid, p->w.args.lds.bytes, c.split_vox,
              c.tile_vox, (double)c.tile_scale, c.list_cap, c.hash_cap, p->w.n_rois, (unsigned long long)items,
              n_split, p->ng, p->K, (double)p->tuned_ms);
     return buf;
@@ -859,7 +876,8 @@ nyx_status nyx_glcm_accumulate(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_im
     if ((s = validate_offsets(ctx, imgs, n_images, offsets, K)) != NYX_OK) return s;
     if (n_bins < 2 || n_bins > 65535) return fail(ctx, NYX_ERR_INVALID, "n_bins must be in [2, 65535]");
     if ((s = validate_bins(ctx, n_bins)) != NYX_OK) return s;
-    if (symmetric != 1) return fail(ctx, NYX_ERR_UNSUPPORTED, "only symmetric matrices are supported");
+    if (symmetric != 0 && symmetric != 1) return fail(ctx, NYX_ERR_INVALID, "symmetric must be 0 or 1");
+    const bool nonsym = symmetric == 0;
     hipStream_t st = (hipStream_t)stream;
     HIPC(ctx, hipSetDevice(ctx->device));
     Work w;
@@ -875,7 +893,7 @@ nyx_status nyx_glcm_accumulate(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_im
     if ((s = fetch_rois(ctx, w, st)) != NYX_OK) return s;
     const uint32_t ng = (uint32_t)n_bins;
     Config cfg;
-    if ((s = choose_config(ctx, w, ng, K, 1, 256, cfg)) != NYX_OK) return s;
+    if ((s = choose_config(ctx, w, ng, K, 1, 256, cfg, nonsym)) != NYX_OK) return s;
     // ROIs in batches whose global matrices fit a fixed budget
     const uint64_t per_roi = (uint64_t)K * ng * ng * 8u;
     const uint64_t budget = 2ull << 30;
@@ -923,7 +941,7 @@ nyx_status nyx_glcm_accumulate(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_im
             if (out->nnz_host) *out->nnz_host = (int64_t)nnz_total;
             out->n_bins = n_bins;
             out->n_offsets = K;
-            out->symmetric = 1;
+            out->symmetric = symmetric;
             out->n_rois = w.n_rois;
             if (out->capacity < (int64_t)nnz_total)
                 return fail(ctx, NYX_ERR_CAPACITY, "COO capacity %lld < %llu nonzero cells", (long long)out->capacity,
@@ -989,14 +1007,16 @@ nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, const nyx_roi_t
     uint64_t nnz = glcm->nnz_host ? (uint64_t)*glcm->nnz_host : 0u;
     if (nnz && (!glcm->key || !glcm->count)) return fail(ctx, NYX_ERR_INVALID, "COO arrays are NULL");
     if (prec != NYX_FP32 && prec != NYX_FP64) return fail(ctx, NYX_ERR_INVALID, "bad precision");
+    if (glcm->symmetric != 0 && glcm->symmetric != 1) return fail(ctx, NYX_ERR_INVALID, "symmetric must be 0 or 1");
     hipStream_t st = (hipStream_t)stream;
     HIPC(ctx, hipSetDevice(ctx->device));
     const uint32_t n_rois = (uint32_t)glcm->n_rois;
     const int K = glcm->n_offsets;
     if (n_rois == 0) return NYX_OK;
-    DevBuf seg, scratch, counters;
+    DevBuf seg, scratch, scratch_y, counters;
     HIPC(ctx, seg.alloc(((size_t)n_rois * K + 1) * 8u));
     HIPC(ctx, scratch.alloc((size_t)n_rois * K * sizeof(DirSums)));
+    HIPC(ctx, scratch_y.alloc((size_t)n_rois * K * sizeof(DirSumsY)));
     HIPC(ctx, counters.alloc(256));
     HIPC(ctx, hipMemsetAsync(counters.p, 0, 256, st));
     StepArgs a;
@@ -1008,7 +1028,9 @@ nyx_status nyx_glcm_features(nyx_ctx *ctx, const nyx_glcm *glcm, const nyx_roi_t
     a.table = table;
     a.table_rows = (uint32_t)std::min<int64_t>(table_capacity_rows, 0xFFFFFFFFll);
     a.counters = counters.as<uint32_t>();
-    HIPC(ctx, launch_coo_features(a, glcm->key, glcm->count, nnz, n_rois, seg.as<uint64_t>(), scratch.as<DirSums>(), st));
+    a.nonsym = glcm->symmetric == 0;
+    HIPC(ctx, launch_coo_features(a, glcm->key, glcm->count, nnz, n_rois, seg.as<uint64_t>(), scratch.as<DirSums>(),
+                                  scratch_y.as<DirSumsY>(), st));
     uint32_t herr = 0;
     HIPC(ctx, hipMemcpyAsync(&herr, counters.as<uint32_t>() + C_ERR, 4, hipMemcpyDeviceToHost, st));
     HIPC(ctx, hipStreamSynchronize(st));
@@ -1030,7 +1052,7 @@ nyx_status plan_init(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images, cons
     if ((s = validate_offsets(ctx, imgs, n_images, opts->offsets_host, opts->n_offsets)) != NYX_OK) return s;
     if (opts->n_bins < 2 || opts->n_bins > 65535) return fail(ctx, NYX_ERR_INVALID, "n_bins must be in [2, 65535]");
     if ((s = validate_bins(ctx, opts->n_bins)) != NYX_OK) return s;
-    if (opts->symmetric != 1) return fail(ctx, NYX_ERR_UNSUPPORTED, "only symmetric matrices are supported");
+    if (opts->symmetric != 0 && opts->symmetric != 1) return fail(ctx, NYX_ERR_INVALID, "symmetric must be 0 or 1");
     if (opts->precision != NYX_FP32 && opts->precision != NYX_FP64) return fail(ctx, NYX_ERR_INVALID, "bad precision");
     if (opts->aggregate != NYX_AGG_PER_OFFSET && opts->aggregate != NYX_AGG_MERGED)
         return fail(ctx, NYX_ERR_INVALID, "aggregate must be NYX_AGG_PER_OFFSET or NYX_AGG_MERGED");
@@ -1047,7 +1069,8 @@ nyx_status plan_init(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images, cons
     const bool merged = opts->aggregate == NYX_AGG_MERGED;
     // the default plan: one copy (or the forced count) at the load-balance tile size
     const uint32_t copies0 = opts->copies > 0 ? (uint32_t)opts->copies : 1u;
-    cands = candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256, merged, copies0);
+    const bool nonsym = opts->symmetric == 0;
+    cands = candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256, merged, copies0, 1.f, nonsym);
     if (cands.empty())
         return fail(ctx, NYX_ERR_UNSUPPORTED, "no LDS configuration fits n_bins=%d with %d offsets%s%s", p->ng, p->K,
                     merged ? " merged in one pass" : "", copies0 > 1u ? " with privatised copies" : "");
@@ -1084,7 +1107,8 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
             if (opts->copies > 0 && cp != copies0) continue;
             for (float ts : {0.5f, 1.f, 2.f}) {
                 if (cp == copies0 && ts == 1.f) continue;
-                for (const Config &c : candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256, merged, cp, ts))
+                for (const Config &c :
+                     candidate_configs(ctx, p->w, (uint32_t)p->ng, p->K, 0, 256, merged, cp, ts, opts->symmetric == 0))
                     if (cp == 1u || c.copies == cp) cands.push_back(c);
             }
         }
@@ -1209,7 +1233,7 @@ nyx_status nyx_plan_profile(nyx_plan *p, void *table, float *ms_host, nyx_stream
     if (he == hipSuccess) he = hipEventRecord(ev[6], st);
     if (he == hipSuccess) he = launch_split_finalize(a, st);
     if (he == hipSuccess) he = hipEventRecord(ev[7], st);
-    if (he == hipSuccess) he = launch_features(a, a.dsums, a.roi_cap, a.counters + C_NROIS, st);
+    if (he == hipSuccess) he = launch_features(a, a.dsums, a.dsums_y, a.roi_cap, a.counters + C_NROIS, st);
     if (he == hipSuccess) he = hipEventRecord(ev[8], st);
     if (he == hipSuccess) he = hipEventSynchronize(ev[8]);
     if (he == hipSuccess)

@@ -92,6 +92,15 @@ struct DirSums {
     double CSHADE, CPROM, MI;
 };
 static_assert(sizeof(DirSums) == 160, "DirSums layout");
+// The column-marginal sums of a non-symmetric matrix (for a symmetric one
+// they equal the row-marginal sums S1, S2, rlr of DirSums):
+//   S1y = sum_j j C(j), S2y = sum_j j^2 C(j), clc = sum_j C(j) log2 C(j)
+// with C the column marginal.
+struct DirSumsY {
+    uint64_t S1y, S2y;
+    double clc, spare;
+};
+static_assert(sizeof(DirSumsY) == 32, "DirSumsY layout");
 constexpr int kSumSlots = 16;
 // ROI discovery tiles: rows (of all z-planes, flattened) x columns; one
 // work-group of kScanTileCols threads per tile.
@@ -131,6 +140,8 @@ struct StepArgs {
     uint64_t *G;                // split-ROI dense matrices: g_cap slots of K * ng * ng
     uint32_t g_cap;
     DirSums *dsums;             // roi_cap * K reduced sums, row-major by ROI
+    DirSumsY *dsums_y;          // roi_cap * K column-marginal sums (non-symmetric matrices only)
+    int32_t nonsym;             // 1: ordered counts P = C (full ng x ng squares), 0: symmetric P = C + C^T
     uint32_t *split_roi;        // g_cap: ROI row of each split slot
     int32_t off[kMaxOffsets][3];
     int32_t K;                  // offsets

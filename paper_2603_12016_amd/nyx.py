@@ -168,9 +168,9 @@ NYX_AGG_PER_OFFSET, NYX_AGG_MERGED = 0, 1
 
 
 def _opts(n_bins, offsets, precision, autotune=0, workspace_cap=0, mode="auto", copies=0,
-          aggregate=NYX_AGG_PER_OFFSET):
+          aggregate=NYX_AGG_PER_OFFSET, symmetric=True):
     arr, K = _offsets(offsets)
-    o = nyx_extract_opts(int(n_bins), ctypes.cast(arr, POINTER(nyx_offset)), K, 1, int(precision),
+    o = nyx_extract_opts(int(n_bins), ctypes.cast(arr, POINTER(nyx_offset)), K, 1 if symmetric else 0, int(precision),
                          int(autotune), int(MODES[mode] if isinstance(mode, str) else mode), int(copies),
                          int(workspace_cap), int(aggregate))
     return o, arr
@@ -223,15 +223,18 @@ class RoiTable:
 
 
 class Glcm:
-    """Sorted COO of upper-triangle counts: keys roi<<38 | dir<<32 | (i-1)<<16 | (j-1)."""
+    """Sorted COO of counts: keys roi<<38 | dir<<32 | (i-1)<<16 | (j-1); the upper
+    triangle of symmetric matrices, or every cell of ordered (non-symmetric) ones."""
 
-    def __init__(self, keys, counts, nnz, n_bins, n_offsets, n_rois):
+    def __init__(self, keys, counts, nnz, n_bins, n_offsets, n_rois, symmetric=True):
         self.keys, self.counts = keys, counts
         self.nnz, self.n_bins, self.n_offsets, self.n_rois = nnz, n_bins, n_offsets, n_rois
+        self.symmetric = bool(symmetric)
 
     def struct(self, nnz_box: c_int64) -> nyx_glcm:
         return nyx_glcm(self.keys.data_ptr() if self.nnz else None, self.counts.data_ptr() if self.nnz else None,
-                        self.nnz, ctypes.pointer(nnz_box), self.n_bins, self.n_offsets, 1, self.n_rois)
+                        self.nnz, ctypes.pointer(nnz_box), self.n_bins, self.n_offsets, 1 if self.symmetric else 0,
+                        self.n_rois)
 
 
 class Plan:
@@ -294,7 +297,8 @@ def nyx_bin_rois(ctx: Ctx, images, n_bins: int, want_bins: bool = False, stream=
     return rois, bins
 
 
-def nyx_glcm_accumulate(ctx: Ctx, images, rois: RoiTable, n_bins: int, offsets, bins=None, stream=None) -> Glcm:
+def nyx_glcm_accumulate(ctx: Ctx, images, rois: RoiTable, n_bins: int, offsets, bins=None, stream=None,
+                        symmetric: bool = True) -> Glcm:
     imgs = _images(images)
     offs, K = _offsets(offsets)
     dev = _dev()
@@ -303,7 +307,7 @@ def nyx_glcm_accumulate(ctx: Ctx, images, rois: RoiTable, n_bins: int, offsets, 
     rs = rois.struct() if rois is not None else None
     bptr = bins.data_ptr() if bins is not None else None
     status = lib().nyx_glcm_accumulate(ctx.handle, imgs, len(images), byref(rs) if rs is not None else None, bptr,
-                                       offs, K, 1, int(n_bins), byref(out), _stream(stream))
+                                       offs, K, 1 if symmetric else 0, int(n_bins), byref(out), _stream(stream))
     if status not in (NYX_OK, NYX_ERR_CAPACITY):
         _check(status, ctx)
     n = int(nnz.value)
@@ -311,8 +315,8 @@ def nyx_glcm_accumulate(ctx: Ctx, images, rois: RoiTable, n_bins: int, offsets, 
     counts = torch.zeros(max(n, 1), dtype=torch.int64, device=dev)
     out = nyx_glcm(keys.data_ptr(), counts.data_ptr(), n, ctypes.pointer(nnz), 0, 0, 1, 0)
     _check(lib().nyx_glcm_accumulate(ctx.handle, imgs, len(images), byref(rs) if rs is not None else None, bptr,
-                                     offs, K, 1, int(n_bins), byref(out), _stream(stream)), ctx)
-    return Glcm(keys[:n], counts[:n], n, int(n_bins), K, int(out.n_rois))
+                                     offs, K, 1 if symmetric else 0, int(n_bins), byref(out), _stream(stream)), ctx)
+    return Glcm(keys[:n], counts[:n], n, int(n_bins), K, int(out.n_rois), symmetric)
 
 
 def nyx_glcm_features(ctx: Ctx, glcm: Glcm, precision: int = NYX_FP32, stream=None, capacity=None,
@@ -359,11 +363,12 @@ def nyx_intensity_features(ctx: Ctx, images, n_bins: int, precision: int = NYX_F
 
 
 def nyx_extract_batch(ctx: Ctx, images, n_bins: int, offsets, precision: int = NYX_FP32, stream=None,
-                      capacity=None, mode="auto", copies: int = 0, aggregate: int = NYX_AGG_PER_OFFSET):
+                      capacity=None, mode="auto", copies: int = 0, aggregate: int = NYX_AGG_PER_OFFSET,
+                      symmetric: bool = True):
     """One-shot extraction: returns (RoiTable, table (n, blocks, 30)), blocks = K + 1, or 1 when the
     offsets' matrices are merged."""
     imgs = _images(images)
-    opts, keep = _opts(n_bins, offsets, precision, mode=mode, copies=copies, aggregate=aggregate)
+    opts, keep = _opts(n_bins, offsets, precision, mode=mode, copies=copies, aggregate=aggregate, symmetric=symmetric)
     dev = _dev()
     if capacity is None:
         probe = RoiTable(0, dev)
@@ -384,11 +389,11 @@ def nyx_extract_batch(ctx: Ctx, images, n_bins: int, offsets, precision: int = N
 
 def nyx_extract_batch_noalloc(ctx: Ctx, images, n_bins: int, offsets, rois: RoiTable, table,
                               precision: int = NYX_FP32, stream=None, mode="auto", copies: int = 0,
-                              aggregate: int = NYX_AGG_PER_OFFSET) -> int:
+                              aggregate: int = NYX_AGG_PER_OFFSET, symmetric: bool = True) -> int:
     """The pass of nyx_extract_batch into caller-allocated `rois` and `table`
     without any device allocation in the library; returns the ROI count."""
     imgs = _images(images)
-    opts, keep = _opts(n_bins, offsets, precision, mode=mode, copies=copies, aggregate=aggregate)
+    opts, keep = _opts(n_bins, offsets, precision, mode=mode, copies=copies, aggregate=aggregate, symmetric=symmetric)
     st = rois.struct()
     cap = int(table.shape[0]) if table is not None else 0
     _check(lib().nyx_extract_batch_noalloc(ctx.handle, imgs, len(images), byref(opts), byref(st),
@@ -399,11 +404,11 @@ def nyx_extract_batch_noalloc(ctx: Ctx, images, n_bins: int, offsets, rois: RoiT
 
 def nyx_plan_create(ctx: Ctx, images, n_bins: int, offsets, precision: int = NYX_FP32, autotune: bool = False,
                     workspace_cap: int = 0, mode="auto", copies: int = 0,
-                    aggregate: int = NYX_AGG_PER_OFFSET) -> Plan:
+                    aggregate: int = NYX_AGG_PER_OFFSET, symmetric: bool = True) -> Plan:
     """mode: accumulation mode name (MODES) or -1/auto; copies: privatised LDS triangle copies per
     direction (0 automatic, else 1, 2 or 4)."""
     imgs = _images(images)
-    opts, keep = _opts(n_bins, offsets, precision, int(autotune), workspace_cap, mode, copies, aggregate)
+    opts, keep = _opts(n_bins, offsets, precision, int(autotune), workspace_cap, mode, copies, aggregate, symmetric)
     h = c_void_p()
     n = c_int64(0)
     _check(lib().nyx_plan_create(ctx.handle, imgs, len(images), byref(opts), byref(h), byref(n)), ctx)
