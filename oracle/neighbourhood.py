@@ -125,6 +125,12 @@ def dependence_features(S: np.ndarray) -> dict:
         "LDLGLE": _fsum(p / (i * i * k * k)),
         "LGLCE": _fsum(p / (i * i)),
     }
+    # a variance of a distribution on one value is exactly 0 [A17 of the
+    # GLCM readings, decided on the integer counts]
+    if np.count_nonzero(rows) == 1:
+        f["GLV"] = 0.0
+    if np.count_nonzero(cols) == 1:
+        f["DCV"] = 0.0
     # the GLDM names of the same quantities [N7]
     g = {"SDE": f["LDE"], "LDE": f["HDE"], "GLN": f["GLNU"], "DN": f["DCNU"], "DNN": f["DCNUN"], "GLV": f["GLV"],
          "DV": f["DCV"], "DE": f["DCENT"], "LGLE": f["LGLCE"], "HGLE": f["HGLCE"], "SDLGLE": f["LDLGLE"],

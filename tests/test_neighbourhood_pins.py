@@ -141,3 +141,4 @@ def test_isolated_voxels():
     f = dict(zip(nb.NAMES, nb.features(I, M, 4)))
     assert all(math.isnan(f["NGTDM_" + k]) for k in nb.NGTDM_NAMES)
     assert f["NGLDM_DCM"] == 1.0 and f["NGLDM_LDE"] == 1.0 and f["GLDM_SDE"] == 1.0
+    assert f["NGLDM_DCV"] == 0.0 and f["GLDM_DV"] == 0.0   # one dependence value
