@@ -230,6 +230,34 @@ nyx_status nyx_intensity_features(nyx_ctx *ctx, const nyx_image *imgs_host, int3
                                   nyx_precision prec, nyx_roi_table *rois, void *table,
                                   int64_t table_capacity_rows, nyx_stream stream);
 
+/* Neighbourhood texture features of every ROI from one scan of each ROI
+ * voxel's neighbourhood: the neighbouring grey level dependence matrix
+ * (NGLDM, Supplementary Table S3 rows 175-192), the neighbourhood grey tone
+ * difference matrix (NGTDM, rows 246-250) and the grey level dependence
+ * matrix (GLDM, rows 251-264), the rows with the NY mark, in the column
+ * order of nyx_neighbourhood_feature_name(0..36): 18 NGLDM_*, 5 NGTDM_*,
+ * 14 GLDM_* columns.  Levels are the fixed-bin-number levels of the texture
+ * features (n_bins); the neighbourhood is Chebyshev distance 1 (8 neighbours
+ * in a plane, 26 in a volume), neighbours outside the image or the ROI do
+ * not take part.  Dependence k = 1 + the neighbours whose level differs by at
+ * most alpha (>= 0); S(i, k) counts the voxels of level i and dependence k,
+ * and the NGLDM and GLDM columns are its emphases, non-uniformities, means,
+ * variances, energy and entropy (log2) with p = S / voxels.  NGTDM: n_i
+ * counts the voxels of level i with at least one neighbour, s_i sums
+ * |i - mean neighbour level| over them; COARSENESS, CONTRAST, BUSYNESS,
+ * COMPLEXITY, STRENGTH use p_i = n_i / sum n; a flat texture gives
+ * COARSENESS = 1e6 and 0 for CONTRAST, BUSYNESS and STRENGTH, an ROI without
+ * neighbouring voxels NaN for all five.  table: n_rois rows of 37 values,
+ * float (NYX_FP32) or double (NYX_FP64), computed in double from exact
+ * integer counts.  rois (nullable) receives the ROI table.  The per-ROI
+ * tables live in LDS: NYX_ERR_UNSUPPORTED above about 1300 levels for 2D
+ * images and 460 with a volume in the batch.  Synchronises the stream. */
+int32_t nyx_neighbourhood_feature_count(void);         /* 37 */
+const char *nyx_neighbourhood_feature_name(int32_t f); /* NULL outside [0, 37) */
+nyx_status nyx_neighbourhood_features(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n_images, int32_t n_bins,
+                                      int32_t alpha, nyx_precision prec, nyx_roi_table *rois, void *table,
+                                      int64_t table_capacity_rows, nyx_stream stream);
+
 /* Whole path in one call: plan, execute once, destroy the plan. */
 nyx_status nyx_extract_batch(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n_images,
                              const nyx_extract_opts *opts, nyx_roi_table *rois, void *table,

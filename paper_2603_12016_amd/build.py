@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/nyx_kernels.hip", "csrc/nyx_intensity.hip", "csrc/nyx_runtime.hip"]
+SOURCES = ["csrc/nyx_kernels.hip", "csrc/nyx_intensity.hip", "csrc/nyx_neighbourhood.hip", "csrc/nyx_runtime.hip"]
 HEADERS = ["csrc/nyx_types.h", "csrc/nyx_device.h", "csrc/nyx_features.h", "csrc/nyx_launch.h"]
 LIB = os.path.join(HERE, "libnyx.so")
 MICRO_SOURCES = ["csrc/nyx_micro.hip"]

@@ -213,6 +213,59 @@ __device__ __forceinline__ F wave_sum_comp(Comp<F> a) {
     return t.s + t.c;
 }
 
+// ------------------------------------------------------------ block reductions
+// Reduction over a work-group of NW wavefronts (every thread gets the
+// result); red is LDS room for one 8-byte value per wavefront.
+template <int NW, class T, class Op>
+__device__ __forceinline__ T block_reduce(T v, uint64_t *red, Op op) {
+    static_assert(sizeof(T) <= 8, "one 8-byte slot per wavefront");
+    v = wave_reduce(v, op);
+    __syncthreads();
+    if (lane() == 0) reinterpret_cast<T *>(red)[threadIdx.x / kWave] = v;
+    __syncthreads();
+    T r = reinterpret_cast<const T *>(red)[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) r = op(r, reinterpret_cast<const T *>(red)[w]);
+    return r;
+}
+
+template <int NW, class T>
+__device__ __forceinline__ T block_sum(T v, uint64_t *red) {
+    return block_reduce<NW>(v, red, OpAdd());
+}
+
+// ------------------------------------------------------------ box walk
+// Walks the voxels of a bounding box of W x H x D voxels, BS at a time:
+// thread t visits f = t + k BS in x-fastest order, tracked as (column, row,
+// plane) offsets without divisions after the first step.
+template <uint32_t BS>
+struct BoxWalk {
+    uint32_t W, H, n, f, x, y, z, dq, dx;
+    __device__ __forceinline__ BoxWalk(uint32_t W_, uint32_t H_, uint32_t D_) : W(W_), H(H_) {
+        n = W * H * D_;
+        f = threadIdx.x;
+        dq = BS / W;
+        dx = BS - dq * W;
+        x = f % W;
+        const uint32_t r = f / W;
+        y = r % H;
+        z = r / H;
+    }
+    __device__ __forceinline__ bool ok() const { return f < n; }
+    __device__ __forceinline__ void next() {
+        f += BS;
+        x += dx;
+        uint32_t adv = dq;
+        if (x >= W) { x -= W; ++adv; }
+        y += adv;
+        if (y >= H) {
+            const uint32_t k = y / H;
+            z += k;
+            y -= k * H;
+        }
+    }
+};
+
 // ------------------------------------------------------------ 128-bit
 typedef unsigned __int128 u128;
 typedef __int128 i128;

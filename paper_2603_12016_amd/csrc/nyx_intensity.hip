@@ -82,61 +82,6 @@ struct FoShared {
     uint32_t n_slots;
 };
 
-// Sum over the work-group (every thread gets the total).
-template <class T>
-__device__ __forceinline__ T block_sum(T v, uint64_t *red) {
-    v = wave_sum(v);
-    __syncthreads();
-    if (lane() == 0) reinterpret_cast<T *>(red)[threadIdx.x / kWave] = v;
-    __syncthreads();
-    T r = 0;
-#pragma unroll
-    for (int w = 0; w < kFoWaves; ++w) r += reinterpret_cast<const T *>(red)[w];
-    return r;
-}
-
-template <class T, class Op>
-__device__ __forceinline__ T block_reduce(T v, uint64_t *red, Op op) {
-    v = wave_reduce(v, op);
-    __syncthreads();
-    if (lane() == 0) reinterpret_cast<T *>(red)[threadIdx.x / kWave] = v;
-    __syncthreads();
-    T r = reinterpret_cast<const T *>(red)[0];
-#pragma unroll
-    for (int w = 1; w < kFoWaves; ++w) r = op(r, reinterpret_cast<const T *>(red)[w]);
-    return r;
-}
-
-// Walks the voxels of a bounding box, kFoBlock at a time: f = threadIdx.x +
-// k kFoBlock in x-fastest order, tracked as (column, row, plane) offsets
-// without divisions after the first step.
-struct BoxWalk {
-    uint32_t W, H, n, f, x, y, z, dq, dx;
-    __device__ __forceinline__ BoxWalk(uint32_t W_, uint32_t H_, uint32_t D_) : W(W_), H(H_) {
-        n = W * H * D_;
-        f = threadIdx.x;
-        dq = kFoBlock / W;
-        dx = kFoBlock - dq * W;
-        x = f % W;
-        const uint32_t r = f / W;
-        y = r % H;
-        z = r / H;
-    }
-    __device__ __forceinline__ bool ok() const { return f < n; }
-    __device__ __forceinline__ void next() {
-        f += kFoBlock;
-        x += dx;
-        uint32_t adv = dq;
-        if (x >= W) { x -= W; ++adv; }
-        y += adv;
-        if (y >= H) {
-            const uint32_t k = y / H;
-            z += k;
-            y -= k * H;
-        }
-    }
-};
-
 }  // namespace
 
 // One work-group per ROI: the kNumIntensityFeat features of ROI blockIdx.x.
@@ -180,7 +125,7 @@ __global__ __launch_bounds__(kFoBlock) void k_intensity(const ImgDesc *imgs, int
     uint32_t cnt = 0, ecnt = 0, emin = 0xFFFFFFFFu, emax = 0u;
     uint64_t s1 = 0, s2 = 0, cx = 0, cy = 0, cz = 0, es1 = 0, es2 = 0;
     const bool vol = im.nz > 1;
-    for (BoxWalk b(W, H, Dz); b.ok(); b.next()) {
+    for (BoxWalk<kFoBlock> b(W, H, Dz); b.ok(); b.next()) {
         const int32_t X = rd.x0 + (int32_t)b.x, Y = rd.y0 + (int32_t)b.y, Z = rd.z0 + (int32_t)b.z;
         const uint32_t v = (uint32_t)Z * plane + (uint32_t)Y * nx + (uint32_t)X;
         if (ldg(im.L, v) != label) continue;
@@ -205,11 +150,11 @@ __global__ __launch_bounds__(kFoBlock) void k_intensity(const ImgDesc *imgs, int
             emax = max(emax, x);
         }
     }
-    const uint64_t n = block_sum<uint64_t>(cnt, S.red);
-    const uint64_t S1 = block_sum(s1, S.red), S2 = block_sum(s2, S.red);
-    const uint64_t CX = block_sum(cx, S.red), CY = block_sum(cy, S.red), CZ = block_sum(cz, S.red);
-    const uint64_t ne = block_sum<uint64_t>(ecnt, S.red), ES1 = block_sum(es1, S.red), ES2 = block_sum(es2, S.red);
-    const uint32_t EMIN = block_reduce(emin, S.red, OpMin()), EMAX = block_reduce(emax, S.red, OpMax());
+    const uint64_t n = block_sum<kFoWaves, uint64_t>(cnt, S.red);
+    const uint64_t S1 = block_sum<kFoWaves>(s1, S.red), S2 = block_sum<kFoWaves>(s2, S.red);
+    const uint64_t CX = block_sum<kFoWaves>(cx, S.red), CY = block_sum<kFoWaves>(cy, S.red), CZ = block_sum<kFoWaves>(cz, S.red);
+    const uint64_t ne = block_sum<kFoWaves, uint64_t>(ecnt, S.red), ES1 = block_sum<kFoWaves>(es1, S.red), ES2 = block_sum<kFoWaves>(es2, S.red);
+    const uint32_t EMIN = block_reduce<kFoWaves>(emin, S.red, OpMin()), EMAX = block_reduce<kFoWaves>(emax, S.red, OpMax());
     if (n == 0) {
         // (cannot happen for a ROI found by discovery)
         for (uint32_t f = threadIdx.x; f < (uint32_t)kNumIntensityFeat; f += kFoBlock) out[f] = (OutT)__builtin_nan("");
@@ -260,7 +205,7 @@ __global__ __launch_bounds__(kFoBlock) void k_intensity(const ImgDesc *imgs, int
     // ---- pass B: centred moments; fine histograms of the rank buckets
     double m2 = 0.0, m3 = 0.0, m4 = 0.0, m5 = 0.0, m6 = 0.0, mad = 0.0;
     const uint32_t fmask = (1u << sh) - 1u;
-    for (BoxWalk b(W, H, Dz); b.ok(); b.next()) {
+    for (BoxWalk<kFoBlock> b(W, H, Dz); b.ok(); b.next()) {
         const uint32_t v = (uint32_t)(rd.z0 + (int32_t)b.z) * plane + (uint32_t)(rd.y0 + (int32_t)b.y) * nx +
                            (uint32_t)(rd.x0 + (int32_t)b.x);
         if (ldg(im.L, v) != label) continue;
@@ -277,12 +222,12 @@ __global__ __launch_bounds__(kFoBlock) void k_intensity(const ImgDesc *imgs, int
             if (s) atomicAdd(&S.fine[s - 1u][q & fmask], 1u);
         }
     }
-    m2 = block_sum(m2, S.red);
-    m3 = block_sum(m3, S.red);
-    m4 = block_sum(m4, S.red);
-    m5 = block_sum(m5, S.red);
-    m6 = block_sum(m6, S.red);
-    mad = block_sum(mad, S.red);
+    m2 = block_sum<kFoWaves>(m2, S.red);
+    m3 = block_sum<kFoWaves>(m3, S.red);
+    m4 = block_sum<kFoWaves>(m4, S.red);
+    m5 = block_sum<kFoWaves>(m5, S.red);
+    m6 = block_sum<kFoWaves>(m6, S.red);
+    mad = block_sum<kFoWaves>(mad, S.red);
     if (fine_needed && threadIdx.x < (uint32_t)kFoRanks) {
         const uint32_t k = threadIdx.x, b = S.rank_bucket[k], s = S.slot[b] - 1u;
         uint32_t acc = 0, f = 0;
@@ -307,7 +252,7 @@ __global__ __launch_bounds__(kFoBlock) void k_intensity(const ImgDesc *imgs, int
     double dmed = 0.0;
     uint32_t rc = 0;
     uint64_t rs = 0;
-    for (BoxWalk b(W, H, Dz); b.ok(); b.next()) {
+    for (BoxWalk<kFoBlock> b(W, H, Dz); b.ok(); b.next()) {
         const uint32_t v = (uint32_t)(rd.z0 + (int32_t)b.z) * plane + (uint32_t)(rd.y0 + (int32_t)b.y) * nx +
                            (uint32_t)(rd.x0 + (int32_t)b.x);
         if (ldg(im.L, v) != label) continue;
@@ -315,14 +260,14 @@ __global__ __launch_bounds__(kFoBlock) void k_intensity(const ImgDesc *imgs, int
         dmed += fabs(x - med);
         if (x >= p10 && x <= p90) { ++rc; rs += (uint64_t)x; }
     }
-    dmed = block_sum(dmed, S.red);
-    const uint64_t RC = block_sum<uint64_t>(rc, S.red), RS = block_sum(rs, S.red);
+    dmed = block_sum<kFoWaves>(dmed, S.red);
+    const uint64_t RC = block_sum<kFoWaves, uint64_t>(rc, S.red), RS = block_sum<kFoWaves>(rs, S.red);
     const double mus = (double)RS / (double)RC;   // NaN when no value lies in [P10, P90]
 
     // ---- pass D: distance of the values within [P10, P90] to their mean
     double rmad = 0.0;
     if (RC) {
-        for (BoxWalk b(W, H, Dz); b.ok(); b.next()) {
+        for (BoxWalk<kFoBlock> b(W, H, Dz); b.ok(); b.next()) {
             const uint32_t v = (uint32_t)(rd.z0 + (int32_t)b.z) * plane + (uint32_t)(rd.y0 + (int32_t)b.y) * nx +
                                (uint32_t)(rd.x0 + (int32_t)b.x);
             if (ldg(im.L, v) != label) continue;
@@ -330,7 +275,7 @@ __global__ __launch_bounds__(kFoBlock) void k_intensity(const ImgDesc *imgs, int
             if (x >= p10 && x <= p90) rmad += fabs(x - mus);
         }
     }
-    rmad = block_sum(rmad, S.red);
+    rmad = block_sum<kFoWaves>(rmad, S.red);
 
     // ---- level histogram: mode (lowest level among ties), entropy, uniformity
     uint32_t best_c = 0, best_l = 0xFFFFFFFFu;
@@ -344,11 +289,11 @@ __global__ __launch_bounds__(kFoBlock) void k_intensity(const ImgDesc *imgs, int
             uni += p * p;
         }
     }
-    ent = block_sum(ent, S.red);
-    uni = block_sum(uni, S.red);
+    ent = block_sum<kFoWaves>(ent, S.red);
+    uni = block_sum<kFoWaves>(uni, S.red);
     // the highest count, then its lowest level: one 64-bit key (count high, ~level low)
     const uint64_t key = ((uint64_t)best_c << 32) | (uint64_t)(0xFFFFFFFFu - best_l);
-    const uint64_t kbest = block_reduce(key, S.red, OpMax());
+    const uint64_t kbest = block_reduce<kFoWaves>(key, S.red, OpMax());
     const uint32_t mode_level = 0xFFFFFFFFu - (uint32_t)kbest + 1u;
 
     if (threadIdx.x != 0) return;

@@ -27,5 +27,8 @@ hipError_t launch_coo_features(const StepArgs &a, const uint64_t *keys, const ui
                                uint32_t n_rois, uint64_t *seg, DirSums *sums, DirSumsY *sums_y, hipStream_t st);
 hipError_t launch_intensity(const StepArgs &a, uint32_t grid, int fp64, void *table, uint32_t table_rows,
                             hipStream_t st);
+uint32_t neighbourhood_lds_bytes(uint32_t ng, int any_volume);
+hipError_t launch_neighbourhood(const StepArgs &a, uint32_t grid, int fp64, uint32_t alpha, int any_volume,
+                                void *table, uint32_t table_rows, hipStream_t st);
 
 }  // namespace nyx

@@ -40,6 +40,14 @@ const char *const kIntensityNames[kNumIntensityFeat] = {
     "WEIGHTED_CENTROID_Y", "WEIGHTED_CENTROID_Z", "EDGE_INTEGRATED_INTENSITY", "EDGE_MIN", "EDGE_MAX",
     "EDGE_MEAN", "EDGE_STDDEV"};
 
+const char *const kNeighbourNames[kNumNeighbourFeat] = {
+    "NGLDM_DCENRG", "NGLDM_DCENT", "NGLDM_DCNU", "NGLDM_DCNUN", "NGLDM_DCM", "NGLDM_DCV", "NGLDM_GLNU",
+    "NGLDM_GLNUN", "NGLDM_GLM", "NGLDM_GLV", "NGLDM_HDE", "NGLDM_HDHGLE", "NGLDM_HDLGLE", "NGLDM_HGLCE",
+    "NGLDM_LDE", "NGLDM_LDHGLE", "NGLDM_LDLGLE", "NGLDM_LGLCE", "NGTDM_BUSYNESS", "NGTDM_COARSENESS",
+    "NGTDM_COMPLEXITY", "NGTDM_CONTRAST", "NGTDM_STRENGTH", "GLDM_SDE", "GLDM_LDE", "GLDM_GLN", "GLDM_DN",
+    "GLDM_DNN", "GLDM_GLV", "GLDM_DV", "GLDM_DE", "GLDM_LGLE", "GLDM_HGLE", "GLDM_SDLGLE", "GLDM_SDHGLE",
+    "GLDM_LDLGLE", "GLDM_LDHGLE"};
+
 constexpr uint32_t kLdsBudget = 160u * 1024u;   // LDS per CU on gfx950
 constexpr uint32_t kRingMin = 2048u, kRingMax = 32768u;   // staged-accumulation level ring (bytes)
 constexpr uint32_t kMaxGroupsPerCu = 5u;                  // k_batch, single precision: 5 waves per SIMD
@@ -987,6 +995,49 @@ nyx_status nyx_intensity_features(nyx_ctx *ctx, const nyx_image *imgs, int32_t n
     HIPC(ctx, launch_compact(a, 0u, 0u, st));
     HIPC(ctx, launch_intensity(a, (uint32_t)n, prec == NYX_FP64, table,
                                (uint32_t)std::min<int64_t>(table_capacity_rows, 0xFFFFFFFFll), st));
+    return check_counters(ctx, w, st);
+}
+
+int32_t nyx_neighbourhood_feature_count(void) { return kNumNeighbourFeat; }
+
+const char *nyx_neighbourhood_feature_name(int32_t f) {
+    return (f >= 0 && f < kNumNeighbourFeat) ? kNeighbourNames[f] : nullptr;
+}
+
+nyx_status nyx_neighbourhood_features(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images, int32_t n_bins,
+                                      int32_t alpha, nyx_precision prec, nyx_roi_table *rois, void *table,
+                                      int64_t table_capacity_rows, nyx_stream stream) {
+    if (!ctx) return NYX_ERR_INVALID;
+    nyx_status s = validate_images(ctx, imgs, n_images);
+    if (s != NYX_OK) return s;
+    if (n_bins < 2 || n_bins > 65535) return fail(ctx, NYX_ERR_INVALID, "n_bins must be in [2, 65535]");
+    if (alpha < 0) return fail(ctx, NYX_ERR_INVALID, "alpha must be >= 0");
+    if (prec != NYX_FP32 && prec != NYX_FP64) return fail(ctx, NYX_ERR_INVALID, "bad precision");
+    int any_volume = 0;
+    for (int i = 0; i < n_images; ++i) any_volume |= imgs[i].nz > 1;
+    if (neighbourhood_lds_bytes((uint32_t)n_bins, any_volume) > kLdsBudget - 1024u)
+        return fail(ctx, NYX_ERR_UNSUPPORTED, "n_bins=%d: the per-ROI %s neighbourhood tables exceed LDS", n_bins,
+                    any_volume ? "3D" : "2D");
+    hipStream_t st = (hipStream_t)stream;
+    HIPC(ctx, hipSetDevice(ctx->device));
+    Work w;
+    if ((s = discover(ctx, imgs, n_images, w, st)) != NYX_OK) return s;
+    const int64_t n = w.n_rois;
+    if (rois && rois->n_rois_host) *rois->n_rois_host = n;
+    if (rois && rois->capacity < n)
+        return fail(ctx, NYX_ERR_CAPACITY, "ROI table capacity %lld < %lld ROIs", (long long)rois->capacity, (long long)n);
+    if (table_capacity_rows < n)
+        return fail(ctx, NYX_ERR_CAPACITY, "table capacity %lld < %lld rows", (long long)table_capacity_rows, (long long)n);
+    if (n > 0 && !table) return fail(ctx, NYX_ERR_INVALID, "table is NULL");
+    StepArgs a = w.args;
+    a.ng = n_bins;
+    a.enqueue = 0;
+    set_outputs(ctx, a, rois, nullptr, 0);
+    HIPC(ctx, launch_reset(a, w.n_counters, st));
+    HIPC(ctx, launch_scan(a, st));
+    HIPC(ctx, launch_compact(a, 0u, 0u, st));
+    HIPC(ctx, launch_neighbourhood(a, (uint32_t)n, prec == NYX_FP64, (uint32_t)alpha, any_volume, table,
+                                   (uint32_t)std::min<int64_t>(table_capacity_rows, 0xFFFFFFFFll), st));
     return check_counters(ctx, w, st);
 }
 

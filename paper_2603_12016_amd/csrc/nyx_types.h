@@ -10,6 +10,7 @@ namespace nyx {
 constexpr int kWave = 64;
 constexpr int kNumFeat = 30;
 constexpr int kNumIntensityFeat = 37;   // first-order intensity features per ROI
+constexpr int kNumNeighbourFeat = 37;   // NGLDM, NGTDM and GLDM features per ROI
 constexpr int kMaxOffsets = 64;
 constexpr int kClasses = 32;           // work-item size classes (log2 of voxels)
 constexpr uint32_t kNone = 0xFFFFFFFFu;

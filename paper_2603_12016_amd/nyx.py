@@ -61,7 +61,8 @@ EXPORTS = ("nyx_create", "nyx_destroy", "nyx_last_error", "nyx_status_string", "
            "nyx_feature_count", "nyx_feature_name", "nyx_bin_rois", "nyx_glcm_accumulate", "nyx_glcm_features",
            "nyx_extract_batch", "nyx_extract_batch_noalloc", "nyx_plan_create", "nyx_plan_execute", "nyx_plan_execute_per_roi",
            "nyx_plan_check", "nyx_plan_describe", "nyx_plan_destroy", "nyx_plan_profile",
-           "nyx_intensity_feature_count", "nyx_intensity_feature_name", "nyx_intensity_features")
+           "nyx_intensity_feature_count", "nyx_intensity_feature_name", "nyx_intensity_features",
+           "nyx_neighbourhood_feature_count", "nyx_neighbourhood_feature_name", "nyx_neighbourhood_features")
 
 PHASES = ("reset", "scan", "compact", "zero", "batch", "band", "split", "features")
 
@@ -95,6 +96,11 @@ def lib():
     L.nyx_intensity_feature_name.restype = c_char_p
     L.nyx_intensity_features.argtypes = [P, POINTER(nyx_image), c_int32, c_int32, c_int, POINTER(nyx_roi_table), P,
                                          c_int64, P]
+    L.nyx_neighbourhood_feature_count.restype = c_int32
+    L.nyx_neighbourhood_feature_name.argtypes = [c_int32]
+    L.nyx_neighbourhood_feature_name.restype = c_char_p
+    L.nyx_neighbourhood_features.argtypes = [P, POINTER(nyx_image), c_int32, c_int32, c_int32, c_int,
+                                             POINTER(nyx_roi_table), P, c_int64, P]
     L.nyx_extract_batch.argtypes = [P, POINTER(nyx_image), c_int32, POINTER(nyx_extract_opts),
                                     POINTER(nyx_roi_table), P, c_int64, P]
     L.nyx_extract_batch_noalloc.argtypes = [P, POINTER(nyx_image), c_int32, POINTER(nyx_extract_opts),
@@ -109,7 +115,7 @@ def lib():
     L.nyx_plan_describe.restype = c_char_p
     L.nyx_plan_destroy.argtypes = [P]
     L.nyx_plan_destroy.restype = None
-    for name in ("nyx_create", "nyx_offsets_default", "nyx_bin_rois", "nyx_intensity_features", "nyx_glcm_accumulate", "nyx_glcm_features",
+    for name in ("nyx_create", "nyx_offsets_default", "nyx_bin_rois", "nyx_intensity_features", "nyx_neighbourhood_features", "nyx_glcm_accumulate", "nyx_glcm_features",
                  "nyx_extract_batch", "nyx_extract_batch_noalloc", "nyx_plan_create", "nyx_plan_execute", "nyx_plan_execute_per_roi",
                  "nyx_plan_check", "nyx_plan_profile"):
         getattr(L, name).restype = c_int
@@ -359,6 +365,37 @@ def nyx_intensity_features(ctx: Ctx, images, n_bins: int, precision: int = NYX_F
     st = rois.struct()
     _check(lib().nyx_intensity_features(ctx.handle, imgs, len(images), int(n_bins), int(precision), byref(st),
                                         table.data_ptr(), int(capacity), _stream(stream)), ctx)
+    return rois, table[:rois.n_rois]
+
+
+def nyx_neighbourhood_feature_count() -> int:
+    return int(lib().nyx_neighbourhood_feature_count())
+
+
+def nyx_neighbourhood_feature_name(f: int):
+    s = lib().nyx_neighbourhood_feature_name(int(f))
+    return None if s is None else s.decode()
+
+
+def nyx_neighbourhood_features(ctx: Ctx, images, n_bins: int, alpha: int = 0, precision: int = NYX_FP32,
+                               stream=None, capacity=None):
+    """NGLDM, NGTDM and GLDM features: returns (RoiTable, table (n, 37))."""
+    imgs = _images(images)
+    dev = _dev()
+    if capacity is None:
+        probe = RoiTable(0, dev)
+        st = probe.struct()
+        status = lib().nyx_neighbourhood_features(ctx.handle, imgs, len(images), int(n_bins), int(alpha),
+                                                  int(precision), byref(st), None, 0, _stream(stream))
+        if status not in (NYX_OK, NYX_ERR_CAPACITY):
+            _check(status, ctx)
+        capacity = probe.n_rois
+    rois = RoiTable(capacity, dev)
+    dtype = torch.float64 if precision == NYX_FP64 else torch.float32
+    table = torch.full((max(capacity, 1), nyx_neighbourhood_feature_count()), float("nan"), dtype=dtype, device=dev)
+    st = rois.struct()
+    _check(lib().nyx_neighbourhood_features(ctx.handle, imgs, len(images), int(n_bins), int(alpha), int(precision),
+                                            byref(st), table.data_ptr(), int(capacity), _stream(stream)), ctx)
     return rois, table[:rois.n_rois]
 
 

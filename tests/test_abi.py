@@ -52,6 +52,13 @@ def test_intensity_feature_names_match_oracle(nyx):
     assert nyx.nyx_intensity_feature_name(fo.NFO) is None and nyx.nyx_intensity_feature_name(-1) is None
 
 
+def test_neighbourhood_feature_names_match_oracle(nyx):
+    from oracle import neighbourhood as nb
+    assert nyx.nyx_neighbourhood_feature_count() == nb.NNF
+    assert tuple(nyx.nyx_neighbourhood_feature_name(f) for f in range(nb.NNF)) == nb.NAMES
+    assert nyx.nyx_neighbourhood_feature_name(nb.NNF) is None
+
+
 @pytest.mark.parametrize("dims,dist", [(2, 1), (2, 3), (3, 1), (3, 2)])
 def test_default_offsets_match_oracle(nyx, oracle_mod, dims, dist):
     assert np.array_equal(np.array(nyx.nyx_offsets_default(dims, dist), np.int32),
