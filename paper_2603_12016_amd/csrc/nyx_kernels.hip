@@ -298,22 +298,25 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
     rd.pad1 = 0u;
     a.tab.row[e] = row;
     const bool take = a.enqueue && row >= roi_lo && row < roi_hi;
+    // banded ROIs get a global matrix but no work items of the batch kernel
+    const bool band = a.band_vox != 0u && rd.n > a.band_vox;
     const Tiling tl = tiles_for(rd.n, rd.rows, (uint32_t)(rd.x1 - rd.x0 + 1), a.split_vox, a.tile_vox);
-    nt = tl.row_blocks * tl.col_blocks;
+    nt = band ? 0u : tl.row_blocks * tl.col_blocks;
     rd.n_tiles = nt;
-    rd.tcols = tl.col_blocks;
+    rd.tcols = band ? 1u : tl.col_blocks;
     rd.gslot = kNone;
-    if (take && (nt > 1u || a.force_split)) {
+    if (take && (nt > 1u || band || a.force_split)) {
         uint32_t s = a.force_split ? row - roi_lo : atomicAdd(&a.counters[C_NSPLIT], 1u);
         if (s >= a.g_cap) {
             atomicOr(&a.counters[C_ERR], (uint32_t)E_SPLIT_CAP);
         } else {
             rd.gslot = s;
             a.split_roi[s] = row;
+            if (band) a.band_roi[atomicAdd(&a.counters[C_NBAND], 1u)] = row;   // at most one per slot
         }
     }
     a.rois[row] = rd;
-    if (take && (rd.gslot != kNone || nt == 1u)) {
+    if (take && !band && (rd.gslot != kNone || nt == 1u)) {
         enq = true;
         cls = size_class((rd.n + nt - 1u) / nt);
         local = atomicAdd(&cls_cnt[cls], nt);
@@ -896,7 +899,7 @@ __device__ void accumulate_sweep2d(const RoiDesc &rd, const ItemCtx &c, uint32_t
 
 // One direction of a finished item: features (unsplit ROI) or a 64-bit
 // atomic merge into the ROI's global matrix (tile of a split ROI).
-template <class Acc, class Src>
+template <class Acc, bool NS, class Src>
 __device__ __forceinline__ void dir_or_flush(const StepArgs &a, const WaveGrp &g, const Src &s, bool split,
                                              const RoiDesc &rd, uint32_t roi, int d, uint32_t *MARG, uint32_t ng) {
     if (split) {
@@ -907,7 +910,7 @@ __device__ __forceinline__ void dir_or_flush(const StepArgs &a, const WaveGrp &g
         g.sync();
         s.clear(g);
         g.sync();
-    } else if (a.nonsym) {
+    } else if constexpr (NS) {
         // marginals: row, column, sum, difference
         const uint64_t at = (uint64_t)roi * a.K_out + d;
         dir_sums_ns<Acc>(g, s, MARG, MARG + ng, MARG + 2u * ng, MARG + 4u * ng - 1u, ng, a.dsums + at, a.dsums_y + at);
@@ -919,8 +922,10 @@ __device__ __forceinline__ void dir_or_flush(const StepArgs &a, const WaveGrp &g
 // Single precision: at most 102 VGPRs, five waves per SIMD (a few bytes of
 // spill at item level; measured faster than four), which with ~30 KB of LDS
 // per work-group at 64 levels keeps five work-groups on a CU; double
-// precision keeps its registers.
-template <int MODE, class OutT>
+// precision keeps its registers.  NS: ordered (non-symmetric) counts, a
+// separate instantiation so the symmetric kernel carries none of its code
+// (and none of its registers).
+template <int MODE, class OutT, bool NS>
 __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(StepArgs a, uint32_t direct_roi) {
     extern __shared__ __align__(16) uint8_t smem[];
     typedef typename std::conditional<sizeof(OutT) == 8, double, float>::type Acc;
@@ -934,7 +939,7 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));   // wave index: uniform
     const int K = a.K;
     const uint32_t ng = (uint32_t)a.ng;
-    const bool ns = a.nonsym != 0;   // ordered counts: squares, gather accumulation, four marginals
+    constexpr bool ns = NS;   // ordered counts: squares, gather accumulation, four marginals
     const uint32_t marg_words = (ns ? 5u : 4u) * ng;
     uint32_t *MARG = reinterpret_cast<uint32_t *>(smem + Ly.marg_off) + w * marg_words;
 
@@ -996,9 +1001,9 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
             const bool split = rd.gslot != kNone;
             for (int d0 = 0, pass = 0; d0 < K; d0 += (int)Ly.kp, ++pass) {
                 const int d1 = min(K, d0 + (int)Ly.kp);
-                if (ns && ra < rb && ca < cb) {
+                if constexpr (NS) {
                     // ordered pairs (level at v, level at v + d) by gather, into squares
-                    if constexpr (MODE != 0) {
+                    if (MODE != 0 && ra < rb && ca < cb) {
                         const bool merged = MODE >= 2 && a.merged;
                         auto add = [&](uint32_t dl, uint32_t la, uint32_t ta, uint32_t lb, uint32_t tb) {
                             add_pair<MODE, true>(a, smem, merged ? 0u : dl, la, ta, lb, tb);
@@ -1035,18 +1040,100 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
                         SrcTriScan<MODE == 3> s{Ud, ns ? ng * ng : (ng * (ng + 1u)) >> 1,
                                                 BUF + (uint32_t)w * kWave * SrcTriScan<MODE == 3>::kPerRead,
                                                 Ly.copies, Ly.tri_pad, ns ? ng : 0u};
-                        dir_or_flush<Acc>(a, g, s, split, rd, roi, a.merged ? 0 : d0 + dl, MARG, ng);
+                        dir_or_flush<Acc, NS>(a, g, s, split, rd, roi, a.merged ? 0 : d0 + dl, MARG, ng);
                     } else if (MODE == 0) {
                         SrcDenseList s{lst, n, Ud};
-                        dir_or_flush<Acc>(a, g, s, split, rd, roi, d0 + dl, MARG, ng);
+                        dir_or_flush<Acc, NS>(a, g, s, split, rd, roi, d0 + dl, MARG, ng);
                     } else {
                         SrcHashList s{lst, n, reinterpret_cast<uint32_t *>(smem + Ly.hkey_off),
                                       reinterpret_cast<uint32_t *>(smem + Ly.hcnt_off)};
-                        dir_or_flush<Acc>(a, g, s, split, rd, roi, d0 + dl, MARG, ng);
+                        dir_or_flush<Acc, NS>(a, g, s, split, rd, roi, d0 + dl, MARG, ng);
                     }
                     if (lane() == 0) LCNT[dl] = 0u;
                 }
                 __syncthreads();
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ banded ROIs
+// Large split ROIs whose triangle does not fit LDS (many levels): a work item
+// is one (ROI, direction, block of bbox rows); the work-group gathers the
+// block's pairs of that direction and counts every pair with |i - j| <
+// band_w into an LDS band of ng x band_w 32-bit cells (cell (lo, hi) at
+// lo * band_w + hi - lo), the rare wider pairs straight into the ROI's
+// global matrix; the band is then added once, cell by nonzero cell, into
+// the global matrix.  Smooth images put nearly every pair near the diagonal,
+// so a block of hundreds of thousands of voxels costs one merge of a few
+// thousand cells instead of one per small tile.  Tickets: one atomic per
+// work item, mapped onto the banded ROIs in list order.
+__global__ __launch_bounds__(1024) void k_band(StepArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint32_t *band = reinterpret_cast<uint32_t *>(smem);
+    __shared__ uint32_t s_it[5];   // ROI row, direction, block, blocks, found
+    const uint32_t ng = (uint32_t)a.ng, B = a.band_w, lgB = 31u - (uint32_t)__builtin_clz(B);
+    const uint32_t cells = ng * B;
+    const uint32_t nb = min(a.counters[C_NBAND], a.g_cap);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            uint32_t t = atomicAdd(&a.counters[C_BAND_TICKET], 1u);
+            s_it[4] = 0u;
+            for (uint32_t j = 0; j < nb; ++j) {
+                const uint32_t row = a.band_roi[j];
+                if (row >= a.roi_cap) continue;
+                const RoiDesc &rd = a.rois[row];
+                const uint32_t nrb = band_blocks(rd.rows, (uint32_t)(rd.x1 - rd.x0 + 1), a.band_tile);
+                const uint32_t items = nrb * (uint32_t)a.K;
+                if (t < items) {
+                    s_it[0] = row; s_it[1] = t / nrb; s_it[2] = t - (t / nrb) * nrb; s_it[3] = nrb; s_it[4] = 1u;
+                    break;
+                }
+                t -= items;
+            }
+        }
+        __syncthreads();
+        if (s_it[4] == 0u) break;
+        const uint32_t row = s_it[0], nrb = s_it[3];
+        const int d = (int)s_it[1];
+        const uint32_t blk = s_it[2];
+        const RoiDesc rd = a.rois[row];
+        __syncthreads();   // every thread has read s_it before thread 0 rewrites it
+        bool ok = rd.gslot < a.g_cap && rd.image < (uint32_t)a.n_images;
+        ImgDesc im{};
+        if (ok) {
+            im = a.imgs[rd.image];
+            ok = !(rd.x0 < 0 || rd.y0 < 0 || rd.z0 < 0 || rd.x1 >= im.nx || rd.y1 >= im.ny || rd.z1 >= im.nz ||
+                   rd.x0 > rd.x1 || rd.y0 > rd.y1 || rd.z0 > rd.z1);
+        }
+        if (!ok) continue;   // uniform: every thread skips the item
+        for (uint32_t i = threadIdx.x; i < cells; i += blockDim.x) band[i] = 0u;
+        __syncthreads();
+        ItemCtx c;
+        c.I = im.I; c.L = im.L; c.B = im.B;
+        c.nx = im.nx; c.ny = im.ny; c.nz = im.nz;
+        c.label = rd.label; c.vmin = rd.vmin; c.D = rd.vmax - rd.vmin; c.ng = ng;
+        c.rcpD = c.D ? 1.0f / (float)c.D : 0.0f;
+        c.err = &a.counters[C_ERR];
+        const uint32_t W = (uint32_t)(rd.x1 - rd.x0 + 1);
+        const uint32_t rpb = (rd.rows + nrb - 1u) / nrb;
+        const uint32_t ra = min(blk * rpb, rd.rows), rb = min(ra + rpb, rd.rows);
+        uint64_t *G = a.G + ((uint64_t)rd.gslot * a.K_out + (a.merged ? 0 : d)) * (uint64_t)ng * ng;
+        auto add = [&](uint32_t, uint32_t la, uint32_t, uint32_t lb, uint32_t) {
+            const uint32_t lo = (la < lb ? la : lb) - 1u, hi = (la < lb ? lb : la) - 1u;
+            if (hi - lo < B)
+                atomicAdd(&band[(lo << lgB) + hi - lo], 1u);
+            else
+                atomicAdd(reinterpret_cast<unsigned long long *>(&G[(uint64_t)lo * ng + hi]), 1ull);
+        };
+        if (ra < rb) accumulate_rows(a, rd, c, ra, rb, 0u, W, d, d + 1, threadIdx.x, blockDim.x, add);
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cells; i += blockDim.x) {
+            const uint32_t v = band[i];
+            if (v) {
+                const uint32_t lo = i >> lgB, hi = lo + (i & (B - 1u));
+                atomicAdd(reinterpret_cast<unsigned long long *>(&G[(uint64_t)lo * ng + hi]), (unsigned long long)v);
             }
         }
         __syncthreads();
@@ -1285,59 +1372,67 @@ hipError_t launch_bin_image(const StepArgs &a, uint16_t *bins, uint64_t total_vo
     return hipSuccess;
 }
 
-template <int MODE, class OutT>
+template <int MODE, class OutT, bool NS>
 static hipError_t launch_batch_t(const StepArgs &a, uint32_t grid, uint32_t block, uint32_t direct_roi,
                                  hipStream_t st) {
     static bool attr_done = false;
     if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<MODE, OutT>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<MODE, OutT, NS>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_done = true;
     }
-    hipLaunchKernelGGL((k_batch<MODE, OutT>), dim3(grid), dim3(block), a.lds.bytes, st, a, direct_roi);
+    hipLaunchKernelGGL((k_batch<MODE, OutT, NS>), dim3(grid), dim3(block), a.lds.bytes, st, a, direct_roi);
     NYX_CHECK_LAUNCH();
     return hipSuccess;
 }
 
+template <int MODE, bool NS>
+static hipError_t launch_batch_m(const StepArgs &a, uint32_t grid, uint32_t block, uint32_t direct_roi,
+                                 hipStream_t st) {
+    return a.fp64 ? launch_batch_t<MODE, double, NS>(a, grid, block, direct_roi, st)
+                  : launch_batch_t<MODE, float, NS>(a, grid, block, direct_roi, st);
+}
+
+// (ordered counts never take the returning-atomic list, mode 0)
 hipError_t launch_batch(const StepArgs &a, uint32_t grid, uint32_t block, uint32_t direct_roi, hipStream_t st) {
+    if (grid == 0u) return hipSuccess;   // (a banded ROI has no batch tiles)
+    const bool ns = a.nonsym != 0;
     switch (a.lds.mode) {
-        case 0: return a.fp64 ? launch_batch_t<0, double>(a, grid, block, direct_roi, st)
-                              : launch_batch_t<0, float>(a, grid, block, direct_roi, st);
-        case 1: return a.fp64 ? launch_batch_t<1, double>(a, grid, block, direct_roi, st)
-                              : launch_batch_t<1, float>(a, grid, block, direct_roi, st);
-        case 2: return a.fp64 ? launch_batch_t<2, double>(a, grid, block, direct_roi, st)
-                              : launch_batch_t<2, float>(a, grid, block, direct_roi, st);
-        default: return a.fp64 ? launch_batch_t<3, double>(a, grid, block, direct_roi, st)
-                               : launch_batch_t<3, float>(a, grid, block, direct_roi, st);
+        case 0: return launch_batch_m<0, false>(a, grid, block, direct_roi, st);
+        case 1: return ns ? launch_batch_m<1, true>(a, grid, block, direct_roi, st)
+                          : launch_batch_m<1, false>(a, grid, block, direct_roi, st);
+        case 2: return ns ? launch_batch_m<2, true>(a, grid, block, direct_roi, st)
+                          : launch_batch_m<2, false>(a, grid, block, direct_roi, st);
+        default: return ns ? launch_batch_m<3, true>(a, grid, block, direct_roi, st)
+                           : launch_batch_m<3, false>(a, grid, block, direct_roi, st);
     }
 }
 
-static const void *batch_kernel(int mode, int fp64) {
+template <int MODE, bool NS>
+static const void *batch_kernel_m(int fp64) {
+    return fp64 ? reinterpret_cast<const void *>(&k_batch<MODE, double, NS>)
+                : reinterpret_cast<const void *>(&k_batch<MODE, float, NS>);
+}
+
+static const void *batch_kernel(int mode, int fp64, int ns) {
     switch (mode) {
-        case 0: return fp64 ? reinterpret_cast<const void *>(&k_batch<0, double>) : reinterpret_cast<const void *>(&k_batch<0, float>);
-        case 1: return fp64 ? reinterpret_cast<const void *>(&k_batch<1, double>) : reinterpret_cast<const void *>(&k_batch<1, float>);
-        case 2: return fp64 ? reinterpret_cast<const void *>(&k_batch<2, double>) : reinterpret_cast<const void *>(&k_batch<2, float>);
-        default: return fp64 ? reinterpret_cast<const void *>(&k_batch<3, double>) : reinterpret_cast<const void *>(&k_batch<3, float>);
+        case 0: return batch_kernel_m<0, false>(fp64);
+        case 1: return ns ? batch_kernel_m<1, true>(fp64) : batch_kernel_m<1, false>(fp64);
+        case 2: return ns ? batch_kernel_m<2, true>(fp64) : batch_kernel_m<2, false>(fp64);
+        default: return ns ? batch_kernel_m<3, true>(fp64) : batch_kernel_m<3, false>(fp64);
     }
 }
 
-hipError_t batch_occupancy(int mode, int fp64, uint32_t block, uint32_t lds_bytes, int *blocks_per_cu) {
-    const void *f = batch_kernel(mode, fp64);
+hipError_t batch_occupancy(int mode, int fp64, int ns, uint32_t block, uint32_t lds_bytes, int *blocks_per_cu) {
+    const void *f = batch_kernel(mode, fp64, ns);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, (int)block, (size_t)lds_bytes);
 }
 
-hipError_t get_batch_attributes(int mode, int fp64, hipFuncAttributes *attr) {
-    const void *f;
-    switch (mode) {
-        case 0: f = fp64 ? reinterpret_cast<const void *>(&k_batch<0, double>) : reinterpret_cast<const void *>(&k_batch<0, float>); break;
-        case 1: f = fp64 ? reinterpret_cast<const void *>(&k_batch<1, double>) : reinterpret_cast<const void *>(&k_batch<1, float>); break;
-        case 2: f = fp64 ? reinterpret_cast<const void *>(&k_batch<2, double>) : reinterpret_cast<const void *>(&k_batch<2, float>); break;
-        default: f = fp64 ? reinterpret_cast<const void *>(&k_batch<3, double>) : reinterpret_cast<const void *>(&k_batch<3, float>); break;
-    }
-    return hipFuncGetAttributes(attr, f);
+hipError_t get_batch_attributes(int mode, int fp64, int ns, hipFuncAttributes *attr) {
+    return hipFuncGetAttributes(attr, batch_kernel(mode, fp64, ns));
 }
 
 static hipError_t set_feature_kernel_attrs() {
@@ -1352,6 +1447,17 @@ static hipError_t set_feature_kernel_attrs() {
         if (e != hipSuccess) return e;
     }
     done = true;
+    return hipSuccess;
+}
+
+hipError_t launch_band(const StepArgs &a, uint32_t grid, hipStream_t st) {
+    if (a.band_vox == 0u || a.g_cap == 0u || grid == 0u) return hipSuccess;
+    const uint32_t lds = (uint32_t)a.ng * a.band_w * 4u;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_band),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_band, dim3(grid), dim3(1024), lds, st, a);
+    NYX_CHECK_LAUNCH();
     return hipSuccess;
 }
 

@@ -53,6 +53,10 @@ constexpr uint32_t kRingMin = 2048u, kRingMax = 32768u;   // staged-accumulation
 constexpr uint32_t kMaxGroupsPerCu = 5u;                  // k_batch, single precision: 5 waves per SIMD
 constexpr uint32_t kMaxNgFused = 8191u;         // hash keys carry 13-bit levels
 constexpr uint64_t kMaxLabelEntries = 1ull << 26;
+// Banded accumulation (hash mode, symmetric matrices): ROIs above
+// kBandMinVox voxels (and above the split size), LDS band of at most
+// kBandLds bytes, work items of about kBandTile bbox voxels.
+constexpr uint32_t kBandMinVox = 32768u, kBandLds = 128u * 1024u, kBandTile = 256u * 1024u, kBandMinW = 8u;
 
 int log_level() {
     static int lvl = -1;
@@ -164,7 +168,7 @@ struct nyx_ctx {
 // All device state of one discovery/step over a batch of images.
 struct Work {
     std::vector<ImgDesc> h_imgs;
-    DevBuf imgs, tab[10], counters, rois, buckets, G, dsums, dsums_y, split_roi, vox_base;
+    DevBuf imgs, tab[10], counters, rois, buckets, G, dsums, dsums_y, split_roi, band_roi, vox_base;
     uint32_t tab_total = 0, n_blocks = 0, n_counters = 0, total_chunks = 0;
     uint32_t n_rois = 0;
     uint64_t total_vox = 0;
@@ -172,7 +176,8 @@ struct Work {
     StepArgs args{};
     // Carve every buffer from `ar` (nullptr: hipMalloc).
     void use_arena(Arena *ar) {
-        for (DevBuf *b : {&imgs, &counters, &rois, &buckets, &G, &dsums, &dsums_y, &split_roi, &vox_base}) b->arena = ar;
+        for (DevBuf *b : {&imgs, &counters, &rois, &buckets, &G, &dsums, &dsums_y, &split_roi, &band_roi, &vox_base})
+            b->arena = ar;
         for (DevBuf &b : tab) b.arena = ar;
     }
 };
@@ -373,7 +378,23 @@ struct Config {
     uint32_t copies = 1;     // privatised copies of each dense triangle (scan modes)
     float tile_scale = 1.f;  // split ROIs above tile_scale x the load-balance share
     int nonsym = 0;          // ordered counts: full squares (dense modes 2 and 3, or the hash)
+    uint32_t band_vox = 0;   // ROIs above this go to the banded kernel (0: none)
+    uint32_t band_w = 0;     // band width (power of two)
 };
+
+// The banded kernel takes the large ROIs of hash-mode plans (triangle larger
+// than LDS) with symmetric matrices: band width = the largest power of two
+// whose ng x width 32-bit cells fit kBandLds.
+void set_band(Config &c, uint32_t ng) {
+    c.band_vox = 0u;
+    c.band_w = 0u;
+    if (c.mode != 1 || c.nonsym) return;
+    uint32_t w = 1u;
+    while (w * 2u <= ng && (uint64_t)ng * (w * 2u) * 4u <= kBandLds) w *= 2u;
+    if (w < kBandMinW) return;
+    c.band_w = w;
+    c.band_vox = std::max(c.split_vox, kBandMinVox);
+}
 
 const char *mode_name(int m) {
     switch (m) {
@@ -557,6 +578,7 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
                 c.mode = 1; c.kp = kp; c.block = block; c.hash_cap = hc; c.split_vox = split; c.tile_vox = split;
                 c.list_cap = list_cap; c.force_split = force_split; c.tile_scale = tile_scale;
                 c.nonsym = nonsym ? 1 : 0;
+                set_band(c, ng);
                 out.push_back(c);
                 return out;
             }
@@ -605,10 +627,11 @@ void count_items(const std::vector<RoiDesc> &rois, const Config &c, uint64_t *it
     if (tiles) tiles->resize(rois.size());
     for (size_t i = 0; i < rois.size(); ++i) {
         const RoiDesc &r = rois[i];
+        const bool band = c.band_vox && r.n > c.band_vox;
         Tiling t = tiles_for(r.n, r.rows, (uint32_t)(r.x1 - r.x0 + 1), c.split_vox, c.tile_vox);
-        uint32_t nt = t.row_blocks * t.col_blocks;
+        uint32_t nt = band ? 0u : t.row_blocks * t.col_blocks;
         it += nt;
-        if (nt > 1u || c.force_split) ++ns;
+        if (nt > 1u || band || c.force_split) ++ns;
         if (tiles) (*tiles)[i] = nt;
     }
     *items = it;
@@ -671,6 +694,7 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     HIPC(ctx, w.dsums.alloc(sums_bytes));
     HIPC(ctx, w.dsums_y.alloc(sums_y_bytes));
     HIPC(ctx, w.split_roi.alloc((size_t)std::max<uint32_t>(n_split, 1u) * 4u));
+    HIPC(ctx, w.band_roi.alloc((size_t)std::max<uint32_t>(n_split, 1u) * 4u));
     a.buckets = w.buckets.as<uint2>();
     a.bucket_cap = bucket_cap;
     a.G = w.G.as<uint64_t>();
@@ -679,6 +703,10 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     a.dsums_y = w.dsums_y.as<DirSumsY>();
     a.nonsym = cfg.nonsym;
     a.split_roi = w.split_roi.as<uint32_t>();
+    a.band_roi = w.band_roi.as<uint32_t>();
+    a.band_vox = cfg.band_vox;
+    a.band_w = cfg.band_w;
+    a.band_tile = kBandTile;
     for (int k = 0; k < K; ++k) {
         a.off[k][0] = off[k].dz;
         a.off[k][1] = off[k].dy;
@@ -726,6 +754,7 @@ nyx_status enqueue_step(nyx_plan *p, hipStream_t st, bool per_roi) {
     } else {
         for (uint32_t r = 0; r < p->w.n_rois; ++r) HIPC(ctx, launch_batch(a, p->roi_tiles[r], p->block, r, st));
     }
+    HIPC(ctx, launch_band(a, (uint32_t)ctx->n_cu, st));
     HIPC(ctx, launch_split_finalize(a, st));
     HIPC(ctx, launch_features(a, a.dsums, a.dsums_y, a.roi_cap, a.counters + C_NROIS, st));
     return NYX_OK;
@@ -751,9 +780,10 @@ std::string describe(const Config &c, const nyx_plan *p, uint64_t items, uint32_
     char buf[512];
     snprintf(buf, sizeof buf,
              "mode=%s kp=%u copies=%u symmetric=%d block=%u grid=%u lds=%uB split_vox=%u tile_vox=%u tile_scale=%g "
-             "list_cap=%u hash_cap=%u rois=%u items=%llu split_rois=%u ng=%d K=%d tuned_ms=%.4f",
+             "list_cap=%u hash_cap=%u band_vox=%u band_w=%u rois=%u items=%llu split_rois=%u ng=%d K=%d tuned_ms=%.4f",
              mode_name(c.mode), c.kp, p->w.args.lds.copies, c.nonsym ? 0 : 1, c.block, p->grid, p->w.args.lds.bytes, c.split_vox,
-             c.tile_vox, (double)c.tile_scale, c.list_cap, c.hash_cap, p->w.n_rois, (unsigned long long)items,
+             c.tile_vox, (double)c.tile_scale, c.list_cap, c.hash_cap, c.band_vox, c.band_w, p->w.n_rois,
+             (unsigned long long)items,
              n_split, p->ng, p->K, (double)p->tuned_ms);
     return buf;
 }
@@ -766,7 +796,7 @@ nyx_status configure(nyx_plan *p, const Config &cfg, const nyx_extract_opts *opt
     if (s != NYX_OK) return s;
     p->block = cfg.block;
     int occ = 0;
-    HIPC(ctx, batch_occupancy(cfg.mode, p->prec == NYX_FP64, cfg.block, p->w.args.lds.bytes, &occ));
+    HIPC(ctx, batch_occupancy(cfg.mode, p->prec == NYX_FP64, cfg.nonsym, cfg.block, p->w.args.lds.bytes, &occ));
     p->grid = (uint32_t)ctx->n_cu * (uint32_t)std::max(occ, 1);
     uint64_t items;
     uint32_t n_split;
@@ -912,7 +942,7 @@ nyx_status nyx_glcm_accumulate(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_im
     int occ = 0;
     {
         hipFuncAttributes fa;
-        HIPC(ctx, get_batch_attributes(a.lds.mode, 0, &fa));
+        HIPC(ctx, get_batch_attributes(a.lds.mode, 0, a.nonsym, &fa));
         occ = 1;
     }
     const uint32_t grid = (uint32_t)ctx->n_cu * (uint32_t)std::max(occ, 1) * 2u;
@@ -931,6 +961,7 @@ nyx_status nyx_glcm_accumulate(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_im
             HIPC(ctx, launch_compact(a, lo, hi, st));
             HIPC(ctx, launch_zero_split(a, st));
             HIPC(ctx, launch_batch(a, grid, cfg.block, kNone, st));
+            HIPC(ctx, launch_band(a, (uint32_t)ctx->n_cu, st));
             HIPC(ctx, launch_coo_count(a, ns, dcount.as<uint64_t>(), st));
             HIPC(ctx, hipMemcpyAsync(hcount.data(), dcount.p, (size_t)ns * K * 8u, hipMemcpyDeviceToHost, st));
             HIPC(ctx, hipStreamSynchronize(st));
@@ -1280,7 +1311,7 @@ nyx_status nyx_plan_profile(nyx_plan *p, void *table, float *ms_host, nyx_stream
     if (he == hipSuccess) he = hipEventRecord(ev[4], st);
     if (he == hipSuccess) he = launch_batch(a, p->grid, p->block, kNone, st);
     if (he == hipSuccess) he = hipEventRecord(ev[5], st);
-    // (no banded-count kernel in this plan: an empty phase)
+    if (he == hipSuccess) he = launch_band(a, (uint32_t)ctx->n_cu, st);
     if (he == hipSuccess) he = hipEventRecord(ev[6], st);
     if (he == hipSuccess) he = launch_split_finalize(a, st);
     if (he == hipSuccess) he = hipEventRecord(ev[7], st);

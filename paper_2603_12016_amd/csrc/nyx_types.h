@@ -25,6 +25,8 @@ enum Counter : int {
     C_NSPLIT = 1,   // ROIs split into several tiles (global-matrix slots used)
     C_ERR = 3,      // error bits (see ErrBit)
     C_NITEMS = 4,   // work items enqueued
+    C_NBAND = 5,    // split ROIs accumulated by the banded kernel
+    C_BAND_TICKET = 6,  // work tickets of the banded kernel
     C_CLASS = 8,    // kClasses counters: work-group items per size class
     C_TICKETS = 128,  // kTicketLanes ticket counters of the persistent kernel, kTicketStride apart
     C_BLOCKS = 128 + 32 * 32, // per-block ROI counts of the compaction (variable length)
@@ -144,6 +146,13 @@ struct StepArgs {
     DirSumsY *dsums_y;          // roi_cap * K column-marginal sums (non-symmetric matrices only)
     int32_t nonsym;             // 1: ordered counts P = C (full ng x ng squares), 0: symmetric P = C + C^T
     uint32_t *split_roi;        // g_cap: ROI row of each split slot
+    // Banded accumulation of large split ROIs whose triangle does not fit LDS:
+    // ROIs above band_vox voxels (0: none) are counted by k_band, one
+    // (ROI, direction, block of bbox rows of about band_tile voxels) per work
+    // item, into an LDS band of ng x band_w cells (|i - j| < band_w, a power
+    // of two) merged once into the ROI's global matrix.
+    uint32_t band_vox, band_w, band_tile;
+    uint32_t *band_roi;         // g_cap: ROI rows of the banded ROIs
     int32_t off[kMaxOffsets][3];
     int32_t K;                  // offsets
     int32_t K_out;              // matrices per ROI: K, or 1 when the offsets' matrices are merged
@@ -253,6 +262,18 @@ inline void ticket_range(uint32_t t, const uint32_t *entries, const uint32_t *fi
     *e0 = (t - first[cl]) * ch;
     const uint32_t end = *e0 + ch;
     *e1 = end < entries[cl] ? end : entries[cl];
+}
+
+// Row blocks a banded ROI of `rows` bbox rows of width W is cut into: about
+// tile voxels each, at most one block per row.
+#ifdef __HIPCC__
+__host__ __device__
+#endif
+inline uint32_t band_blocks(uint32_t rows, uint32_t W, uint32_t tile) {
+    const uint64_t vox = (uint64_t)rows * W;
+    uint64_t nb = tile ? (vox + tile - 1u) / tile : 1u;
+    if (nb < 1u) nb = 1u;
+    return (uint32_t)(nb < rows ? nb : rows);
 }
 
 #ifdef __HIPCC__

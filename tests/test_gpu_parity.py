@@ -638,3 +638,55 @@ def test_plan_profile_phases(env, workloads):
     a, b = t1.cpu().numpy(), t2.cpu().numpy()
     assert ((a == b) | (np.isnan(a) & np.isnan(b))).all()
 
+
+
+# ------------------------------------------------------------------ banded accumulation
+@pytest.mark.parametrize("shape,ng,smooth", [((28, 44, 44), 512, False), ((1, 300, 320), 2048, True)])
+def test_banded_counts_exact(env, oracle_mod, shape, ng, smooth):
+    """ROIs above the banded kernel's size threshold at bin counts whose
+    triangle exceeds LDS: exact counts through nyx_glcm_accumulate and the
+    batched features, with pairs inside the LDS band and (uniform noise) far
+    outside it."""
+    import torch
+    from types import SimpleNamespace
+    nyx, ctx, dev = env
+    rng = np.random.default_rng(ng)
+    if smooth:
+        y, x = np.mgrid[0:shape[1], 0:shape[2]]
+        I = (20000 + 15000 * np.sin(x / 37.0) * np.cos(y / 23.0) + rng.integers(0, 400, shape[1:]))[None]
+    else:
+        I = rng.integers(0, 60000, shape)
+    I = np.ascontiguousarray(I, np.uint16)
+    L = np.ones(shape, np.uint32)
+    L[:, :5, :] = 2                                   # a second, smaller ROI
+    L[0, 0, 0] = 0
+    offs = nyx.nyx_offsets_default(3 if shape[0] > 1 else 2, 1)
+    say(f"case banded counts {shape} ng={ng} smooth={smooth}")
+    w = SimpleNamespace(intensity=I[None], labels=L[None], n_images=1)
+    imgs = device_images(w, dev)
+    plan = nyx.nyx_plan_create(ctx, imgs, ng, offs, nyx.NYX_FP64)
+    desc = nyx.nyx_plan_describe(plan)
+    say("  plan:", desc)
+    assert "mode=hash" in desc and "band_vox=0 " not in desc
+    rois, _ = nyx.nyx_bin_rois(ctx, imgs, ng)
+    g = nyx.nyx_glcm_accumulate(ctx, imgs, rois, ng, offs)
+    keys = g.keys.cpu().numpy().view(np.uint64)
+    cnt = g.counts.cpu().numpy().view(np.uint64)
+    st = oracle_mod.roi_stats(I, L)
+    roi = (keys >> np.uint64(38)).astype(np.int64)
+    for r in range(st["label"].size):
+        P = oracle_mod.glcm_roi(I, L, st["label"][r], st["vmin"][r], st["vmax"][r], st["bbox"][r], ng,
+                                np.array(offs, np.int32))
+        U = _triangle(P)
+        kk, cc = keys[roi == r], cnt[roi == r]
+        d = ((kk >> np.uint64(32)) & np.uint64(63)).astype(np.int64)
+        i = ((kk >> np.uint64(16)) & np.uint64(0xFFFF)).astype(np.int64)
+        j = (kk & np.uint64(0xFFFF)).astype(np.int64)
+        assert len(kk) == np.count_nonzero(U), r
+        assert np.array_equal(U[d, i, j], cc), r
+    t = nyx.new_table(plan, len(offs), nyx.NYX_FP64)
+    nyx.nyx_plan_execute(plan, t)
+    torch.cuda.synchronize()
+    nyx.nyx_plan_check(plan)
+    want, Ps = _oracle_direct(oracle_mod, I, L, ng, offs)
+    _check_features(t.cpu().numpy()[:plan.n_rois], want, Ps, TOL_FP64, "banded")
