@@ -320,11 +320,13 @@ struct SrcSquare {
     bool all = false;        // every cell (ordered counts), not only the upper triangle
     template <class Grp, class Fn>
     __device__ __forceinline__ void for_each(const Grp &g, Fn &&fn) const {
-        for (uint32_t e = g.rank(); e < ng * ng; e += g.size()) {
-            const uint32_t lo = e / ng, hi = e - lo * ng;
-            if (lo > hi && !all) continue;
-            const uint64_t c = G[e];
-            if (c) fn(lo, hi, (uint32_t)c);
+        // row by row (no division per cell), the upper triangle unless all
+        for (uint32_t lo = 0; lo < ng; ++lo) {
+            const uint64_t *row = G + (uint64_t)lo * ng;
+            for (uint32_t hi = (all ? 0u : lo) + (uint32_t)g.rank(); hi < ng; hi += (uint32_t)g.size()) {
+                const uint64_t c = row[hi];
+                if (c) fn(lo, hi, (uint32_t)c);
+            }
         }
     }
     template <class Grp> __device__ __forceinline__ void clear(const Grp &) const {}

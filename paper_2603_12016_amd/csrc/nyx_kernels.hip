@@ -79,9 +79,13 @@ __global__ void k_zero_split(StepArgs a) {
     uint32_t used = a.counters[C_NSPLIT];
     if (used > a.g_cap) used = a.g_cap;
     uint64_t n = (uint64_t)used * a.K_out * (uint64_t)a.ng * a.ng;
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        a.G[i] = 0ull;
+    const uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x, ts = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = t0; i < n; i += ts) a.G[i] = 0ull;
+    if (a.smarg) {
+        const uint64_t m = (uint64_t)used * a.K_out;
+        for (uint64_t i = t0; i < m * 4u * (uint64_t)a.ng; i += ts) a.smarg[i] = 0u;
+        for (uint64_t i = t0; i < m * 4u; i += ts) a.stot[i] = 0ull;
+    }
 }
 
 // ------------------------------------------------------------------ scan
@@ -1144,7 +1148,7 @@ __global__ __launch_bounds__(1024) void k_band(StepArgs a) {
 // One work-group per (split slot, direction): features from the merged global
 // matrix (dense square, upper triangle).
 template <class Acc>
-__global__ __launch_bounds__(512) void k_split_features(StepArgs a) {
+__global__ __launch_bounds__(1024) void k_split_features(StepArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint32_t ng = (uint32_t)a.ng;
     const int K = a.K_out;
@@ -1165,6 +1169,164 @@ __global__ __launch_bounds__(512) void k_split_features(StepArgs a) {
         dir_sums_ns<Acc>(g, s, R, R + ng, R + 2u * ng, R + 4u * ng - 1u, ng, a.dsums + at, a.dsums_y + at);
     else
         dir_sums<Acc, uint64_t>(g, s, R, R + ng, R + 3u * ng - 1u, ng, a.dsums + at);
+}
+
+// Split ROIs with symmetric matrices, first pass: one work-group per (slot,
+// direction, chunk of matrix rows) visits the chunk's nonzero upper-triangle
+// cells (a cell (lo < hi) with count c stands for P(lo, hi) = P(hi, lo) = c,
+// a diagonal one for P = 2c), counts the marginals in LDS and adds them to
+// the matrix's global marginals, and adds its exact integer cell totals; its
+// sum of P log2 P goes to its own slot (added in chunk order later).
+template <class Acc>
+__global__ __launch_bounds__(256) void k_split_cells(StepArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint64_t red[4];
+    const uint32_t ng = (uint32_t)a.ng, K = (uint32_t)a.K_out, chunks = a.split_chunks;
+    const uint32_t sd = blockIdx.x / chunks, ch = blockIdx.x - sd * chunks;
+    const uint32_t slot = sd / K;
+    if (slot >= min(a.counters[C_NSPLIT], a.g_cap)) return;
+    uint32_t *M = reinterpret_cast<uint32_t *>(smem);   // R [ng] | Sp [2 ng - 1] | Sm [ng]
+    uint32_t *R = M, *Sp = M + ng, *Sm = M + 3u * ng - 1u;
+    for (uint32_t i = threadIdx.x; i < 4u * ng; i += blockDim.x) M[i] = 0u;
+    __syncthreads();
+    const uint32_t rpc = (ng + chunks - 1u) / chunks, r0 = min(ch * rpc, ng), r1 = min(r0 + rpc, ng);
+    const uint64_t *G = a.G + (uint64_t)sd * ng * ng;
+    uint64_t T = 0, S11 = 0, sumP2 = 0, maxP = 0;
+    LaneSum<Acc> plp;
+    for (uint32_t lo = r0; lo < r1; ++lo)
+        for (uint32_t hi = lo + threadIdx.x; hi < ng; hi += blockDim.x) {
+            const uint64_t cw = G[(uint64_t)lo * ng + hi];
+            if (!cw) continue;
+            const uint32_t c = (uint32_t)cw;
+            atomicAdd(&R[lo], c);
+            atomicAdd(&R[hi], c);
+            atomicAdd(&Sp[lo + hi], 2u * c);
+            atomicAdd(&Sm[hi - lo], 2u * c);
+            const bool diag = lo == hi;
+            const uint64_t P = diag ? 2ull * c : (uint64_t)c, Pm = diag ? P : 2u * P;
+            T += 2ull * c;
+            sumP2 += Pm * P;
+            maxP = P > maxP ? P : maxP;
+            S11 += Pm * (uint64_t)__umul24(lo + 1u, hi + 1u);
+            plp.add((Acc)Pm * term_log2<Acc>((Acc)P));
+        }
+    __syncthreads();
+    uint32_t *gm = a.smarg + (uint64_t)sd * 4u * ng;
+    for (uint32_t i = threadIdx.x; i < 4u * ng; i += blockDim.x)
+        if (M[i]) atomicAdd(&gm[i], M[i]);
+    T = block_sum<4>(T, red);
+    S11 = block_sum<4>(S11, red);
+    sumP2 = block_sum<4>(sumP2, red);
+    maxP = block_reduce<4>(maxP, red, OpMax());
+    const double plp_t = block_sum<4>(comp_value(plp), red);
+    if (threadIdx.x == 0) {
+        uint64_t *tot = a.stot + (uint64_t)sd * 4u;
+        atomicAdd(reinterpret_cast<unsigned long long *>(&tot[0]), (unsigned long long)T);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&tot[1]), (unsigned long long)S11);
+        atomicAdd(reinterpret_cast<unsigned long long *>(&tot[2]), (unsigned long long)sumP2);
+        atomicMax(reinterpret_cast<unsigned long long *>(&tot[3]), (unsigned long long)maxP);
+        a.splp[(uint64_t)sd * chunks + ch] = plp_t;
+    }
+}
+
+// Second pass: one work-group per (slot, direction) finishes the reduced sums
+// from the global marginals and cell totals (the level sweeps, cluster
+// moments and the mutual-information decision of dir_sums; a re-summed
+// mutual information visits the matrix's cells once more).
+template <class Acc>
+__global__ __launch_bounds__(1024) void k_split_finish(StepArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t ng = (uint32_t)a.ng, K = (uint32_t)a.K_out;
+    const uint32_t sd = blockIdx.x, slot = sd / K, d = sd - slot * K;
+    if (slot >= min(a.counters[C_NSPLIT], a.g_cap)) return;
+    const uint32_t roi = a.split_roi[slot];
+    if (roi >= a.roi_cap) return;
+    uint32_t *M = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *R = M, *Sp = M + ng, *Sm = M + 3u * ng - 1u;
+    uint64_t *scratch = reinterpret_cast<uint64_t *>(smem + 16u * ng);
+    const uint32_t *gm = a.smarg + (uint64_t)sd * 4u * ng;
+    for (uint32_t i = threadIdx.x; i < 4u * ng; i += blockDim.x) M[i] = gm[i];
+    __syncthreads();
+    BlockGrp g{scratch};
+    const int r0 = g.rank(), gs = g.size();
+    const uint64_t *tot = a.stot + (uint64_t)sd * 4u;
+    const uint64_t T = tot[0], S11t = tot[1], sumP2t = tot[2], maxPt = tot[3];
+    double plp_t = 0.0;
+    for (uint32_t c = 0; c < a.split_chunks; ++c) plp_t += a.splp[(uint64_t)sd * a.split_chunks + c];
+    DirSums *out = a.dsums + (uint64_t)roi * K + d;
+    // level sweeps over the marginals (as in dir_sums)
+    uint64_t S1 = 0, S2 = 0, Sm1 = 0;
+    LaneSum<Acc> rlr, slp, hom1, hom2, idmn, idn, iv, plps;
+    const Acc ngf = (Acc)ng, rng = (Acc)1 / ngf, rng2 = rng * rng;
+    for (uint32_t i = r0; i < ng; i += gs) {
+        const uint32_t r = R[i];
+        if (r) {
+            const uint64_t lv = i + 1u;
+            S1 += lv * r;
+            S2 += lv * lv * r;
+            rlr.add((Acc)r * term_log2<Acc>((Acc)r));
+        }
+        const uint32_t sm = Sm[i];
+        if (sm) {
+            Sm1 += (uint64_t)i * sm;
+            const Acc sf = (Acc)sm, k = (Acc)i;
+            slp.add(sf * term_log2<Acc>(sf));
+            hom1.add(term_div<Acc>(sf, (Acc)1 + k));
+            hom2.add(term_div<Acc>(sf, (Acc)1 + k * k));
+            idmn.add(term_div<Acc>(sf, (Acc)1 + (k * k) * rng2));
+            idn.add(term_div<Acc>(sf, (Acc)1 + k * rng));
+            if (i > 0) iv.add(term_div<Acc>(sf, k * k));
+        }
+    }
+    for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) {
+        const uint32_t sp = Sp[k];
+        if (sp) plps.add((Acc)sp * term_log2<Acc>((Acc)sp));
+    }
+    const uint64_t S1t = g.sum(S1), S2t = g.sum(S2), Sm1t = g.sum(Sm1);
+    const double rlr_t = g.sum(comp_value(rlr)), slp_t = g.sum(comp_value(slp)), plps_t = g.sum(comp_value(plps));
+    const double hom1_t = g.sum(comp_value(hom1)), hom2_t = g.sum(comp_value(hom2));
+    const double idmn_t = g.sum(comp_value(idmn)), idn_t = g.sum(comp_value(idn)), iv_t = g.sum(comp_value(iv));
+    double CSHADE = 0.0, CPROM = 0.0, MI = __builtin_nan("");
+    if (T) {
+        const double Td = (double)T, invT = 1.0 / Td;
+        const double two_mu = (double)(2u * S1t) / Td;   // one rounding
+        double cs = 0.0, cp = 0.0;
+        for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) {
+            const uint32_t sp = Sp[k];
+            if (sp) {
+                const double p = (double)sp * invT, dd = (double)(k + 2u) - two_mu, d3 = dd * dd * dd;
+                cs += d3 * p;
+                cp += d3 * dd * p;
+            }
+        }
+        CSHADE = g.sum(cs);
+        CPROM = g.sum(cp);
+        const double mi_cf = (double)__log2f((float)Td) - (2.0 * rlr_t - plp_t) * invT;
+        if (mi_cf < mi_resum_threshold<Acc>()) {
+            Comp<Acc> m;
+            const Acc invTa = (Acc)invT;
+            SrcSquare src{a.G + (uint64_t)sd * ng * ng, ng};
+            src.for_each(g, [&](uint32_t lo, uint32_t hi, uint32_t c) {
+                const bool diag = lo == hi;
+                const uint64_t P = diag ? 2ull * c : (uint64_t)c;
+                const Acc mult = diag ? (Acc)1 : (Acc)2;
+                const uint64_t A = P * T, B = (uint64_t)R[lo] * (uint64_t)R[hi];
+                const Acc delta = A >= B ? (Acc)(A - B) / (Acc)B : -((Acc)(B - A) / (Acc)B);
+                m.add(mult * (Acc)P * invTa * log1p_<Acc>(delta) * (Acc)1.4426950408889634);
+            });
+            MI = g.sum(comp_value(m));
+        }
+    }
+    if (r0 == 0) {
+        out->T = T; out->S1 = S1t; out->S2 = S2t; out->Sm1 = Sm1t; out->S11 = S11t; out->sumP2 = sumP2t;
+        out->plp = plp_t; out->rlr = rlr_t; out->slp = slp_t; out->plps = plps_t;
+        out->hom1 = hom1_t; out->hom2 = hom2_t; out->idmn = idmn_t; out->idn = idn_t; out->iv = iv_t;
+        out->spare = 0.0;
+        out->maxP = maxPt;
+        out->CSHADE = CSHADE;
+        out->CPROM = CPROM;
+        out->MI = MI;
+    }
 }
 
 // ------------------------------------------------------------------ features
@@ -1220,10 +1382,8 @@ __global__ __launch_bounds__(256) void k_coo_count(StepArgs a, uint32_t n_slots,
     if (sd >= n_slots * (uint32_t)a.K_out) return;
     const uint64_t *G = a.G + (uint64_t)sd * ng * ng;
     uint64_t c = 0;
-    for (uint32_t e = threadIdx.x; e < ng * ng; e += blockDim.x) {
-        uint32_t i = e / ng, j = e - i * ng;
-        if ((i <= j || a.nonsym) && G[e]) ++c;
-    }
+    for (uint32_t i = 0; i < ng; ++i)
+        for (uint32_t j = (a.nonsym ? 0u : i) + threadIdx.x; j < ng; j += blockDim.x) c += G[(uint64_t)i * ng + j] != 0u;
     __shared__ uint64_t part[4];
     c = wave_sum(c);
     if (lane() == 0) part[threadIdx.x / 64] = c;
@@ -1440,10 +1600,15 @@ static hipError_t set_feature_kernel_attrs() {
     if (done) return hipSuccess;
     const void *fs[] = {reinterpret_cast<const void *>(&k_split_features<float>),
                         reinterpret_cast<const void *>(&k_split_features<double>),
+                        reinterpret_cast<const void *>(&k_split_cells<float>),
+                        reinterpret_cast<const void *>(&k_split_cells<double>),
+                        reinterpret_cast<const void *>(&k_split_finish<float>),
+                        reinterpret_cast<const void *>(&k_split_finish<double>),
                         reinterpret_cast<const void *>(&k_coo_features<float>),
                         reinterpret_cast<const void *>(&k_coo_features<double>)};
     for (const void *f : fs) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        // (some of these kernels keep a few bytes of static LDS besides)
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 159 * 1024);
         if (e != hipSuccess) return e;
     }
     done = true;
@@ -1467,10 +1632,22 @@ hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st) {
         hipError_t e = set_feature_kernel_attrs();
         if (e != hipSuccess) return e;
     }
-    uint32_t lds = (a.nonsym ? 20u : 16u) * a.ng + 16 * 8;
     uint32_t grid = a.g_cap * a.K_out;
-    if (a.fp64) hipLaunchKernelGGL(k_split_features<double>, dim3(grid), dim3(512), lds, st, a);
-    else hipLaunchKernelGGL(k_split_features<float>, dim3(grid), dim3(512), lds, st, a);
+    if (!a.nonsym && a.smarg) {
+        // two passes: row chunks in parallel, then one work-group per matrix
+        const uint32_t lds1 = 16u * a.ng;
+        if (a.fp64) hipLaunchKernelGGL(k_split_cells<double>, dim3(grid * a.split_chunks), dim3(256), lds1, st, a);
+        else hipLaunchKernelGGL(k_split_cells<float>, dim3(grid * a.split_chunks), dim3(256), lds1, st, a);
+        NYX_CHECK_LAUNCH();
+        const uint32_t lds2 = 16u * a.ng + 16 * 8;
+        if (a.fp64) hipLaunchKernelGGL(k_split_finish<double>, dim3(grid), dim3(1024), lds2, st, a);
+        else hipLaunchKernelGGL(k_split_finish<float>, dim3(grid), dim3(1024), lds2, st, a);
+        NYX_CHECK_LAUNCH();
+        return hipSuccess;
+    }
+    uint32_t lds = (a.nonsym ? 20u : 16u) * a.ng + 16 * 8;
+    if (a.fp64) hipLaunchKernelGGL(k_split_features<double>, dim3(grid), dim3(1024), lds, st, a);
+    else hipLaunchKernelGGL(k_split_features<float>, dim3(grid), dim3(1024), lds, st, a);
     NYX_CHECK_LAUNCH();
     return hipSuccess;
 }

@@ -168,7 +168,7 @@ struct nyx_ctx {
 // All device state of one discovery/step over a batch of images.
 struct Work {
     std::vector<ImgDesc> h_imgs;
-    DevBuf imgs, tab[10], counters, rois, buckets, G, dsums, dsums_y, split_roi, band_roi, vox_base;
+    DevBuf imgs, tab[10], counters, rois, buckets, G, dsums, dsums_y, split_roi, band_roi, smarg, stot, splp, vox_base;
     uint32_t tab_total = 0, n_blocks = 0, n_counters = 0, total_chunks = 0;
     uint32_t n_rois = 0;
     uint64_t total_vox = 0;
@@ -176,7 +176,8 @@ struct Work {
     StepArgs args{};
     // Carve every buffer from `ar` (nullptr: hipMalloc).
     void use_arena(Arena *ar) {
-        for (DevBuf *b : {&imgs, &counters, &rois, &buckets, &G, &dsums, &dsums_y, &split_roi, &band_roi, &vox_base})
+        for (DevBuf *b : {&imgs, &counters, &rois, &buckets, &G, &dsums, &dsums_y, &split_roi, &band_roi, &smarg, &stot,
+                          &splp, &vox_base})
             b->arena = ar;
         for (DevBuf &b : tab) b.arena = ar;
     }
@@ -682,7 +683,9 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     const uint64_t sums_bytes = (uint64_t)std::max<uint32_t>(w.n_rois, 1u) * K_out * sizeof(DirSums);
     const uint64_t sums_y_bytes =
         cfg.nonsym ? (uint64_t)std::max<uint32_t>(w.n_rois, 1u) * K_out * sizeof(DirSumsY) : 16u;
-    uint64_t need = (uint64_t)kClasses * bucket_cap * 8u + g_bytes + sums_bytes + sums_y_bytes + n_split * 4u;
+    const uint64_t mats0 = (uint64_t)std::max<uint32_t>(n_split, 1u) * K_out;
+    uint64_t need = (uint64_t)kClasses * bucket_cap * 8u + g_bytes + sums_bytes + sums_y_bytes + n_split * 8u +
+                    mats0 * (16u * ng + 32u + 8u * std::max(1u, ng / 8u));
     for (auto &b : w.tab) need += b.bytes;
     need += w.rois.bytes + w.counters.bytes;
     if (ws_bytes) *ws_bytes = (int64_t)need;
@@ -695,6 +698,13 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     HIPC(ctx, w.dsums_y.alloc(sums_y_bytes));
     HIPC(ctx, w.split_roi.alloc((size_t)std::max<uint32_t>(n_split, 1u) * 4u));
     HIPC(ctx, w.band_roi.alloc((size_t)std::max<uint32_t>(n_split, 1u) * 4u));
+    // two-pass reduction of split matrices: enough row chunks to fill the chip
+    const uint64_t mats = (uint64_t)std::max<uint32_t>(n_split, 1u) * K_out;
+    const uint32_t chunks = (uint32_t)std::max<uint64_t>(
+        1u, std::min<uint64_t>(std::max(1u, ng / 8u), (2u * (uint64_t)std::max(ctx->n_cu, 1) + mats - 1u) / mats));
+    HIPC(ctx, w.smarg.alloc((size_t)mats * 4u * ng * 4u));
+    HIPC(ctx, w.stot.alloc((size_t)mats * 4u * 8u));
+    HIPC(ctx, w.splp.alloc((size_t)mats * chunks * 8u));
     a.buckets = w.buckets.as<uint2>();
     a.bucket_cap = bucket_cap;
     a.G = w.G.as<uint64_t>();
@@ -704,6 +714,10 @@ nyx_status setup_step(nyx_ctx *ctx, Work &w, const Config &cfg, const nyx_offset
     a.nonsym = cfg.nonsym;
     a.split_roi = w.split_roi.as<uint32_t>();
     a.band_roi = w.band_roi.as<uint32_t>();
+    a.smarg = w.smarg.as<uint32_t>();
+    a.stot = w.stot.as<uint64_t>();
+    a.splp = w.splp.as<double>();
+    a.split_chunks = chunks;
     a.band_vox = cfg.band_vox;
     a.band_w = cfg.band_w;
     a.band_tile = kBandTile;

@@ -153,6 +153,15 @@ struct StepArgs {
     // of two) merged once into the ROI's global matrix.
     uint32_t band_vox, band_w, band_tile;
     uint32_t *band_roi;         // g_cap: ROI rows of the banded ROIs
+    // Reduced sums of split ROIs (symmetric matrices) in two passes: chunks
+    // of rows of each global matrix in parallel (marginals and cell totals),
+    // then one work-group per matrix.  smarg: 4 ng u32 per (slot, direction)
+    // (row, sum, difference marginals); stot: T, S11, sum P^2, max P (u64);
+    // splp: the chunks' sums of P log2 P, added in chunk order.
+    uint32_t *smarg;
+    uint64_t *stot;
+    double *splp;
+    uint32_t split_chunks;
     int32_t off[kMaxOffsets][3];
     int32_t K;                  // offsets
     int32_t K_out;              // matrices per ROI: K, or 1 when the offsets' matrices are merged
