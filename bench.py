@@ -33,7 +33,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-KERNEL_SYMBOLS = {"k_batch": "nyx::k_batch<", "k_scan": "nyx::k_scan(", "k_band": "nyx::k_band<"}
+KERNEL_SYMBOLS = {"k_batch": "nyx::k_batch<", "k_scan": "nyx::k_scan(", "k_band": "nyx::k_band("}
 COPY_SYMBOL = "k_copy("
 
 

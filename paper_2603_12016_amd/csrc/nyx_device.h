@@ -36,6 +36,20 @@ __device__ __forceinline__ uint32_t fbn_level(uint32_t I, uint32_t vmin, uint32_
     return b > ng ? ng : b;
 }
 
+// The same level without the constant-ROI branch: Dm = max(D, 1) and rcpDm =
+// 1 / Dm, so a constant ROI (every value vmin) gives num = 0 and level 1.
+// Values outside the ROI's range give some level in [0, ng] (callers mask
+// them by label).
+__device__ __forceinline__ uint32_t fbn_level_any(uint32_t I, uint32_t vmin, uint32_t Dm, float rcpDm, uint32_t ng) {
+    uint32_t num = __umul24(ng, I - vmin);
+    uint32_t q = (uint32_t)((float)num * rcpDm);
+    uint32_t qd = __umul24(q, Dm);
+    if (qd > num) q -= 1u;
+    else if (num - qd >= Dm) q += 1u;
+    uint32_t b = q + 1u;
+    return b > ng ? ng : b;
+}
+
 // ------------------------------------------------------------ wave ops
 // Wave-wide reductions with DPP: four in-row steps (quad_perm [1,0,3,2],
 // quad_perm [2,3,0,1], row_half_mirror, row_mirror) leave every lane of each

@@ -443,6 +443,8 @@ struct ItemCtx {
     int32_t nx, ny, nz;
     uint32_t label, vmin, D, ng;
     float rcpD;
+    uint32_t Dm;      // max(D, 1), with rcpDm = 1 / Dm (fbn_level_any)
+    float rcpDm;
     uint32_t *err;
     // The stored value under voxel v (bin or intensity) and its level, split
     // so a caller can issue many loads before converting any of them.  A
@@ -517,6 +519,11 @@ template <class T> __device__ __forceinline__ T lds_uniform(const T *p) {
 __device__ __forceinline__ uint32_t row_off(uint32_t x) { return (__umul24(x - 1u, x) >> 1) - 1u; }
 struct RowOff {
     __device__ __forceinline__ uint32_t operator()(uint32_t x) const { return row_off(x); }
+};
+// The same offsets read from an LDS table of levels 0..ng (entry 0 unused).
+struct RowOffTab {
+    const uint32_t *t;
+    __device__ __forceinline__ uint32_t operator()(uint32_t x) const { return t[x]; }
 };
 // Square (ordered counts) offset of a 1-based level x: the ordered pair
 // (a, b) lands at sq_off(a) + b = (a - 1) ng + b - 1.
@@ -827,9 +834,25 @@ __device__ __forceinline__ uint32_t lane_next(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true);  // wave_shl1; lane 63 reads 0
 }
 
-template <class Add>
+// BINS: levels from a caller-supplied bin image (else from intensity); ro:
+// the triangle row offsets of the levels.
+template <bool BINS, class RO, class Add>
 __device__ void accumulate_sweep2d(const RoiDesc &rd, const ItemCtx &c, uint32_t ra, uint32_t rb, uint32_t ca,
-                                   uint32_t cb, int h, int v, int d45, int d135, int w, int nw, Add &&add) {
+                                   uint32_t cb, int h, int v, int d45, int d135, int w, int nw, RO ro, Add &&add) {
+    // a voxel's level, 0 outside the ROI: computed for every lane and then
+    // selected by label (no branch per voxel)
+    const auto level = [&](uint32_t lab, uint32_t raw) -> uint32_t {
+        if constexpr (BINS) {
+            return lab == c.label ? c.level_of(raw) : 0u;
+        } else {
+            const uint32_t b = fbn_level_any(raw, c.vmin, c.Dm, c.rcpDm, c.ng);
+            return lab == c.label ? b : 0u;
+        }
+    };
+    const auto raw = [&](uint32_t i) -> uint32_t {
+        if constexpr (BINS) return (uint32_t)ldg(c.B, i);
+        else return (uint32_t)ldg(c.I, i);
+    };
     const uint32_t ln = (uint32_t)lane();
     const uint32_t Wt = cb - ca, H = rb - ra;
     // sub-rows per step: the fewest steps over the tile (ties: fewer sub-rows)
@@ -865,7 +888,7 @@ __device__ void accumulate_sweep2d(const RoiDesc &rd, const ItemCtx &c, uint32_t
         if (xin && sub == S - 1u && y0 > rd.y0) {
             const uint32_t iu = (uint32_t)(y0 - 1) * nx + (uint32_t)x;
             lab_up = c.lab(iu);
-            val_up = c.raw(iu);
+            val_up = raw(iu);
         }
 #pragma unroll
         for (uint32_t j = 0; j < kSweepSteps; ++j) {
@@ -874,20 +897,20 @@ __device__ void accumulate_sweep2d(const RoiDesc &rd, const ItemCtx &c, uint32_t
             if (xin && j * S + sub < nr) {
                 const uint32_t idx = idx0 + j * S * nx;
                 lab[j] = c.lab(idx);
-                val[j] = c.raw(idx);
+                val[j] = raw(idx);
             }
         }
-        uint32_t prev = lab_up == c.label ? c.level_of(val_up) : 0u;   // this lane's previous step
+        uint32_t prev = level(lab_up, val_up);   // this lane's previous step
 #pragma unroll
         for (uint32_t j = 0; j < kSweepSteps; ++j) {
             if (j * S >= nr) break;
-            const uint32_t cur = lab[j] == c.label ? c.level_of(val[j]) : 0u;
+            const uint32_t cur = level(lab[j], val[j]);
             uint32_t above = prev;
             if (S > 1u) {
                 const uint32_t offer = sub == S - 1u ? prev : cur;
                 above = (uint32_t)__builtin_amdgcn_ds_bpermute((int)up_lane, (int)offer);
             }
-            const uint32_t tcur = row_off(cur), tabove = row_off(above);
+            const uint32_t tcur = ro(cur), tabove = ro(above);
             const uint32_t cur_r = lane_next(cur), above_r = lane_next(above);
             const uint32_t tcur_r = lane_next(tcur), tabove_r = lane_next(tabove);
             if (owner && cur) {
@@ -960,6 +983,9 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
     for (uint32_t i = threadIdx.x; i < Ly.marg_sets * marg_words; i += blockDim.x)
         reinterpret_cast<uint32_t *>(smem + Ly.marg_off)[i] = 0u;
     for (uint32_t i = threadIdx.x; i < Ly.kp; i += blockDim.x) LCNT[i] = 0u;
+    if ((MODE == 2 || MODE == 3) && !NS)
+        for (uint32_t x = threadIdx.x; x <= ng; x += blockDim.x)
+            reinterpret_cast<uint32_t *>(smem + Ly.ro_off)[x] = x ? row_off(x) : 0u;
     if (direct_roi == kNone) ticket_load(MISC, a.counters + C_CLASS, a.bucket_cap, threadIdx.x);
     __syncthreads();
     if (threadIdx.x == 0 && direct_roi == kNone) ticket_prefix(MISC);
@@ -1000,6 +1026,8 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
             c.nx = it.nx; c.ny = it.ny; c.nz = it.nz;
             c.label = rd.label; c.vmin = rd.vmin; c.D = rd.vmax - rd.vmin; c.ng = ng;
             c.rcpD = it.rcpD;
+            c.Dm = c.D ? c.D : 1u;
+            c.rcpDm = c.D ? it.rcpD : 1.0f;
             c.err = &a.counters[C_ERR];
             const uint32_t ra = it.ra, rb = it.rb, ca = it.ca, cb = it.cb;
             const bool split = rd.gslot != kNone;
@@ -1023,10 +1051,17 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
                     const uint32_t W = (uint32_t)(rd.x1 - rd.x0 + 1), H = (uint32_t)(rd.y1 - rd.y0 + 1);
                     const uint32_t ring_rows = Ly.ring_bytes / W;
                     const uint32_t reach = Ly.ring_bytes ? staged_reach(a, d0, d1, H, W) : 0u;
-                    if (a.sweep_ok && pass < kMaxSweepPasses)
-                        accumulate_sweep2d(rd, c, ra, rb, ca, cb, a.sweep[pass][0], a.sweep[pass][1], a.sweep[pass][2],
-                                           a.sweep[pass][3], w, nw, add);
-                    else if (MODE != 1 && Ly.ring_bytes && ca == 0u && cb == W && ring_rows >= reach + kStagedMinRows) {
+                    if (a.sweep_ok && pass < kMaxSweepPasses && !c.B) {
+                        // (a caller-supplied bin image takes the gather below)
+                        const int8_t *sw = a.sweep[pass];
+                        if constexpr (MODE == 2 || MODE == 3) {
+                            const RowOffTab ro{reinterpret_cast<const uint32_t *>(smem + Ly.ro_off)};
+                            accumulate_sweep2d<false>(rd, c, ra, rb, ca, cb, sw[0], sw[1], sw[2], sw[3], w, nw, ro, add);
+                        } else {
+                            accumulate_sweep2d<false>(rd, c, ra, rb, ca, cb, sw[0], sw[1], sw[2], sw[3], w, nw, RowOff{},
+                                                      add);
+                        }
+                    } else if (MODE != 1 && Ly.ring_bytes && ca == 0u && cb == W && ring_rows >= reach + kStagedMinRows) {
                         // (the hash layout reserves no ring)
                         if constexpr (MODE != 1)
                             accumulate_staged(a, rd, c, ra, rb, d0, d1, smem + Ly.ring_off, ring_rows, reach, add);

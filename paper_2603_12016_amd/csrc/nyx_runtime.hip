@@ -455,6 +455,7 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K, bool ring) {
     L.marg_sets = std::min(L.nwaves, c.merged ? 1u : c.kp);   // one set per wave that reduces a matrix
     L.marg_off = take(L.marg_sets * marg_words(ng, c.nonsym != 0) * 4u);
     L.misc_off = take(128u * 4u);
+    if ((c.mode == 2 || c.mode == 3) && !c.nonsym) L.ro_off = take((ng + 1u) * 4u);
     L.item_off = take((uint32_t)kTicketChunk * kItemBytes);
     if (ring && ng <= 255u && c.mode != 1 && !c.nonsym) {
         // work-groups per CU: LDS-bound, and at most kMaxGroupsPerCu (the
@@ -507,7 +508,9 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
     // LDS besides triangles / hash / lists: marginals for up to nw directions
     // at a time, misc, alignment slack
     auto fixed_for = [&](uint32_t kp) {
-        return (std::min(nw, kp) * marg_words(ng, nonsym) * 4u + 15u) / 16u * 16u + 128u * 4u + 64u * 4u + 64;
+        // (marginal sets, misc words, staged item descriptors, row-offset table, alignment slack)
+        return (std::min(nw, kp) * marg_words(ng, nonsym) * 4u + 15u) / 16u * 16u + 128u * 4u +
+               (uint32_t)kTicketChunk * kItemBytes + ((ng + 1u) * 4u + 15u) / 16u * 16u + 64u * 4u + 64;
     };
     const uint32_t fixed = fixed_for(1u);
     uint64_t total_vox = 0;
@@ -791,12 +794,17 @@ nyx_status check_counters(nyx_ctx *ctx, Work &w, hipStream_t st) {
 }
 
 std::string describe(const Config &c, const nyx_plan *p, uint64_t items, uint32_t n_split) {
-    char buf[512];
+    uint64_t band_voxels = 0;
+    for (const RoiDesc &r : p->w.h_rois)
+        if (c.band_vox && r.n > c.band_vox) band_voxels += r.n;
+    char buf[640];
     snprintf(buf, sizeof buf,
              "mode=%s kp=%u copies=%u symmetric=%d block=%u grid=%u lds=%uB split_vox=%u tile_vox=%u tile_scale=%g "
-             "list_cap=%u hash_cap=%u band_vox=%u band_w=%u rois=%u items=%llu split_rois=%u ng=%d K=%d tuned_ms=%.4f",
+             "list_cap=%u hash_cap=%u band_vox=%u band_w=%u band_voxels=%llu rois=%u items=%llu split_rois=%u ng=%d K=%d "
+             "tuned_ms=%.4f",
              mode_name(c.mode), c.kp, p->w.args.lds.copies, c.nonsym ? 0 : 1, c.block, p->grid, p->w.args.lds.bytes, c.split_vox,
-             c.tile_vox, (double)c.tile_scale, c.list_cap, c.hash_cap, c.band_vox, c.band_w, p->w.n_rois,
+             c.tile_vox, (double)c.tile_scale, c.list_cap, c.hash_cap, c.band_vox, c.band_w,
+             (unsigned long long)band_voxels, p->w.n_rois,
              (unsigned long long)items,
              n_split, p->ng, p->K, (double)p->tuned_ms);
     return buf;
@@ -808,6 +816,9 @@ nyx_status configure(nyx_plan *p, const Config &cfg, const nyx_extract_opts *opt
     nyx_status s = setup_step(ctx, p->w, cfg, opts->offsets_host, p->K, (uint32_t)p->ng, p->prec == NYX_FP64, 0,
                               opts->workspace_cap_bytes, &p->workspace_bytes);
     if (s != NYX_OK) return s;
+    if (p->w.args.lds.bytes > kLdsBudget)
+        return fail(ctx, NYX_ERR_UNSUPPORTED, "LDS layout of %u bytes exceeds the %u available", p->w.args.lds.bytes,
+                    kLdsBudget);
     p->block = cfg.block;
     int occ = 0;
     HIPC(ctx, batch_occupancy(cfg.mode, p->prec == NYX_FP64, cfg.nonsym, cfg.block, p->w.args.lds.bytes, &occ));

@@ -122,6 +122,7 @@ struct LdsLayout {
     uint32_t u_off, list_off, lcnt_off, marg_off, feat_off, sums_off, misc_off, hkey_off, hcnt_off, buf_off;
     uint32_t item_off;    // staged descriptors of the current ticket (work-group kernel)
     uint32_t ring_off, ring_bytes;   // level ring of the staged accumulation (0 bytes: none)
+    uint32_t ro_off;      // triangle row offsets of the levels 0..ng (dense symmetric modes; 0: none)
     uint32_t bytes;       // total dynamic LDS
     uint32_t nwaves;      // waves per work-group
     uint32_t marg_sets;   // marginal sets at marg_off (one per wave that reduces a matrix)
