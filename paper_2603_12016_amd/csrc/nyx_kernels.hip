@@ -53,6 +53,47 @@ __global__ void k_max_label(const ImgDesc *imgs, int n_images, uint32_t *out) {
     if (lane() == 0) atomicMax(&out[im], m);
 }
 
+// Distinct nonzero labels of a batch, as (image << 32 | label) entries of
+// `list`: a work-group takes `chunk` voxels of image blockIdx.y, drops the
+// repeats in an LDS hash table (label 0 marks a free slot) and appends the
+// survivors.  A label may be listed by several work-groups (and by one when
+// its hash probes fail); the host removes the repeats.  count receives the
+// number of entries even beyond cap (the host then retries with room for all).
+__global__ __launch_bounds__(256) void k_label_collect(const ImgDesc *imgs, int n_images, uint32_t chunk,
+                                                       uint64_t *list, uint32_t cap, uint32_t *count) {
+    constexpr uint32_t kSlots = 1024u;
+    __shared__ uint32_t H[kSlots];
+    for (uint32_t i = threadIdx.x; i < kSlots; i += blockDim.x) H[i] = 0u;
+    __syncthreads();
+    const int im = (int)blockIdx.y;
+    const auto emit = [&](uint32_t l) {
+        const uint32_t pos = atomicAdd(count, 1u);
+        if (pos < cap) list[pos] = (uint64_t)(uint32_t)im << 32 | l;
+    };
+    if (im < n_images) {
+        const ImgDesc d = imgs[im];
+        const uint64_t v0 = (uint64_t)blockIdx.x * chunk;
+        const uint64_t v1 = v0 + chunk < d.nvox ? v0 + chunk : d.nvox;
+        uint32_t prev = 0u;
+        for (uint64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+            const uint32_t l = d.L[v];
+            if (l == 0u || l == prev) continue;
+            prev = l;
+            uint32_t h = hash_u32(l) & (kSlots - 1u);
+            bool done = false;
+            for (int probe = 0; probe < 32 && !done; ++probe) {
+                const uint32_t cur = atomicCAS(&H[h], 0u, l);
+                done = cur == 0u || cur == l;
+                h = (h + 1u) & (kSlots - 1u);
+            }
+            if (!done) emit(l);
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kSlots; i += blockDim.x)
+        if (H[i]) emit(H[i]);
+}
+
 // ------------------------------------------------------------------ reset
 __global__ void k_reset(StepArgs a, uint32_t n_counters) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -140,6 +181,15 @@ __device__ __forceinline__ void scan_flush_run(const StepArgs &a, ScanLds &S, ui
     scan_flush_global(a, K, r.c, r.mn, r.mx, r.x0, r.x1, r.y0, r.y1, r.z0, r.z1);
 }
 
+// Flushes a finished run (key != 0) under its label's table entry; a label
+// without one sets `bad`.
+__device__ __forceinline__ void scan_flush_label(const StepArgs &a, ScanLds &S, const ImgDesc &d, const RunRec &r,
+                                                 uint32_t &bad) {
+    const uint32_t e = d.dict ? label_entry(d.dict, d.dict_n, d.max_label, r.key) : r.key;
+    if (e) scan_flush_run(a, S, d.tab_base + e, r);
+    else bad = 1u;
+}
+
 // Segmented inclusive combination over each 16-lane row: the lanes of a
 // maximal group of adjacent lanes with the same key form a segment, and
 // after the row_shr 1, 2, 4, 8 steps the last lane of a segment holds the
@@ -214,9 +264,9 @@ __global__ __launch_bounds__(256) void k_scan(StepArgs a) {
         for (uint32_t j = 0; j < kScanTileRows; ++j) {
             if (j >= nr) break;
             uint32_t l = lab[j];
-            if (l > d.max_label) { bad = 1u; l = 0u; }
+            if (!d.dict && l > d.max_label) { bad = 1u; l = 0u; }
             if (l != run.key || z != run.z0) {
-                if (run.key) scan_flush_run(a, S, d.tab_base + run.key, run);
+                if (run.key) scan_flush_label(a, S, d, run, bad);
                 run = RunRec{l, 0u, 0xFFFFu, 0u, x, x, y, y, z, z};
             }
             if (l) {
@@ -231,7 +281,7 @@ __global__ __launch_bounds__(256) void k_scan(StepArgs a) {
     // The runs still open at the tile's last row: adjacent lanes of a row
     // holding the same label are combined first, so one lane per group
     // flushes (a wide ROI would otherwise send every lane to one slot).
-    if (row_segment_combine(run) && run.key) scan_flush_run(a, S, d.tab_base + run.key, run);
+    if (row_segment_combine(run) && run.key) scan_flush_label(a, S, d, run, bad);
     if (bad) atomicOr(&a.counters[C_ERR], (uint32_t)E_LABEL_RANGE);
     __syncthreads();
     for (int i = threadIdx.x; i < kScanSlots; i += blockDim.x) {
@@ -290,7 +340,8 @@ __global__ __launch_bounds__(1024) void k_compact_write(StepArgs a, uint32_t roi
     uint32_t cls = 0u, nt = 1u, local = 0u;
     if (live) {
     const int im = find_image_entry(a.imgs, a.n_images, e);
-    const uint32_t label = e - a.imgs[im].tab_base;
+    const uint32_t ent = e - a.imgs[im].tab_base;   // >= 1: entry 0 never counts a voxel
+    const uint32_t label = a.imgs[im].dict ? a.imgs[im].dict[ent - 1u] : ent;
     rd.label = label;
     rd.image = (uint32_t)im;
     rd.n = a.tab.cnt[e];
@@ -391,8 +442,9 @@ __global__ __launch_bounds__(256) void k_bin_image(StepArgs a, uint16_t *bins_ou
         uint32_t v = (uint32_t)(g - img_vox_base[lo]);
         uint32_t l = d.L[v];
         uint16_t b = 0;
-        if (l != 0u && l <= d.max_label) {
-            uint32_t r = a.tab.row[d.tab_base + l];
+        const uint32_t ent = label_entry(d.dict, d.dict_n, d.max_label, l);
+        if (ent) {
+            uint32_t r = a.tab.row[d.tab_base + ent];
             if (r != kNone && r < a.roi_cap) {
                 const RoiDesc &rd = a.rois[r];
                 uint32_t D = rd.vmax - rd.vmin;
@@ -1503,6 +1555,17 @@ __global__ __launch_bounds__(512) void k_coo_features(StepArgs a, const uint64_t
 hipError_t launch_max_label(const ImgDesc *imgs, int n_images, uint32_t *out, hipStream_t st) {
     dim3 grid(256, n_images);
     hipLaunchKernelGGL(k_max_label, grid, dim3(256), 0, st, imgs, n_images, out);
+    NYX_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_label_collect(const ImgDesc *imgs, int n_images, uint64_t max_vox, uint64_t *list, uint32_t cap,
+                                uint32_t *count, hipStream_t st) {
+    constexpr uint32_t chunk = 1u << 16;
+    const uint32_t gx = (uint32_t)((max_vox + chunk - 1u) / chunk);
+    if (gx == 0u || n_images <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_label_collect, dim3(gx, (uint32_t)n_images), dim3(256), 0, st, imgs, n_images, chunk, list,
+                       cap, count);
     NYX_CHECK_LAUNCH();
     return hipSuccess;
 }

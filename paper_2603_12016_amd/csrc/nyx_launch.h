@@ -7,6 +7,8 @@
 namespace nyx {
 
 hipError_t launch_max_label(const ImgDesc *imgs, int n_images, uint32_t *out, hipStream_t st);
+hipError_t launch_label_collect(const ImgDesc *imgs, int n_images, uint64_t max_vox, uint64_t *list, uint32_t cap,
+                                uint32_t *count, hipStream_t st);
 hipError_t launch_reset(const StepArgs &a, uint32_t n_counters, hipStream_t st);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t st);
 hipError_t launch_zero_split(const StepArgs &a, hipStream_t st);

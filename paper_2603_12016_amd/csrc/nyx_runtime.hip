@@ -168,7 +168,8 @@ struct nyx_ctx {
 // All device state of one discovery/step over a batch of images.
 struct Work {
     std::vector<ImgDesc> h_imgs;
-    DevBuf imgs, tab[10], counters, rois, buckets, G, dsums, dsums_y, split_roi, band_roi, smarg, stot, splp, vox_base;
+    DevBuf imgs, tab[10], counters, rois, buckets, G, dsums, dsums_y, split_roi, band_roi, smarg, stot, splp, vox_base,
+        dict;
     uint32_t tab_total = 0, n_blocks = 0, n_counters = 0, total_chunks = 0;
     uint32_t n_rois = 0;
     uint64_t total_vox = 0;
@@ -177,7 +178,7 @@ struct Work {
     // Carve every buffer from `ar` (nullptr: hipMalloc).
     void use_arena(Arena *ar) {
         for (DevBuf *b : {&imgs, &counters, &rois, &buckets, &G, &dsums, &dsums_y, &split_roi, &band_roi, &smarg, &stot,
-                          &splp, &vox_base})
+                          &splp, &vox_base, &dict})
             b->arena = ar;
         for (DevBuf &b : tab) b.arena = ar;
     }
@@ -259,6 +260,52 @@ nyx_status validate_bins(nyx_ctx *ctx, int32_t ng) {
     return NYX_OK;
 }
 
+// Distinct nonzero labels of every image, ascending, uploaded to w.dict;
+// sets dict, dict_n and max_label (= dict_n) of w.h_imgs.  Labels present in
+// a later execution but absent here have no table entry (E_LABEL_RANGE).
+nyx_status build_label_dict(nyx_ctx *ctx, Work &w, int32_t n, hipStream_t st) {
+    uint64_t max_vox = 0;
+    for (int i = 0; i < n; ++i) max_vox = std::max<uint64_t>(max_vox, w.h_imgs[i].nvox);
+    DevBuf list, cnt;
+    list.arena = cnt.arena = w.imgs.arena;
+    HIPC(ctx, cnt.alloc(sizeof(uint32_t)));
+    uint32_t cap = 1u << 16, got = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        HIPC(ctx, list.alloc(sizeof(uint64_t) * cap));
+        const uint32_t zero = 0u;
+        HIPC(ctx, hipMemcpyAsync(cnt.p, &zero, sizeof zero, hipMemcpyHostToDevice, st));
+        HIPC(ctx, launch_label_collect(w.imgs.as<ImgDesc>(), n, max_vox, list.as<uint64_t>(), cap, cnt.as<uint32_t>(),
+                                       st));
+        HIPC(ctx, hipMemcpyAsync(&got, cnt.p, sizeof got, hipMemcpyDeviceToHost, st));
+        HIPC(ctx, hipStreamSynchronize(st));
+        if (got <= cap) break;
+        cap = got;   // every entry fits the second time (same images)
+    }
+    if (got > cap) return fail(ctx, NYX_ERR_INTERNAL, "label collection did not converge");
+    std::vector<uint64_t> h(got);
+    if (got) HIPC(ctx, hipMemcpyAsync(h.data(), list.p, sizeof(uint64_t) * got, hipMemcpyDeviceToHost, st));
+    HIPC(ctx, hipStreamSynchronize(st));
+    std::sort(h.begin(), h.end());
+    h.erase(std::unique(h.begin(), h.end()), h.end());
+    std::vector<uint32_t> labels(h.size());
+    std::vector<uint64_t> first(n + 1, 0);
+    for (size_t k = 0; k < h.size(); ++k) {
+        labels[k] = (uint32_t)h[k];
+        first[(size_t)(h[k] >> 32) + 1u]++;
+    }
+    for (int i = 0; i < n; ++i) first[i + 1] += first[i];
+    HIPC(ctx, w.dict.alloc(sizeof(uint32_t) * std::max<size_t>(labels.size(), 1)));
+    if (!labels.empty())
+        HIPC(ctx, hipMemcpyAsync(w.dict.p, labels.data(), sizeof(uint32_t) * labels.size(), hipMemcpyHostToDevice, st));
+    HIPC(ctx, hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) {
+        w.h_imgs[i].dict = w.dict.as<uint32_t>() + first[i];
+        w.h_imgs[i].dict_n = (uint32_t)(first[i + 1] - first[i]);
+        w.h_imgs[i].max_label = w.h_imgs[i].dict_n;
+    }
+    return NYX_OK;
+}
+
 // Label tables, ROI discovery and the ROI table (no work items).
 nyx_status discover(nyx_ctx *ctx, const nyx_image *imgs, int32_t n, Work &w, hipStream_t st) {
     w.h_imgs.resize(n);
@@ -301,14 +348,29 @@ nyx_status discover(nyx_ctx *ctx, const nyx_image *imgs, int32_t n, Work &w, hip
     HIPC(ctx, hipMemcpyAsync(hmax.data(), dmax.p, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, st));
     HIPC(ctx, hipStreamSynchronize(st));
     uint64_t total = 0;
+    for (int i = 0; i < n; ++i) total += (uint64_t)hmax[i] + 1u;
+    if (total > kMaxLabelEntries || total > tv + (uint64_t)n) {
+        // Label values too large (or too sparse) to index the table: the
+        // table gets one entry per distinct label of each image instead.
+        nyx_status s = build_label_dict(ctx, w, n, st);
+        if (s != NYX_OK) return s;
+        total = 0;
+        for (int i = 0; i < n; ++i) total += (uint64_t)w.h_imgs[i].dict_n + 1u;
+        if (total > kMaxLabelEntries)
+            return fail(ctx, NYX_ERR_UNSUPPORTED, "%llu distinct labels (limit %llu)", (unsigned long long)total,
+                        (unsigned long long)kMaxLabelEntries);
+    } else {
+        for (int i = 0; i < n; ++i) {
+            w.h_imgs[i].dict = nullptr;
+            w.h_imgs[i].dict_n = 0u;
+            w.h_imgs[i].max_label = hmax[i];
+        }
+    }
+    total = 0;
     for (int i = 0; i < n; ++i) {
         w.h_imgs[i].tab_base = (uint32_t)total;
-        w.h_imgs[i].max_label = hmax[i];
-        total += (uint64_t)hmax[i] + 1u;
+        total += (uint64_t)w.h_imgs[i].max_label + 1u;
     }
-    if (total > kMaxLabelEntries)
-        return fail(ctx, NYX_ERR_UNSUPPORTED, "label values too large: %llu label-table entries (limit %llu)",
-                    (unsigned long long)total, (unsigned long long)kMaxLabelEntries);
     w.tab_total = (uint32_t)total;
     HIPC(ctx, hipMemcpyAsync(w.imgs.p, w.h_imgs.data(), sizeof(ImgDesc) * n, hipMemcpyHostToDevice, st));
     for (auto &b : w.tab) HIPC(ctx, b.alloc(sizeof(uint32_t) * (size_t)total));

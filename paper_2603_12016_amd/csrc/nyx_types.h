@@ -55,9 +55,11 @@ struct ImgDesc {
     const uint16_t *B;     // optional bin image (nullptr: bin on the fly)
     int32_t nz, ny, nx;
     uint32_t nvox;
-    uint32_t tab_base;     // label-table index of label 0 of this image
-    uint32_t max_label;    // label-table capacity of this image (labels 0..max_label)
+    uint32_t tab_base;     // label-table index of entry 0 of this image (entry 0 is never used)
+    uint32_t max_label;    // label-table entries of this image are 0..max_label
     uint32_t chunk_base;   // first scan tile of this image
+    uint32_t dict_n;       // entries of dict
+    const uint32_t *dict;  // the image's distinct nonzero labels, ascending (nullptr: a label is its own entry)
 };
 
 // Per-label statistics, one entry per (image, label), struct of arrays.
@@ -293,6 +295,22 @@ inline uint32_t size_class(uint32_t vox) {
     uint32_t c = 0;
     while ((vox >> c) > 1u && c < 31u) ++c;
     return c;
+}
+
+// Label-table entry (within its image) of label l, 0 when l has none.  With
+// no dictionary a label is its own entry (labels up to max_label); with one,
+// the entry is 1 + the rank of l among the image's distinct labels, found by
+// binary search (labels absent from the dictionary have none).
+__host__ __device__
+inline uint32_t label_entry(const uint32_t *dict, uint32_t dict_n, uint32_t max_label, uint32_t l) {
+    if (l == 0u) return 0u;
+    if (!dict) return l <= max_label ? l : 0u;
+    uint32_t lo = 0u, hi = dict_n;   // first index with dict[i] >= l lies in [lo, hi]
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (dict[mid] < l) lo = mid + 1u; else hi = mid;
+    }
+    return lo < dict_n && dict[lo] == l ? lo + 1u : 0u;
 }
 
 }  // namespace nyx

@@ -34,4 +34,8 @@ void rules_ticket_range(uint32_t t, const uint32_t *entries, const uint32_t *fir
     *cl = c;
 }
 
+uint32_t rules_label_entry(const uint32_t *dict, uint32_t dict_n, uint32_t max_label, uint32_t l) {
+    return nyx::label_entry(dict, dict_n, max_label, l);
+}
+
 }  // extern "C"

@@ -119,7 +119,26 @@ def rules():
     L.rules_ticket_offsets.argtypes = [P, P]
     L.rules_ticket_offsets.restype = u32
     L.rules_ticket_range.argtypes = [u32, P, P, P, P, P]
+    L.rules_label_entry.argtypes = [P, u32, u32, u32]
+    L.rules_label_entry.restype = u32
     return L
+
+
+def test_label_entry_rule(rules):
+    # the compiled label-to-entry rule: direct indexing up to max_label, else
+    # 1 + rank in the sorted dictionary, 0 for background and absent labels
+    for l in (0, 1, 7, 8, 9, 1000):
+        assert rules.rules_label_entry(None, 0, 8, l) == (l if 0 < l <= 8 else 0)
+    rng = np.random.default_rng(5)
+    for n in (0, 1, 2, 3, 17, 256, 1001):
+        d = np.unique(rng.integers(1, 2**32, size=n, dtype=np.uint64)).astype(np.uint32)
+        d = np.concatenate([d, np.array([2**32 - 1], np.uint32)]) if n == 2 else d
+        d = np.ascontiguousarray(np.unique(d))
+        probes = np.concatenate([d, d - 1, d + 1, [0, 1, 2**32 - 1, 2**31]]).astype(np.uint32)
+        pos = {int(v): k + 1 for k, v in enumerate(d)}
+        for l in probes:
+            want = pos.get(int(l), 0) if l != 0 else 0
+            assert rules.rules_label_entry(d.ctypes.data if d.size else None, d.size, d.size, int(l)) == want
 
 
 def test_split_rule_covers_rows_and_columns(rules):
