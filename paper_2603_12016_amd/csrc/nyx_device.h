@@ -17,6 +17,14 @@ __device__ __forceinline__ T ldg(const T *p, uint32_t i) {
     return ((const __attribute__((address_space(1))) T *)p)[i];
 }
 
+// Element at byte offset `off` (< 2^32) from a wave-uniform pointer p: the
+// global_load form with the base in SGPRs and a 32-bit VGPR offset, so the
+// lane's address costs no 64-bit arithmetic.
+template <class T>
+__device__ __forceinline__ T ldb(const T *p, uint32_t off) {
+    return *(const __attribute__((address_space(1))) T *)((const __attribute__((address_space(1))) char *)p + off);
+}
+
 // ------------------------------------------------------------ binning
 // Fixed-bin-number level (paper: "number of bins" / grey depth, Materials and
 // methods, "Feature Control and Tunability"): 1 + floor(ng (I - vmin) / D),
@@ -32,20 +40,6 @@ __device__ __forceinline__ uint32_t fbn_level(uint32_t I, uint32_t vmin, uint32_
     uint32_t qd = __umul24(q, D);
     if (qd > num) q -= 1u;
     else if (num - qd >= D) q += 1u;
-    uint32_t b = q + 1u;
-    return b > ng ? ng : b;
-}
-
-// The same level without the constant-ROI branch: Dm = max(D, 1) and rcpDm =
-// 1 / Dm, so a constant ROI (every value vmin) gives num = 0 and level 1.
-// Values outside the ROI's range give some level in [0, ng] (callers mask
-// them by label).
-__device__ __forceinline__ uint32_t fbn_level_any(uint32_t I, uint32_t vmin, uint32_t Dm, float rcpDm, uint32_t ng) {
-    uint32_t num = __umul24(ng, I - vmin);
-    uint32_t q = (uint32_t)((float)num * rcpDm);
-    uint32_t qd = __umul24(q, Dm);
-    if (qd > num) q -= 1u;
-    else if (num - qd >= Dm) q += 1u;
     uint32_t b = q + 1u;
     return b > ng ? ng : b;
 }

@@ -465,7 +465,7 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
     // One sweep over the nonzero cells: marginals and cell terms.  A cell
     // (lo < hi) with count c stands for P(lo, hi) = P(hi, lo) = c, a diagonal
     // one for P = 2c.
-    ISum Tl = 0, sumP2 = 0, S11 = 0;
+    ISum sumP2 = 0;
     uint32_t maxP = 0;
     LaneSum<Acc> plp;
     src.for_each(g, [&](uint32_t lo, uint32_t hi, uint32_t c) {
@@ -476,21 +476,23 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
         const bool diag = lo == hi;
         const uint32_t P = diag ? 2u * c : c;
         const ISum Pm = diag ? (ISum)P : (ISum)(2ull * P);    // P summed over both orders
-        Tl += (ISum)(2ull * c);
         sumP2 += Pm * (ISum)P;
         maxP = P > maxP ? P : maxP;
-        S11 += Pm * (ISum)__umul24(lo + 1u, hi + 1u);   // levels < 2^16: exact
         plp.add((Acc)Pm * term_log2<Acc>((Acc)P));
     });
     g.sync();
-    // Level sweeps over the marginals (unnormalised).
-    ISum S1 = 0, S2 = 0, Sm1 = 0;
+    // Level sweeps over the marginals (unnormalised).  T = sum R(i), and
+    // S11 comes from the difference marginal: sum (i - j)^2 P = 2 S2 - 2 S11
+    // for a symmetric matrix, so S11 = S2 - K2 / 2 with K2 = sum k^2 Sm(k)
+    // (even, exact).  The slot of S11 carries K2 through the reduction.
+    ISum Tl = 0, S1 = 0, S2 = 0, Sm1 = 0, S11 = 0;
     LaneSum<Acc> rlr, slp, hom1, hom2, idmn, idn, iv, plps;
     const Acc ngf = (Acc)ng, rng = (Acc)1 / ngf, rng2 = rng * rng;
     for (uint32_t i = r0; i < ng; i += gs) {
         const uint32_t r = R[i];
         if (r) {
             const ISum lv = (ISum)(i + 1u);
+            Tl += (ISum)r;
             S1 += lv * (ISum)r;
             S2 += lv * lv * (ISum)r;
             rlr.add((Acc)r * term_log2<Acc>((Acc)r));
@@ -498,6 +500,7 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
         const uint32_t s = Sm[i];
         if (s) {
             Sm1 += (ISum)i * (ISum)s;
+            S11 += (ISum)(i * i) * (ISum)s;   // K2 (i < 2^13)
             const Acc sf = (Acc)s, k = (Acc)i;
             slp.add(sf * term_log2<Acc>(sf));
             hom1.add(term_div<Acc>(sf, (Acc)1 + k));
@@ -526,11 +529,13 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
         slot = g.reduce_slots(v);
         T = (uint64_t)g.bcast(slot, 0);
         S1t = (uint64_t)g.bcast(slot, 1);
+        const double S2t = g.bcast(slot, 2);
+        if (rk == 4) slot = S2t - 0.5 * slot;   // S11 = S2 - K2 / 2 (exact integers below 2^53)
         plp_t = g.bcast(slot, 6);
         rlr_t = g.bcast(slot, 7);
     } else {
         tot_u[0] = (uint64_t)g.sum(Tl); tot_u[1] = (uint64_t)g.sum(S1); tot_u[2] = (uint64_t)g.sum(S2);
-        tot_u[3] = (uint64_t)g.sum(Sm1); tot_u[4] = (uint64_t)g.sum(S11); tot_u[5] = (uint64_t)g.sum(sumP2);
+        tot_u[3] = (uint64_t)g.sum(Sm1); tot_u[4] = tot_u[2] - (uint64_t)g.sum(S11) / 2u; tot_u[5] = (uint64_t)g.sum(sumP2);
         tot_d[0] = g.sum(comp_value(plp)); tot_d[1] = g.sum(comp_value(rlr)); tot_d[2] = g.sum(comp_value(slp));
         tot_d[3] = g.sum(comp_value(plps)); tot_d[4] = g.sum(comp_value(hom1)); tot_d[5] = g.sum(comp_value(hom2));
         tot_d[6] = g.sum(comp_value(idmn)); tot_d[7] = g.sum(comp_value(idn)); tot_d[8] = g.sum(comp_value(iv));

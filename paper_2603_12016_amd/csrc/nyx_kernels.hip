@@ -493,10 +493,8 @@ struct ItemCtx {
     const uint32_t *L;
     const uint16_t *B;
     int32_t nx, ny, nz;
-    uint32_t label, vmin, D, ng;
-    float rcpD;
-    uint32_t Dm;      // max(D, 1), with rcpDm = 1 / Dm (fbn_level_any)
-    float rcpDm;
+    uint32_t label, vmin, ng;
+    double rcp;       // 1 / max(vmax - vmin, 1), rounded up (fbn_level_rd)
     uint32_t *err;
     // The stored value under voxel v (bin or intensity) and its level, split
     // so a caller can issue many loads before converting any of them.  A
@@ -507,7 +505,7 @@ struct ItemCtx {
     }
     __device__ __forceinline__ uint32_t lab(uint32_t v) const { return ldg(L, v); }
     __device__ __forceinline__ uint32_t level_of(uint32_t r) const {
-        if (!B) return fbn_level(r, vmin, D, rcpD, ng);
+        if (!B) return fbn_level_rd(r, vmin, rcp, ng);
         if (r == 0u || r > ng) {
             atomicOr(err, (uint32_t)E_BIN_RANGE);
             r = r == 0u ? 1u : ng;
@@ -525,16 +523,15 @@ struct ItemDesc {
     const uint32_t *L;
     const uint16_t *B;
     int32_t nx, ny, nz;
-    uint32_t roi, ra, rb, ca, cb;   // bbox rows [ra, rb) and columns [ca, cb) of the tile
-    float rcpD;                     // 1 / (vmax - vmin), 0 for a constant ROI
-    uint32_t ok;                    // 0: the entry names no valid ROI tile (skipped)
+    uint32_t roi;                   // kNone: the entry names no valid ROI tile (skipped)
+    uint32_t ra, rb, ca, cb;        // bbox rows [ra, rb) and columns [ca, cb) of the tile
+    double rcp;                     // 1 / max(vmax - vmin, 1), rounded up (fbn_level_rd)
 };
 static_assert(sizeof(ItemDesc) <= kItemBytes, "staged descriptor exceeds its LDS slot");
 
 __device__ void stage_item(const StepArgs &a, uint32_t roi, uint32_t tile, ItemDesc *dst) {
     ItemDesc it;
-    it.ok = 0u;
-    it.roi = roi;
+    it.roi = kNone;
     if (roi < a.roi_cap) {
         const RoiDesc rd = a.rois[roi];
         it.rd = rd;
@@ -547,8 +544,8 @@ __device__ void stage_item(const StepArgs &a, uint32_t roi, uint32_t tile, ItemD
                 tile_bounds(rd.rows, (uint32_t)(rd.x1 - rd.x0 + 1), rd.n_tiles, rd.tcols, tile, &it.ra, &it.rb,
                             &it.ca, &it.cb);
                 const uint32_t D = rd.vmax - rd.vmin;
-                it.rcpD = D ? 1.0f / (float)D : 0.0f;
-                it.ok = 1u;
+                it.rcp = fbn_rcp_up(D ? D : 1u);
+                it.roi = roi;
             }
         }
     }
@@ -584,6 +581,14 @@ struct SqOff {
     __device__ __forceinline__ uint32_t operator()(uint32_t x) const { return __umul24(x - 1u, ng) - 1u; }
 };
 
+// i >> 1 as an opaque shift: the compiler would otherwise fold the word
+// address (i >> 1) * 4 + base into three operations instead of two.
+__device__ __forceinline__ uint32_t half_index(uint32_t i) {
+    uint32_t w;
+    asm("v_lshrrev_b32 %0, 1, %1" : "=v"(w) : "v"(i));
+    return w;
+}
+
 // Add one level pair (1-based la, lb, with their row offsets ta, tb) to
 // local direction dl: unordered into the triangle (SQ false), or ordered
 // (la at v, lb at v + d) into the square of ordered counts (SQ true; ta from
@@ -596,14 +601,19 @@ __device__ __forceinline__ void add_pair(const StepArgs &a, uint8_t *smem, uint3
     uint32_t *LCNT = reinterpret_cast<uint32_t *>(smem + Ly.lcnt_off);
     uint32_t *LST = reinterpret_cast<uint32_t *>(smem + Ly.list_off) + dl * Ly.list_cap;
     if (MODE == 2 || MODE == 3) {
-        // privatised copies: lane l adds to copy l mod copies (copies is a power of two)
+        // privatised copies: lane l adds to copy l mod copies (copies is a power
+        // of two); 24-bit multiply (full rate): both factors are small
         const uint32_t cp = Ly.copies > 1u ? (uint32_t)lane() & (Ly.copies - 1u) : 0u;
-        uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + (dl * Ly.copies + cp) * Ly.tri_pad;
-        const uint32_t i = SQ ? ta + lb : (la <= lb ? tb + la : ta + lb);
+        uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + __umul24(dl * Ly.copies + cp, Ly.tri_pad);
+        // the triangle index of the unordered pair is the larger of the two
+        // candidates: row_off(b) + a - (row_off(a) + b) = sum over x in [a, b)
+        // of (x - 1) >= 0 for 1 <= a <= b, so no comparison of the levels
+        const uint32_t i = SQ ? ta + lb : max(tb + la, ta + lb);
         if (MODE == 2)
             __hip_atomic_fetch_add(&U[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         else
-            __hip_atomic_fetch_add(&U[i >> 1], 1u << ((i & 1u) << 4), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&U[half_index(i)], 1u << ((i & 1u) << 4), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
     } else if (MODE == 0) {
         uint32_t *U = reinterpret_cast<uint32_t *>(smem + Ly.u_off) + dl * Ly.tri_pad;
         uint32_t old = atomicAdd(&U[tri_idx(lo, hi)], 1u);
@@ -897,14 +907,11 @@ __device__ void accumulate_sweep2d(const RoiDesc &rd, const ItemCtx &c, uint32_t
         if constexpr (BINS) {
             return lab == c.label ? c.level_of(raw) : 0u;
         } else {
-            const uint32_t b = fbn_level_any(raw, c.vmin, c.Dm, c.rcpDm, c.ng);
+            const uint32_t b = fbn_level_rd(raw, c.vmin, c.rcp, c.ng);
             return lab == c.label ? b : 0u;
         }
     };
-    const auto raw = [&](uint32_t i) -> uint32_t {
-        if constexpr (BINS) return (uint32_t)ldg(c.B, i);
-        else return (uint32_t)ldg(c.I, i);
-    };
+    const uint16_t *const V = BINS ? c.B : c.I;   // the stored values (bins or intensity)
     const uint32_t ln = (uint32_t)lane();
     const uint32_t Wt = cb - ca, H = rb - ra;
     // sub-rows per step: the fewest steps over the tile (ties: fewer sub-rows)
@@ -916,18 +923,32 @@ __device__ void accumulate_sweep2d(const RoiDesc &rd, const ItemCtx &c, uint32_t
     }
     const uint32_t S = 1u << lg, Wl = 64u >> lg, Wo = Wl - 1u;
     const uint32_t sub = ln >> (6u - lg), col = ln & (Wl - 1u);
-    const uint32_t nstrip = (Wt + Wo - 1u) / Wo;
+    // (constant divisors: no division sequence per item)
+    const uint32_t nstrip = lg == 0u ? (Wt + 62u) / 63u : (lg == 1u ? (Wt + 30u) / 31u : (Wt + 14u) / 15u);
     // steps per unit: kSweepSteps, or fewer (at least 2) when a small tile
-    // would otherwise leave some of the nw wavefronts without a unit
-    uint32_t su = (((H + S - 1u) >> lg) * nstrip + (uint32_t)nw - 1u) / (uint32_t)nw;
+    // would otherwise leave some of the nw wavefronts without a unit (nw is
+    // a power of two: work-groups are 256 threads)
+    uint32_t su = (((H + S - 1u) >> lg) * nstrip + (uint32_t)nw - 1u) >> __builtin_ctz((uint32_t)nw);
     su = su < 2u ? 2u : (su > kSweepSteps ? kSweepSteps : su);
     const uint32_t unit_rows = su * S;
-    const uint32_t units = nstrip * ((H + unit_rows - 1u) / unit_rows);
+    // row blocks ceil(H / unit_rows): single-precision estimate, one correction
+    const uint32_t nrows_up = H + unit_rows - 1u;   // < 2^17: exact in single precision
+    uint32_t nblk = (uint32_t)((float)nrows_up * __builtin_amdgcn_rcpf((float)unit_rows));
+    if (nblk * unit_rows > nrows_up) --nblk;
+    else if ((nblk + 1u) * unit_rows <= nrows_up) ++nblk;
+    const uint32_t units = nstrip * nblk;
     const int32_t xt0 = rd.x0 + (int32_t)ca, xt1 = rd.x0 + (int32_t)cb;   // owned columns [xt0, xt1)
     const uint32_t nx = (uint32_t)c.nx;
     const uint32_t up_lane = ((ln - Wl) & 63u) << 2;   // byte index of the lane above (permute address)
+    // unit u is strip s = u mod nstrip of row block ch = u / nstrip, walked
+    // incrementally (no division per unit)
+    uint32_t s = (uint32_t)w, ch = 0u;
+    while (s >= nstrip) { s -= nstrip; ++ch; }
     for (uint32_t u = (uint32_t)w; u < units; u += (uint32_t)nw) {
-        const uint32_t s = u % nstrip, ch = u / nstrip;
+        if (u != (uint32_t)w) {
+            s += (uint32_t)nw;
+            while (s >= nstrip) { s -= nstrip; ++ch; }
+        }
         const int32_t x = xt0 + (int32_t)(Wo * s + col);
         const bool xin = x < c.nx && x <= xt1;   // owned columns and the right neighbour of the last
         const bool owner = col < Wo && x < xt1;
@@ -936,20 +957,24 @@ __device__ void accumulate_sweep2d(const RoiDesc &rd, const ItemCtx &c, uint32_t
         // step j: image row y0 + j S + sub; the last sub-row also fetches the
         // row above the unit (its "previous step")
         uint32_t lab[kSweepSteps], val[kSweepSteps], lab_up = 0u, val_up = 0u;
-        const uint32_t idx0 = (uint32_t)(y0 + (int32_t)sub) * nx + (uint32_t)x;
+        // the unit's row y0 as a uniform base; lanes add 32-bit byte offsets
+        // (at most (kSweepSteps * 4 + 1) rows of nx voxels)
+        const size_t row0 = (size_t)(uint32_t)y0 * nx;
+        const uint32_t *Lu = c.L + row0;
+        const uint16_t *Vu = V + row0;
+        const uint32_t o0 = sub * nx + (uint32_t)x;
         if (xin && sub == S - 1u && y0 > rd.y0) {
-            const uint32_t iu = (uint32_t)(y0 - 1) * nx + (uint32_t)x;
-            lab_up = c.lab(iu);
-            val_up = raw(iu);
+            lab_up = ldb(Lu - nx, (uint32_t)x << 2);
+            val_up = ldb(Vu - nx, (uint32_t)x << 1);
         }
 #pragma unroll
         for (uint32_t j = 0; j < kSweepSteps; ++j) {
             lab[j] = 0u;
             val[j] = 0u;
             if (xin && j * S + sub < nr) {
-                const uint32_t idx = idx0 + j * S * nx;
-                lab[j] = c.lab(idx);
-                val[j] = raw(idx);
+                const uint32_t o = o0 + j * S * nx;
+                lab[j] = ldb(Lu, o << 2);
+                val[j] = ldb(Vu, o << 1);
             }
         }
         uint32_t prev = level(lab_up, val_up);   // this lane's previous step
@@ -1069,17 +1094,15 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
         __syncthreads();
         for (uint32_t q = 0; q < n_items; ++q) {
             // an entry that does not name a valid ROI tile is skipped
-            if (__builtin_amdgcn_readfirstlane(ITEMS[q].ok) == 0u) continue;
+            if (__builtin_amdgcn_readfirstlane(ITEMS[q].roi) == kNone) continue;
             const ItemDesc it = lds_uniform(ITEMS + q);
             const RoiDesc &rd = it.rd;
             const uint32_t roi = it.roi;
             ItemCtx c;
             c.I = it.I; c.L = it.L; c.B = it.B;
             c.nx = it.nx; c.ny = it.ny; c.nz = it.nz;
-            c.label = rd.label; c.vmin = rd.vmin; c.D = rd.vmax - rd.vmin; c.ng = ng;
-            c.rcpD = it.rcpD;
-            c.Dm = c.D ? c.D : 1u;
-            c.rcpDm = c.D ? it.rcpD : 1.0f;
+            c.label = rd.label; c.vmin = rd.vmin; c.ng = ng;
+            c.rcp = it.rcp;
             c.err = &a.counters[C_ERR];
             const uint32_t ra = it.ra, rb = it.rb, ca = it.ca, cb = it.cb;
             const bool split = rd.gslot != kNone;
@@ -1204,8 +1227,8 @@ __global__ __launch_bounds__(1024) void k_band(StepArgs a) {
         ItemCtx c;
         c.I = im.I; c.L = im.L; c.B = im.B;
         c.nx = im.nx; c.ny = im.ny; c.nz = im.nz;
-        c.label = rd.label; c.vmin = rd.vmin; c.D = rd.vmax - rd.vmin; c.ng = ng;
-        c.rcpD = c.D ? 1.0f / (float)c.D : 0.0f;
+        c.label = rd.label; c.vmin = rd.vmin; c.ng = ng;
+        c.rcp = fbn_rcp_up(rd.vmax > rd.vmin ? rd.vmax - rd.vmin : 1u);
         c.err = &a.counters[C_ERR];
         const uint32_t W = (uint32_t)(rd.x1 - rd.x0 + 1);
         const uint32_t rpb = (rd.rows + nrb - 1u) / nrb;

@@ -313,4 +313,31 @@ inline uint32_t label_entry(const uint32_t *dict, uint32_t dict_n, uint32_t max_
     return lo < dict_n && dict[lo] == l ? lo + 1u : 0u;
 }
 
+// Fixed-bin-number level 1 + floor(ng (I - vmin) / Dm), clamped to [1, ng]
+// (Dm = max(vmax - vmin, 1); a constant ROI has every I = vmin, level 1),
+// from a double-precision reciprocal rounded up: rcp_up = (1 / Dm)(1 + delta)
+// with 0 <= delta <= 2^-51.  num = ng (I - vmin) is exact in double and
+// num / Dm <= ng < 2^13, so the rounded product never falls below num / Dm
+// (an integral quotient stays integral) and stays below the next integer by
+// more than 1 / Dm - 2^-38 > 0: truncation gives floor(num / Dm) with no
+// correction step.  Values outside the ROI's range give some level in
+// [1, ng] (callers mask them by label).
+__host__ __device__
+inline uint32_t fbn_level_rd(uint32_t I, uint32_t vmin, double rcp_up, uint32_t ng) {
+#ifdef __HIP_DEVICE_COMPILE__
+    const uint32_t num = __umul24(ng, I - vmin);   // 24-bit operands, low 32 bits of the product
+#else
+    const uint32_t num = (uint32_t)((uint64_t)(ng & 0xFFFFFFu) * ((I - vmin) & 0xFFFFFFu));
+#endif
+    const double q = __builtin_fmin((double)num * rcp_up, (double)(ng - 1u));
+    return (uint32_t)q + 1u;
+}
+
+// rcp_up for fbn_level_rd: the rounded reciprocal of Dm plus one unit in the
+// last place (at least 1 / Dm, at most 1.5 units above it).
+__host__ __device__
+inline double fbn_rcp_up(uint32_t Dm) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, 1.0 / (double)Dm) + 1ull);
+}
+
 }  // namespace nyx

@@ -38,4 +38,9 @@ uint32_t rules_label_entry(const uint32_t *dict, uint32_t dict_n, uint32_t max_l
     return nyx::label_entry(dict, dict_n, max_label, l);
 }
 
+void rules_fbn_levels(const uint32_t *I, uint32_t n, uint32_t vmin, uint32_t vmax, uint32_t ng, uint32_t *out) {
+    const double r = nyx::fbn_rcp_up(vmax > vmin ? vmax - vmin : 1u);
+    for (uint32_t k = 0; k < n; ++k) out[k] = nyx::fbn_level_rd(I[k], vmin, r, ng);
+}
+
 }  // extern "C"

@@ -121,7 +121,28 @@ def rules():
     L.rules_ticket_range.argtypes = [u32, P, P, P, P, P]
     L.rules_label_entry.argtypes = [P, u32, u32, u32]
     L.rules_label_entry.restype = u32
+    L.rules_fbn_levels.argtypes = [P, u32, u32, u32, u32, P]
     return L
+
+
+def test_fbn_level_rule_exact(rules):
+    # the compiled level rule (double reciprocal rounded up, no correction
+    # step) against exact integer division, over every value of each range,
+    # for ranges where the quotient lands exactly on integers often (powers
+    # of two, multiples of ng) and random ones, and bin counts up to 8191
+    rng = np.random.default_rng(2)
+    cases = [(0, 0, 8), (5, 5, 64), (0, 1, 2), (0, 65535, 8191), (0, 65535, 64), (100, 164, 64), (7, 7 + 1024, 1024),
+             (0, 4096, 8), (3, 3 + 63, 64), (1, 1 + 255, 256), (0, 30, 10), (0, 99, 100), (12, 12 + 8191, 8191)]
+    cases += [(int(a), int(a + d), int(g)) for a, d, g in zip(rng.integers(0, 30000, 40), rng.integers(1, 35535, 40),
+                                                            rng.integers(2, 8192, 40))]
+    for vmin, vmax, ng in cases:
+        I = np.arange(vmin, vmax + 1, dtype=np.uint32)
+        out = np.zeros(I.size, np.uint32)
+        rules.rules_fbn_levels(I.ctypes.data, I.size, vmin, vmax, ng, out.ctypes.data)
+        D = vmax - vmin
+        want = np.ones(I.size, np.int64) if D == 0 else \
+            np.minimum(1 + (ng * (I.astype(np.int64) - vmin)) // D, ng)
+        assert np.array_equal(out, want), (vmin, vmax, ng)
 
 
 def test_label_entry_rule(rules):
