@@ -129,6 +129,54 @@ def summarize_trace(stats_csv: str, workload: str, command: str, top: int = 14) 
             break
 
 
+def summarize_sq(sq_csv: str, workload: str, command: str, roi_vox: int) -> None:
+    """Writes profiles/<kernel>_<workload>_counters.md from a rocprofv3 --pmc
+    run of this script with the SQ counters below: the median per dispatch of
+    every counter for each kernel in KERNEL_SYMBOLS, and what follows from
+    them (SQ_BUSY_CYCLES is summed over the 32 shader engines, the LDS
+    conflict counters over the 256 CUs; a wave64 VALU instruction occupies its
+    SIMD for 4 cycles)."""
+    import csv
+    import statistics
+    vals = {}
+    with open(sq_csv) as f:
+        for r in csv.DictReader(f):
+            for k, sym in KERNEL_SYMBOLS.items():
+                if sym in r["Kernel_Name"]:
+                    vals.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    med = {k: {c: statistics.median(v) for c, v in cs.items()} for k, cs in vals.items()}
+    names = sorted({c for cs in med.values() for c in cs})
+    ks = [k for k in KERNEL_SYMBOLS if k in med]
+    lines = [f"# rocprofv3 SQ counters: {workload}", "", "Command (from the repository root on the GPU host):", "",
+             f"    {command}", "", f"Sources: `paper_2603_12016_amd/csrc` digest {source_digest()}.", "",
+             "Median per dispatch.", "", "| counter | " + " | ".join(ks) + " |", "|---" * (len(ks) + 1) + "|"]
+    for c in names:
+        lines.append(f"| {c} | " + " | ".join(f"{med[k].get(c, float('nan')):.4g}" for k in ks) + " |")
+    lines += ["", "| derived | " + " | ".join(ks) + " |", "|---" * (len(ks) + 1) + "|"]
+    rows = {"kernel cycles (SQ_BUSY_CYCLES / 32)": [], "VALU busy (4 x ACTIVE_INST_VALU / (1024 SIMDs x cycles))": [],
+            "LDS bank-conflict cycles per CU / kernel cycles": [], "LDS address-conflict cycles per CU / kernel cycles": [],
+            "SALU / VALU instructions": [], "VALU wave-instructions per ROI voxel": []}
+    for k in ks:
+        m = med[k]
+        cyc = m.get("SQ_BUSY_CYCLES", float("nan")) / 32.0
+        rows["kernel cycles (SQ_BUSY_CYCLES / 32)"].append(f"{cyc:.4g}")
+        rows["VALU busy (4 x ACTIVE_INST_VALU / (1024 SIMDs x cycles))"].append(
+            f"{4.0 * m.get('SQ_ACTIVE_INST_VALU', float('nan')) / (1024.0 * cyc):.2f}")
+        rows["LDS bank-conflict cycles per CU / kernel cycles"].append(
+            f"{m.get('SQ_LDS_BANK_CONFLICT', float('nan')) / 256.0 / cyc:.2f}")
+        rows["LDS address-conflict cycles per CU / kernel cycles"].append(
+            f"{m.get('SQ_LDS_ADDR_CONFLICT', float('nan')) / 256.0 / cyc:.2f}")
+        rows["SALU / VALU instructions"].append(f"{m.get('SQ_INSTS_SALU', 0.0) / max(m.get('SQ_INSTS_VALU', 1.0), 1.0):.2f}")
+        rows["VALU wave-instructions per ROI voxel"].append(f"{m.get('SQ_INSTS_VALU', float('nan')) / roi_vox:.2f}")
+    for n, v in rows.items():
+        lines.append(f"| {n} | " + " | ".join(v) + " |")
+    path = os.path.join(ROOT, "profiles", f"{ks[0]}_{workload}_counters.md") if ks else None
+    if path:
+        with open(path, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        log(f"wrote {path}")
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -301,6 +349,8 @@ def main() -> int:
                     help="write profiles/*_traffic.txt from rocprofv3 counter CSVs of this script and exit")
     ap.add_argument("--summarize-trace", metavar="STATS_CSV",
                     help="write profiles/<kernel>_<workload>.md from a rocprofv3 kernel_stats.csv and exit")
+    ap.add_argument("--summarize-sq", metavar="SQ_CSV",
+                    help="write profiles/<kernel>_<workload>_counters.md from a rocprofv3 SQ counter CSV and exit")
     ap.add_argument("--pmc-command", default="", help="the command the profile CSVs came from (recorded)")
     ap.add_argument("--cost-grid", action="store_true",
                     help="time the step over a grid of bin counts x nested offset sets and check that the "
@@ -308,6 +358,11 @@ def main() -> int:
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.workload, args.pmc_command)
+        return 0
+    if args.summarize_sq:
+        import synth
+        summarize_sq(args.summarize_sq, args.workload, args.pmc_command,
+                     int(np.count_nonzero(synth.make(args.workload).labels)))
         return 0
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, COPY_BYTES, args.pmc_command)

@@ -156,23 +156,27 @@ __device__ __forceinline__ void tri_decode(uint32_t i, uint32_t &lo, uint32_t &h
     lo = i - (__umul24(h, h + 1u) >> 1);
 }
 
-// LDS triangle of one direction, visited in index order.  Per chunk each
-// lane reads one 16-byte run of the triangle (8 packed 16-bit or 4 32-bit
-// counters); the group forms the exclusive prefix of the runs' nonzero-cell
-// counts and each lane appends its nonzero cells, as cell indices, to `buf`
-// (room for size() * kPerRead entries).  fn runs over the buffered entries
-// (count re-read from the triangle, index decoded to (lo, hi)) whenever the
-// next chunk might not fit, and at the end: lanes stay busy however sparse
-// the triangle is, and the order of every floating sum is fixed.  U must be
-// 16-byte aligned and padded with zero words to a multiple of 4 words.
-// The triangle may be held in `ncp` privatised copies `stride` words apart;
-// every read sums them (packed 16-bit halves add without carry: a cell's
-// total over the copies stays below 2^16, as for a single copy).
+// LDS triangle of one direction, visited in index order, in two levels.
+// First, per block of kChunkRounds x size() 16-byte runs of the triangle
+// (8 packed 16-bit or 4 32-bit counters each), every lane reads one run per
+// round and the group lists the nonzero runs in index order (u16 run
+// indices; in the workloads here most runs are empty).  Then each lane reads
+// one listed run, the group forms the exclusive prefix of the runs'
+// nonzero-cell counts, and each lane appends its nonzero cells, as u16 cell
+// indices, to `buf` (room for size() * kPerRead entries).  fn runs over the
+// buffered entries (count re-read from the triangle, index decoded to
+// (lo, hi)) whenever the next round might not fit, and at the end: lanes stay
+// busy however sparse the triangle is, and the order of every floating sum
+// is fixed.  U must be 16-byte aligned and padded with zero words to a
+// multiple of 4 words; cell indices must fit 16 bits (dense triangles in LDS
+// always do).  The triangle may be held in `ncp` privatised copies `stride`
+// words apart; every read sums them (packed 16-bit halves add without carry:
+// a cell's total over the copies stays below 2^16, as for a single copy).
 template <bool PACKED>
 struct SrcTriScan {
     uint32_t *U;
     uint32_t tri;            // cells: ng (ng + 1) / 2, or ng^2 for a square
-    uint32_t *buf;
+    uint16_t *buf;           // scan_buf_entries(kPerRead) entries: cells, then the run list
     uint32_t ncp = 1u;
     uint32_t stride = 0u;
     uint32_t sq_ng = 0u;     // > 0: a full row-major square of sq_ng x sq_ng ordered cells
@@ -196,6 +200,15 @@ struct SrcTriScan {
             c += PACKED ? (uint32_t)reinterpret_cast<const uint16_t *>(U + k * stride)[i] : U[k * stride + i];
         return c;
     }
+    // 16-byte run j summed over the copies.
+    __device__ __forceinline__ uint4 run(uint32_t j) const {
+        uint4 v = *reinterpret_cast<const uint4 *>(U + 4u * j);
+        for (uint32_t k = 1; k < ncp; ++k) {
+            const uint4 u = *reinterpret_cast<const uint4 *>(U + k * stride + 4u * j);
+            v.x += u.x; v.y += u.y; v.z += u.z; v.w += u.w;
+        }
+        return v;
+    }
     template <class Grp, class Fn>
     __device__ __forceinline__ void flush(const Grp &g, uint32_t n, Fn &&fn) const {
         g.sync();
@@ -210,49 +223,65 @@ struct SrcTriScan {
     template <class Grp, class Fn>
     __device__ __forceinline__ void for_each(const Grp &g, Fn &&fn) const {
         const uint32_t gs = (uint32_t)g.size(), r = (uint32_t)g.rank();
-        const uint32_t words = PACKED ? (tri + 1u) >> 1 : tri;
+        const uint32_t runs = ((PACKED ? (tri + 1u) >> 1 : tri) + 3u) >> 2;
         const uint32_t cap = gs * kPerRead;
+        uint16_t *const list = buf + cap;   // room for gs * kChunkRounds run indices
         uint32_t held = 0;   // entries waiting in buf (group-uniform)
-        for (uint32_t wbase = 0; wbase < words; wbase += 4u * gs) {
-            const uint32_t w0 = wbase + 4u * r;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (w0 < words) {
-                v = *reinterpret_cast<const uint4 *>(U + w0);
-                for (uint32_t k = 1; k < ncp; ++k) {
-                    const uint4 u = *reinterpret_cast<const uint4 *>(U + k * stride + w0);
-                    v.x += u.x; v.y += u.y; v.z += u.z; v.w += u.w;
+        for (uint32_t jb = 0; jb < runs; jb += gs * (uint32_t)kChunkRounds) {
+            const uint32_t je = min(runs, jb + gs * (uint32_t)kChunkRounds);
+            uint32_t nrun = 0;   // nonzero runs listed (group-uniform)
+            for (uint32_t j0 = jb; j0 < je; j0 += gs) {
+                const uint32_t j = j0 + r;
+                bool nz = false;
+                if (j < je) {
+                    const uint4 v = run(j);
+                    nz = (v.x | v.y | v.z | v.w) != 0u;
                 }
+                const uint64_t m = g.ballot(nz);
+                if (nz) list[nrun + (uint32_t)__popcll(m & g.below())] = (uint16_t)j;
+                nrun += (uint32_t)__popcll(m);
             }
-            // nonzero flags of the run's cells (cells past tri are zero
-            // padding); packed: 0/1 in each 16-bit half
-            uint32_t f[4];
-            uint32_t n;
-            if (PACKED) {
-                f[0] = nz_halves(v.x); f[1] = nz_halves(v.y); f[2] = nz_halves(v.z); f[3] = nz_halves(v.w);
-                const uint32_t s = f[0] + f[1] + f[2] + f[3];
-                n = (s & 0xFFFFu) + (s >> 16);
-            } else {
-                f[0] = v.x != 0u; f[1] = v.y != 0u; f[2] = v.z != 0u; f[3] = v.w != 0u;
-                n = f[0] + f[1] + f[2] + f[3];
-            }
-            uint32_t cnt;
-            const uint32_t pos = g.excl_scan(n, &cnt);
-            if (held + cnt > cap) {
-                flush(g, held, fn);
-                held = 0;
-            }
-            uint32_t *p = buf + held + pos;
-            const uint32_t i0 = PACKED ? 2u * w0 : w0;   // first cell of the run
-#pragma unroll
-            for (uint32_t k = 0; k < 4u; ++k) {
+            g.sync();
+            for (uint32_t e0 = 0; e0 < nrun; e0 += gs) {
+                const uint32_t e = e0 + r;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                uint32_t j = 0u;
+                if (e < nrun) {
+                    j = list[e];
+                    v = run(j);
+                }
+                // nonzero flags of the run's cells (cells past tri are zero
+                // padding); packed: 0/1 in each 16-bit half
+                uint32_t f[4];
+                uint32_t n;
                 if (PACKED) {
-                    if (f[k] & 0xFFFFu) *p++ = i0 + 2u * k;
-                    if (f[k] >> 16) *p++ = i0 + 2u * k + 1u;
+                    f[0] = nz_halves(v.x); f[1] = nz_halves(v.y); f[2] = nz_halves(v.z); f[3] = nz_halves(v.w);
+                    const uint32_t s = f[0] + f[1] + f[2] + f[3];
+                    n = (s & 0xFFFFu) + (s >> 16);
                 } else {
-                    if (f[k]) *p++ = i0 + k;
+                    f[0] = v.x != 0u; f[1] = v.y != 0u; f[2] = v.z != 0u; f[3] = v.w != 0u;
+                    n = f[0] + f[1] + f[2] + f[3];
                 }
+                uint32_t cnt;
+                const uint32_t pos = g.excl_scan(n, &cnt);
+                if (held + cnt > cap) {
+                    flush(g, held, fn);
+                    held = 0;
+                }
+                uint16_t *p = buf + held + pos;
+                const uint32_t i0 = PACKED ? 8u * j : 4u * j;   // first cell of the run
+#pragma unroll
+                for (uint32_t k = 0; k < 4u; ++k) {
+                    if (PACKED) {
+                        if (f[k] & 0xFFFFu) *p++ = (uint16_t)(i0 + 2u * k);
+                        if (f[k] >> 16) *p++ = (uint16_t)(i0 + 2u * k + 1u);
+                    } else {
+                        if (f[k]) *p++ = (uint16_t)(i0 + k);
+                    }
+                }
+                held += cnt;
             }
-            held += cnt;
+            g.sync();   // the run list is refilled by the next block
         }
         if (held) flush(g, held, fn);
     }

@@ -248,14 +248,19 @@ __global__ __launch_bounds__(256) void k_scan(StepArgs a) {
         const uint32_t nr = min((uint32_t)kScanTileRows, rows - row0);
         const uint32_t nx = (uint32_t)d.nx;
         uint32_t lab[kScanTileRows], val[kScanTileRows];
-        const uint32_t base = row0 * nx + (uint32_t)x;
+        // the tile's first row as a uniform base; lanes add 32-bit byte
+        // offsets (kScanTileRows rows of nx voxels)
+        const size_t base = (size_t)row0 * nx;
+        const uint32_t *Lt = d.L + base;
+        const uint16_t *It = d.I + base;
 #pragma unroll
         for (uint32_t j = 0; j < kScanTileRows; ++j) {
             lab[j] = 0u;
             val[j] = 0u;
             if (j < nr) {
-                lab[j] = ldg(d.L, base + j * nx);
-                val[j] = ldg(d.I, base + j * nx);
+                const uint32_t o = j * nx + (uint32_t)x;
+                lab[j] = ldb(Lt, o << 2);
+                val[j] = ldb(It, o << 1);
             }
         }
         // plane and row of the tile's first row (tile rows are uniform)
@@ -1152,7 +1157,8 @@ __global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(Step
                     WaveGrp g;
                     if (MODE == 2 || MODE == 3) {
                         SrcTriScan<MODE == 3> s{Ud, ns ? ng * ng : (ng * (ng + 1u)) >> 1,
-                                                BUF + (uint32_t)w * kWave * SrcTriScan<MODE == 3>::kPerRead,
+                                                reinterpret_cast<uint16_t *>(BUF) +
+                                                    (uint32_t)w * scan_buf_entries(SrcTriScan<MODE == 3>::kPerRead),
                                                 Ly.copies, Ly.tri_pad, ns ? ng : 0u};
                         dir_or_flush<Acc, NS>(a, g, s, split, rd, roi, a.merged ? 0 : d0 + dl, MARG, ng);
                     } else if (MODE == 0) {

@@ -513,7 +513,7 @@ LdsLayout make_layout(const Config &c, uint32_t ng, int K, bool ring) {
     }
     L.list_off = take(c.kp * c.list_cap * 4u);
     L.lcnt_off = take(c.kp * 4u);
-    L.buf_off = take((c.mode == 2 || c.mode == 3) ? L.nwaves * kWave * scan_cells(c.mode) * 4u : 0u);
+    L.buf_off = take((c.mode == 2 || c.mode == 3) ? L.nwaves * scan_buf_entries(scan_cells(c.mode)) * 2u : 0u);
     L.marg_sets = std::min(L.nwaves, c.merged ? 1u : c.kp);   // one set per wave that reduces a matrix
     L.marg_off = take(L.marg_sets * marg_words(ng, c.nonsym != 0) * 4u);
     L.misc_off = take(128u * 4u);
@@ -596,7 +596,7 @@ std::vector<Config> candidate_configs(const nyx_ctx *ctx, const Work &w, uint32_
         if (merged && mode == 3 && split < std::min<uint32_t>(lb, 65535u)) continue;
         const bool scan = mode == 2 || mode == 3;
         const uint32_t list_cap = scan ? 0u : (uint32_t)std::min<uint64_t>(tri, std::max<uint64_t>(mi, 1u));
-        const uint64_t scan_buf = scan ? (uint64_t)nw * kWave * scan_cells(mode) * 4u : 0u;
+        const uint64_t scan_buf = scan ? (uint64_t)nw * scan_buf_entries(scan_cells(mode)) * 2u : 0u;
         const uint32_t cp = scan ? copies : 1u;
         for (uint32_t kp = (uint32_t)K; kp >= (merged ? (uint32_t)K : 1u); --kp) {
             const uint32_t n_tri = merged ? 1u : kp;

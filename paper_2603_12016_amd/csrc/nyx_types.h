@@ -114,6 +114,15 @@ constexpr uint32_t kScanTileCols = 256;
 // Compaction buffer entries (u32 cell indices) per lane of an ordered
 // triangle scan (one 16-byte read: at most 8 packed counters).
 constexpr int kScanCells = 8;
+// First-pass rounds of the two-level triangle scan per block: the nonzero
+// 16-byte runs of kChunkRounds x 64 runs are listed (u16 entries) before
+// their cells are.
+constexpr int kChunkRounds = 5;
+// u16 entries per wavefront of the scan buffer: cell indices (64 x cells per
+// read), then the run list (64 x kChunkRounds).
+__host__ __device__ constexpr uint32_t scan_buf_entries(uint32_t cells_per_read) {
+    return 64u * cells_per_read + 64u * (uint32_t)kChunkRounds;
+}
 
 struct LdsLayout {
     uint32_t mode;        // 0 = dense triangles, 1 = hash table
