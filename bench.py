@@ -120,13 +120,14 @@ def summarize_trace(stats_csv: str, workload: str, command: str, top: int = 14) 
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
                      f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
-    for k, sym in KERNEL_SYMBOLS.items():
-        if any(sym in r["Name"] for r in rows):
-            path = os.path.join(ROOT, "profiles", f"{k}_{workload}.md")
-            with open(path, "w") as f:
-                f.write("\n".join(lines) + "\n")
-            log(f"wrote {path}")
-            break
+    # named for the dominant kernel of KERNEL_SYMBOLS (largest total time)
+    tot = {k: sum(float(r["TotalDurationNs"]) for r in rows if sym in r["Name"]) for k, sym in KERNEL_SYMBOLS.items()}
+    k = max(tot, key=tot.get)
+    if tot[k] > 0:
+        path = os.path.join(ROOT, "profiles", f"{k}_{workload}.md")
+        with open(path, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        log(f"wrote {path}")
 
 
 def summarize_sq(sq_csv: str, workload: str, command: str, roi_vox: int) -> None:
@@ -170,7 +171,9 @@ def summarize_sq(sq_csv: str, workload: str, command: str, roi_vox: int) -> None
         rows["VALU wave-instructions per ROI voxel"].append(f"{m.get('SQ_INSTS_VALU', float('nan')) / roi_vox:.2f}")
     for n, v in rows.items():
         lines.append(f"| {n} | " + " | ".join(v) + " |")
-    path = os.path.join(ROOT, "profiles", f"{ks[0]}_{workload}_counters.md") if ks else None
+    # named for the dominant kernel (most busy cycles)
+    dom = max(ks, key=lambda k: med[k].get("SQ_BUSY_CYCLES", 0.0)) if ks else None
+    path = os.path.join(ROOT, "profiles", f"{dom}_{workload}_counters.md") if ks else None
     if path:
         with open(path, "w") as f:
             f.write("\n".join(lines) + "\n")
