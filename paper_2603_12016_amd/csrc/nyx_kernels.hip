@@ -185,7 +185,7 @@ __device__ __forceinline__ void scan_flush_run(const StepArgs &a, ScanLds &S, ui
 // without one sets `bad`.
 __device__ __forceinline__ void scan_flush_label(const StepArgs &a, ScanLds &S, const ImgDesc &d, const RunRec &r,
                                                  uint32_t &bad) {
-    const uint32_t e = d.dict ? label_entry(d.dict, d.dict_n, d.max_label, r.key) : r.key;
+    const uint32_t e = label_entry(d.dict, d.dict_n, d.max_label, r.key);
     if (e) scan_flush_run(a, S, d.tab_base + e, r);
     else bad = 1u;
 }
@@ -263,25 +263,33 @@ __global__ __launch_bounds__(256) void k_scan(StepArgs a) {
                 val[j] = ldb(It, o << 1);
             }
         }
-        // plane and row of the tile's first row (tile rows are uniform)
-        int32_t z = (int32_t)(row0 / (uint32_t)d.ny), y = (int32_t)(row0 - (uint32_t)z * (uint32_t)d.ny);
+        // Per voxel only the label test and the count and range of the
+        // current run; the run's rows [j0, j) become its box when it ends.
+        // A run never crosses a plane boundary (rows of different planes are
+        // not neighbours): jb, the tile row where the next plane starts, is
+        // uniform.  Background runs (key 0) are counted too and never flushed.
+        const uint32_t ny = (uint32_t)d.ny;
+        uint32_t jb = ny - row0 % ny;
+        uint32_t key = 0u, c = 0u, mn = 0xFFFFu, mx = 0u, j0 = 0u;
+        const auto rec = [&](uint32_t j_end) {   // rows [j0, j_end) of the run, j_end > j0
+            const uint32_t r = row0 + j0, z = r / ny, y = r - z * ny;
+            return RunRec{key, c, mn, mx, x, x, (int32_t)y, (int32_t)(y + (j_end - 1u - j0)), (int32_t)z, (int32_t)z};
+        };
 #pragma unroll
         for (uint32_t j = 0; j < kScanTileRows; ++j) {
             if (j >= nr) break;
-            uint32_t l = lab[j];
-            if (!d.dict && l > d.max_label) { bad = 1u; l = 0u; }
-            if (l != run.key || z != run.z0) {
-                if (run.key) scan_flush_label(a, S, d, run, bad);
-                run = RunRec{l, 0u, 0xFFFFu, 0u, x, x, y, y, z, z};
+            const uint32_t l = lab[j];
+            const bool plane = j == jb;
+            if (l != key || plane) {
+                if (key) scan_flush_label(a, S, d, rec(j), bad);
+                key = l; c = 0u; mn = 0xFFFFu; mx = 0u; j0 = j;
             }
-            if (l) {
-                ++run.c;
-                run.mn = min(run.mn, val[j]);
-                run.mx = max(run.mx, val[j]);
-                run.y1 = y;
-            }
-            if (++y == d.ny) { y = 0; ++z; }
+            if (plane) jb += ny;
+            ++c;
+            mn = min(mn, val[j]);
+            mx = max(mx, val[j]);
         }
+        if (key) run = rec(nr);
     }
     // The runs still open at the tile's last row: adjacent lanes of a row
     // holding the same label are combined first, so one lane per group
