@@ -154,30 +154,47 @@ typedef struct nyx_extract_opts {
     int32_t aggregate;           /* NYX_AGG_PER_OFFSET or NYX_AGG_MERGED (table layout above) */
 } nyx_extract_opts;
 
-/* Context on one device (hipSetDevice ordinal).  NYX_ERR_DEVICE if absent. */
+/* Context on one device (hipSetDevice ordinal).  NYX_ERR_DEVICE if absent.
+ * Owns the library's scratch for the one-shot calls; not thread-safe. */
 nyx_status nyx_create(nyx_ctx **out, int device_ordinal);
 void nyx_destroy(nyx_ctx *ctx);
 const char *nyx_last_error(const nyx_ctx *ctx);
 const char *nyx_status_string(nyx_status s);
 
-/* Default offsets at a distance: dims 2 -> 0, 45, 90, 135 degrees
+/* The offset / scan-angle hyper-parameter of texture (Methods, "Feature
+ * Control and Tunability"; Fig. 7 offsets).
+ * Default offsets at a distance: dims 2 -> 0, 45, 90, 135 degrees
  * ((0,0,1), (0,-1,1), (0,-1,0), (0,-1,-1)); dims 3 -> the 13 directions
  * that represent the 26-neighbourhood up to sign.  out_host needs room for
  * 13 entries; *n receives 4 or 13. */
 nyx_status nyx_offsets_default(int32_t dims, int32_t distance, nyx_offset *out_host, int32_t *n);
 
+/* The GLCM feature columns: Supplementary Table S3 rows with the NY mark
+ * (AVEAMP left out), in table order. */
 int32_t nyx_feature_count(void);               /* 30 */
 const char *nyx_feature_name(int32_t f);       /* NULL outside [0, 30) */
 
 /* ROI discovery and per-ROI statistics (count, min, max, bbox) over a batch
- * of images; optionally the per-voxel grey level under each voxel's own ROI
- * (0 for background) into bins_out, laid out like the input images one after
- * another.  Synchronises once to report the ROI count. */
+ * of images: one row per unique nonzero label of each image (Supplementary
+ * Table S7, "ROI/FOV"; the regional extraction of the Main section); the
+ * levels are the fixed-bin-number grey levels of the texture
+ * hyper-parameter n_bins (Methods, "Feature Control and Tunability").
+ * Optionally the per-voxel grey level under each voxel's own ROI (0 for
+ * background) into bins_out (device, caller-owned, one uint16 per voxel of
+ * every image, laid out like the input images one after another).  rois:
+ * caller-owned device arrays of rois->capacity rows; a smaller capacity than
+ * the ROI count gives NYX_ERR_CAPACITY with the count in *n_rois_host and
+ * nothing written.  Synchronises once to report the ROI count. */
 nyx_status nyx_bin_rois(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n_images, int32_t n_bins,
                         nyx_roi_table *rois, uint16_t *bins_out, nyx_stream stream);
 
-/* Co-occurrence counts of the ROIs in `rois` (as produced by nyx_bin_rois,
- * with *rois->n_rois_host rows) for the given offsets, as a sorted COO list.
+/* Co-occurrence counts (the grey-level co-occurrence matrix of the GLCM
+ * rows of Supplementary Table S3, per offset: texture cost O(m, g, s) in
+ * Methods, "Feature Control and Tunability") of the ROIs in `rois` (as
+ * produced by nyx_bin_rois, with *rois->n_rois_host rows) for the given
+ * offsets, as a sorted COO list in caller-owned device arrays (out->capacity
+ * entries; too few gives NYX_ERR_CAPACITY with the count in *out->nnz_host
+ * and nothing written).
  * `bins` (nullable) is a bin image as written by nyx_bin_rois; when NULL,
  * levels are computed on the fly from intensity and the ROI min/max.
  * Synchronises to report the nonzero count. */
@@ -186,8 +203,9 @@ nyx_status nyx_glcm_accumulate(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t
                                const nyx_offset *offsets_host, int32_t n_offsets, int32_t symmetric,
                                int32_t n_bins, nyx_glcm *out, nyx_stream stream);
 
-/* Feature table (normalisation, marginals and the 30 features per direction
- * and their mean) from a COO list as written by nyx_glcm_accumulate: row r
+/* Feature table (normalisation, marginals and the 30 GLCM features of
+ * Supplementary Table S3 per direction and their mean) from a COO list as
+ * written by nyx_glcm_accumulate, into the caller-owned device table: row r
  * of the table belongs to ROI r of the list.  `rois` (nullable) is the ROI
  * table the list was accumulated for; when given, its *n_rois_host must equal
  * glcm->n_rois (NYX_ERR_INVALID otherwise), so a table is never paired with
@@ -258,7 +276,12 @@ nyx_status nyx_neighbourhood_features(nyx_ctx *ctx, const nyx_image *imgs_host, 
                                       int32_t alpha, nyx_precision prec, nyx_roi_table *rois, void *table,
                                       int64_t table_capacity_rows, nyx_stream stream);
 
-/* Whole path in one call: plan, execute once, destroy the plan. */
+/* Whole path in one call (regional GLCM texture of every ROI, Supplementary
+ * Tables S3 and S7, with the hyper-parameters n_bins and offsets of Methods,
+ * "Feature Control and Tunability"): plan, execute once, destroy the plan.
+ * rois (nullable) and table are caller-owned device buffers; a table or ROI
+ * capacity below the ROI count gives NYX_ERR_CAPACITY with the count in
+ * *rois->n_rois_host. */
 nyx_status nyx_extract_batch(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n_images,
                              const nyx_extract_opts *opts, nyx_roi_table *rois, void *table,
                              int64_t table_capacity_rows, nyx_stream stream);
@@ -283,7 +306,9 @@ nyx_status nyx_extract_batch_noalloc(nyx_ctx *ctx, const nyx_image *imgs_host, i
                                      const nyx_extract_opts *opts, nyx_roi_table *rois, void *table,
                                      int64_t table_capacity_rows, nyx_stream stream);
 
-/* Plan for repeated extraction over images with the same geometry and
+/* Plan for repeated extraction (the batched execution of the regional
+ * extraction, Supplementary Table S7; "Scalability" in Results for the
+ * many-small-ROI regime) over images with the same geometry and
  * labels-per-image capacity: discovers the ROIs once (one synchronisation),
  * sizes the work queue and scratch, and (with opts->autotune) picks the
  * kernel configuration by timing.  *n_rois_host receives the ROI count.
@@ -297,7 +322,9 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs_host, int32_t n_i
  * features) as one graph replay on `stream`.  rois may be NULL. */
 nyx_status nyx_plan_execute(nyx_plan *plan, nyx_roi_table *rois, void *table, nyx_stream stream);
 
-/* The same pass with one kernel launch per ROI (comparison baseline). */
+/* The same pass with one kernel launch per ROI: the comparison baseline, the
+ * per-ROI GPU regime the paper reports losing to the CPU for many small ROIs
+ * (Results, "Scalability", Fig. 3f). */
 nyx_status nyx_plan_execute_per_roi(nyx_plan *plan, nyx_roi_table *rois, void *table,
                                     nyx_stream stream);
 
