@@ -88,20 +88,24 @@ def test_noalloc_matches_extract_batch_twice(env):
     _compare(nyx, ctx, dev, second, nyx.NYX_FP32, mode="dense16-scan")
     say("noalloc: c1_tiny, FP64")
     _compare(nyx, ctx, dev, synth.make("c1_tiny"), nyx.NYX_FP64)
+    # label values near 2^32: discovery takes the per-image label dictionary,
+    # whose arrays come from the same scratch array
+    from test_gpu_labels import relabel
+    say("noalloc: c3_small with label values near 2^32 (label dictionary)")
+    _compare(nyx, ctx, dev, relabel(first, seed=5), nyx.NYX_FP32, mode="dense16-scan")
 
 
 def test_noalloc_rejects_batches_beyond_its_scratch(env):
     import torch
     nyx, ctx, dev = env
-    # labels up to 8e6: the per-label statistics alone need 10 x 4 B x 8e6
-    # = 320 MB, more than the 256 MiB array
-    I = torch.zeros((64, 64), dtype=torch.int16, device=dev)
-    L = torch.zeros((64, 64), dtype=torch.int32, device=dev)
-    L[3, 5] = 8_000_000
-    L[10, 10] = 1
+    # 2^23 distinct labels (every voxel of a 4096 x 2048 image its own ROI):
+    # the per-label statistics alone need 10 x 4 B x 2^23 = 320 MiB, more
+    # than the 256 MiB array
+    I = torch.zeros((4096, 2048), dtype=torch.int16, device=dev)
+    L = torch.arange(1, 4096 * 2048 + 1, dtype=torch.int32, device=dev).reshape(4096, 2048)
     rois = nyx.RoiTable(2, dev)
     table = torch.zeros((2, 5, 30), dtype=torch.float32, device=dev)
-    say("noalloc: 8e6 label values (scratch too small)")
+    say("noalloc: 2^23 labels (scratch too small)")
     with pytest.raises(nyx.NyxError) as e:
         nyx.nyx_extract_batch_noalloc(ctx, [(I, L)], 8, nyx.nyx_offsets_default(2, 1), rois, table)
     assert e.value.status == nyx.NYX_ERR_CAPACITY
