@@ -271,8 +271,9 @@ __global__ __launch_bounds__(256) void k_scan(StepArgs a) {
         const uint32_t ny = (uint32_t)d.ny;
         uint32_t jb = ny - row0 % ny;
         uint32_t key = 0u, c = 0u, mn = 0xFFFFu, mx = 0u, j0 = 0u;
+        const bool flat = d.nz == 1;   // a 2D image: the row is y, no division
         const auto rec = [&](uint32_t j_end) {   // rows [j0, j_end) of the run, j_end > j0
-            const uint32_t r = row0 + j0, z = r / ny, y = r - z * ny;
+            const uint32_t r = row0 + j0, z = flat ? 0u : r / ny, y = r - z * ny;
             return RunRec{key, c, mn, mx, x, x, (int32_t)y, (int32_t)(y + (j_end - 1u - j0)), (int32_t)z, (int32_t)z};
         };
 #pragma unroll
@@ -1481,8 +1482,11 @@ __global__ __launch_bounds__(128) void k_features(StepArgs a, const DirSums *ds,
     // K direction blocks and their mean, or the one block of the merged matrix
     const uint32_t per = (a.merged ? 1u : K + 1u) * kNumFeat;
     OutT *out = reinterpret_cast<OutT *>(a.table) + (uint64_t)row0 * per;
+    // element i of the block's rows is (row rr, position q): one division for
+    // the thread's first element, then stepped (no division per element)
+    uint32_t rr = threadIdx.x / per, q = threadIdx.x - rr * per;
     for (uint32_t i = threadIdx.x; i < rows * per; i += blockDim.x) {
-        const uint32_t rr = i / per, q = i - rr * per, blk = q / kNumFeat, f = q - blk * kNumFeat;
+        const uint32_t blk = q / (uint32_t)kNumFeat, f = q - blk * (uint32_t)kNumFeat;
         const double *fr = feat + rr * K * kNumFeat;
         double v;
         if (blk < K) {
@@ -1495,6 +1499,8 @@ __global__ __launch_bounds__(128) void k_features(StepArgs a, const DirSums *ds,
             v = m ? s / (double)m : __builtin_nan("");
         }
         out[i] = (OutT)v;
+        q += blockDim.x;
+        while (q >= per) { q -= per; ++rr; }
     }
 }
 
