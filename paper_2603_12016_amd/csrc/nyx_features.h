@@ -343,19 +343,38 @@ struct SrcHashList {
 };
 
 // Global dense square (upper triangle used) of a merged split ROI.
+// Position (lo, hi) of a lane walking an ng x ng matrix from row r0 in
+// row-major order with a fixed stride: one division at the start, then whole
+// rows plus a remainder per step.
+struct SquareWalk {
+    uint32_t lo, hi, dq, dr;
+    __device__ __forceinline__ SquareWalk(uint32_t ng, uint32_t r0, uint32_t start, uint32_t stride) {
+        lo = start / ng;
+        hi = start - lo * ng;
+        lo += r0;
+        dq = stride / ng;
+        dr = stride - dq * ng;
+    }
+    __device__ __forceinline__ void next(uint32_t ng) {
+        hi += dr;
+        lo += dq;
+        if (hi >= ng) { hi -= ng; ++lo; }
+    }
+};
+
 struct SrcSquare {
     const uint64_t *G;
     uint32_t ng;
     bool all = false;        // every cell (ordered counts), not only the upper triangle
     template <class Grp, class Fn>
     __device__ __forceinline__ void for_each(const Grp &g, Fn &&fn) const {
-        // row by row (no division per cell), the upper triangle unless all
-        for (uint32_t lo = 0; lo < ng; ++lo) {
-            const uint64_t *row = G + (uint64_t)lo * ng;
-            for (uint32_t hi = (all ? 0u : lo) + (uint32_t)g.rank(); hi < ng; hi += (uint32_t)g.size()) {
-                const uint64_t c = row[hi];
-                if (c) fn(lo, hi, (uint32_t)c);
-            }
+        // flat over the square in row-major order, so every lane has a cell
+        // whatever ng is next to the group size; the upper triangle unless all
+        SquareWalk p(ng, 0u, (uint32_t)g.rank(), (uint32_t)g.size());
+        for (uint64_t e = (uint32_t)g.rank(); p.lo < ng; e += (uint32_t)g.size(), p.next(ng)) {
+            if (!all && p.hi < p.lo) continue;
+            const uint64_t c = G[e];
+            if (c) fn(p.lo, p.hi, (uint32_t)c);
         }
     }
     template <class Grp> __device__ __forceinline__ void clear(const Grp &) const {}

@@ -1318,23 +1318,27 @@ __global__ __launch_bounds__(256) void k_split_cells(StepArgs a) {
     const uint64_t *G = a.G + (uint64_t)sd * ng * ng;
     uint64_t T = 0, S11 = 0, sumP2 = 0, maxP = 0;
     LaneSum<Acc> plp;
-    for (uint32_t lo = r0; lo < r1; ++lo)
-        for (uint32_t hi = lo + threadIdx.x; hi < ng; hi += blockDim.x) {
-            const uint64_t cw = G[(uint64_t)lo * ng + hi];
-            if (!cw) continue;
-            const uint32_t c = (uint32_t)cw;
-            atomicAdd(&R[lo], c);
-            atomicAdd(&R[hi], c);
-            atomicAdd(&Sp[lo + hi], 2u * c);
-            atomicAdd(&Sm[hi - lo], 2u * c);
-            const bool diag = lo == hi;
-            const uint64_t P = diag ? 2ull * c : (uint64_t)c, Pm = diag ? P : 2u * P;
-            T += 2ull * c;
-            sumP2 += Pm * P;
-            maxP = P > maxP ? P : maxP;
-            S11 += Pm * (uint64_t)__umul24(lo + 1u, hi + 1u);
-            plp.add((Acc)Pm * term_log2<Acc>((Acc)P));
-        }
+    // the chunk's rows flat in row-major order (every lane busy however
+    // short the rows are), upper-triangle cells only
+    SquareWalk p(ng, r0, threadIdx.x, blockDim.x);
+    for (uint64_t e = (uint64_t)r0 * ng + threadIdx.x; p.lo < r1; e += blockDim.x, p.next(ng)) {
+        const uint32_t lo = p.lo, hi = p.hi;
+        if (hi < lo) continue;
+        const uint64_t cw = G[e];
+        if (!cw) continue;
+        const uint32_t c = (uint32_t)cw;
+        atomicAdd(&R[lo], c);
+        atomicAdd(&R[hi], c);
+        atomicAdd(&Sp[lo + hi], 2u * c);
+        atomicAdd(&Sm[hi - lo], 2u * c);
+        const bool diag = lo == hi;
+        const uint64_t P = diag ? 2ull * c : (uint64_t)c, Pm = diag ? P : 2u * P;
+        T += 2ull * c;
+        sumP2 += Pm * P;
+        maxP = P > maxP ? P : maxP;
+        S11 += Pm * (uint64_t)__umul24(lo + 1u, hi + 1u);
+        plp.add((Acc)Pm * term_log2<Acc>((Acc)P));
+    }
     __syncthreads();
     uint32_t *gm = a.smarg + (uint64_t)sd * 4u * ng;
     for (uint32_t i = threadIdx.x; i < 4u * ng; i += blockDim.x)
@@ -1774,8 +1778,10 @@ hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st) {
         if (e != hipSuccess) return e;
     }
     uint32_t grid = a.g_cap * a.K_out;
-    if (!a.nonsym && a.smarg) {
-        // two passes: row chunks in parallel, then one work-group per matrix
+    // Enough small matrices to fill the chip: one 256-thread work-group per
+    // matrix.  Few or large ones (symmetric): two passes, row chunks in
+    // parallel, then one work-group per matrix.
+    if (!a.nonsym && a.smarg && (a.split_chunks > 1u || a.ng > 256)) {
         const uint32_t lds1 = 16u * a.ng;
         if (a.fp64) hipLaunchKernelGGL(k_split_cells<double>, dim3(grid * a.split_chunks), dim3(256), lds1, st, a);
         else hipLaunchKernelGGL(k_split_cells<float>, dim3(grid * a.split_chunks), dim3(256), lds1, st, a);
@@ -1787,8 +1793,9 @@ hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st) {
         return hipSuccess;
     }
     uint32_t lds = (a.nonsym ? 20u : 16u) * a.ng + 16 * 8;
-    if (a.fp64) hipLaunchKernelGGL(k_split_features<double>, dim3(grid), dim3(1024), lds, st, a);
-    else hipLaunchKernelGGL(k_split_features<float>, dim3(grid), dim3(1024), lds, st, a);
+    const uint32_t bs = a.ng <= 256 ? 256u : 1024u;
+    if (a.fp64) hipLaunchKernelGGL(k_split_features<double>, dim3(grid), dim3(bs), lds, st, a);
+    else hipLaunchKernelGGL(k_split_features<float>, dim3(grid), dim3(bs), lds, st, a);
     NYX_CHECK_LAUNCH();
     return hipSuccess;
 }
