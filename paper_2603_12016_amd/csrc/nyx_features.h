@@ -410,8 +410,10 @@ struct SrcCoo {
 // ------------------------------------------------------------- sums
 // The 30 features of one direction from its reduced sums (one lane).
 // y: the column-marginal sums of a non-symmetric matrix (nullptr: the matrix
-// is symmetric and its column marginal is its row marginal).
-__device__ __noinline__ void finalize_dir(const DirSums &s, const DirSumsY *y, double *out) {
+// is symmetric and its column marginal is its row marginal).  Computed in
+// double precision; out holds the output precision (OutT: float or double).
+template <class OutT>
+__device__ __noinline__ void finalize_dir(const DirSums &s, const DirSumsY *y, OutT *out) {
     const uint64_t T = s.T;
     if (T == 0) {
         for (int f = 0; f < kNumFeat; ++f) out[f] = __builtin_nan("");

@@ -1464,10 +1464,12 @@ __global__ __launch_bounds__(1024) void k_split_finish(StepArgs a) {
 // the non-empty directions, written as one contiguous run of the table.
 // Rows [0, n) with n = min(*n_ptr, n_cap) (n_cap without n_ptr).
 template <class OutT>
-__global__ __launch_bounds__(128) void k_features(StepArgs a, const DirSums *ds, const DirSumsY *dsy,
+__global__ __launch_bounds__(128, 4) void k_features(StepArgs a, const DirSums *ds, const DirSumsY *dsy,
                                                   uint32_t n_cap, const uint32_t *n_ptr) {
     extern __shared__ __align__(16) uint8_t smem[];
-    double *feat = reinterpret_cast<double *>(smem);
+    // staged in the output precision: single-precision tables take half the
+    // LDS, so twice as many work-groups fit a CU
+    OutT *feat = reinterpret_cast<OutT *>(smem);
     const uint32_t K = (uint32_t)a.K_out;
     const uint32_t rpb = blockDim.x / K;
     const uint32_t n = n_ptr ? min(*n_ptr, n_cap) : n_cap;
@@ -1476,7 +1478,7 @@ __global__ __launch_bounds__(128) void k_features(StepArgs a, const DirSums *ds,
     uint32_t rows = min(rpb, n - row0);
     if (threadIdx.x < rows * K) {
         const uint64_t at = (uint64_t)row0 * K + threadIdx.x;
-        finalize_dir(ds[at], a.nonsym ? dsy + at : nullptr, feat + threadIdx.x * kNumFeat);
+        finalize_dir<OutT>(ds[at], a.nonsym ? dsy + at : nullptr, feat + threadIdx.x * kNumFeat);
     }
     __syncthreads();
     if (row0 + rows > a.table_rows) {
@@ -1491,7 +1493,7 @@ __global__ __launch_bounds__(128) void k_features(StepArgs a, const DirSums *ds,
     uint32_t rr = threadIdx.x / per, q = threadIdx.x - rr * per;
     for (uint32_t i = threadIdx.x; i < rows * per; i += blockDim.x) {
         const uint32_t blk = q / (uint32_t)kNumFeat, f = q - blk * (uint32_t)kNumFeat;
-        const double *fr = feat + rr * K * kNumFeat;
+        const OutT *fr = feat + rr * K * kNumFeat;
         double v;
         if (blk < K) {
             v = fr[blk * kNumFeat + f];
@@ -1499,7 +1501,7 @@ __global__ __launch_bounds__(128) void k_features(StepArgs a, const DirSums *ds,
             double s = 0.0;
             int m = 0;
             for (uint32_t k = 0; k < K; ++k)
-                if (!isnan(fr[k * kNumFeat])) { s += fr[k * kNumFeat + f]; ++m; }
+                if (!isnan(fr[k * kNumFeat])) { s += (double)fr[k * kNumFeat + f]; ++m; }
             v = m ? s / (double)m : __builtin_nan("");
         }
         out[i] = (OutT)v;
@@ -1805,7 +1807,7 @@ hipError_t launch_features(const StepArgs &a, const DirSums *ds, const DirSumsY 
     if (n_cap == 0) return hipSuccess;
     const uint32_t block = 128u, rpb = block / (uint32_t)a.K_out;
     const uint32_t grid = (n_cap + rpb - 1u) / rpb;
-    const uint32_t lds = rpb * (uint32_t)a.K_out * kNumFeat * 8u;
+    const uint32_t lds = rpb * (uint32_t)a.K_out * kNumFeat * (a.fp64 ? 8u : 4u);
     if (a.fp64) hipLaunchKernelGGL(k_features<double>, dim3(grid), dim3(block), lds, st, a, ds, dsy, n_cap, n_ptr);
     else hipLaunchKernelGGL(k_features<float>, dim3(grid), dim3(block), lds, st, a, ds, dsy, n_cap, n_ptr);
     NYX_CHECK_LAUNCH();
