@@ -1042,9 +1042,12 @@ __device__ __forceinline__ void dir_or_flush(const StepArgs &a, const WaveGrp &g
 // per work-group at 64 levels keeps five work-groups on a CU; double
 // precision keeps its registers.  NS: ordered (non-symmetric) counts, a
 // separate instantiation so the symmetric kernel carries none of its code
-// (and none of its registers).
-template <int MODE, class OutT, bool NS>
-__global__ __launch_bounds__(256, (sizeof(OutT) == 4 ? 5 : 1)) void k_batch(StepArgs a, uint32_t direct_roi) {
+// (and none of its registers).  BS: threads per work-group, 256, or 512 for
+// layouts whose LDS leaves room for one work-group per CU only (eight waves
+// instead of four then share the CU's latency).
+template <int MODE, class OutT, bool NS, int BS>
+__global__ __launch_bounds__(BS, ((BS == 256 && sizeof(OutT) == 4) ? 5 : 1)) void k_batch(StepArgs a,
+                                                                                      uint32_t direct_roi) {
     extern __shared__ __align__(16) uint8_t smem[];
     typedef typename std::conditional<sizeof(OutT) == 8, double, float>::type Acc;
     const LdsLayout &Ly = a.lds;
@@ -1679,19 +1682,27 @@ hipError_t launch_bin_image(const StepArgs &a, uint16_t *bins, uint64_t total_vo
     return hipSuccess;
 }
 
-template <int MODE, class OutT, bool NS>
-static hipError_t launch_batch_t(const StepArgs &a, uint32_t grid, uint32_t block, uint32_t direct_roi,
-                                 hipStream_t st) {
+template <int MODE, class OutT, bool NS, int BS>
+static hipError_t launch_batch_b(const StepArgs &a, uint32_t grid, uint32_t direct_roi, hipStream_t st) {
     static bool attr_done = false;
     if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<MODE, OutT, NS>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_batch<MODE, OutT, NS, BS>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_done = true;
     }
-    hipLaunchKernelGGL((k_batch<MODE, OutT, NS>), dim3(grid), dim3(block), a.lds.bytes, st, a, direct_roi);
+    hipLaunchKernelGGL((k_batch<MODE, OutT, NS, BS>), dim3(grid), dim3(BS), a.lds.bytes, st, a, direct_roi);
     NYX_CHECK_LAUNCH();
     return hipSuccess;
+}
+
+// (work-groups of 256 or 512 threads: any other size is refused)
+template <int MODE, class OutT, bool NS>
+static hipError_t launch_batch_t(const StepArgs &a, uint32_t grid, uint32_t block, uint32_t direct_roi,
+                                 hipStream_t st) {
+    if (block == 512u) return launch_batch_b<MODE, OutT, NS, 512>(a, grid, direct_roi, st);
+    if (block != 256u) return hipErrorInvalidConfiguration;
+    return launch_batch_b<MODE, OutT, NS, 256>(a, grid, direct_roi, st);
 }
 
 template <int MODE, bool NS>
@@ -1717,29 +1728,33 @@ hipError_t launch_batch(const StepArgs &a, uint32_t grid, uint32_t block, uint32
 }
 
 template <int MODE, bool NS>
-static const void *batch_kernel_m(int fp64) {
-    return fp64 ? reinterpret_cast<const void *>(&k_batch<MODE, double, NS>)
-                : reinterpret_cast<const void *>(&k_batch<MODE, float, NS>);
+static const void *batch_kernel_m(int fp64, uint32_t block) {
+    if (block == 512u)
+        return fp64 ? reinterpret_cast<const void *>(&k_batch<MODE, double, NS, 512>)
+                    : reinterpret_cast<const void *>(&k_batch<MODE, float, NS, 512>);
+    return fp64 ? reinterpret_cast<const void *>(&k_batch<MODE, double, NS, 256>)
+                : reinterpret_cast<const void *>(&k_batch<MODE, float, NS, 256>);
 }
 
-static const void *batch_kernel(int mode, int fp64, int ns) {
+static const void *batch_kernel(int mode, int fp64, int ns, uint32_t block) {
     switch (mode) {
-        case 0: return batch_kernel_m<0, false>(fp64);
-        case 1: return ns ? batch_kernel_m<1, true>(fp64) : batch_kernel_m<1, false>(fp64);
-        case 2: return ns ? batch_kernel_m<2, true>(fp64) : batch_kernel_m<2, false>(fp64);
-        default: return ns ? batch_kernel_m<3, true>(fp64) : batch_kernel_m<3, false>(fp64);
+        case 0: return batch_kernel_m<0, false>(fp64, block);
+        case 1: return ns ? batch_kernel_m<1, true>(fp64, block) : batch_kernel_m<1, false>(fp64, block);
+        case 2: return ns ? batch_kernel_m<2, true>(fp64, block) : batch_kernel_m<2, false>(fp64, block);
+        default: return ns ? batch_kernel_m<3, true>(fp64, block) : batch_kernel_m<3, false>(fp64, block);
     }
 }
 
 hipError_t batch_occupancy(int mode, int fp64, int ns, uint32_t block, uint32_t lds_bytes, int *blocks_per_cu) {
-    const void *f = batch_kernel(mode, fp64, ns);
+    if (block != 256u && block != 512u) return hipErrorInvalidConfiguration;
+    const void *f = batch_kernel(mode, fp64, ns, block);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, (int)block, (size_t)lds_bytes);
 }
 
-hipError_t get_batch_attributes(int mode, int fp64, int ns, hipFuncAttributes *attr) {
-    return hipFuncGetAttributes(attr, batch_kernel(mode, fp64, ns));
+hipError_t get_batch_attributes(int mode, int fp64, int ns, uint32_t block, hipFuncAttributes *attr) {
+    return hipFuncGetAttributes(attr, batch_kernel(mode, fp64, ns, block));
 }
 
 static hipError_t set_feature_kernel_attrs() {

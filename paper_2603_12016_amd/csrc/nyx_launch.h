@@ -17,7 +17,7 @@ hipError_t launch_compact(const StepArgs &a, uint32_t roi_lo, uint32_t roi_hi, h
 hipError_t launch_bin_image(const StepArgs &a, uint16_t *bins, uint64_t total_vox, const uint64_t *img_vox_base,
                             hipStream_t st);
 hipError_t launch_batch(const StepArgs &a, uint32_t grid, uint32_t block, uint32_t direct_roi, hipStream_t st);
-hipError_t get_batch_attributes(int mode, int fp64, int ns, hipFuncAttributes *attr);
+hipError_t get_batch_attributes(int mode, int fp64, int ns, uint32_t block, hipFuncAttributes *attr);
 hipError_t batch_occupancy(int mode, int fp64, int ns, uint32_t block, uint32_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_band(const StepArgs &a, uint32_t grid, hipStream_t st);
 hipError_t launch_split_finalize(const StepArgs &a, hipStream_t st);

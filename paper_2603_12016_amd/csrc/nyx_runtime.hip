@@ -677,6 +677,17 @@ Config default_config(const std::vector<Config> &cands, const Work &w, uint32_t 
     return best ? *best : cands.front();
 }
 
+// A configuration whose LDS leaves room for one 256-thread work-group per CU
+// runs with 512 threads instead when its layout (a scan buffer and a set of
+// marginals per reducing wave) still fits: eight waves then share the CU's
+// latency instead of four.
+Config widen_block(const Config &c, uint32_t ng, int K) {
+    if (c.block != 256u || groups_per_cu(make_layout(c, ng, K, false).bytes) != 1u) return c;
+    Config w = c;
+    w.block = 512u;
+    return make_layout(w, ng, K, false).bytes <= kLdsBudget ? w : c;
+}
+
 nyx_status choose_config(nyx_ctx *ctx, const Work &w, uint32_t ng, int K, int force_split, uint32_t block,
                          Config &cfg, bool nonsym = false) {
     std::vector<Config> c = candidate_configs(ctx, w, ng, K, force_split, block, false, 1u, 1.f, nonsym);
@@ -1029,7 +1040,7 @@ nyx_status nyx_glcm_accumulate(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_im
     int occ = 0;
     {
         hipFuncAttributes fa;
-        HIPC(ctx, get_batch_attributes(a.lds.mode, 0, a.nonsym, &fa));
+        HIPC(ctx, get_batch_attributes(a.lds.mode, 0, a.nonsym, cfg.block, &fa));
         occ = 1;
     }
     const uint32_t grid = (uint32_t)ctx->n_cu * (uint32_t)std::max(occ, 1) * 2u;
@@ -1250,6 +1261,7 @@ nyx_status plan_init(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images, cons
             if (c.mode == opts->accum_mode) { cfg = c; found = true; break; }
         if (!found) return fail(ctx, NYX_ERR_UNSUPPORTED, "accumulation mode %d does not fit this workload", opts->accum_mode);
     }
+    cfg = widen_block(cfg, (uint32_t)p->ng, p->K);
     return NYX_OK;
 }
 
@@ -1281,6 +1293,12 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
                     if (cp == 1u || c.copies == cp) cands.push_back(c);
             }
         }
+        // and the work-group size: 512 threads where 256 leave one group per CU
+        const size_t n256 = cands.size();
+        for (size_t i = 0; i < n256; ++i) {
+            const Config c = widen_block(cands[i], (uint32_t)p->ng, p->K);
+            if (c.block != cands[i].block) cands.push_back(c);
+        }
     }
     if (opts->autotune && cands.size() > 1) {
         // every candidate: one warm-up step, then the median of kTuneSteps timed steps
@@ -1309,8 +1327,8 @@ nyx_status nyx_plan_create(nyx_ctx *ctx, const nyx_image *imgs, int32_t n_images
             std::sort(t, t + kTuneSteps);
             const float ms = t[kTuneSteps / 2];
             if (log_level() > 0)
-                fprintf(stderr, "[nyx] autotune %s kp=%u copies=%u tile_scale=%g: %.3f ms\n", mode_name(c.mode), c.kp,
-                        c.copies, (double)c.tile_scale, ms);
+                fprintf(stderr, "[nyx] autotune %s kp=%u copies=%u tile_scale=%g block=%u: %.3f ms\n", mode_name(c.mode),
+                        c.kp, c.copies, (double)c.tile_scale, c.block, ms);
             if (ms < best) { best = ms; cfg = c; }
         }
         for (auto &e : ev) (void)hipEventDestroy(e);

@@ -282,6 +282,38 @@ def test_plan_batched_and_per_roi(env, workloads, oracle_mod, name, mode, copies
         assert np.array_equal(replays[0], per_roi, equal_nan=True)
 
 
+@pytest.mark.parametrize("name,mode,prec", [("c2_small", "dense-list", 0), ("c2_small", "dense-list", 1),
+                                            ("c2_small", "dense-scan", 0), ("c5_small", "auto", 0)])
+def test_wide_work_groups(env, workloads, oracle_mod, name, mode, prec):
+    """Layouts that leave LDS for one work-group per CU run 512-thread
+    work-groups (eight waves sharing the item's LDS): the plan says so, and the
+    batched and per-ROI tables match the oracle."""
+    import torch
+    nyx, ctx, dev = env
+    w = workloads(name)
+    say(f"case {name} 512-thread work-groups, mode {mode}, prec {prec}")
+    imgs = device_images(w, dev)
+    offs = _offsets(nyx, w)
+    kw = {} if mode == "auto" else {"mode": mode}
+    precision = nyx.NYX_FP64 if prec else nyx.NYX_FP32
+    tol = TOL_FP64 if prec else TOL_FP32
+    plan = nyx.nyx_plan_create(ctx, imgs, w.n_bins, offs, precision, **kw)
+    desc = nyx.nyx_plan_describe(plan)
+    say("  plan:", desc)
+    assert "block=512 " in desc
+    want, Ps = _oracle_table(oracle_mod, w, offs)
+    t = nyx.new_table(plan, len(offs), precision)
+    nyx.nyx_plan_execute(plan, t)
+    torch.cuda.synchronize()
+    nyx.nyx_plan_check(plan)
+    _check_features(t.cpu().numpy()[:plan.n_rois], want, Ps, tol, f"{name} wide batched")
+    t.fill_(float("nan"))
+    nyx.nyx_plan_execute_per_roi(plan, t)
+    torch.cuda.synchronize()
+    nyx.nyx_plan_check(plan)
+    _check_features(t.cpu().numpy()[:plan.n_rois], want, Ps, tol, f"{name} wide per-roi")
+
+
 # ------------------------------------------------------------------ edge cases
 def _run_extract(nyx, ctx, dev, I, L, ng, offs, prec=1, copies=0):
     from types import SimpleNamespace
