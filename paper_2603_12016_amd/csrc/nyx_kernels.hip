@@ -583,6 +583,10 @@ __device__ __forceinline__ uint32_t row_off(uint32_t x) { return (__umul24(x - 1
 struct RowOff {
     __device__ __forceinline__ uint32_t operator()(uint32_t x) const { return row_off(x); }
 };
+// No triangle row offsets (adders that index by the levels alone).
+struct NoRowOff {
+    __device__ __forceinline__ uint32_t operator()(uint32_t) const { return 0u; }
+};
 // The same offsets read from an LDS table of levels 0..ng (entry 0 unused).
 struct RowOffTab {
     const uint32_t *t;
@@ -1192,8 +1196,10 @@ __global__ __launch_bounds__(BS, ((BS == 256 && sizeof(OutT) == 4) ? 5 : 1)) voi
 
 // ------------------------------------------------------------------ banded ROIs
 // Large split ROIs whose triangle does not fit LDS (many levels): a work item
-// is one (ROI, direction, block of bbox rows); the work-group gathers the
-// block's pairs of that direction and counts every pair with |i - j| <
+// is one (ROI, direction, block of bbox rows); the work-group takes the
+// block's pairs of that direction (by the row sweep for an in-plane
+// distance-1 offset of a 2D image, else by gather) and counts every pair with
+// |i - j| <
 // band_w into an LDS band of ng x band_w 32-bit cells (cell (lo, hi) at
 // lo * band_w + hi - lo), the rare wider pairs straight into the ROI's
 // global matrix; the band is then added once, cell by nonzero cell, into
@@ -1259,7 +1265,22 @@ __global__ __launch_bounds__(1024) void k_band(StepArgs a) {
             else
                 atomicAdd(reinterpret_cast<unsigned long long *>(&G[(uint64_t)lo * ng + hi]), 1ull);
         };
-        if (ra < rb) accumulate_rows(a, rd, c, ra, rb, 0u, W, d, d + 1, threadIdx.x, blockDim.x, add);
+        // an in-plane distance-1 offset of a 2D image: the row sweep (each
+        // voxel's level once, neighbours by lane exchange); others: gather
+        const int32_t oz = a.off[d][0], oy = a.off[d][1], ox = a.off[d][2];
+        int cls = -1;
+        if (im.nz == 1 && !c.B && oz == 0 && (oy | ox) != 0 && oy >= -1 && oy <= 1 && ox >= -1 && ox <= 1)
+            cls = oy == 0 ? 0 : (ox == 0 ? 1 : (oy * ox < 0 ? 2 : 3));
+        if (ra < rb) {
+            if (cls >= 0) {
+                const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+                accumulate_sweep2d<false>(rd, c, ra, rb, 0u, W, cls == 0 ? 0 : -1, cls == 1 ? 0 : -1,
+                                          cls == 2 ? 0 : -1, cls == 3 ? 0 : -1, w, (int)(blockDim.x / kWave),
+                                          NoRowOff{}, add);
+            } else {
+                accumulate_rows(a, rd, c, ra, rb, 0u, W, d, d + 1, threadIdx.x, blockDim.x, add);
+            }
+        }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cells; i += blockDim.x) {
             const uint32_t v = band[i];
