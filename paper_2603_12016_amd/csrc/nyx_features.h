@@ -81,32 +81,6 @@ struct WaveGrp {
     __device__ __forceinline__ uint64_t below() const { return __lanemask_lt(); }
 };
 
-// One 16-lane DPP row of a wavefront: four independent groups per wavefront,
-// reduced together by the same DPP instructions.
-struct RowGrp {
-    static constexpr bool kBatched = true;
-    __device__ __forceinline__ int rank() const { return lane() & 15; }
-    __device__ __forceinline__ int size() const { return 16; }
-    __device__ __forceinline__ double reduce_slots(double (&v)[kSumSlots]) const { return row_reduce_slots(v); }
-    __device__ __forceinline__ double reduce_pair(double a, double b) const { return row_reduce_pair(a, b); }
-    __device__ __forceinline__ double bcast(double v, int r) const { return __shfl(v, r, 16); }
-    __device__ __forceinline__ uint32_t bcast_u32(uint32_t v, int r) const { return __shfl(v, r, 16); }
-    __device__ __forceinline__ uint32_t excl_scan(uint32_t n, uint32_t *total) const {
-        const uint32_t x = row_incl_scan(n);
-        *total = (uint32_t)__shfl((int)x, 15, 16);
-        return x - n;
-    }
-    __device__ __forceinline__ int row() const { return lane() >> 4; }
-    __device__ __forceinline__ void sync() const {
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    }
-    template <class T> __device__ __forceinline__ T sum(T v) const { return row_reduce(v, OpAdd()); }
-    template <class T> __device__ __forceinline__ T max(T v) const { return row_reduce(v, OpMax()); }
-    __device__ __forceinline__ uint64_t ballot(bool p) const { return (__ballot(p) >> (16 * row())) & 0xFFFFull; }
-    __device__ __forceinline__ uint64_t below() const { return (__lanemask_lt() >> (16 * row())) & 0xFFFFull; }
-};
-
 // The whole work-group; `scratch` is LDS room for one 8-byte value per wave.
 struct BlockGrp {
     static constexpr bool kBatched = false;
