@@ -474,6 +474,40 @@ template <class Acc> __device__ __forceinline__ double mi_resum_threshold();
 template <> __device__ __forceinline__ double mi_resum_threshold<float>() { return 0.25; }
 template <> __device__ __forceinline__ double mi_resum_threshold<double>() { return 1e-3; }
 
+// Entries [0, n) of one or two LDS arrays, lane r0 taking r0, r0 + gs, ...
+// in that order: U entries per lane are read before any is used, so their
+// LDS round trips overlap (wide level ranges); fn(i, a[i]) or
+// fn(i, a[i], b[i]).  The per-lane order, and so every sum, is the same for
+// any U.
+constexpr uint32_t kWideLevels = 256u;
+template <class Src> struct is_tri_scan : std::false_type {};
+template <bool P> struct is_tri_scan<SrcTriScan<P>> : std::true_type {};
+template <uint32_t U, class Fn>
+__device__ __forceinline__ void level_sweep(uint32_t r0, uint32_t gs, uint32_t n, const uint32_t *a, Fn &&fn) {
+    for (uint32_t i0 = r0; i0 < n; i0 += U * gs) {
+        uint32_t v[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) v[u] = i0 + u * gs < n ? a[i0 + u * gs] : 0u;
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) fn(i0 + u * gs, v[u]);
+    }
+}
+template <uint32_t U, class Fn>
+__device__ __forceinline__ void level_sweep(uint32_t r0, uint32_t gs, uint32_t n, const uint32_t *a,
+                                            const uint32_t *b, Fn &&fn) {
+    for (uint32_t i0 = r0; i0 < n; i0 += U * gs) {
+        uint32_t v[U], w[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * gs;
+            v[u] = i < n ? a[i] : 0u;
+            w[u] = i < n ? b[i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) fn(i0 + u * gs, v[u], w[u]);
+    }
+}
+
 // Reduced sums of one direction.  R, Sp, Sm are zeroed LDS arrays of ng,
 // 2 ng - 1 and ng u32 (row, sum and difference marginals of the symmetric
 // matrix); they are zeroed again on return, and the source is cleared.
@@ -512,8 +546,7 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
     ISum Tl = 0, S1 = 0, S2 = 0, Sm1 = 0, S11 = 0;
     LaneSum<Acc> rlr, slp, hom1, hom2, idmn, idn, iv, plps;
     const Acc ngf = (Acc)ng, rng = (Acc)1 / ngf, rng2 = rng * rng;
-    for (uint32_t i = r0; i < ng; i += gs) {
-        const uint32_t r = R[i];
+    auto row_diff = [&](uint32_t i, uint32_t r, uint32_t s) {
         if (r) {
             const ISum lv = (ISum)(i + 1u);
             Tl += (ISum)r;
@@ -521,7 +554,6 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
             S2 += lv * lv * (ISum)r;
             rlr.add((Acc)r * term_log2<Acc>((Acc)r));
         }
-        const uint32_t s = Sm[i];
         if (s) {
             Sm1 += (ISum)i * (ISum)s;
             S11 += (ISum)(i * i) * (ISum)s;   // K2 (i < 2^13)
@@ -533,10 +565,21 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
             idn.add(term_div<Acc>(sf, (Acc)1 + k * rng));
             if (i > 0) iv.add(term_div<Acc>(sf, k * k));
         }
-    }
-    for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) {
-        const uint32_t s = Sp[k];
+    };
+    auto sum_ent = [&](uint32_t, uint32_t s) {
         if (s) plps.add((Acc)s * term_log2<Acc>((Acc)s));
+    };
+    // (the scan sources serve the small level counts: one entry at a time)
+    constexpr bool wide_ok = !is_tri_scan<Src>::value;
+    const bool wide = wide_ok && ng >= kWideLevels;
+    if (wide) {
+        if constexpr (wide_ok) {
+            level_sweep<4>(r0, gs, ng, R, Sm, row_diff);
+            level_sweep<4>(r0, gs, 2u * ng - 1u, Sp, sum_ent);
+        }
+    } else {
+        level_sweep<1>(r0, gs, ng, R, Sm, row_diff);
+        level_sweep<1>(r0, gs, 2u * ng - 1u, Sp, sum_ent);
     }
     // Group totals.  Batched groups reduce the sixteen slots of DirSums at
     // once (rank r < 16 ends with slot r); the others reduce value by value.
@@ -585,8 +628,7 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
     // gives d = 0 exactly)
     const double two_mu = (double)(2u * S1t) / Td;
     double cs = 0.0, cp = 0.0;
-    for (uint32_t k = r0; k < 2u * ng - 1u; k += gs) {
-        const uint32_t s = Sp[k];
+    auto shade = [&](uint32_t k, uint32_t s) {
         if (s) {
             const double p = (double)s * invT;
             const double d = (double)(k + 2u) - two_mu;
@@ -594,6 +636,11 @@ __device__ uint64_t dir_sums(const Grp &g, const Src &src, uint32_t *R, uint32_t
             cs += d3 * p;
             cp += d3 * d * p;
         }
+    };
+    if (wide) {
+        if constexpr (wide_ok) level_sweep<4>(r0, gs, 2u * ng - 1u, Sp, shade);
+    } else {
+        level_sweep<1>(r0, gs, 2u * ng - 1u, Sp, shade);
     }
     double CSHADE, CPROM;
     if constexpr (Grp::kBatched) {
