@@ -673,12 +673,19 @@ def test_plan_profile_phases(env, workloads):
 
 
 # ------------------------------------------------------------------ banded accumulation
-@pytest.mark.parametrize("shape,ng,smooth", [((28, 44, 44), 512, False), ((1, 300, 320), 2048, True)])
-def test_banded_counts_exact(env, oracle_mod, shape, ng, smooth):
+# flipped in-plane offsets (the same unordered pairs as the default four,
+# pointing the other way) and an in-plane offset at distance 2 (gathered)
+_FLIPPED_2D = [(0, 0, -1), (0, 1, 1), (0, 1, 0), (0, 1, -1), (0, -2, 2)]
+
+
+@pytest.mark.parametrize("shape,ng,smooth,offs", [((28, 44, 44), 512, False, None), ((1, 300, 320), 2048, True, None),
+                                                  ((1, 300, 320), 2048, True, _FLIPPED_2D)])
+def test_banded_counts_exact(env, oracle_mod, shape, ng, smooth, offs):
     """ROIs above the banded kernel's size threshold at bin counts whose
     triangle exceeds LDS: exact counts through nyx_glcm_accumulate and the
     batched features, with pairs inside the LDS band and (uniform noise) far
-    outside it."""
+    outside it; in 2D the in-plane distance-1 offsets go through the row
+    sweep whichever way they point, others through the gather."""
     import torch
     from types import SimpleNamespace
     nyx, ctx, dev = env
@@ -692,8 +699,9 @@ def test_banded_counts_exact(env, oracle_mod, shape, ng, smooth):
     L = np.ones(shape, np.uint32)
     L[:, :5, :] = 2                                   # a second, smaller ROI
     L[0, 0, 0] = 0
-    offs = nyx.nyx_offsets_default(3 if shape[0] > 1 else 2, 1)
-    say(f"case banded counts {shape} ng={ng} smooth={smooth}")
+    if offs is None:
+        offs = nyx.nyx_offsets_default(3 if shape[0] > 1 else 2, 1)
+    say(f"case banded counts {shape} ng={ng} smooth={smooth} offsets={offs}")
     w = SimpleNamespace(intensity=I[None], labels=L[None], n_images=1)
     imgs = device_images(w, dev)
     plan = nyx.nyx_plan_create(ctx, imgs, ng, offs, nyx.NYX_FP64)
