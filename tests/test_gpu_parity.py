@@ -377,6 +377,7 @@ _OFF3 = [(0, 0, 1), (0, 1, 0), (1, 0, 0), (0, 1, 1), (0, 1, -1), (1, 0, 1), (1, 
 # backwards, at distance 2, or few): the staged and gather accumulations.
 @pytest.mark.parametrize("offs,shape", [([(0, 0, 2), (0, -2, 2), (0, -2, 0), (0, -2, -2)], (1, 30, 31)),
                                         ([(0, 1, 3), (0, 0, -1), (0, 2, 0)], (1, 30, 31)),
+                                        ([(0, 0, -1), (0, 1, 1), (0, 1, 0), (0, 1, -1)], (1, 30, 31)),
                                         ([(-a, -b, -c) for a, b, c in _OFF3], (7, 19, 23)),
                                         ([(2 * a, 2 * b, 2 * c) for a, b, c in _OFF3], (9, 17, 15)),
                                         ([(1, 0, 0), (0, -1, 2), (-2, 1, 1)], (8, 12, 40))])
