@@ -386,11 +386,15 @@ struct SrcCoo {
 // y: the column-marginal sums of a non-symmetric matrix (nullptr: the matrix
 // is symmetric and its column marginal is its row marginal).  Computed in
 // double precision; out holds the output precision (OutT: float or double).
+// xd (may be null): cluster shade and correlation in double as well, the two
+// features whose directions can differ in sign, so that a direction mean
+// formed from single-precision values does not lose their cancellation.
 template <class OutT>
-__device__ __noinline__ void finalize_dir(const DirSums &s, const DirSumsY *y, OutT *out) {
+__device__ __noinline__ void finalize_dir(const DirSums &s, const DirSumsY *y, OutT *out, double *xd) {
     const uint64_t T = s.T;
     if (T == 0) {
         for (int f = 0; f < kNumFeat; ++f) out[f] = __builtin_nan("");
+        if (xd) xd[0] = xd[1] = __builtin_nan("");
         return;
     }
     const uint64_t S1 = s.S1, S2 = s.S2, S11 = s.S11, Sm1 = s.Sm1;
@@ -419,9 +423,14 @@ __device__ __noinline__ void finalize_dir(const DirSums &s, const DirSumsY *y, O
     out[F_CLUSHADE] = s.CSHADE;
     out[F_CLUTEND] = out[F_SUMVAR] = i128_to_double((i128)nvar + (i128)nvary + 2 * ncov) / T2;
     out[F_CONTRAST] = u128_to_double(sm2) / Td;
-    out[F_CORR] = single ? 1.0
-                         : i128_to_double(ncov) /
-                               (y ? sqrt(u128_to_double(nvar)) * sqrt(u128_to_double(nvary)) : u128_to_double(nvar));
+    const double corr = single ? 1.0
+                               : i128_to_double(ncov) / (y ? sqrt(u128_to_double(nvar)) * sqrt(u128_to_double(nvary))
+                                                           : u128_to_double(nvar));
+    out[F_CORR] = corr;
+    if (xd) {
+        xd[0] = s.CSHADE;
+        xd[1] = corr;
+    }
     out[F_DIFAVE] = out[F_DIS] = (double)Sm1 / Td;
     out[F_DIFENTRO] = lgT - s.slp * invT;
     out[F_DIFVAR] = u128_to_double(ndv) / T2;

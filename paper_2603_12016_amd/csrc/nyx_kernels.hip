@@ -1492,17 +1492,21 @@ __global__ __launch_bounds__(128, 4) void k_features(StepArgs a, const DirSums *
                                                   uint32_t n_cap, const uint32_t *n_ptr) {
     extern __shared__ __align__(16) uint8_t smem[];
     // staged in the output precision: single-precision tables take half the
-    // LDS, so twice as many work-groups fit a CU
+    // LDS, so twice as many work-groups fit a CU; they keep cluster shade and
+    // correlation in double beside (xd), for the direction mean
+    constexpr bool kXd = sizeof(OutT) == 4;
     OutT *feat = reinterpret_cast<OutT *>(smem);
     const uint32_t K = (uint32_t)a.K_out;
     const uint32_t rpb = blockDim.x / K;
+    double *xd = reinterpret_cast<double *>(smem + (size_t)rpb * K * kNumFeat * sizeof(OutT));
     const uint32_t n = n_ptr ? min(*n_ptr, n_cap) : n_cap;
     const uint32_t row0 = blockIdx.x * rpb;
     if (row0 >= n) return;
     uint32_t rows = min(rpb, n - row0);
     if (threadIdx.x < rows * K) {
         const uint64_t at = (uint64_t)row0 * K + threadIdx.x;
-        finalize_dir<OutT>(ds[at], a.nonsym ? dsy + at : nullptr, feat + threadIdx.x * kNumFeat);
+        finalize_dir<OutT>(ds[at], a.nonsym ? dsy + at : nullptr, feat + threadIdx.x * kNumFeat,
+                           kXd ? xd + 2u * threadIdx.x : nullptr);
     }
     __syncthreads();
     if (row0 + rows > a.table_rows) {
@@ -1522,10 +1526,16 @@ __global__ __launch_bounds__(128, 4) void k_features(StepArgs a, const DirSums *
         if (blk < K) {
             v = fr[blk * kNumFeat + f];
         } else {
+            // (cluster shade and correlation from their double copies)
+            const int x = !kXd ? -1 : (f == F_CLUSHADE ? 0 : (f == F_CORR ? 1 : -1));
+            const double *xr = xd + 2u * rr * K;
             double s = 0.0;
             int m = 0;
             for (uint32_t k = 0; k < K; ++k)
-                if (!isnan(fr[k * kNumFeat])) { s += (double)fr[k * kNumFeat + f]; ++m; }
+                if (!isnan(fr[k * kNumFeat])) {
+                    s += x >= 0 ? xr[2u * k + (uint32_t)x] : (double)fr[k * kNumFeat + f];
+                    ++m;
+                }
             v = m ? s / (double)m : __builtin_nan("");
         }
         out[i] = (OutT)v;
@@ -1843,7 +1853,7 @@ hipError_t launch_features(const StepArgs &a, const DirSums *ds, const DirSumsY 
     if (n_cap == 0) return hipSuccess;
     const uint32_t block = 128u, rpb = block / (uint32_t)a.K_out;
     const uint32_t grid = (n_cap + rpb - 1u) / rpb;
-    const uint32_t lds = rpb * (uint32_t)a.K_out * kNumFeat * (a.fp64 ? 8u : 4u);
+    const uint32_t lds = rpb * (uint32_t)a.K_out * (a.fp64 ? kNumFeat * 8u : kNumFeat * 4u + 16u);
     if (a.fp64) hipLaunchKernelGGL(k_features<double>, dim3(grid), dim3(block), lds, st, a, ds, dsy, n_cap, n_ptr);
     else hipLaunchKernelGGL(k_features<float>, dim3(grid), dim3(block), lds, st, a, ds, dsy, n_cap, n_ptr);
     NYX_CHECK_LAUNCH();
